@@ -46,6 +46,10 @@ def lib():
         L.oracle_lattice_f0.argtypes = [d, d, i64]
         L.oracle_eval.restype = None
         L.oracle_eval.argtypes = [P, i32, P, i64, i64, P, P, P, P, P]
+        L.oracle_eval_list.restype = None
+        L.oracle_eval_list.argtypes = [P, i32, P, P, i64, P, P, P, P, P]
+        L.oracle_threads.restype = i32
+        L.oracle_threads.argtypes = []
         L.oracle_track_bins.restype = None
         L.oracle_track_bins.argtypes = [P, d, d, d, P, d, P]
         L.oracle_count_q.restype = d
@@ -200,6 +204,27 @@ def evaluate(dets, grid: Grid, begin=0, end=None):
     lib().oracle_eval(C.cast(arr, C.c_void_p), len(dets), C.byref(gs), int(begin), int(end),
                       _p(out["s"]), _p(out["c"]), _p(out["N"]), _p(out["W1"]), _p(out["W2"]))
     return out
+
+
+def evaluate_list(dets, grid: Grid, index):
+    """Statistic for the template indices in `index` (any order, repeats allowed)."""
+    if isinstance(dets, Detector):
+        dets = [dets]
+    index = np.ascontiguousarray(index, dtype=np.int64)
+    n = index.size
+    out = {"s": np.empty(n, np.float64), "c": np.empty(n, np.int32),
+           "N": np.empty(n, np.int32), "W1": np.empty(n, np.float64),
+           "W2": np.empty(n, np.float64)}
+    arr = (_Det * len(dets))(*[d._struct() for d in dets])
+    gs = grid._struct()
+    lib().oracle_eval_list(C.cast(arr, C.c_void_p), len(dets), C.byref(gs), _p(index), n,
+                           _p(out["s"]), _p(out["c"]), _p(out["N"]), _p(out["W1"]), _p(out["W2"]))
+    return out
+
+
+def threads():
+    """Threads the oracle's parallel loops use."""
+    return lib().oracle_threads()
 
 
 def count_q(rho_th=1.6):

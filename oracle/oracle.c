@@ -28,6 +28,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORACLE_C_LIGHT 299792458.0 /* m/s, exact by SI definition */
 
@@ -123,7 +126,8 @@ static void decode_index(const oracle_grid *g, int64_t t, int64_t *i_f0,
 /* Per-segment tables that do not depend on f0: g[d][n][tau][j] and
  * D[d][sky][j].  Hoisting them changes no result (both are pure functions
  * of their arguments). */
-static double **build_g(const oracle_det *dets, int32_t n_det, const oracle_grid *g)
+static double **build_g(const oracle_det *dets, int32_t n_det, const oracle_grid *g,
+                        const unsigned char *need /* [n_brake*n_tau] or NULL = all */)
 {
     double **tab = (double **)calloc((size_t)n_det, sizeof(double *));
     for (int32_t d = 0; d < n_det; ++d) {
@@ -131,9 +135,10 @@ static double **build_g(const oracle_det *dets, int32_t n_det, const oracle_grid
         int64_t ng = (int64_t)g->n_brake * g->n_tau;
         tab[d] = (double *)malloc((size_t)(ng * ns) * sizeof(double));
         double *T = tab[d];
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 256)
         for (int64_t q = 0; q < ng * ns; ++q) {
             int64_t j = q % ns, grp = q / ns;
+            if (need && !need[grp]) { T[q] = 0.0; continue; }
             int64_t it = grp % g->n_tau, in = grp / g->n_tau;
             T[q] = oracle_spin_factor(dets[d].t_seg[j], g->t0, g->tau[it], g->brake[in]);
         }
@@ -166,14 +171,20 @@ static void free_tabs(double **t, int32_t n)
  *   N  = number of in-band (d, j); W1 = sum w_j ; W2 = sum w_j^2
  * Outputs are indexed by t - t_begin.  Masked (t_j < T0) and out-of-band
  * segments contribute nothing. */
-void oracle_eval(const oracle_det *dets, int32_t n_det, const oracle_grid *g,
-                 int64_t t_begin, int64_t t_end, double *s, int32_t *c,
-                 int32_t *N, double *W1, double *W2)
+static void eval_templates(const oracle_det *dets, int32_t n_det, const oracle_grid *g,
+                           const int64_t *list, int64_t t_begin, int64_t n, double *s,
+                           int32_t *c, int32_t *N, double *W1, double *W2)
 {
-    double **gt = build_g(dets, n_det, g);
+    unsigned char *need = NULL;
+    if (list) {
+        need = (unsigned char *)calloc((size_t)g->n_brake * g->n_tau, 1);
+        for (int64_t q = 0; q < n; ++q) need[(list[q] / g->n_f0) % ((int64_t)g->n_brake * g->n_tau)] = 1;
+    }
+    double **gt = build_g(dets, n_det, g, need);
     double **Dt = build_D(dets, n_det, g);
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t t = t_begin; t < t_end; ++t) {
+    for (int64_t o = 0; o < n; ++o) {
+        int64_t t = list ? list[o] : t_begin + o;
         int64_t i_f0, i_tau, i_n, i_sky;
         decode_index(g, t, &i_f0, &i_tau, &i_n, &i_sky);
         double f0 = oracle_lattice_f0(g->f0_min, g->f0_step, i_f0);
@@ -196,7 +207,6 @@ void oracle_eval(const oracle_det *dets, int32_t n_det, const oracle_grid *g,
                 w2 = w2 + wj * wj;
             }
         }
-        int64_t o = t - t_begin;
         if (s) s[o] = acc;
         if (c) c[o] = cnt;
         if (N) N[o] = nin;
@@ -205,6 +215,22 @@ void oracle_eval(const oracle_det *dets, int32_t n_det, const oracle_grid *g,
     }
     free_tabs(gt, n_det);
     free_tabs(Dt, n_det);
+    free(need);
+}
+
+void oracle_eval(const oracle_det *dets, int32_t n_det, const oracle_grid *g,
+                 int64_t t_begin, int64_t t_end, double *s, int32_t *c,
+                 int32_t *N, double *W1, double *W2)
+{
+    eval_templates(dets, n_det, g, NULL, t_begin, t_end - t_begin, s, c, N, W1, W2);
+}
+
+/* The same statistic for an explicit list of template indices. */
+void oracle_eval_list(const oracle_det *dets, int32_t n_det, const oracle_grid *g,
+                      const int64_t *list, int64_t n, double *s, int32_t *c, int32_t *N,
+                      double *W1, double *W2)
+{
+    eval_templates(dets, n_det, g, list, 0, n, s, c, N, W1, W2);
 }
 
 /* Bins of one template on one detector: b_out[j] = column, or INT64_MIN for a
@@ -358,4 +384,14 @@ void oracle_spin_factor_array(const double *t, int64_t n, double t0, double tau,
                               double brake, double *out)
 {
     for (int64_t i = 0; i < n; ++i) out[i] = oracle_spin_factor(t[i], t0, tau, brake);
+}
+
+/* Threads the oracle's parallel loops use. */
+int32_t oracle_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -1,0 +1,164 @@
+// Correctly rounded FP64 power u^e for the spin-down factor of Eq. 1
+// (g = (1 + (t - T0)/tau)^(1/(1-n))), in double-double arithmetic.
+//
+// Building blocks are the error-free transformations of Knuth (TwoSum) and
+// Dekker (Fast2Sum; exact product via a fused multiply-add), combined into
+// double-double add/multiply/divide in the way of Hida, Li and Bailey's
+// double-double arithmetic.  On top of them:
+//   exp:  Y = k ln2 + r with a three-part ln2 (so k*ln2_1 is exact for
+//         |k| < 2^11), r scaled by 2^-8, Taylor series of expm1(r) to r^10,
+//         then eight doublings expm1(2x) = expm1(x) (expm1(x) + 2).
+//   log:  one Newton step on exp: y0 = log(u) from the device math library,
+//         d = u e^-y0 - 1, log u = y0 + d - d^2/2 (+O(d^3), |d| < 2^-50).
+//   pow:  exp(e * log u); result error below 2^-98 relative.  The nearest
+//         double is returned; when the double-double value lies too close to
+//         a rounding boundary to decide, the caller is told (undecided = 1).
+//
+// ln 2 = 0.693147180559945309417232121458176568075500134360255254120680...
+// split as ln2_1 (42 significant bits) + ln2_2 + ln2_3 (each the nearest
+// double of the remainder); the split is checked by a host test against a
+// 60-digit decimal ln 2.
+//
+// Everything here must be compiled without floating-point contraction.
+#pragma once
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#ifdef __HIPCC__
+#define LTGW_HD __host__ __device__ inline
+#else
+#define LTGW_HD inline
+#endif
+
+#pragma clang fp contract(off)
+
+namespace ltgw {
+
+struct dd {
+    double hi, lo;
+};
+
+constexpr double kLn2_1 = 0x1.62e42fefa3800p-1;
+constexpr double kLn2_2 = 0x1.ef35793c76730p-45;
+constexpr double kLn2_3 = 0x1.f97b57a079a19p-103;
+constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+
+LTGW_HD dd two_sum(double a, double b) {
+    double s = a + b;
+    double bb = s - a;
+    double e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+// requires |a| >= |b| or a == 0
+LTGW_HD dd fast_two_sum(double a, double b) {
+    double s = a + b;
+    double e = b - (s - a);
+    return {s, e};
+}
+LTGW_HD dd two_prod(double a, double b) {
+    double p = a * b;
+    double e = std::fma(a, b, -p);
+    return {p, e};
+}
+LTGW_HD dd dd_add(dd a, dd b) {
+    dd s = two_sum(a.hi, b.hi);
+    dd t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = fast_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return fast_two_sum(s.hi, s.lo);
+}
+LTGW_HD dd dd_add_d(dd a, double b) {
+    dd s = two_sum(a.hi, b);
+    s.lo += a.lo;
+    return fast_two_sum(s.hi, s.lo);
+}
+LTGW_HD dd dd_mul(dd a, dd b) {
+    dd p = two_prod(a.hi, b.hi);
+    p.lo += a.hi * b.lo + a.lo * b.hi;
+    return fast_two_sum(p.hi, p.lo);
+}
+LTGW_HD dd dd_mul_d(dd a, double b) {
+    dd p = two_prod(a.hi, b);
+    p.lo += a.lo * b;
+    return fast_two_sum(p.hi, p.lo);
+}
+LTGW_HD dd dd_div_d(dd a, double b) {
+    double q1 = a.hi / b;
+    dd p = two_prod(q1, b);
+    dd s = two_sum(a.hi, -p.hi);
+    s.lo -= p.lo;
+    s.lo += a.lo;
+    double q2 = (s.hi + s.lo) / b;
+    return fast_two_sum(q1, q2);
+}
+
+// e^Y for |Y.hi| < 700.
+LTGW_HD dd dd_exp(dd Y) {
+    double kf = std::rint(Y.hi * kInvLn2);
+    // Y - k ln2: k*ln2_1 is exact and Y.hi - k*ln2_1 is exact (Sterbenz)
+    double a = Y.hi - kf * kLn2_1;
+    dd r = two_sum(a, Y.lo);
+    dd kl2 = two_prod(kf, kLn2_2);
+    kl2.lo += kf * kLn2_3;
+    r = dd_add(r, dd{-kl2.hi, -kl2.lo});
+    // r in [-0.35, 0.35]; scale into |r| < 1.36e-3
+    r.hi *= 0x1p-8;
+    r.lo *= 0x1p-8;
+    // expm1(r) = r (1 + r/2 (1 + r/3 (... (1 + r/10))))
+    dd p = dd_div_d(r, 10.0);
+    for (int m = 9; m >= 2; --m) p = dd_div_d(dd_mul(dd_add_d(p, 1.0), r), (double)m);
+    p = dd_mul(dd_add_d(p, 1.0), r);
+    for (int i = 0; i < 8; ++i) p = dd_mul(p, dd_add_d(p, 2.0));
+    dd e = dd_add_d(p, 1.0);
+    int k = (int)kf;
+    return {std::ldexp(e.hi, k), std::ldexp(e.lo, k)};
+}
+
+// log(u) for finite u > 0.
+LTGW_HD dd dd_log(double u) {
+    double y0 = std::log(u);
+    dd E = dd_exp(dd{y0, 0.0});
+    dd d = two_sum(u, -E.hi);
+    double num = d.hi + (d.lo - E.lo);
+    double dl = num / E.hi;
+    double corr = dl - 0.5 * dl * dl;
+    return fast_two_sum(y0, corr);
+}
+
+LTGW_HD uint64_t bits_of(double x) {
+    uint64_t b;
+    std::memcpy(&b, &x, 8);
+    return b;
+}
+LTGW_HD double from_bits(uint64_t b) {
+    double x;
+    std::memcpy(&x, &b, 8);
+    return x;
+}
+
+// RN(u^e) for finite u > 0, finite e, with u^e a normal double.
+// *undecided = 1 when the double-double result (relative error < 2^-98) is
+// within that error of the midpoint between two doubles.
+LTGW_HD double pow_cr(double u, double e, int *undecided) {
+    *undecided = 0;
+    if (u == 1.0) return 1.0;
+    dd L = dd_log(u);
+    dd Y = dd_mul_d(L, e);
+    if (!(std::fabs(Y.hi) < 700.0)) {
+        *undecided = 1;
+        return std::exp(Y.hi);
+    }
+    dd R = dd_exp(Y);
+    R = fast_two_sum(R.hi, R.lo);
+    double G = R.hi;
+    uint64_t gb = bits_of(G);
+    double up = from_bits(gb + 1) - G;   // G > 0 and normal
+    double dn = G - from_bits(gb - 1);
+    double tol = G * 0x1p-98;
+    if (!(R.lo + tol < 0.5 * up) || !(R.lo - tol > -0.5 * dn)) *undecided = 1;
+    return G;
+}
+
+}  // namespace ltgw

@@ -1,0 +1,600 @@
+// C-ABI of the ltgw library: context, validation, device buffers, launches.
+// The declarations and their contracts are in include/ltgw.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ltgw_internal.h"
+
+using namespace ltgw;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct Det {
+    bool loaded = false, has_v = false;
+    int32_t n_seg = 0, n_bins = 0, store = 0;
+    int64_t k_lo = 0, pitch = 0;
+    double t_sft = 0.0;
+    float rho_th = 1.6f;
+    bool weighted = false;
+    float w_uniform = 1.0f;
+    double v_max = 0.0;  // max |v| / c
+    DevBuf store_buf, t_seg, w, wq, scale, v, g, H;
+};
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct ltgw_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    Det det[LTGW_MAX_DET];
+    DevBuf staging, counters;
+    DevBuf tau_d, brake_d, sky_d;
+    DevBuf res_s, res_c, res_n, res_w1, res_w2;
+    DevBuf cand_pa, cand_ia, cand_pb, cand_ib, cand_out, n_out;
+    std::vector<double> h_tau, h_brake, h_sky;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // tables start, eval start, eval end
+    hipEvent_t ev_h2d = nullptr;  // after the grid uploads from h_tau/h_brake/h_sky
+    // last eval
+    bool have_eval = false;
+    int64_t n_templates = 0, n_evals = 0;
+    double f0_min = 0.0, f0_step = 0.0;
+    int32_t n_f0 = 0, n_tau = 0, n_brake = 0, n_sky = 0;
+    float rho_th = 1.6f;
+};
+
+namespace {
+
+int fail(ltgw_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+int hip_fail(ltgw_ctx *c, hipError_t e, const char *what) {
+    return fail(c, e == hipErrorOutOfMemory ? LTGW_E_NOMEM : LTGW_E_DEVICE, "%s: %s (%s)", what,
+                hipGetErrorName(e), hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr, what)                           \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+int ensure(ltgw_ctx *c, DevBuf &b, size_t bytes, const char *what) {
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return LTGW_OK;
+    if (b.p) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "synchronize before realloc");
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, LTGW_E_NOMEM, "device allocation of %zu bytes for %s failed: %s", bytes, what,
+                    hipGetErrorString(e));
+    }
+    b.p = p;
+    b.cap = bytes;
+    return LTGW_OK;
+}
+
+void release(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// Copy n bytes from a host-or-device pointer to host memory.
+int to_host(ltgw_ctx *c, void *dst, const void *src, size_t n, const char *what) {
+    if (n == 0) return LTGW_OK;
+    if (is_device_ptr(src)) {
+        HIP_TRY(c, hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, c->stream), what);
+        HIP_TRY(c, hipStreamSynchronize(c->stream), what);
+    } else {
+        std::memcpy(dst, src, n);
+    }
+    return LTGW_OK;
+}
+
+int h2d(ltgw_ctx *c, void *dst, const void *src, size_t n, const char *what) {
+    if (n == 0) return LTGW_OK;
+    HIP_TRY(c, hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, c->stream), what);
+    return LTGW_OK;
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+int zero_counter(ltgw_ctx *c, int first, int n) {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, c->stream,
+                       (unsigned long long *)c->counters.p + first, n);
+    HIP_TRY(c, hipGetLastError(), "zero counters");
+    return LTGW_OK;
+}
+
+// counters: [0] pow undecided, [1] bad power values, [2] in-band total
+constexpr int kCntUndecided = 0, kCntBad = 1, kCntInBand = 2, kNumCnt = 4;
+
+int read_counter(ltgw_ctx *c, int i, unsigned long long *out) {
+    HIP_TRY(c, hipMemcpyAsync(out, (unsigned long long *)c->counters.p + i, sizeof *out,
+                              hipMemcpyDeviceToHost, c->stream),
+            "read counter");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "read counter");
+    return LTGW_OK;
+}
+
+bool fin(double x) { return std::isfinite(x); }
+
+struct Enter {
+    explicit Enter(ltgw_ctx *c) {
+        if (c) {
+            c->err.clear();
+            (void)hipSetDevice(c->device);
+        }
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t ltgw_create(int32_t device, void *hip_stream, ltgw_ctx **out) {
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "ltgw_create: out is NULL";
+        return LTGW_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        g_create_error = std::string("ltgw_create: no HIP device: ") + hipGetErrorString(e);
+        return LTGW_E_DEVICE;
+    }
+    if (device < 0 || device >= n) {
+        g_create_error = "ltgw_create: device index out of range";
+        return LTGW_E_INVALID_ARG;
+    }
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        g_create_error = std::string("ltgw_create: hipSetDevice: ") + hipGetErrorString(e);
+        return LTGW_E_DEVICE;
+    }
+    ltgw_ctx *c = new (std::nothrow) ltgw_ctx();
+    if (!c) {
+        g_create_error = "ltgw_create: host allocation failed";
+        return LTGW_E_NOMEM;
+    }
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    int rc = ensure(c, c->counters, kNumCnt * sizeof(unsigned long long), "counters");
+    if (rc == LTGW_OK) rc = zero_counter(c, 0, kNumCnt);
+    for (int i = 0; i < 3 && rc == LTGW_OK; ++i) {
+        hipError_t ee = hipEventCreate(&c->ev[i]);
+        if (ee != hipSuccess) rc = hip_fail(c, ee, "event create");
+    }
+    if (rc == LTGW_OK) {
+        hipError_t ee = hipEventCreateWithFlags(&c->ev_h2d, hipEventDisableTiming);
+        if (ee != hipSuccess) rc = hip_fail(c, ee, "event create");
+    }
+    if (rc != LTGW_OK) {
+        g_create_error = c->err;
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return LTGW_OK;
+}
+
+void ltgw_destroy(ltgw_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->ev_h2d) (void)hipEventDestroy(c->ev_h2d);
+    for (auto &d : c->det) {
+        release(d.store_buf); release(d.t_seg); release(d.w); release(d.wq);
+        release(d.scale); release(d.v); release(d.g); release(d.H);
+    }
+    DevBuf *all[] = {&c->staging, &c->counters, &c->tau_d, &c->brake_d, &c->sky_d,
+                     &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2,
+                     &c->cand_pa, &c->cand_ia, &c->cand_pb, &c->cand_ib, &c->cand_out, &c->n_out};
+    for (DevBuf *b : all) release(*b);
+    delete c;
+}
+
+const char *ltgw_last_error(const ltgw_ctx *c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+int32_t ltgw_load_spectrogram(ltgw_ctx *c, int32_t det, const ltgw_spec_desc *d,
+                              const float *power) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (det < 0 || det >= LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "detector %d out of range", det);
+    if (!d || !power) return fail(c, LTGW_E_INVALID_ARG, "descriptor or power is NULL");
+    if (d->n_seg < 1 || d->n_bins < 1) return fail(c, LTGW_E_INVALID_ARG, "n_seg and n_bins must be >= 1");
+    if (d->k_lo < 2 || d->k_lo + d->n_bins >= (int64_t)1 << 30)
+        return fail(c, LTGW_E_INVALID_ARG, "k_lo must satisfy 2 <= k_lo and k_lo + n_bins < 2^30");
+    if (!(d->t_sft > 0.0) || !fin(d->t_sft)) return fail(c, LTGW_E_INVALID_ARG, "t_sft must be finite and > 0");
+    if (!d->t_seg) return fail(c, LTGW_E_INVALID_ARG, "t_seg is NULL");
+    if (!std::isfinite(d->rho_th)) return fail(c, LTGW_E_INVALID_ARG, "rho_th must be finite");
+    if (d->store != LTGW_STORE_F32 && d->store != LTGW_STORE_BF16 && d->store != LTGW_STORE_FP8)
+        return fail(c, LTGW_E_INVALID_ARG, "unknown store %d", d->store);
+    Det &D = c->det[det];
+    D.loaded = false;
+    D.has_v = false;
+    const int64_t ns = d->n_seg, nb = d->n_bins;
+    std::vector<double> ht(ns);
+    std::vector<float> hw(ns, 1.0f);
+    int rc;
+    if ((rc = to_host(c, ht.data(), d->t_seg, ns * sizeof(double), "t_seg")) != LTGW_OK) return rc;
+    if (d->weights && (rc = to_host(c, hw.data(), d->weights, ns * sizeof(float), "weights")) != LTGW_OK)
+        return rc;
+    for (int64_t j = 0; j < ns; ++j) {
+        if (!fin(ht[j])) return fail(c, LTGW_E_INVALID_ARG, "t_seg[%lld] is not finite", (long long)j);
+        if (!(hw[j] > 0.0f) || !std::isfinite(hw[j]))
+            return fail(c, LTGW_E_INVALID_ARG, "weights[%lld] must be finite and > 0", (long long)j);
+    }
+    bool weighted = false;
+    for (int64_t j = 1; j < ns; ++j) weighted |= (hw[j] != hw[0]);
+    const int esize = d->store == LTGW_STORE_F32 ? 4 : d->store == LTGW_STORE_BF16 ? 2 : 1;
+    const int64_t pitch = ((nb + 2 + 63) / 64) * 64;
+    if (ns * pitch * esize >= ((int64_t)1 << 31))
+        return fail(c, LTGW_E_UNSUPPORTED, "spectrogram store of %lld bytes exceeds 2^31 per detector",
+                    (long long)(ns * pitch * esize));
+    if ((rc = ensure(c, D.store_buf, (size_t)(ns * pitch * esize), "spectrogram store")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, D.t_seg, ns * sizeof(double), "t_seg")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, D.w, ns * sizeof(float), "weights")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, D.wq, ns * sizeof(float), "scaled weights")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, D.scale, ns * sizeof(float), "scales")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, D.t_seg.p, ht.data(), ns * sizeof(double), "t_seg upload")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, D.w.p, hw.data(), ns * sizeof(float), "weights upload")) != LTGW_OK) return rc;
+    const float *src = power;
+    if (!is_device_ptr(power)) {
+        if ((rc = ensure(c, c->staging, (size_t)(ns * nb) * sizeof(float), "power staging")) != LTGW_OK)
+            return rc;
+        if ((rc = h2d(c, c->staging.p, power, (size_t)(ns * nb) * sizeof(float), "power upload")) != LTGW_OK)
+            return rc;
+        src = (const float *)c->staging.p;
+    }
+    if ((rc = zero_counter(c, kCntBad, 1)) != LTGW_OK) return rc;
+    HIP_TRY(c, launch_ingest(d->store, src, d->n_seg, d->n_bins, pitch, D.store_buf.p,
+                             (float *)D.scale.p, (const float *)D.w.p, (float *)D.wq.p, d->rho_th,
+                             (unsigned long long *)c->counters.p + kCntBad, c->stream),
+            "ingest launch");
+    unsigned long long bad = 0;
+    if ((rc = read_counter(c, kCntBad, &bad)) != LTGW_OK) return rc;
+    if (bad) return fail(c, LTGW_E_INVALID_ARG, "%llu power values are negative or not finite", bad);
+    D.n_seg = d->n_seg;
+    D.n_bins = d->n_bins;
+    D.store = d->store;
+    D.k_lo = d->k_lo;
+    D.pitch = pitch;
+    D.t_sft = d->t_sft;
+    D.rho_th = d->rho_th;
+    D.weighted = weighted;
+    D.w_uniform = hw[0];
+    D.loaded = true;
+    c->have_eval = false;
+    return LTGW_OK;
+}
+
+int32_t ltgw_set_velocity_table(ltgw_ctx *c, int32_t det, const double *v, int32_t n_seg) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (det < 0 || det >= LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "detector %d out of range", det);
+    Det &D = c->det[det];
+    if (!D.loaded) return fail(c, LTGW_E_STATE, "no spectrogram loaded for detector %d", det);
+    if (!v) return fail(c, LTGW_E_INVALID_ARG, "velocity table is NULL");
+    if (n_seg != D.n_seg)
+        return fail(c, LTGW_E_INVALID_ARG, "velocity table has %d rows, spectrogram %d", n_seg, D.n_seg);
+    std::vector<double> hv((size_t)n_seg * 3);
+    int rc;
+    if ((rc = to_host(c, hv.data(), v, hv.size() * sizeof(double), "velocity")) != LTGW_OK) return rc;
+    double vmax = 0.0;
+    for (int32_t j = 0; j < n_seg; ++j) {
+        const double *r = &hv[3 * (size_t)j];
+        if (!fin(r[0]) || !fin(r[1]) || !fin(r[2]))
+            return fail(c, LTGW_E_INVALID_ARG, "velocity row %d is not finite", j);
+        const double m = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) / kC;
+        if (!(m < 1.0)) return fail(c, LTGW_E_INVALID_ARG, "|v| >= c at row %d", j);
+        vmax = m > vmax ? m : vmax;
+    }
+    if ((rc = ensure(c, D.v, hv.size() * sizeof(double), "velocity")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, D.v.p, hv.data(), hv.size() * sizeof(double), "velocity upload")) != LTGW_OK) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "velocity upload");
+    D.v_max = vmax;
+    D.has_v = true;
+    c->have_eval = false;
+    return LTGW_OK;
+}
+
+int32_t ltgw_eval_templates(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s,
+                            int32_t *out_c, int32_t *out_n) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    c->have_eval = false;
+    if (!g) return fail(c, LTGW_E_INVALID_ARG, "grid is NULL");
+    if (stats == 0 || (stats & ~(LTGW_STAT_POWER | LTGW_STAT_COUNT)))
+        return fail(c, LTGW_E_INVALID_ARG, "stats must be a non-empty mask of POWER and COUNT");
+    if (g->n_f0 < 1 || g->n_tau < 1 || g->n_brake < 1 || g->n_sky < 1)
+        return fail(c, LTGW_E_INVALID_ARG, "grid axes must have at least one point");
+    if (!g->tau || !g->brake || !g->sky) return fail(c, LTGW_E_INVALID_ARG, "grid arrays are NULL");
+    if (!fin(g->f0_min) || !(g->f0_min > 0.0)) return fail(c, LTGW_E_INVALID_ARG, "f0_min must be finite and > 0");
+    if (!fin(g->f0_step) || g->f0_step < 0.0) return fail(c, LTGW_E_INVALID_ARG, "f0_step must be finite and >= 0");
+    if (!fin(g->t0)) return fail(c, LTGW_E_INVALID_ARG, "t0 must be finite");
+    for (int i = 0; i < g->n_tau; ++i)
+        if (!fin(g->tau[i]) || !(g->tau[i] > 0.0)) return fail(c, LTGW_E_INVALID_ARG, "tau[%d] must be finite and > 0", i);
+    for (int i = 0; i < g->n_brake; ++i)
+        if (!fin(g->brake[i]) || !(g->brake[i] > 1.0)) return fail(c, LTGW_E_INVALID_ARG, "braking index [%d] must be finite and > 1", i);
+    for (int i = 0; i < g->n_sky; ++i) {
+        const double *s = g->sky + 3 * i;
+        if (!fin(s[0]) || !fin(s[1]) || !fin(s[2]))
+            return fail(c, LTGW_E_INVALID_ARG, "sky[%d] is not finite", i);
+        if (std::fabs(std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]) - 1.0) > 1e-12)
+            return fail(c, LTGW_E_INVALID_ARG, "sky[%d] is not a unit vector", i);
+    }
+    const double f0_max = g->f0_min + (double)(g->n_f0 - 1) * g->f0_step;
+    if (!fin(f0_max)) return fail(c, LTGW_E_INVALID_ARG, "f0 range overflows");
+    const int64_t n_groups = (int64_t)g->n_tau * g->n_brake * g->n_sky;
+    const int64_t n_tpl = n_groups * g->n_f0;
+    if (n_tpl >= ((int64_t)1 << 31) || n_groups > 65535)
+        return fail(c, LTGW_E_UNSUPPORTED, "grid of %lld templates (%lld groups) exceeds 2^31 templates or 65535 groups",
+                    (long long)n_tpl, (long long)n_groups);
+    int sel[LTGW_MAX_DET], n_sel = 0;
+    for (int d = 0; d < LTGW_MAX_DET; ++d) {
+        const bool want = g->det_mask ? ((g->det_mask >> d) & 1u) : c->det[d].loaded;
+        if (!want) continue;
+        if (!c->det[d].loaded) return fail(c, LTGW_E_STATE, "detector %d selected but not loaded", d);
+        if (!c->det[d].has_v) return fail(c, LTGW_E_STATE, "detector %d has no velocity table", d);
+        sel[n_sel++] = d;
+    }
+    if (g->det_mask >> LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "det_mask selects detectors beyond %d", LTGW_MAX_DET);
+    if (n_sel == 0) return fail(c, LTGW_E_STATE, "no detector loaded");
+    const float rho_th = c->det[sel[0]].rho_th;
+    bool weighted = false;
+    const float wu = c->det[sel[0]].w_uniform;
+    int64_t n_evals = 0;
+    for (int q = 0; q < n_sel; ++q) {
+        const Det &D = c->det[sel[q]];
+        if (D.rho_th != rho_th) return fail(c, LTGW_E_UNSUPPORTED, "selected detectors have different rho_th");
+        if (D.store != c->det[sel[0]].store) return fail(c, LTGW_E_UNSUPPORTED, "selected detectors have different stores");
+        weighted |= D.weighted || D.w_uniform != wu;
+        // g <= 1 (u >= 1, e < 0) and D < 1 + v_max: x < 2^30 keeps the bin arithmetic exact
+        if (!(f0_max * D.t_sft * (1.0 + D.v_max) < (double)(1 << 30) - 4.0))
+            return fail(c, LTGW_E_INVALID_ARG, "f0_max * t_sft too large for detector %d", sel[q]);
+        n_evals += (int64_t)D.n_seg * n_tpl;
+    }
+    const int store = c->det[sel[0]].store;
+    // grid arrays to the device; the host copies must outlive the previous upload
+    HIP_TRY(c, hipEventSynchronize(c->ev_h2d), "previous grid upload");
+    c->h_tau.assign(g->tau, g->tau + g->n_tau);
+    c->h_brake.assign(g->brake, g->brake + g->n_brake);
+    c->h_sky.assign(g->sky, g->sky + 3 * (size_t)g->n_sky);
+    int rc;
+    if ((rc = ensure(c, c->tau_d, c->h_tau.size() * 8, "tau")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->brake_d, c->h_brake.size() * 8, "brake")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->sky_d, c->h_sky.size() * 8, "sky")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, c->tau_d.p, c->h_tau.data(), c->h_tau.size() * 8, "tau upload")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, c->brake_d.p, c->h_brake.data(), c->h_brake.size() * 8, "brake upload")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, c->sky_d.p, c->h_sky.data(), c->h_sky.size() * 8, "sky upload")) != LTGW_OK) return rc;
+    HIP_TRY(c, hipEventRecord(c->ev_h2d, c->stream), "event record");
+    const int32_t n_tn = g->n_tau * g->n_brake;
+    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream), "event record");
+    EvalArgs a;
+    std::memset(&a, 0, sizeof a);
+    for (int q = 0; q < n_sel; ++q) {
+        Det &D = c->det[sel[q]];
+        if ((rc = ensure(c, D.g, (size_t)n_tn * D.n_seg * 8, "spin-factor table")) != LTGW_OK) return rc;
+        if ((rc = ensure(c, D.H, (size_t)n_groups * D.n_seg * 8, "track-factor table")) != LTGW_OK) return rc;
+        HIP_TRY(c, launch_spin_factor((const double *)D.t_seg.p, D.n_seg, g->t0, (const double *)c->tau_d.p,
+                                      g->n_tau, (const double *)c->brake_d.p, g->n_brake, (double *)D.g.p,
+                                      (unsigned long long *)c->counters.p + kCntUndecided, c->stream),
+                "spin-factor launch");
+        HIP_TRY(c, launch_track_factor((const double *)D.g.p, n_tn, (const double *)D.v.p, D.n_seg,
+                                       (const double *)c->sky_d.p, g->n_sky, D.t_sft, (double *)D.H.p,
+                                       c->stream),
+                "track-factor launch");
+        DetView &V = a.det[q];
+        V.store = D.store_buf.p;
+        V.pitch_bytes = (int32_t)(D.pitch * (D.store == LTGW_STORE_F32 ? 4 : D.store == LTGW_STORE_BF16 ? 2 : 1));
+        V.store_elems = (int32_t)(D.pitch * D.n_seg);
+        V.H = (const double *)D.H.p;
+        V.wq = (const float *)D.wq.p;
+        V.w = (const float *)D.w.p;
+        V.cshift = 1.5 - (double)D.k_lo;
+        V.n_seg = D.n_seg;
+        V.n_bins = D.n_bins;
+    }
+    if ((rc = ensure(c, c->res_s, n_tpl * 8, "results s")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->res_c, n_tpl * 4, "results c")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->res_n, n_tpl * 4, "results N")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->res_w1, n_tpl * 8, "results W1")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->res_w2, n_tpl * 8, "results W2")) != LTGW_OK) return rc;
+    if ((rc = zero_counter(c, kCntInBand, 1)) != LTGW_OK) return rc;
+    a.n_det = n_sel;
+    a.n_f0 = g->n_f0;
+    a.n_groups = (int32_t)n_groups;
+    a.f0_min = g->f0_min;
+    a.f0_step = g->f0_step;
+    a.w_uniform = wu;
+    a.s = (double *)c->res_s.p;
+    a.c = (int32_t *)c->res_c.p;
+    a.n = (int32_t *)c->res_n.p;
+    a.w1 = (double *)c->res_w1.p;
+    a.w2 = (double *)c->res_w2.p;
+    a.out_s = out_s;
+    a.out_c = out_c;
+    a.out_n = out_n;
+    a.in_band_total = (unsigned long long *)c->counters.p + kCntInBand;
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream), "event record");
+    HIP_TRY(c, launch_eval(store, weighted, a, c->stream), "eval launch");
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream), "event record");
+    c->have_eval = true;
+    c->n_templates = n_tpl;
+    c->n_evals = n_evals;
+    c->f0_min = g->f0_min;
+    c->f0_step = g->f0_step;
+    c->n_f0 = g->n_f0;
+    c->n_tau = g->n_tau;
+    c->n_brake = g->n_brake;
+    c->n_sky = g->n_sky;
+    c->rho_th = rho_th;
+    return LTGW_OK;
+}
+
+int32_t ltgw_psi(ltgw_ctx *c, uint32_t stat, double *out) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (!c->have_eval) return fail(c, LTGW_E_STATE, "no evaluation to rank");
+    if (stat != LTGW_STAT_POWER && stat != LTGW_STAT_COUNT) return fail(c, LTGW_E_INVALID_ARG, "stat must be POWER or COUNT");
+    if (!out) return fail(c, LTGW_E_INVALID_ARG, "out_psi is NULL");
+    const double q = std::exp(-(double)c->rho_th);
+    HIP_TRY(c, launch_psi(stat, c->n_templates, (const double *)c->res_s.p, (const int32_t *)c->res_c.p,
+                          (const int32_t *)c->res_n.p, (const double *)c->res_w1.p,
+                          (const double *)c->res_w2.p, q, out, c->stream),
+            "psi launch");
+    return LTGW_OK;
+}
+
+int32_t ltgw_topk_candidates(ltgw_ctx *c, uint32_t stat, int32_t k, ltgw_candidate *out_host,
+                             int32_t *n_out) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (!c->have_eval) return fail(c, LTGW_E_STATE, "no evaluation to rank");
+    if (stat != LTGW_STAT_POWER && stat != LTGW_STAT_COUNT) return fail(c, LTGW_E_INVALID_ARG, "stat must be POWER or COUNT");
+    if (k < 1 || k > LTGW_MAX_TOPK) return fail(c, LTGW_E_INVALID_ARG, "k must be in 1..%d", LTGW_MAX_TOPK);
+    if (!out_host || !n_out) return fail(c, LTGW_E_INVALID_ARG, "output pointers are NULL");
+    const int64_t cap = topk_scratch_entries(c->n_templates, k);
+    int rc;
+    if ((rc = ensure(c, c->cand_pa, cap * 8, "top-k scratch")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->cand_ia, cap * 8, "top-k scratch")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->cand_pb, cap * 8, "top-k scratch")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->cand_ib, cap * 8, "top-k scratch")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->cand_out, (size_t)k * sizeof(ltgw_candidate), "top-k records")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->n_out, 8, "top-k count")) != LTGW_OK) return rc;
+    TopkDecode dec;
+    dec.f0_min = c->f0_min;
+    dec.f0_step = c->f0_step;
+    dec.n_f0 = c->n_f0;
+    dec.n_tau = c->n_tau;
+    dec.n_brake = c->n_brake;
+    dec.tau = (const double *)c->tau_d.p;
+    dec.brake = (const double *)c->brake_d.p;
+    const double q = std::exp(-(double)c->rho_th);
+    HIP_TRY(c, launch_topk(stat, c->n_templates, (const double *)c->res_s.p, (const int32_t *)c->res_c.p,
+                           (const int32_t *)c->res_n.p, (const double *)c->res_w1.p,
+                           (const double *)c->res_w2.p, q, k, (double *)c->cand_pa.p,
+                           (int64_t *)c->cand_ia.p, (double *)c->cand_pb.p, (int64_t *)c->cand_ib.p,
+                           cap, dec, (ltgw_candidate *)c->cand_out.p, (int32_t *)c->n_out.p, c->stream),
+            "top-k launch");
+    HIP_TRY(c, hipMemcpyAsync(out_host, c->cand_out.p, (size_t)k * sizeof(ltgw_candidate),
+                              hipMemcpyDeviceToHost, c->stream),
+            "top-k download");
+    HIP_TRY(c, hipMemcpyAsync(n_out, c->n_out.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream),
+            "top-k download");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "top-k");
+    return LTGW_OK;
+}
+
+int32_t ltgw_diagnostics(ltgw_ctx *c, ltgw_diag *out) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (!out) return fail(c, LTGW_E_INVALID_ARG, "out is NULL");
+    unsigned long long v[kNumCnt];
+    HIP_TRY(c, hipMemcpyAsync(v, c->counters.p, sizeof v, hipMemcpyDeviceToHost, c->stream), "diagnostics");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "diagnostics");
+    out->pow_undecided = (int64_t)v[kCntUndecided];
+    out->templates = c->have_eval ? c->n_templates : 0;
+    out->evals = c->have_eval ? c->n_evals : 0;
+    out->in_band = c->have_eval ? (int64_t)v[kCntInBand] : 0;
+    out->eval_kernel_ms = 0.0;
+    out->tables_ms = 0.0;
+    if (c->have_eval) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, c->ev[1], c->ev[2]) == hipSuccess) out->eval_kernel_ms = a;
+        if (hipEventElapsedTime(&b, c->ev[0], c->ev[1]) == hipSuccess) out->tables_ms = b;
+        (void)hipGetLastError();
+    }
+    return LTGW_OK;
+}
+
+int32_t ltgw_inject_track(ltgw_ctx *c, int32_t det, float *power, double f0, double tau,
+                          double brake, const double *sky3, double t0, float amp) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (det < 0 || det >= LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "detector %d out of range", det);
+    Det &D = c->det[det];
+    if (!D.loaded || !D.has_v) return fail(c, LTGW_E_STATE, "detector %d needs a spectrogram and a velocity table", det);
+    if (!power || !sky3) return fail(c, LTGW_E_INVALID_ARG, "power or sky is NULL");
+    if (!is_device_ptr(power)) return fail(c, LTGW_E_INVALID_ARG, "power must be a device buffer");
+    if (!fin(f0) || !(f0 > 0.0) || !fin(tau) || !(tau > 0.0) || !fin(brake) || !(brake > 1.0) ||
+        !fin(t0) || !std::isfinite(amp))
+        return fail(c, LTGW_E_INVALID_ARG, "invalid template parameters");
+    const double n2 = sky3[0] * sky3[0] + sky3[1] * sky3[1] + sky3[2] * sky3[2];
+    if (!fin(n2) || std::fabs(std::sqrt(n2) - 1.0) > 1e-12) return fail(c, LTGW_E_INVALID_ARG, "sky is not a unit vector");
+    if (!(f0 * D.t_sft * (1.0 + D.v_max) < (double)(1 << 30))) return fail(c, LTGW_E_INVALID_ARG, "f0 too large");
+    HIP_TRY(c, launch_inject(power, D.n_seg, D.n_bins, D.k_lo, D.t_sft, (const double *)D.t_seg.p,
+                             (const double *)D.v.p, (const float *)D.w.p, f0, tau, brake, sky3[0],
+                             sky3[1], sky3[2], t0, amp,
+                             (unsigned long long *)c->counters.p + kCntUndecided, c->stream),
+            "inject launch");
+    return LTGW_OK;
+}
+
+int32_t ltgw_read_store(ltgw_ctx *c, int32_t det, void *out_host, float *scale_host) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (det < 0 || det >= LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "detector %d out of range", det);
+    Det &D = c->det[det];
+    if (!D.loaded) return fail(c, LTGW_E_STATE, "no spectrogram loaded for detector %d", det);
+    if (!out_host) return fail(c, LTGW_E_INVALID_ARG, "out_host is NULL");
+    const size_t es = D.store == LTGW_STORE_F32 ? 4 : D.store == LTGW_STORE_BF16 ? 2 : 1;
+    HIP_TRY(c, hipMemcpy2DAsync(out_host, (size_t)D.n_bins * es, (const char *)D.store_buf.p + es,
+                                (size_t)D.pitch * es, (size_t)D.n_bins * es, (size_t)D.n_seg,
+                                hipMemcpyDeviceToHost, c->stream),
+            "store download");
+    if (scale_host)
+        HIP_TRY(c, hipMemcpyAsync(scale_host, D.scale.p, (size_t)D.n_seg * 4, hipMemcpyDeviceToHost, c->stream),
+                "scale download");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "store download");
+    return LTGW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+- the library loads and exports every function include/ltgw.h declares;
+- the ctypes structures match the C layout (sizes and offsets from a C
+  program compiled against the header);
+- the double-double ln 2 split used by the correctly rounded power matches a
+  60-digit decimal ln 2;
+- without a GPU, ltgw_create fails with a message instead of crashing.
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+from decimal import Decimal, getcontext
+from fractions import Fraction
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ltgw.h")
+DDPOW = os.path.join(ROOT, "paper_2507_07816_amd", "csrc", "ddpow.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ltgw_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2507_07816_amd import ltgw
+
+    L = ltgw.library()
+    declared = _declared()
+    assert len(declared) >= 11
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(ltgw.EXPORTS) == declared
+    out = subprocess.run(["nm", "-D", "--defined-only", ltgw.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (ltgw_\w+)", out))
+    assert set(declared) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    from paper_2507_07816_amd import ltgw
+
+    prog = tmp_path / "layout.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "ltgw.h"
+#define F(T, m) printf("%s.%s %zu\n", #T, #m, offsetof(T, m))
+int main(void) {
+  printf("ltgw_spec_desc %zu\n", sizeof(ltgw_spec_desc));
+  F(ltgw_spec_desc, k_lo); F(ltgw_spec_desc, t_sft); F(ltgw_spec_desc, t_seg);
+  F(ltgw_spec_desc, weights); F(ltgw_spec_desc, rho_th); F(ltgw_spec_desc, store);
+  printf("ltgw_grid %zu\n", sizeof(ltgw_grid));
+  F(ltgw_grid, n_f0); F(ltgw_grid, tau); F(ltgw_grid, n_tau); F(ltgw_grid, brake);
+  F(ltgw_grid, n_brake); F(ltgw_grid, sky); F(ltgw_grid, n_sky); F(ltgw_grid, t0);
+  F(ltgw_grid, det_mask);
+  printf("ltgw_candidate %zu\n", sizeof(ltgw_candidate));
+  F(ltgw_candidate, f0); F(ltgw_candidate, sky); F(ltgw_candidate, n_valid);
+  F(ltgw_candidate, stat); F(ltgw_candidate, psi);
+  printf("ltgw_diag %zu\n", sizeof(ltgw_diag));
+  F(ltgw_diag, in_band); F(ltgw_diag, eval_kernel_ms); F(ltgw_diag, tables_ms);
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)],
+                   check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.splitlines())
+    for name in ("ltgw_spec_desc", "ltgw_grid", "ltgw_candidate", "ltgw_diag"):
+        cls = getattr(ltgw, name)
+        assert int(got[name]) == C.sizeof(cls), name
+        for key, val in got.items():
+            if key.startswith(name + "."):
+                assert int(val) == getattr(cls, key.split(".")[1]).offset, key
+
+
+def test_ln2_split_constants():
+    getcontext().prec = 60
+    src = open(DDPOW).read()
+    vals = {m.group(1): float.fromhex(m.group(2))
+            for m in re.finditer(r"constexpr double (kLn2_\d) = (0x[0-9a-fp.+-]+);", src)}
+    assert set(vals) == {"kLn2_1", "kLn2_2", "kLn2_3"}
+    ln2 = Fraction(Decimal(2).ln())
+    a1 = Fraction(vals["kLn2_1"])
+    # 42 significant bits: k * ln2_1 is exact for |k| < 2^11
+    assert (a1 * 2 ** 42).denominator == 1
+    assert vals["kLn2_2"] == float(ln2 - a1)
+    assert vals["kLn2_3"] == float(ln2 - a1 - Fraction(vals["kLn2_2"]))
+    resid = ln2 - a1 - Fraction(vals["kLn2_2"]) - Fraction(vals["kLn2_3"])
+    assert abs(float(resid)) < 2.0 ** -150
+
+
+def test_create_without_gpu_reports_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2507_07816_amd import ltgw
+
+    with pytest.raises(ltgw.LtgwError) as ei:
+        ltgw.ltgw_create(0)
+    assert ei.value.code in (ltgw.LTGW_E_DEVICE, ltgw.LTGW_E_INVALID_ARG)
+    assert ltgw.ltgw_last_error(None)
