@@ -393,10 +393,10 @@ def test_realistic_full_size_sampled():
                 assert abs(t["psi"] - psi[o]) <= tol[o] + 1e-12
             assert t["psi"] <= prev
             prev = t["psi"]
-    # no sampled template outranks the 10th candidate
-    ok = ~np.isnan(pp)
+    # no sampled template outside the lists outranks the 10th candidate
+    ok = ~np.isnan(pp) & ~np.isin(idx, top_p)
     assert np.all(pp[ok] <= gpu["top_power"][-1]["psi"] + tol[ok] + 1e-9)
-    ok = ~np.isnan(pc)
+    ok = ~np.isnan(pc) & ~np.isin(idx, top_c)
     assert np.all(pc[ok] <= gpu["top_count"][-1]["psi"] + 1e-12)
     assert gpu["diag"]["pow_undecided"] == 0
     assert gpu["diag"]["evals"] == grid.n_templates * det.n_seg
@@ -411,7 +411,13 @@ def test_realistic_full_size_bin_checksum():
     gpu = run_gpu([det], grid)
     idx = _sample_indices(grid.n_templates, seed=1)
     ref = oracle.evaluate_list(det, grid, idx)
-    assert np.array_equal(gpu["s"][idx], ref["s"])
+    # sums reach 7e7 > 2^24, beyond what the FP32 output holds exactly; with
+    # unit weights Psi = (s - N)/sqrt(N) in FP64 gives the exact sum back
+    N = gpu["N"][idx].astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        s_exact = np.where(N > 0, np.rint(gpu["psi_power"][idx] * np.sqrt(N) + N), 0.0)
+    assert np.array_equal(s_exact, ref["s"])
     assert np.array_equal(gpu["N"][idx], ref["N"])
+    assert np.array_equal(gpu["s"][idx], ref["s"].astype(np.float32).astype(np.float64))
     frac = gpu["diag"]["in_band"] / gpu["diag"]["evals"]
     assert 0.6 < frac < 0.8
