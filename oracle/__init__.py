@@ -48,6 +48,10 @@ def lib():
         L.oracle_eval.argtypes = [P, i32, P, i64, i64, P, P, P, P, P]
         L.oracle_eval_list.restype = None
         L.oracle_eval_list.argtypes = [P, i32, P, P, i64, P, P, P, P, P]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_philox4x32_10.argtypes = [P, P, P]
+        L.oracle_exp_noise.restype = None
+        L.oracle_exp_noise.argtypes = [C.c_uint64, C.c_uint32, i32, i64, P]
         L.oracle_threads.restype = i32
         L.oracle_threads.argtypes = []
         L.oracle_track_bins.restype = None
@@ -287,3 +291,20 @@ def dequantised(rho, store):
     sc = np.empty(rho.shape[0], np.float32) if code == 2 else None
     lib().oracle_dequantised(_p(rho), rho.shape[0], rho.shape[1], code, _p(out), _p(sc))
     return out, sc
+
+
+# --- counter-based noise (proposer training data) --------------------------
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block: 4 counter words, 2 key words -> 4 output words."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().oracle_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def exp_noise(seed, stream, r, n):
+    """Exp(1) noise of realisation r (n values), as the proposer's generator defines it."""
+    out = np.empty(int(n), np.float32)
+    lib().oracle_exp_noise(int(seed), int(stream), int(r), int(n), _p(out))
+    return out

@@ -395,3 +395,52 @@ int32_t oracle_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC11).  Ten rounds of
+ *   (c0, c1, c2, c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
+ * with the key advanced by the Weyl constants between rounds.  Used for the
+ * synthetic noise of the learned proposer's training data; the library has
+ * its own implementation and the tests compare the two. */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += PHILOX_W0;
+        k1 += PHILOX_W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Exp(1) noise for realisation r of a [n_seg][n_bins] spectrogram: element e
+ * takes word e % 4 of Philox(counter = (e/4 low, e/4 high, r, stream),
+ * key = (seed low, seed high)); u = (word + 1/2) 2^-32 in (0, 1) is exact in
+ * FP64, and the value is RN_32(-log(u)) with log taken in FP64. */
+void oracle_exp_noise(uint64_t seed, uint32_t stream, int32_t r, int64_t n, float *out)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    for (int64_t e = 0; e < n; ++e) {
+        if ((e & 3) == 0 || e == 0) {
+            const uint64_t b = (uint64_t)e >> 2;
+            const uint32_t ctr[4] = {(uint32_t)b, (uint32_t)(b >> 32), (uint32_t)r, stream};
+            oracle_philox4x32_10(ctr, key, w);
+        }
+        double u = ((double)w[e & 3] + 0.5) * 0x1p-32;
+        out[e] = (float)(-log(u));
+    }
+}
