@@ -13,8 +13,27 @@ target cell (target -1: no target, no loss).  The parameters are one flat
 vector in the order W1, b1, W2, b2, W3, b3, W4, b4 with W[o][c][t] row-major.
 Plain numpy in FP64, written from these definitions; pinned by central
 finite differences in tests/test_oracle_cnn.py.
+
+With rnd=bf16_operands every product takes both operands rounded to FP32
+and then to bfloat16 (round to nearest even), the sums staying exact: the
+arithmetic of BF16 matrix units.  Forward: weights and layer inputs;
+backward: weights and upstream gradients (input gradients), upstream
+gradients and layer inputs (weight gradients).  Bias gradients and the loss
+take no rounding.
 """
 import numpy as np
+
+from oracle import bf16_rne
+
+
+def bf16_operands(a):
+    """a rounded to FP32, then to bfloat16 (RNE), returned as FP64."""
+    codes = bf16_rne(np.asarray(a, dtype=np.float32)).astype(np.uint32) << 16
+    return codes.view(np.float32).astype(np.float64)
+
+
+def _id(a):
+    return a
 
 WIDTH = 32
 K = 5
@@ -52,8 +71,10 @@ def init_params(c_in, c_out, seed):
     return np.concatenate(parts).astype(np.float32)
 
 
-def conv(x, W, b):
+def conv(x, W, b, rnd=None):
     """x [B][C][L], W [O][C][k], b [O] -> [B][O][L], zero padding (k-1)/2."""
+    rnd = rnd or _id
+    x, W = rnd(x), rnd(W)
     B, C, L = x.shape
     O, _, k = W.shape
     p = (k - 1) // 2
@@ -65,8 +86,11 @@ def conv(x, W, b):
     return y
 
 
-def conv_backward(x, W, dy):
+def conv_backward(x, W, dy, rnd=None):
     """Gradients of conv(x, W, b) for upstream dy: (dx, dW, db)."""
+    db = dy.sum(axis=(0, 2))
+    rnd = rnd or _id
+    x, W, dy = rnd(x), rnd(W), rnd(dy)
     B, C, L = x.shape
     O, _, k = W.shape
     p = (k - 1) // 2
@@ -77,32 +101,32 @@ def conv_backward(x, W, dy):
     for t in range(k):
         dW[:, :, t] = np.einsum("bol,bcl->oc", dy, xp[:, :, t:t + L])
         dxp[:, :, t:t + L] += np.einsum("oc,bol->bcl", W[:, :, t], dy)
-    return dxp[:, :, p:p + L], dW, dy.sum(axis=(0, 2))
+    return dxp[:, :, p:p + L], dW, db
 
 
-def forward(params, x, c_in, c_out):
+def forward(params, x, c_in, c_out, rnd=None):
     W1, b1, W2, b2, W3, b3, W4, b4 = unpack(params, c_in, c_out)
     x = np.asarray(x, np.float64)
-    a1 = conv(x, W1, b1)
+    a1 = conv(x, W1, b1, rnd)
     h1 = np.maximum(a1, 0.0)
-    a2 = conv(h1, W2, b2)
+    a2 = conv(h1, W2, b2, rnd)
     h2 = np.maximum(a2, 0.0)
-    a3 = conv(h2, W3, b3)
+    a3 = conv(h2, W3, b3, rnd)
     h3 = np.maximum(a3, 0.0)
-    z = conv(h3, W4, b4)
+    z = conv(h3, W4, b4, rnd)
     return z, (x, a1, h1, a2, h2, a3, h3)
 
 
-def backward(params, cache, dz, c_in, c_out):
+def backward(params, cache, dz, c_in, c_out, rnd=None):
     W1, b1, W2, b2, W3, b3, W4, b4 = unpack(params, c_in, c_out)
     x, a1, h1, a2, h2, a3, h3 = cache
-    dh3, dW4, db4 = conv_backward(h3, W4, dz)
+    dh3, dW4, db4 = conv_backward(h3, W4, dz, rnd)
     da3 = dh3 * (a3 > 0)
-    dh2, dW3, db3 = conv_backward(h2, W3, da3)
+    dh2, dW3, db3 = conv_backward(h2, W3, da3, rnd)
     da2 = dh2 * (a2 > 0)
-    dh1, dW2, db2 = conv_backward(h1, W2, da2)
+    dh1, dW2, db2 = conv_backward(h1, W2, da2, rnd)
     da1 = dh1 * (a1 > 0)
-    _, dW1, db1 = conv_backward(x, W1, da1)
+    _, dW1, db1 = conv_backward(x, W1, da1, rnd)
     return np.concatenate([g.ravel() for g in (dW1, db1, dW2, db2, dW3, db3, dW4, db4)])
 
 
@@ -124,3 +148,12 @@ def softmax_xent(z, target):
         d[i] = p[i]
         d[i, target[i]] -= 1.0
     return loss / n, (d / n).reshape(z.shape)
+
+
+def adam(p, g, m, v, lr, beta1, beta2, eps, step):
+    """One Adam step (Kingma and Ba, Algorithm 1) in FP64: returns (p, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** step)
+    vh = v / (1.0 - beta2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -1,0 +1,84 @@
+"""Reference definitions of the learned proposer's data path (test
+infrastructure only: the product never imports this module).
+
+- coarse_power: the 2x2-coarsened map.  Pixel (j', m) is the FP32 sum
+  (P[2j'][2m] + P[2j'][2m+1]) + (P[2j'+1][2m] + P[2j'+1][2m+1]), rounded to
+  bfloat16; under noise alone it is a sum of four Exp(1) values (mean 4,
+  variance 4).
+- coarse_psi: the power critical ratio (Eq. 4 with that mean and variance)
+  of a template on the coarse map.  The template's column in segment pair
+  j' is its fine column (Eqs. 1-2 and the bin rule of Sec. 2) at the pair's
+  first segment, halved (floor); the pair's weight is the FP32 mean of its
+  two segments' weights.
+- cells and templates: network output cell (channel ch, position l) is fine
+  template (group ch // 2, f0 index 2 l + ch % 2).
+- best_template: the largest Psi of a list (ties: lowest template index),
+  the quantity the proposer reports per realisation.
+"""
+import numpy as np
+
+import oracle
+
+
+def coarse_power(P):
+    """P: FP32 [n_seg][n_bins] (both even) -> FP64 values of the BF16 coarse map."""
+    P = np.asarray(P, dtype=np.float32)
+    a = P[0::2, 0::2] + P[0::2, 1::2]
+    b = P[1::2, 0::2] + P[1::2, 1::2]
+    s = (a + b).astype(np.float32)
+    codes = oracle.bf16_rne(s).astype(np.uint32) << 16
+    return codes.view(np.float32).astype(np.float64)
+
+
+def coarse_weights(w, n_seg):
+    w = np.ones(n_seg, np.float32) if w is None else np.asarray(w, np.float32)
+    return ((w[0::2] + w[1::2]) * np.float32(0.5)).astype(np.float32)
+
+
+def coarse_psi(det: "oracle.Detector", grid: "oracle.Grid", P, nan_to_zero=False):
+    """Coarse power critical ratio of every template of grid on det's geometry
+    with fine power P (FP32 [n_seg][n_bins]); FP64 [n_templates]."""
+    C = coarse_power(P)
+    w2 = coarse_weights(det.w, det.n_seg).astype(np.float64)
+    nb2 = det.n_bins // 2
+    out = np.empty(grid.n_templates)
+    for t in range(grid.n_templates):
+        f0, tau, brake, i_sky = grid.params(t)
+        b = oracle.track_bins(det, float(f0), float(tau), float(brake), grid.sky[int(i_sky)], grid.t0)
+        b = b[0::2]
+        m = np.where(b == np.iinfo(np.int64).min, -1, b // 2)
+        inb = (m >= 0) & (m < nb2)
+        j = np.nonzero(inb)[0]
+        if j.size == 0:
+            out[t] = 0.0 if nan_to_zero else np.nan
+            continue
+        s = np.sum(w2[j] * C[j, m[j]])
+        W1 = np.sum(w2[j])
+        W2 = np.sum(w2[j] ** 2)
+        out[t] = (s - 4.0 * W1) / np.sqrt(4.0 * W2)
+    return out
+
+
+def cell_to_template(cell, L):
+    """Network cell (ch * L + l) -> fine template index (fine n_f0 = 2 L)."""
+    cell = np.asarray(cell, dtype=np.int64)
+    ch, l = cell // L, cell % L
+    return (ch // 2) * (2 * L) + 2 * l + (ch % 2)
+
+
+def template_to_cell(tpl, L):
+    tpl = np.asarray(tpl, dtype=np.int64)
+    grp, i = tpl // (2 * L), tpl % (2 * L)
+    return (2 * grp + i % 2) * L + i // 2
+
+
+def best_template(psi, index):
+    """(index, psi) of the largest finite psi (ties: lowest index); (-1, -inf) if none."""
+    psi = np.asarray(psi, dtype=np.float64)
+    index = np.asarray(index, dtype=np.int64)
+    ok = np.isfinite(psi)
+    if not ok.any():
+        return -1, -np.inf
+    p, i = psi[ok], index[ok]
+    top = p.max()
+    return int(i[p == top].min()), float(top)

@@ -1,0 +1,117 @@
+"""Pins of the proposer's reference definitions (oracle/proposer.py, oracle/cnn.py
+operand rounding and Adam).
+
+- the coarse map is the 2x2 block sum, rounded to bfloat16 (hand values, a tie);
+- the coarse critical ratio against the fine oracle: with each segment pair
+  sharing one time and velocity and power constant on 2x2 blocks, the coarse
+  ratio is sqrt(2) times the fine one (s halves, W1 and W2 double);
+- only the first segment of a pair places the coarse column;
+- noise-free constant power gives Psi = 0 on every in-band template;
+- cells <-> templates is a bijection; best_template's tie rule;
+- BF16 operand rounding; Adam's first step on a constant gradient moves every
+  parameter by lr against the gradient's sign.
+"""
+import math
+
+import numpy as np
+
+import oracle
+from oracle import cnn
+from oracle import proposer as op
+
+
+def _geometry(n_seg, seed=0, spacing=40.0, dup=False):
+    r = np.random.default_rng(seed)
+    t = np.arange(n_seg) * spacing + 2.0
+    v = r.normal(size=(n_seg, 3))
+    v = v / np.linalg.norm(v, axis=1, keepdims=True) * 3.0e4
+    if dup:
+        t[1::2] = t[0::2]
+        v[1::2] = v[0::2]
+    return t, v
+
+
+GRID = dict(f0_min=480.0, f0_step=0.25, n_f0=24, tau=[4000.0, 15000.0], brake=[3.0, 5.0],
+            sky=[[0.6, 0.0, 0.8]], t0=0.0)
+
+
+def _grid():
+    return oracle.Grid(GRID["f0_min"], GRID["f0_step"], GRID["n_f0"], GRID["tau"], GRID["brake"],
+                       GRID["sky"], GRID["t0"])
+
+
+def test_coarse_power_block_sums_and_bf16_tie():
+    P = np.zeros((4, 6), np.float32)
+    P[0, 0], P[0, 1], P[1, 0], P[1, 1] = 1.0, 2.0, 3.0, 4.0
+    P[2, 4], P[3, 5] = 128.5, 128.5          # 257 ties between 256 and 258 -> 256
+    P[2, 2] = 3.0                             # 3 exact
+    C = op.coarse_power(P)
+    assert C.shape == (2, 3)
+    assert C[0, 0] == 10.0 and C[1, 2] == 256.0 and C[1, 1] == 3.0
+    assert C[0, 1] == 0.0 and C[0, 2] == 0.0 and C[1, 0] == 0.0
+
+
+def test_coarse_psi_is_sqrt2_times_fine_on_duplicated_pairs():
+    n_seg, n_bins, k_lo, t_sft = 64, 96, 1900, 4.0
+    t, v = _geometry(n_seg, dup=True)
+    r = np.random.default_rng(3)
+    q = r.integers(0, 6, size=(n_seg // 2, n_bins // 2)).astype(np.float32)
+    P = np.repeat(np.repeat(q, 2, axis=0), 2, axis=1)        # constant on 2x2 blocks
+    w = np.repeat(r.uniform(0.5, 2.0, n_seg // 2).astype(np.float32), 2)  # equal within a pair
+    det = oracle.Detector(P, t, v, k_lo, t_sft, weights=w)
+    g = _grid()
+    fine = oracle.psi_power(oracle.evaluate(det, g))
+    coarse = op.coarse_psi(det, g, P)
+    ok = np.isfinite(fine)
+    assert ok.sum() > 50
+    assert np.array_equal(ok, np.isfinite(coarse))
+    assert np.allclose(coarse[ok], math.sqrt(2.0) * fine[ok], rtol=1e-12, atol=1e-12)
+
+
+def test_coarse_psi_uses_the_first_segment_of_each_pair():
+    n_seg, n_bins, k_lo, t_sft = 48, 128, 1890, 4.0
+    t, v = _geometry(n_seg, seed=5)
+    P = np.random.default_rng(6).exponential(size=(n_seg, n_bins)).astype(np.float32)
+    g = _grid()
+    a = op.coarse_psi(oracle.Detector(P, t, v, k_lo, t_sft), g, P)
+    t2, v2 = t.copy(), v.copy()
+    t2[1::2] += 17.0
+    v2[1::2] *= -1.0
+    b = op.coarse_psi(oracle.Detector(P, t2, v2, k_lo, t_sft), g, P)
+    assert np.array_equal(a, b, equal_nan=True)
+    t3 = t.copy()
+    t3[0::2] += 17.0                           # moving the first segments does matter
+    c = op.coarse_psi(oracle.Detector(P, t3, v, k_lo, t_sft), g, P)
+    assert not np.array_equal(a, c, equal_nan=True)
+
+
+def test_coarse_psi_constant_power_is_zero():
+    n_seg, n_bins = 32, 64
+    t, v = _geometry(n_seg)
+    P = np.ones((n_seg, n_bins), np.float32)
+    det = oracle.Detector(P, t, v, 1900, 4.0)
+    psi = op.coarse_psi(det, _grid(), P, nan_to_zero=True)
+    assert np.all(psi == 0.0)
+
+
+def test_cells_templates_bijection_and_best():
+    L, c_out = 7, 6
+    cells = np.arange(c_out * L)
+    tpl = op.cell_to_template(cells, L)
+    assert sorted(tpl.tolist()) == list(range(c_out * L))
+    assert np.array_equal(op.template_to_cell(tpl, L), cells)
+    assert op.cell_to_template([1 * L + 3], L)[0] == 0 * 2 * L + 2 * 3 + 1
+    assert op.best_template([1.0, np.nan, 3.0, 3.0], [9, 1, 7, 4]) == (4, 3.0)
+    assert op.best_template([np.nan], [0]) == (-1, -np.inf)
+
+
+def test_bf16_operands_and_adam_first_step():
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -9, -2.0 ** -130, 3.4e38])
+    assert np.array_equal(cnn.bf16_operands(x)[:3], [1.0, 1.0, 1.0078125])
+    assert cnn.bf16_operands(x)[3] == -2.0 ** -130 and np.isinf(cnn.bf16_operands(x)[4])
+    g = np.array([0.3, -2.0, 1e-3, -5e2])
+    p0 = np.zeros(4)
+    p, m, v = cnn.adam(p0, g, np.zeros(4), np.zeros(4), 1e-2, 0.9, 0.999, 1e-12, 1)
+    assert np.allclose(p, -1e-2 * np.sign(g), rtol=1e-9)
+    p, m, v = cnn.adam(p, g, m, v, 1e-2, 0.9, 0.999, 1e-12, 2)
+    assert np.allclose(p, -2e-2 * np.sign(g), rtol=1e-9)
