@@ -68,8 +68,9 @@ extern "C" {
 #define LTGW_STAT_POWER 1u /* weighted normalised-power sum s (Sec. 2)          */
 #define LTGW_STAT_COUNT 2u /* number count c of pixels above rho_th (Sec. 2)    */
 
-#define LTGW_MAX_DET 4    /* detectors per context                              */
-#define LTGW_MAX_TOPK 256 /* largest k accepted by ltgw_topk_candidates         */
+#define LTGW_MAX_DET 256        /* detector slots per context                      */
+#define LTGW_MAX_SEARCH_DET 4   /* detectors summed by one search                  */
+#define LTGW_MAX_TOPK 256       /* largest k accepted by the top-k calls           */
 
 typedef struct ltgw_ctx ltgw_ctx;
 
@@ -143,7 +144,8 @@ typedef struct {
     const double *sky;   /* [n_sky][3] host, unit vectors (|1 - |n|| <= 1e-12) */
     int32_t n_sky;       /* >= 1                                            */
     double t0;           /* T0 of Eq. 1, same epoch as t_seg                */
-    uint32_t det_mask;   /* bit d selects detector d; 0 = every loaded one  */
+    uint32_t det_mask;   /* bit d selects detector slot d (< 32); 0 = every
+                            loaded slot below 32; at most LTGW_MAX_SEARCH_DET */
 } ltgw_grid;
 
 /* ltgw_eval_templates: statistic of every template of the grid, summed over
@@ -204,7 +206,9 @@ typedef struct {
     double eval_kernel_ms;  /* duration of the last eval's statistic kernel,
                                from HIP events on the context's stream       */
     double tables_ms;       /* duration of the last eval's track-table kernels
-                               (Eq. 1 powers, Eq. 2 factors)                 */
+                               (Eq. 1 powers, Eq. 2 factors, in-band moments) */
+    int32_t tile_shape;     /* tile shape of the last eval's statistic kernel */
+    int32_t reserved;
 } ltgw_diag;
 
 /* ltgw_diagnostics: synchronous; reads the device counters of the last eval. */
@@ -219,6 +223,194 @@ int32_t ltgw_diagnostics(ltgw_ctx *ctx, ltgw_diag *out);
  * Asynchronous.  Errors: STATE, INVALID_ARG, DEVICE. */
 int32_t ltgw_inject_track(ltgw_ctx *ctx, int32_t det, float *power, double f0, double tau,
                           double brake, const double *sky3, double t0, float amp);
+
+/* ---- many searches in one launch --------------------------------------------
+ * A batch of independent searches (own detectors, T_obs, band, sky patch and
+ * lattice; Sec. 2 bank, wide sky coverage of the abstract, batched templates
+ * of Sec. 3).  The work is split into tiles (search, (sky, n, tau) group,
+ * run of 64 x templates-per-lane f0) processed by one persistent launch:
+ * every resident wavefront takes the next tile from an atomic counter,
+ * largest search first, until the list is exhausted.  The whole sequence of a batch (Eq. 1 and Eq. 2
+ * tables, in-band moments, the statistic, critical ratios and per-search
+ * top-k) is captured into a HIP graph on first use and replayed by later
+ * calls with an identical batch.  The tile shape is chosen by the context's
+ * autotuner (timed on the batch itself on first use, or taken from the
+ * tuning cache). */
+typedef struct {
+    ltgw_grid grid;                     /* lattice; grid.det_mask is ignored */
+    int32_t dets[LTGW_MAX_SEARCH_DET];  /* detector slots this search sums   */
+    int32_t n_dets;                     /* 1 .. LTGW_MAX_SEARCH_DET          */
+} ltgw_search;
+
+typedef struct {
+    int32_t graph_replayed;  /* 1 when this call replayed a captured graph       */
+    int32_t variant;         /* tile shape used (index into the shapes below)    */
+    int32_t templates_per_lane;
+    int32_t segments_per_batch;
+    int32_t workgroups;      /* persistent grid size (4 wavefronts each)        */
+    int32_t tiles;           /* wavefront tiles                                 */
+    int64_t templates;
+    int64_t evals;           /* template x segment evaluations of the batch     */
+    int64_t in_band;
+    double kernel_ms;        /* persistent statistic launch, start to last tile */
+    double total_ms;         /* whole batch sequence, HIP events                 */
+} ltgw_batch_stats;
+
+/* ltgw_eval_batch: evaluate n_searches searches and rank each.
+ *   searches: host array; every referenced slot must hold a spectrogram and
+ *             velocity table; all searches use the same store format.
+ *   k: 1 .. LTGW_MAX_TOPK candidates per search and statistic.
+ *   top_power, top_count: host arrays [n_searches][k] (caller-owned).
+ *   n_power, n_count: host arrays [n_searches], records written per search.
+ *   stats: optional host struct.
+ * Per-search results stay in the context until the next batch
+ * (ltgw_batch_results).  Synchronous.
+ * Errors: INVALID_ARG, STATE (slot not loaded), UNSUPPORTED (mixed stores),
+ * NOMEM, DEVICE. */
+int32_t ltgw_eval_batch(ltgw_ctx *ctx, const ltgw_search *searches, int32_t n_searches, int32_t k,
+                        ltgw_candidate *top_power, ltgw_candidate *top_count, int32_t *n_power,
+                        int32_t *n_count, ltgw_batch_stats *stats);
+
+/* ltgw_batch_results: copy search i's per-template results of the last batch
+ * into device buffers (each optional): FP32 s, int32 c, int32 N, FP64
+ * critical ratios of the power (psi_power) and of the count (psi_count).
+ * Asynchronous.  Errors: STATE (no batch), INVALID_ARG. */
+int32_t ltgw_batch_results(ltgw_ctx *ctx, int32_t search, float *out_s, int32_t *out_c,
+                           int32_t *out_n, double *psi_power, double *psi_count);
+
+/* ltgw_batch_latency: per-search completion time of the last batch launch,
+ * milliseconds from the start of its persistent statistic launch to the end
+ * of the search's last tile (device wall clock), into out_ms[n_searches]
+ * (host).  Errors: STATE (no batch), INVALID_ARG. */
+int32_t ltgw_batch_latency(ltgw_ctx *ctx, double *out_ms);
+
+/* ---- autotuner -----------------------------------------------------------
+ * Tile shapes (templates per lane, segments per gather batch):
+ *   0 = (1, 8)   1 = (1, 16)   2 = (2, 8)   3 = (2, 16)
+ * Keys describe the work (single search or batch, store, moment mode and
+ * size classes); values are the fastest shape measured on this device.
+ * ltgw_autotune times every shape on the given grid (single search) and
+ * records the winner; ltgw_eval_batch tunes a new batch key by itself.
+ * ltgw_tune_save / ltgw_tune_load write and read the cache as JSON text
+ * ({"ltgw_tune": {"<key>": <shape>, ...}}). */
+int32_t ltgw_autotune(ltgw_ctx *ctx, const ltgw_grid *g, int32_t *best_variant);
+/* ltgw_set_tile_shape: use shape `variant` (0..3) for every later
+ * evaluation, or -1 to return to the autotuner.  Drops a captured batch. */
+int32_t ltgw_set_tile_shape(ltgw_ctx *ctx, int32_t variant);
+int32_t ltgw_tune_save(ltgw_ctx *ctx, const char *path);
+int32_t ltgw_tune_load(ltgw_ctx *ctx, const char *path);
+
+/* ---- learned proposer -------------------------------------------------------
+ * A system pattern on top of the method (not part of the paper): a small
+ * network reads a coarse statistic map and picks the fine-grid cells that
+ * are then evaluated exactly; the exhaustive grid stays the fallback and the
+ * judge of its recall (detection as in Sec. 3: Psi above the largest noise-only
+ * value).  Training data are realisations generated on the device. */
+
+/* ltgw_generate_noise: Exp(1) noise for realisations r0 .. r0+R-1, n values
+ * each, into the device array out[R][n].  Element e of realisation r is word
+ * e % 4 of Philox4x32-10 (Salmon et al., SC11) with counter (e/4 low, e/4
+ * high, r, stream) and key (seed low, seed high); u = (word + 1/2) 2^-32 and
+ * the value is -log(u) in FP64 rounded to FP32.  Asynchronous. */
+int32_t ltgw_generate_noise(ltgw_ctx *ctx, uint64_t seed, uint32_t stream, int32_t r0, int32_t R,
+                            int64_t n, float *out);
+
+/* ltgw_inject_stack: add injected tracks to a device stack of R spectrograms
+ * ([R][n_seg][n_bins] FP32, the shape of detector slot det) using det's
+ * segment times, weights and velocity table: realisation r gets amp * w_j at
+ * the bin of template params[r] = (f0, tau, brake, amp) (FP64, host or
+ * device; amp 0 = none) in every in-band segment. */
+int32_t ltgw_inject_stack(ltgw_ctx *ctx, int32_t det, float *stack, int32_t R, const double *params,
+                          const double *sky3, double t0);  /* synchronous */
+
+/* ltgw_load_stack: R realisations of detector slot det's geometry (its
+ * segment times, weights and velocity table are used for all): a fine store
+ * of format `store` from the device FP32 stack [R][n_seg][n_bins], and with
+ * coarse != 0 a 2x2-coarsened BF16 store (sums over pairs of segments and of
+ * bins; n_seg and n_bins must be even).  The stack data must be finite and
+ * >= 0.  Synchronous.  Errors: STATE (slot not loaded), INVALID_ARG, NOMEM. */
+int32_t ltgw_load_stack(ltgw_ctx *ctx, int32_t det, int32_t R, const float *stack, int32_t store,
+                        int32_t coarse);
+
+/* ltgw_stack_psi: power critical ratio of every template of grid g on every
+ * realisation of the loaded stack into the device array out_psi[R][n_templates].
+ * level 0: fine store (Exp(1) pixels: mean 1, variance 1); level 1: coarse
+ * store, the track's column halved at the first segment of each pair (pixels
+ * are sums of 4 Exp(1): mean 4, variance 4).  N = 0 gives NaN, or 0 with
+ * nan_to_zero.  Asynchronous.  Errors: STATE (no stack / no coarse store). */
+int32_t ltgw_stack_psi(ltgw_ctx *ctx, const ltgw_grid *g, int32_t level, int32_t nan_to_zero,
+                       double *out_psi);
+
+/* ltgw_stack_psi_list: the same on the fine store for listed templates:
+ * idx[R][m] (device int32 template indices of g) -> out_psi[R][m] (device).
+ * Asynchronous. */
+int32_t ltgw_stack_psi_list(ltgw_ctx *ctx, const ltgw_grid *g, const int32_t *idx, int32_t m,
+                            double *out_psi);
+
+/* ltgw_stack_features: the network's input from the coarse store: coarse
+ * critical ratios of grid g (NaN -> 0) in FP32, x[R][groups][n_f0] (device).
+ * Asynchronous.  Errors: STATE (no coarse store). */
+int32_t ltgw_stack_features(ltgw_ctx *ctx, const ltgw_grid *g, float *x);
+
+/* ltgw_stack_best: exhaustive search of grid g on every realisation of the
+ * fine store: best template (largest Psi, ties to the lowest index; -1 and
+ * -inf when no template has N > 0) into device best_index[R], best_psi[R].
+ * Asynchronous. */
+int32_t ltgw_stack_best(ltgw_ctx *ctx, const ltgw_grid *g, int32_t *best_index, double *best_psi);
+
+/* ltgw_cells_from_templates: fine template t (group g, f0 index i, with fine
+ * n_f0 = 2 L) -> network cell (2 g + i % 2) L + i / 2; -1 where t < 0 or
+ * mask[k] == 0 (mask may be NULL).  Device arrays of n; asynchronous. */
+int32_t ltgw_cells_from_templates(ltgw_ctx *ctx, const int32_t *tpl, int32_t n, int32_t L, const int32_t *mask,
+                                  int32_t *cells);
+
+/* The ranking network: x[B][c_in][L] -> logits[B][c_out][L] through three
+ * width-32, kernel-5 convolutions with ReLU and a kernel-1 output
+ * convolution; parameters are one FP32 vector W1 b1 W2 b2 W3 b3 W4 b4
+ * (W[o][c][t] row-major, ltgw_cnn_param_count values).  Products on BF16
+ * matrix cores with FP32 accumulation.  act: device [3][B][32][L] (the three
+ * hidden activations, kept for the backward pass).  All pointers device;
+ * asynchronous. */
+int64_t ltgw_cnn_param_count(int32_t c_in, int32_t c_out);
+int64_t ltgw_cnn_work_floats(int32_t B, int32_t c_in, int32_t c_out, int32_t L);
+int32_t ltgw_cnn_forward(ltgw_ctx *ctx, const float *params, const float *x, int32_t B, int32_t c_in,
+                         int32_t c_out, int32_t L, float *act, float *logits);
+/* grads[ltgw_cnn_param_count]: gradient of the loss whose logit gradient is
+ * dlogits; work: ltgw_cnn_work_floats floats.  Deterministic. */
+int32_t ltgw_cnn_backward(ltgw_ctx *ctx, const float *params, const float *x, int32_t B, int32_t c_in,
+                          int32_t c_out, int32_t L, const float *act, const float *dlogits, float *work,
+                          int64_t work_floats, float *grads);
+/* Softmax cross-entropy of each sample's n_cells logits against target[b]
+ * (-1: no target); loss[B] per sample, dlogits already divided by n_valid. */
+int32_t ltgw_softmax_xent(ltgw_ctx *ctx, const float *logits, int32_t B, int32_t n_cells,
+                          const int32_t *target, int32_t n_valid, float *loss, float *dlogits);
+/* One Adam step (Kingma and Ba) on FP32 master weights; step counts from 1. */
+int32_t ltgw_adam_step(ltgw_ctx *ctx, float *params, const float *grads, float *m, float *v, int64_t n,
+                       float lr, float beta1, float beta2, float eps, int32_t step);
+/* Per row of n scores (n <= 8192): the M best indices (score desc, index asc). */
+int32_t ltgw_select_top(ltgw_ctx *ctx, const float *score, int32_t R, int32_t n, int32_t M,
+                        int32_t *out_idx);
+
+typedef struct {
+    const float *params;      /* network parameters (device)                      */
+    int32_t c_in, c_out, L;   /* network shape                                    */
+    int32_t n_select;         /* fine cells evaluated exactly per realisation     */
+    double psi_threshold;     /* detection threshold on Psi (largest noise value)  */
+    double coarse_threshold;  /* fallback when the coarse map exceeds this but no
+                                 selected cell passes psi_threshold               */
+} ltgw_proposer;
+
+/* ltgw_propose: on the loaded stack, for every realisation: coarse critical
+ * ratios on the coarse grid (channels = its (tau, n) groups, positions = its
+ * f0) -> network logits over the fine cells -> the n_select best cells ->
+ * exact fine critical ratios of those cells -> the best of them; realisations
+ * that trip the fallback rule are evaluated exhaustively on the fine grid.
+ * Cell (channel ch, position l) is fine template ((ch / 2) group, f0 index
+ * 2 l + ch % 2): the fine grid has twice the coarse positions in f0 and
+ * c_out / 2 (tau, n) groups.  Outputs (host, [R]): best template index and
+ * Psi, fallback flag.  Synchronous. */
+int32_t ltgw_propose(ltgw_ctx *ctx, const ltgw_grid *fine, const ltgw_grid *coarse,
+                     const ltgw_proposer *p, int32_t *best_index, double *best_psi, int32_t *fallback);
 
 /* ltgw_read_store: copy detector det's device store to host for inspection.
  *   out_host: n_seg rows of n_bins elements (guards dropped), each element 4

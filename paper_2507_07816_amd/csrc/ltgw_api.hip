@@ -9,54 +9,15 @@
 #include <string>
 #include <vector>
 
-#include "ltgw_internal.h"
+#include "ltgw_ctx.h"
 
 using namespace ltgw;
 
 namespace {
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t cap = 0;
-};
-
-struct Det {
-    bool loaded = false, has_v = false;
-    int32_t n_seg = 0, n_bins = 0, store = 0;
-    int64_t k_lo = 0, pitch = 0;
-    double t_sft = 0.0;
-    float rho_th = 1.6f;
-    bool weighted = false;
-    float w_uniform = 1.0f;
-    double v_max = 0.0;  // max |v| / c
-    DevBuf store_buf, t_seg, w, wq, scale, v, g, H;
-};
-
 thread_local std::string g_create_error;
-
 }  // namespace
 
-struct ltgw_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
-    Det det[LTGW_MAX_DET];
-    DevBuf staging, counters;
-    DevBuf tau_d, brake_d, sky_d;
-    DevBuf res_s, res_c, res_n, res_w1, res_w2;
-    DevBuf cand_pa, cand_ia, cand_pb, cand_ib, cand_out, n_out;
-    std::vector<double> h_tau, h_brake, h_sky;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // tables start, eval start, eval end
-    hipEvent_t ev_h2d = nullptr;  // after the grid uploads from h_tau/h_brake/h_sky
-    // last eval
-    bool have_eval = false;
-    int64_t n_templates = 0, n_evals = 0;
-    double f0_min = 0.0, f0_step = 0.0;
-    int32_t n_f0 = 0, n_tau = 0, n_brake = 0, n_sky = 0;
-    float rho_th = 1.6f;
-};
-
-namespace {
+namespace ltgw {
 
 int fail(ltgw_ctx *c, int code, const char *fmt, ...) {
     char buf[512];
@@ -72,12 +33,6 @@ int hip_fail(ltgw_ctx *c, hipError_t e, const char *what) {
     return fail(c, e == hipErrorOutOfMemory ? LTGW_E_NOMEM : LTGW_E_DEVICE, "%s: %s (%s)", what,
                 hipGetErrorName(e), hipGetErrorString(e));
 }
-
-#define HIP_TRY(ctx, expr, what)                           \
-    do {                                                   \
-        hipError_t e_ = (expr);                            \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
-    } while (0)
 
 int ensure(ltgw_ctx *c, DevBuf &b, size_t bytes, const char *what) {
     if (bytes == 0) bytes = 16;
@@ -135,6 +90,12 @@ int h2d(ltgw_ctx *c, void *dst, const void *src, size_t n, const char *what) {
     return LTGW_OK;
 }
 
+bool fin(double x) { return std::isfinite(x); }
+
+}  // namespace ltgw
+
+namespace ltgw {
+
 __global__ void zero_u64_kernel(unsigned long long *p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
@@ -146,9 +107,6 @@ int zero_counter(ltgw_ctx *c, int first, int n) {
     return LTGW_OK;
 }
 
-// counters: [0] pow undecided, [1] bad power values, [2] in-band total
-constexpr int kCntUndecided = 0, kCntBad = 1, kCntInBand = 2, kNumCnt = 4;
-
 int read_counter(ltgw_ctx *c, int i, unsigned long long *out) {
     HIP_TRY(c, hipMemcpyAsync(out, (unsigned long long *)c->counters.p + i, sizeof *out,
                               hipMemcpyDeviceToHost, c->stream),
@@ -157,18 +115,8 @@ int read_counter(ltgw_ctx *c, int i, unsigned long long *out) {
     return LTGW_OK;
 }
 
-bool fin(double x) { return std::isfinite(x); }
+}  // namespace ltgw
 
-struct Enter {
-    explicit Enter(ltgw_ctx *c) {
-        if (c) {
-            c->err.clear();
-            (void)hipSetDevice(c->device);
-        }
-    }
-};
-
-}  // namespace
 
 extern "C" {
 
@@ -211,6 +159,14 @@ int32_t ltgw_create(int32_t device, void *hip_stream, ltgw_ctx **out) {
         hipError_t ee = hipEventCreateWithFlags(&c->ev_h2d, hipEventDisableTiming);
         if (ee != hipSuccess) rc = hip_fail(c, ee, "event create");
     }
+    if (rc == LTGW_OK) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0)
+            c->cu_count = v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, device) == hipSuccess && v > 0)
+            c->wall_khz = v;
+        (void)hipGetLastError();
+    }
     if (rc != LTGW_OK) {
         g_create_error = c->err;
         delete c;
@@ -227,12 +183,14 @@ void ltgw_destroy(ltgw_ctx *c) {
     for (hipEvent_t e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->ev_h2d) (void)hipEventDestroy(c->ev_h2d);
+    free_batch(c->batch);
+    free_stack(c->stack);
     for (auto &d : c->det) {
         release(d.store_buf); release(d.t_seg); release(d.w); release(d.wq);
-        release(d.scale); release(d.v); release(d.g); release(d.H);
+        release(d.scale); release(d.v); release(d.g); release(d.H); release(d.wfix);
     }
     DevBuf *all[] = {&c->staging, &c->counters, &c->tau_d, &c->brake_d, &c->sky_d,
-                     &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2,
+                     &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2, &c->diff,
                      &c->cand_pa, &c->cand_ia, &c->cand_pb, &c->cand_ib, &c->cand_out, &c->n_out};
     for (DevBuf *b : all) release(*b);
     delete c;
@@ -310,6 +268,8 @@ int32_t ltgw_load_spectrogram(ltgw_ctx *c, int32_t det, const ltgw_spec_desc *d,
     D.rho_th = d->rho_th;
     D.weighted = weighted;
     D.w_uniform = hw[0];
+    D.h_w = hw;
+    D.h_t = ht;
     D.loaded = true;
     c->have_eval = false;
     return LTGW_OK;
@@ -340,19 +300,18 @@ int32_t ltgw_set_velocity_table(ltgw_ctx *c, int32_t det, const double *v, int32
     if ((rc = h2d(c, D.v.p, hv.data(), hv.size() * sizeof(double), "velocity upload")) != LTGW_OK) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream), "velocity upload");
     D.v_max = vmax;
+    D.h_v = hv;
     D.has_v = true;
     c->have_eval = false;
     return LTGW_OK;
 }
 
-int32_t ltgw_eval_templates(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s,
-                            int32_t *out_c, int32_t *out_n) {
-    if (!c) return LTGW_E_INVALID_ARG;
-    Enter en(c);
-    c->have_eval = false;
+}  // extern "C"
+
+namespace ltgw {
+
+int plan_search(ltgw_ctx *c, const ltgw_grid *g, const int *slots, int n_slots, SearchPlan &P) {
     if (!g) return fail(c, LTGW_E_INVALID_ARG, "grid is NULL");
-    if (stats == 0 || (stats & ~(LTGW_STAT_POWER | LTGW_STAT_COUNT)))
-        return fail(c, LTGW_E_INVALID_ARG, "stats must be a non-empty mask of POWER and COUNT");
     if (g->n_f0 < 1 || g->n_tau < 1 || g->n_brake < 1 || g->n_sky < 1)
         return fail(c, LTGW_E_INVALID_ARG, "grid axes must have at least one point");
     if (!g->tau || !g->brake || !g->sky) return fail(c, LTGW_E_INVALID_ARG, "grid arrays are NULL");
@@ -360,9 +319,11 @@ int32_t ltgw_eval_templates(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, flo
     if (!fin(g->f0_step) || g->f0_step < 0.0) return fail(c, LTGW_E_INVALID_ARG, "f0_step must be finite and >= 0");
     if (!fin(g->t0)) return fail(c, LTGW_E_INVALID_ARG, "t0 must be finite");
     for (int i = 0; i < g->n_tau; ++i)
-        if (!fin(g->tau[i]) || !(g->tau[i] > 0.0)) return fail(c, LTGW_E_INVALID_ARG, "tau[%d] must be finite and > 0", i);
+        if (!fin(g->tau[i]) || !(g->tau[i] > 0.0))
+            return fail(c, LTGW_E_INVALID_ARG, "tau[%d] must be finite and > 0", i);
     for (int i = 0; i < g->n_brake; ++i)
-        if (!fin(g->brake[i]) || !(g->brake[i] > 1.0)) return fail(c, LTGW_E_INVALID_ARG, "braking index [%d] must be finite and > 1", i);
+        if (!fin(g->brake[i]) || !(g->brake[i] > 1.0))
+            return fail(c, LTGW_E_INVALID_ARG, "braking index [%d] must be finite and > 1", i);
     for (int i = 0; i < g->n_sky; ++i) {
         const double *s = g->sky + 3 * i;
         if (!fin(s[0]) || !fin(s[1]) || !fin(s[2]))
@@ -372,88 +333,194 @@ int32_t ltgw_eval_templates(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, flo
     }
     const double f0_max = g->f0_min + (double)(g->n_f0 - 1) * g->f0_step;
     if (!fin(f0_max)) return fail(c, LTGW_E_INVALID_ARG, "f0 range overflows");
-    const int64_t n_groups = (int64_t)g->n_tau * g->n_brake * g->n_sky;
-    const int64_t n_tpl = n_groups * g->n_f0;
-    if (n_tpl >= ((int64_t)1 << 31) || n_groups > 65535)
-        return fail(c, LTGW_E_UNSUPPORTED, "grid of %lld templates (%lld groups) exceeds 2^31 templates or 65535 groups",
-                    (long long)n_tpl, (long long)n_groups);
-    int sel[LTGW_MAX_DET], n_sel = 0;
-    for (int d = 0; d < LTGW_MAX_DET; ++d) {
-        const bool want = g->det_mask ? ((g->det_mask >> d) & 1u) : c->det[d].loaded;
-        if (!want) continue;
-        if (!c->det[d].loaded) return fail(c, LTGW_E_STATE, "detector %d selected but not loaded", d);
-        if (!c->det[d].has_v) return fail(c, LTGW_E_STATE, "detector %d has no velocity table", d);
-        sel[n_sel++] = d;
-    }
-    if (g->det_mask >> LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "det_mask selects detectors beyond %d", LTGW_MAX_DET);
-    if (n_sel == 0) return fail(c, LTGW_E_STATE, "no detector loaded");
-    const float rho_th = c->det[sel[0]].rho_th;
-    bool weighted = false;
-    const float wu = c->det[sel[0]].w_uniform;
-    int64_t n_evals = 0;
-    for (int q = 0; q < n_sel; ++q) {
-        const Det &D = c->det[sel[q]];
-        if (D.rho_th != rho_th) return fail(c, LTGW_E_UNSUPPORTED, "selected detectors have different rho_th");
-        if (D.store != c->det[sel[0]].store) return fail(c, LTGW_E_UNSUPPORTED, "selected detectors have different stores");
-        weighted |= D.weighted || D.w_uniform != wu;
+    P = SearchPlan();
+    P.n_f0 = g->n_f0;
+    P.n_tau = g->n_tau;
+    P.n_brake = g->n_brake;
+    P.n_sky = g->n_sky;
+    P.n_tn = g->n_tau * g->n_brake;
+    P.n_groups = (int64_t)P.n_tn * g->n_sky;
+    P.n_tpl = P.n_groups * g->n_f0;
+    if (P.n_tpl >= ((int64_t)1 << 31) || P.n_groups >= ((int64_t)1 << 24))
+        return fail(c, LTGW_E_UNSUPPORTED, "grid of %lld templates (%lld groups) exceeds 2^31 templates or 2^24 groups",
+                    (long long)P.n_tpl, (long long)P.n_groups);
+    if (n_slots < 1) return fail(c, LTGW_E_STATE, "no detector selected");
+    if (n_slots > LTGW_MAX_SEARCH_DET)
+        return fail(c, LTGW_E_UNSUPPORTED, "a search sums at most %d detectors", LTGW_MAX_SEARCH_DET);
+    for (int q = 0; q < n_slots; ++q) {
+        const int d = slots[q];
+        if (d < 0 || d >= LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "detector slot %d out of range", d);
+        for (int r = 0; r < q; ++r)
+            if (slots[r] == d) return fail(c, LTGW_E_INVALID_ARG, "detector slot %d listed twice", d);
+        const Det &D = c->det[d];
+        if (!D.loaded) return fail(c, LTGW_E_STATE, "detector %d selected but not loaded", d);
+        if (!D.has_v) return fail(c, LTGW_E_STATE, "detector %d has no velocity table", d);
+        if (q > 0 && D.rho_th != c->det[slots[0]].rho_th)
+            return fail(c, LTGW_E_UNSUPPORTED, "selected detectors have different rho_th");
+        if (q > 0 && D.store != c->det[slots[0]].store)
+            return fail(c, LTGW_E_UNSUPPORTED, "selected detectors have different stores");
         // g <= 1 (u >= 1, e < 0) and D < 1 + v_max: x < 2^30 keeps the bin arithmetic exact
         if (!(f0_max * D.t_sft * (1.0 + D.v_max) < (double)(1 << 30) - 4.0))
-            return fail(c, LTGW_E_INVALID_ARG, "f0_max * t_sft too large for detector %d", sel[q]);
-        n_evals += (int64_t)D.n_seg * n_tpl;
+            return fail(c, LTGW_E_INVALID_ARG, "f0_max * t_sft too large for detector %d", d);
+        P.sel[q] = d;
+        P.n_evals += (int64_t)D.n_seg * P.n_tpl;
+        P.n_seg_total += D.n_seg;
+        P.max_bins = D.n_bins > P.max_bins ? D.n_bins : P.max_bins;
     }
-    const int store = c->det[sel[0]].store;
+    P.n_sel = n_slots;
+    P.store = c->det[slots[0]].store;
+    P.rho_th = c->det[slots[0]].rho_th;
+    return LTGW_OK;
+}
+
+// In-band moments: uniform weights need only N; otherwise the weights get an
+// exact fixed-point form w = wfix * 2^e0 (w^2 = (hi * 2^32 + lo) * 2^(2 e0))
+// when their exponents span at most 7 binades, so W1 and W2 come from exact
+// integer range sums; failing that, the statistic kernel accumulates them.
+Moments plan_moments(ltgw_ctx *c, const int *slots, int n_slots) {
+    Moments M;
+    M.w_uniform = c->det[slots[0]].w_uniform;
+    bool uniform = true;
+    for (int q = 0; q < n_slots; ++q) {
+        const Det &D = c->det[slots[q]];
+        uniform &= !D.weighted && D.w_uniform == M.w_uniform;
+    }
+    if (uniform) return M;
+    int emin = 1 << 30, emax = -(1 << 30);
+    for (int q = 0; q < n_slots; ++q)
+        for (float wv : c->det[slots[q]].h_w) {
+            int ex;
+            (void)std::frexp(wv, &ex);  // w = f 2^ex, f in [0.5, 1)
+            emin = ex < emin ? ex : emin;
+            emax = ex > emax ? ex : emax;
+        }
+    if (emax - emin > 7) {
+        M.mode = 2;
+        return M;
+    }
+    M.mode = 1;
+    M.e0 = emin - 24;
+    for (int q = 0; q < n_slots; ++q) {
+        Det &D = c->det[slots[q]];
+        D.h_wfix.resize(3 * (size_t)D.n_seg);
+        for (int32_t j = 0; j < D.n_seg; ++j) {
+            const uint64_t m = (uint64_t)std::ldexp((double)D.h_w[j], -M.e0);  // exact integer
+            const unsigned __int128 m2 = (unsigned __int128)m * m;
+            D.h_wfix[3 * (size_t)j + 0] = (int64_t)m;
+            D.h_wfix[3 * (size_t)j + 1] = (int64_t)(uint64_t)(m2 >> 32);
+            D.h_wfix[3 * (size_t)j + 2] = (int64_t)(uint64_t)(m2 & 0xffffffffu);
+        }
+    }
+    return M;
+}
+
+static int ilog2(int64_t v) {
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+std::string tune_key_eval(const SearchPlan &P, bool moments_in_loop) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "eval/store%d/mom%d/seg%d/bins%d/tpl%d", P.store, moments_in_loop ? 1 : 0,
+             ilog2(P.n_seg_total), ilog2(P.max_bins), ilog2(P.n_tpl));
+    return buf;
+}
+
+std::string tune_key_batch(int store, bool moments_in_loop, int n_searches, int64_t evals) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "batch/store%d/mom%d/n%d/evals%d", store, moments_in_loop ? 1 : 0,
+             ilog2(n_searches), ilog2(evals));
+    return buf;
+}
+
+}  // namespace ltgw
+
+namespace {
+
+// The single-search evaluation; variant < 0 takes the tuned (or default) shape.
+int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, int32_t *out_c,
+                int32_t *out_n, int variant) {
+    c->have_eval = false;
+    if (!g) return fail(c, LTGW_E_INVALID_ARG, "grid is NULL");
+    if (stats == 0 || (stats & ~(LTGW_STAT_POWER | LTGW_STAT_COUNT)))
+        return fail(c, LTGW_E_INVALID_ARG, "stats must be a non-empty mask of POWER and COUNT");
+    int slots[32], n_slots = 0;
+    for (int d = 0; d < 32; ++d) {
+        const bool want = g->det_mask ? ((g->det_mask >> d) & 1u) : c->det[d].loaded;
+        if (!want) continue;
+        if (n_slots == LTGW_MAX_SEARCH_DET)
+            return fail(c, LTGW_E_UNSUPPORTED, "a search sums at most %d detectors", LTGW_MAX_SEARCH_DET);
+        slots[n_slots++] = d;
+    }
+    SearchPlan P;
+    int rc = plan_search(c, g, slots, n_slots, P);
+    if (rc != LTGW_OK) return rc;
     // grid arrays to the device; the host copies must outlive the previous upload
     HIP_TRY(c, hipEventSynchronize(c->ev_h2d), "previous grid upload");
+    const Moments M = plan_moments(c, P.sel, P.n_sel);
+    const bool moments_in_loop = M.mode == 2;
     c->h_tau.assign(g->tau, g->tau + g->n_tau);
     c->h_brake.assign(g->brake, g->brake + g->n_brake);
     c->h_sky.assign(g->sky, g->sky + 3 * (size_t)g->n_sky);
-    int rc;
     if ((rc = ensure(c, c->tau_d, c->h_tau.size() * 8, "tau")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->brake_d, c->h_brake.size() * 8, "brake")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->sky_d, c->h_sky.size() * 8, "sky")) != LTGW_OK) return rc;
     if ((rc = h2d(c, c->tau_d.p, c->h_tau.data(), c->h_tau.size() * 8, "tau upload")) != LTGW_OK) return rc;
     if ((rc = h2d(c, c->brake_d.p, c->h_brake.data(), c->h_brake.size() * 8, "brake upload")) != LTGW_OK) return rc;
     if ((rc = h2d(c, c->sky_d.p, c->h_sky.data(), c->h_sky.size() * 8, "sky upload")) != LTGW_OK) return rc;
-    HIP_TRY(c, hipEventRecord(c->ev_h2d, c->stream), "event record");
-    const int32_t n_tn = g->n_tau * g->n_brake;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream), "event record");
     EvalArgs a;
     std::memset(&a, 0, sizeof a);
-    for (int q = 0; q < n_sel; ++q) {
-        Det &D = c->det[sel[q]];
-        if ((rc = ensure(c, D.g, (size_t)n_tn * D.n_seg * 8, "spin-factor table")) != LTGW_OK) return rc;
-        if ((rc = ensure(c, D.H, (size_t)n_groups * D.n_seg * 8, "track-factor table")) != LTGW_OK) return rc;
+    for (int q = 0; q < P.n_sel; ++q) {
+        Det &D = c->det[P.sel[q]];
+        if ((rc = ensure(c, D.g, (size_t)P.n_tn * D.n_seg * 8, "spin-factor table")) != LTGW_OK) return rc;
+        if ((rc = ensure(c, D.H, (size_t)P.n_groups * D.n_seg * 8, "track-factor table")) != LTGW_OK) return rc;
         HIP_TRY(c, launch_spin_factor((const double *)D.t_seg.p, D.n_seg, g->t0, (const double *)c->tau_d.p,
                                       g->n_tau, (const double *)c->brake_d.p, g->n_brake, (double *)D.g.p,
                                       (unsigned long long *)c->counters.p + kCntUndecided, c->stream),
                 "spin-factor launch");
-        HIP_TRY(c, launch_track_factor((const double *)D.g.p, n_tn, (const double *)D.v.p, D.n_seg,
+        HIP_TRY(c, launch_track_factor((const double *)D.g.p, P.n_tn, (const double *)D.v.p, D.n_seg,
                                        (const double *)c->sky_d.p, g->n_sky, D.t_sft, (double *)D.H.p,
                                        c->stream),
                 "track-factor launch");
         DetView &V = a.det[q];
         V.store = D.store_buf.p;
         V.pitch_bytes = (int32_t)(D.pitch * (D.store == LTGW_STORE_F32 ? 4 : D.store == LTGW_STORE_BF16 ? 2 : 1));
-        V.store_elems = (int32_t)(D.pitch * D.n_seg);
         V.H = (const double *)D.H.p;
+        V.g = (const double *)D.g.p;
+        V.D = nullptr;
+        V.t_sft = D.t_sft;
         V.wq = (const float *)D.wq.p;
         V.w = (const float *)D.w.p;
         V.cshift = 1.5 - (double)D.k_lo;
+        V.wfix = nullptr;
         V.n_seg = D.n_seg;
         V.n_bins = D.n_bins;
+        if (M.mode == 1) {
+            if ((rc = ensure(c, D.wfix, D.h_wfix.size() * 8, "fixed-point weights")) != LTGW_OK) return rc;
+            if ((rc = h2d(c, D.wfix.p, D.h_wfix.data(), D.h_wfix.size() * 8, "weights upload")) != LTGW_OK)
+                return rc;
+            V.wfix = (const int64_t *)D.wfix.p;
+        }
     }
+    const int64_t n_tpl = P.n_tpl;
     if ((rc = ensure(c, c->res_s, n_tpl * 8, "results s")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->res_c, n_tpl * 4, "results c")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->res_n, n_tpl * 4, "results N")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->res_w1, n_tpl * 8, "results W1")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->res_w2, n_tpl * 8, "results W2")) != LTGW_OK) return rc;
     if ((rc = zero_counter(c, kCntInBand, 1)) != LTGW_OK) return rc;
-    a.n_det = n_sel;
+    a.n_det = P.n_sel;
     a.n_f0 = g->n_f0;
-    a.n_groups = (int32_t)n_groups;
+    a.n_groups = (int32_t)P.n_groups;
+    a.n_tn = P.n_tn;
     a.f0_min = g->f0_min;
     a.f0_step = g->f0_step;
-    a.w_uniform = wu;
+    a.w_uniform = M.w_uniform;
     a.s = (double *)c->res_s.p;
     a.c = (int32_t *)c->res_c.p;
     a.n = (int32_t *)c->res_n.p;
@@ -463,19 +530,136 @@ int32_t ltgw_eval_templates(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, flo
     a.out_c = out_c;
     a.out_n = out_n;
     a.in_band_total = (unsigned long long *)c->counters.p + kCntInBand;
+    if (!moments_in_loop) {
+        const size_t n_diff = (size_t)(M.mode ? 4 : 1) * (size_t)P.n_groups * (size_t)(g->n_f0 + 1);
+        if ((rc = ensure(c, c->diff, n_diff * 8, "moment difference arrays")) != LTGW_OK) return rc;
+        HIP_TRY(c, launch_moments(a, M.mode, M.e0, (int64_t *)c->diff.p, c->stream), "moments launch");
+    }
+    if (variant < 0) variant = c->forced_variant;
+    if (variant < 0) {
+        const auto it = c->tune.find(tune_key_eval(P, moments_in_loop));
+        variant = it == c->tune.end() ? 1 : it->second;
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_h2d, c->stream), "event record");
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream), "event record");
-    HIP_TRY(c, launch_eval(store, weighted, a, c->stream), "eval launch");
+    HIP_TRY(c, launch_eval(P.store, moments_in_loop, variant, a, c->stream), "eval launch");
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream), "event record");
     c->have_eval = true;
+    c->last_variant = variant;
     c->n_templates = n_tpl;
-    c->n_evals = n_evals;
+    c->n_evals = P.n_evals;
     c->f0_min = g->f0_min;
     c->f0_step = g->f0_step;
     c->n_f0 = g->n_f0;
     c->n_tau = g->n_tau;
     c->n_brake = g->n_brake;
     c->n_sky = g->n_sky;
-    c->rho_th = rho_th;
+    c->rho_th = P.rho_th;
+    return LTGW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ltgw_eval_templates(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s,
+                            int32_t *out_c, int32_t *out_n) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    return eval_single(c, g, stats, out_s, out_c, out_n, -1);
+}
+
+int32_t ltgw_autotune(ltgw_ctx *c, const ltgw_grid *g, int32_t *best_variant) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    float best_ms = 0.0f;
+    int best = -1;
+    std::string key;
+    for (int v = 0; v < kNumVariants; ++v) {
+        int rc = eval_single(c, g, LTGW_STAT_POWER | LTGW_STAT_COUNT, nullptr, nullptr, nullptr, v);
+        if (rc != LTGW_OK) return rc;
+        HIP_TRY(c, hipEventSynchronize(c->ev[2]), "autotune");
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]), "autotune timing");
+        if (best < 0 || ms < best_ms) {
+            best = v;
+            best_ms = ms;
+        }
+    }
+    {
+        int slots[32], n_slots = 0;
+        for (int d = 0; d < 32 && n_slots < LTGW_MAX_SEARCH_DET; ++d)
+            if (g->det_mask ? ((g->det_mask >> d) & 1u) : c->det[d].loaded) slots[n_slots++] = d;
+        SearchPlan P;
+        int rc = plan_search(c, g, slots, n_slots, P);
+        if (rc != LTGW_OK) return rc;
+        const Moments M = plan_moments(c, P.sel, P.n_sel);
+        c->tune[tune_key_eval(P, M.mode == 2)] = best;
+    }
+    if (best_variant) *best_variant = best;
+    c->have_eval = false;  // the last tuning run left results of a forced shape; evaluate again
+    return LTGW_OK;
+}
+
+int32_t ltgw_set_tile_shape(ltgw_ctx *c, int32_t variant) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (variant < -1 || variant >= kNumVariants)
+        return fail(c, LTGW_E_INVALID_ARG, "tile shape must be -1 or 0..%d", kNumVariants - 1);
+    c->forced_variant = variant;
+    free_batch(c->batch);  // a captured batch used the previous shape
+    return LTGW_OK;
+}
+
+int32_t ltgw_tune_save(ltgw_ctx *c, const char *path) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (!path) return fail(c, LTGW_E_INVALID_ARG, "path is NULL");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(c, LTGW_E_INVALID_ARG, "cannot write %s", path);
+    fprintf(f, "{\"ltgw_tune\": {");
+    bool first = true;
+    for (const auto &kv : c->tune) {
+        fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+        first = false;
+    }
+    fprintf(f, "\n}}\n");
+    fclose(f);
+    return LTGW_OK;
+}
+
+int32_t ltgw_tune_load(ltgw_ctx *c, const char *path) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (!path) return fail(c, LTGW_E_INVALID_ARG, "path is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(c, LTGW_E_INVALID_ARG, "cannot read %s", path);
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+    fclose(f);
+    // entries are "key": integer pairs after the top-level "ltgw_tune" key
+    size_t pos = txt.find("\"ltgw_tune\"");
+    if (pos == std::string::npos) return fail(c, LTGW_E_INVALID_ARG, "%s has no ltgw_tune object", path);
+    pos = txt.find('{', pos);
+    std::map<std::string, int> got;
+    while (pos != std::string::npos) {
+        const size_t k0 = txt.find('"', pos + 1);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = txt.find('"', k0 + 1);
+        if (k1 == std::string::npos) break;
+        const size_t colon = txt.find(':', k1);
+        if (colon == std::string::npos) break;
+        char *end = nullptr;
+        const long v = strtol(txt.c_str() + colon + 1, &end, 10);
+        if (end == txt.c_str() + colon + 1 || v < 0 || v >= kNumVariants)
+            return fail(c, LTGW_E_INVALID_ARG, "%s: bad tile shape for %s", path, txt.substr(k0 + 1, k1 - k0 - 1).c_str());
+        got[txt.substr(k0 + 1, k1 - k0 - 1)] = (int)v;
+        pos = txt.find_first_of(",}", (size_t)(end - txt.c_str()));
+        if (pos == std::string::npos || txt[pos] == '}') break;
+    }
+    for (const auto &kv : got) c->tune[kv.first] = kv.second;
     return LTGW_OK;
 }
 
@@ -546,6 +730,8 @@ int32_t ltgw_diagnostics(ltgw_ctx *c, ltgw_diag *out) {
     out->in_band = c->have_eval ? (int64_t)v[kCntInBand] : 0;
     out->eval_kernel_ms = 0.0;
     out->tables_ms = 0.0;
+    out->tile_shape = c->have_eval ? c->last_variant : -1;
+    out->reserved = 0;
     if (c->have_eval) {
         float a = 0.f, b = 0.f;
         if (hipEventElapsedTime(&a, c->ev[1], c->ev[2]) == hipSuccess) out->eval_kernel_ms = a;

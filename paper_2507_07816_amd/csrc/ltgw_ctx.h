@@ -1,0 +1,172 @@
+// Context state and host helpers shared by the C-ABI translation units
+// (ltgw_api.hip, ltgw_batch.hip).  Not part of the public boundary.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ltgw_internal.h"
+
+namespace ltgw {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct Det {
+    bool loaded = false, has_v = false;
+    int32_t n_seg = 0, n_bins = 0, store = 0;
+    int64_t k_lo = 0, pitch = 0;
+    double t_sft = 0.0;
+    float rho_th = 1.6f;
+    bool weighted = false;        // weights not all equal
+    float w_uniform = 1.0f;       // the weight when they are
+    double v_max = 0.0;           // max |v| / c
+    std::vector<float> h_w;       // weights as loaded
+    std::vector<double> h_t;      // segment times as loaded
+    std::vector<double> h_v;      // velocity table as set
+    std::vector<int64_t> h_wfix;  // [n_seg][3] fixed-point w, w^2 high, w^2 low
+    DevBuf store_buf, t_seg, w, wq, scale, v, g, H, wfix;
+};
+
+// How the in-band moments W1, W2 are formed for a set of detectors.
+struct Moments {
+    int mode = 0;            // 0 uniform weights, 1 exact fixed point, 2 in the statistic kernel
+    int e0 = 0;              // fixed point: w = wfix * 2^e0
+    float w_uniform = 1.0f;  // mode 0
+};
+
+// A validated search: grid plus detector slots.
+struct SearchPlan {
+    int sel[LTGW_MAX_SEARCH_DET] = {0, 0, 0, 0};
+    int n_sel = 0;
+    int store = 0;
+    float rho_th = 1.6f;
+    int32_t n_f0 = 0, n_tau = 0, n_brake = 0, n_sky = 0, n_tn = 0;
+    int64_t n_groups = 0, n_tpl = 0, n_evals = 0, n_seg_total = 0;
+    int32_t max_bins = 0;
+};
+
+struct BatchState {
+    bool valid = false;
+    std::vector<unsigned char> sig;  // everything a captured graph depends on
+    int n = 0, k = 0, store = 0, variant = 0, grid = 0, n_tiles = 0;
+    bool moments_in_loop = false;
+    int64_t templates = 0, evals = 0;
+    std::vector<SearchPlan> plans;
+    std::vector<Moments> mom;
+    int e0 = 0;                           // shared fixed-point exponent of the weights
+    std::vector<double> t0;               // T0 of each search
+    std::vector<int64_t> tau_off, brake_off, sky_off;
+    std::vector<double> latency_ms;       // per search, last launch
+    std::vector<int32_t> order;           // searches, largest first
+    std::vector<int64_t> tpl_off;         // first template of each search in the result arrays
+    std::vector<EvalArgs> args;           // per search, for moments and ranking
+    std::vector<TopkDecode> dec;
+    std::vector<BatchSearch> hsearch;     // host copy of the device descriptors
+    std::vector<int64_t> g_off, d_off;    // per (search, det) offsets into the g and D tables
+    DevBuf searches, tiles, ctr, tiles_done, t_done, t_start, in_band;
+    DevBuf s, c, n_res, w1, w2, gtab, dtab, tau, brake, sky, cand, n_out, diff;
+    DevBuf pa, ia, pb, ib;
+    int64_t topk_cap = 0, diff_entries = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// Grid axes and track-factor tables of one level of a stack.
+struct StackLevel {
+    std::vector<double> h_tau, h_brake, h_sky;  // host copies of the last upload
+    DevBuf tau, brake, sky, g, H;
+};
+
+// A stack of realisations sharing one detector slot's geometry (the learned
+// proposer's data): fine store [R][n_seg][pitch], coarse BF16 store
+// [R][n_seg / 2][pitch2], weights replicated per realisation.
+struct StackState {
+    bool valid = false, coarse = false;
+    int det = 0, R = 0, store = 0, n_seg = 0, n_bins = 0;
+    int64_t k_lo = 0, pitch = 0, pitch2 = 0;
+    double t_sft = 0.0;
+    DevBuf fine, crs, w, wq, scale, w2, t, v, t2, v2, params;
+    StackLevel lv[2];
+    hipEvent_t ev_h2d = nullptr;  // after the last grid upload
+    DevBuf psi_c, x, act, logits, cells, tpl, psi_sel, best_idx, best_psi, fb, rmap, idx_all, psi_all;
+};
+
+}  // namespace ltgw
+
+struct ltgw_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    ltgw::Det det[LTGW_MAX_DET];
+    ltgw::DevBuf staging, counters;
+    ltgw::DevBuf tau_d, brake_d, sky_d;
+    ltgw::DevBuf res_s, res_c, res_n, res_w1, res_w2, diff;
+    ltgw::DevBuf cand_pa, cand_ia, cand_pb, cand_ib, cand_out, n_out;
+    std::vector<double> h_tau, h_brake, h_sky;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // tables start, eval start, eval end
+    hipEvent_t ev_h2d = nullptr;  // after the grid uploads from h_tau/h_brake/h_sky
+    int cu_count = 256;
+    int wall_khz = 100000;        // device wall-clock rate
+    std::map<std::string, int> tune;  // autotuner cache: key -> tile shape
+    // last single-search eval
+    bool have_eval = false;
+    int64_t n_templates = 0, n_evals = 0;
+    double f0_min = 0.0, f0_step = 0.0;
+    int32_t n_f0 = 0, n_tau = 0, n_brake = 0, n_sky = 0;
+    float rho_th = 1.6f;
+    int last_variant = 1;
+    int forced_variant = -1;      // ltgw_set_tile_shape; -1 = autotuner
+    ltgw::BatchState batch;
+    ltgw::StackState stack;
+};
+
+namespace ltgw {
+
+int fail(ltgw_ctx *c, int code, const char *fmt, ...);
+int hip_fail(ltgw_ctx *c, hipError_t e, const char *what);
+int ensure(ltgw_ctx *c, DevBuf &b, size_t bytes, const char *what);
+void release(DevBuf &b);
+bool is_device_ptr(const void *p);
+int to_host(ltgw_ctx *c, void *dst, const void *src, size_t n, const char *what);
+int h2d(ltgw_ctx *c, void *dst, const void *src, size_t n, const char *what);
+bool fin(double x);
+
+// Context counters: [0] pow undecided, [1] bad power values, [2] in-band total.
+constexpr int kCntUndecided = 0, kCntBad = 1, kCntInBand = 2, kNumCnt = 4;
+int zero_counter(ltgw_ctx *c, int first, int n);
+int read_counter(ltgw_ctx *c, int i, unsigned long long *out);
+
+// Sets the context's device and clears its error for the duration of a call.
+struct Enter {
+    explicit Enter(ltgw_ctx *c) {
+        if (c) {
+            c->err.clear();
+            (void)hipSetDevice(c->device);
+        }
+    }
+};
+
+// Validate a grid and its detector slots (grid->det_mask is not used here).
+int plan_search(ltgw_ctx *c, const ltgw_grid *g, const int *slots, int n_slots, SearchPlan &P);
+// Choose the moment mode for a set of slots; fixed point fills Det::h_wfix.
+Moments plan_moments(ltgw_ctx *c, const int *slots, int n_slots);
+// Autotuner keys.
+std::string tune_key_eval(const SearchPlan &P, bool moments_in_loop);
+std::string tune_key_batch(int store, bool moments_in_loop, int n_searches, int64_t evals);
+void free_batch(BatchState &B);
+void free_stack(StackState &S);
+
+}  // namespace ltgw
+
+#define HIP_TRY(ctx, expr, what)                                         \
+    do {                                                                 \
+        hipError_t e_ = (expr);                                          \
+        if (e_ != hipSuccess) return ::ltgw::hip_fail(ctx, e_, what);    \
+    } while (0)

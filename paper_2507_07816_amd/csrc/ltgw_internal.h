@@ -14,20 +14,25 @@ constexpr double kC = 299792458.0;  // m/s, exact by SI definition
 struct DetView {
     const void *store;      // [n_seg][pitch] elements, element 0 of a row = 0 guard
     int32_t pitch_bytes;    // bytes between rows (whole store < 2^31 bytes)
-    int32_t store_elems;    // n_seg * pitch
-    const double *H;        // [n_groups][n_seg] bin-scaled track factor (0 = masked)
+    const double *H;        // [n_groups][n_seg] bin-scaled track factor (0 = masked), or
+                            // NULL: formed on the fly from g and D
+    const double *g;        // [n_tn][n_seg] spin-down factors (Eq. 1)
+    const double *D;        // [n_sky][n_seg] Doppler factors (Eq. 2)
+    double t_sft;
     const float *wq;        // [n_seg] weight times per-segment store scale
     const float *w;         // [n_seg] weights (for W1, W2)
+    const int64_t *wfix;    // [n_seg][3] exact fixed-point w, w^2 high, w^2 low (moments pass)
     double cshift;          // 1.5 - k_lo
     int32_t n_seg;
     int32_t n_bins;
 };
 
 struct EvalArgs {
-    DetView det[LTGW_MAX_DET];
+    DetView det[LTGW_MAX_SEARCH_DET];  // detectors one search sums
     int32_t n_det;
     int32_t n_f0;
     int32_t n_groups;       // n_sky * n_brake * n_tau
+    int32_t n_tn;           // n_brake * n_tau
     double f0_min, f0_step;
     float w_uniform;        // weight value when all weights are equal
     // context-owned results
@@ -55,7 +60,94 @@ hipError_t launch_spin_factor(const double *t_seg, int32_t n_seg, double t0, con
 hipError_t launch_track_factor(const double *g, int32_t n_tn, const double *v, int32_t n_seg,
                                const double *sky, int32_t n_sky, double t_sft, double *H,
                                hipStream_t st);
-hipError_t launch_eval(int store, bool weighted, const EvalArgs &a, hipStream_t st);
+// Statistic kernel.  moments_in_loop: also accumulate N, W1, W2 per segment
+// (used when the weights have no exact fixed-point form); otherwise only s
+// and c, with N, W1, W2 from launch_moments.  variant: tile shape
+// (templates per lane, segments per gather batch) = (1,8), (1,16), (2,8), (2,16).
+constexpr int kNumVariants = 4;
+int variant_templates_per_block(int variant);
+hipError_t launch_eval(int store, bool moments_in_loop, int variant, const EvalArgs &a,
+                       hipStream_t st);
+
+// Batched searches (device-resident descriptors).
+struct BatchSearch {
+    DetView det[LTGW_MAX_SEARCH_DET];
+    int32_t n_det;
+    int32_t n_f0;
+    int32_t n_tn;           // n_brake * n_tau; group = sky * n_tn + tn
+    int32_t n_tiles;        // tiles of this search
+    double f0_min, f0_step;
+    double *s;
+    int32_t *c;
+    int32_t *n;
+    double *w1;
+    double *w2;
+    unsigned *tiles_done;
+    unsigned long long *t_done;
+};
+struct BatchTile {
+    int32_t search, grp, tile, pad;
+};
+struct BatchArgs {
+    const BatchSearch *searches;
+    const BatchTile *tiles;
+    int32_t n_tiles;
+    unsigned *counter;
+    unsigned long long *t_start;
+    unsigned long long *in_band_total;
+};
+hipError_t launch_batch(int store, bool moments_in_loop, int variant, const BatchArgs &a, int grid,
+                        hipStream_t st);
+int batch_blocks_per_cu(int store, bool moments_in_loop, int variant);
+hipError_t launch_doppler(const double *v, int32_t n_seg, const double *sky, int32_t n_sky,
+                          double *D, hipStream_t st);
+hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t st);
+hipError_t launch_f64_to_f32(const double *in, float *out, int64_t n, hipStream_t st);
+
+// Proposer data and kernels.
+hipError_t launch_stack_eval(int store, int shift, const EvalArgs &a, int R, int64_t stack_bytes,
+                             int64_t stack_rows, double mu, double var, int nan_to_zero,
+                             double *out_psi, int32_t *out_c, hipStream_t st);
+hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,
+                            const int32_t *idx, int m, const int32_t *rmap, double *out_psi, hipStream_t st);
+hipError_t launch_cells_to_templates(const int32_t *cells, int64_t n, int L, int32_t *tpl, hipStream_t st);
+hipError_t launch_propose_reduce(int R, const double *psi_sel, const int32_t *tpl_sel, int M,
+                                 const double *psi_coarse, int nc, double thr, double cthr,
+                                 int32_t *best_idx, double *best_psi, int32_t *fallback, hipStream_t st);
+hipError_t launch_iota_rows(int32_t *idx, int rows, int n, hipStream_t st);
+hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t *idx, int32_t *best_idx,
+                           double *best_psi, hipStream_t st);
+hipError_t launch_templates_to_cells(const int32_t *tpl, int n, int L, const int32_t *mask, int32_t *cells,
+                                     hipStream_t st);
+hipError_t launch_noise(uint64_t seed, uint32_t stream, int r0, int R, int64_t n_per, float *out,
+                        hipStream_t st);
+hipError_t launch_inject_stack(float *power, int R, int32_t n_seg, int32_t n_bins, int64_t k_lo,
+                               double t_sft, const double *t_seg, const double *v, const float *w,
+                               const double *params, double sx, double sy, double sz, double t0,
+                               unsigned long long *undecided, hipStream_t st);
+hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins, int64_t pitch2,
+                          unsigned short *out, hipStream_t st);
+hipError_t launch_cnn_forward(const float *params, const float *x, int B, int c_in, int c_out, int L,
+                              float *act /* [3][B][32][L] */, float *logits, hipStream_t st);
+hipError_t launch_cnn_backward(const float *params, const float *x, int B, int c_in, int c_out, int L,
+                               const float *act, const float *dlogits, float *work, int64_t work_floats,
+                               float *grads, hipStream_t st);
+int64_t cnn_work_floats(int B, int c_in, int c_out, int L);
+int64_t cnn_n_params(int c_in, int c_out);
+hipError_t launch_softmax_xent(const float *logits, int B, int n_cells, const int32_t *target,
+                               int n_valid, float *loss, float *dlogits, hipStream_t st);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t st);
+hipError_t launch_select_top(const float *score, int R, int n, int M, int32_t *out_idx, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t st);
+
+// In-band moments N, W1, W2 of every template from the in-band f0 range of
+// each (group, segment): exact int64 range-adds into diff (4 arrays of
+// [n_groups][n_f0 + 1], zeroed here) and a prefix scan per group.
+// weights: 0 = uniform (W1 = N w, W2 = N w^2), 1 = fixed point
+// (W1 = sum wfix * 2^e0, W2 = (sum hi * 2^32 + sum lo) * 2^(2 e0)).
+hipError_t launch_moments(const EvalArgs &a, int weights, int e0, int64_t *diff,
+                          hipStream_t st);
 hipError_t launch_psi(uint32_t stat, int64_t n, const double *s, const int32_t *c,
                       const int32_t *N, const double *w1, const double *w2, double q,
                       double *out, hipStream_t st);

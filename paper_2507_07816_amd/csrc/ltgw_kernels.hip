@@ -13,16 +13,18 @@
 //
 // Evaluation kernel: one lane per template, 256 consecutive f0 per block,
 // one (sky, n, tau) group per block row.  Per segment a lane does
-//   x = f0*H (FP64)  v = x + (1.5 - k_lo)  i = min((unsigned)trunc(v), n_bins+1)
+//   x = f0*H (FP64)  v = x + (1.5 - k_lo)  i = (unsigned)trunc(v)
 // and gathers element i of the segment's row with a structured buffer load
-// (idxen; stride = element size).  Neighbouring f0 lanes read neighbouring
+// (idxen; stride = element size; the row as the scalar byte offset).  The
+// resource holds n_bins + 2 records, so the hardware range check returns 0
+// for every index past the upper guard, including negative ones (large as
+// unsigned).  Neighbouring f0 lanes read neighbouring
 // columns, so a wavefront's 64 gathers fall in a few cache lines.  The
 // per-segment H, weight and row address are wavefront-uniform (SGPRs).
 // trunc(v) - 1 equals floor(RN(x + 0.5)) - k_lo whenever the latter is in
 // band, for k_lo >= 2 and x < 2^30 (both checked by the host): x + 1.5 - k_lo
 // is exact in FP64 whenever its magnitude is at most x, and every other case
-// lands on a guard (a negative trunc(v) wraps to a large unsigned value and is
-// clamped onto the upper guard).
+// lands on the lower guard or out of range.
 #include "ltgw_internal.h"
 #include "ddpow.h"
 
@@ -229,114 +231,829 @@ hipError_t launch_track_factor(const double *g, int32_t n_tn, const double *v, i
 }
 
 // ---------------------------------------------------------------------------
-// Statistic (Sec. 2): one lane per template.  FP32 partial sums over chunks
-// of 32 segments, carried in FP64.  Segments are processed in batches of 8
-// so that 8 independent gathers are in flight per wavefront.
+// Statistic (Sec. 2).  A lane carries TPL templates (f0 256 apart, so each
+// of them is a coalesced wavefront access); segments go in batches of U so
+// that U*TPL independent gathers are in flight per wavefront.  FP32 partial
+// sums over chunks of 32 segments are carried in FP64.
 constexpr int kChunk = 32;
-constexpr int kBatch = 8;
 
-template <int STORE, bool WEIGHTED, int U>
-__device__ __forceinline__ void seg_batch(const DetView &D, __amdgpu_buffer_rsrc_t rs,
-                                          const double *__restrict__ H, int j, double f0,
-                                          float &sc, float &w1c, float &w2c, int &cnt, int &nin) {
-    const unsigned nb = (unsigned)D.n_bins;
-    const unsigned hi = nb + 1u;
-    unsigned idx[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-        const double x = f0 * H[j + k];
-        const double vv = x + D.cshift;
-        // negative values wrap to large unsigned and clamp onto the upper guard
-        const unsigned u = (unsigned)__double2int_rz(vv);
-        idx[k] = u < hi ? u : hi;
+// Bin-scaled track factor H_j of one (detector, group): from a table, or
+// formed on the fly as RN(RN(g_j D_j) T_sft) (batched searches, whose sky
+// patches would make a full table too large).  Both are wavefront-uniform.
+struct HTable {
+    const double *H;
+    __device__ double operator()(int j) const { return H[j]; }
+};
+struct HFromGD {
+    const double *g;  // [n_seg] of the group's (n, tau)
+    const double *D;  // [n_seg] of the group's sky direction
+    double t_sft;
+    __device__ double operator()(int j) const {
+        const double h = g[j] * D[j];
+        return h * t_sft;
     }
-    float p[U];
+};
+
+template <int TPL>
+struct Acc {
+    double s[TPL], w1[TPL], w2[TPL];
+    int cnt[TPL], nin[TPL];
+    __device__ void zero() {
+        for (int t = 0; t < TPL; ++t) {
+            s[t] = w1[t] = w2[t] = 0.0;
+            cnt[t] = nin[t] = 0;
+        }
+    }
+};
+
+// SHIFT = 1 reads a 2x2-coarsened store (pairs of segments and of bins; the
+// caller passes cshift + 1 and the pair's first-segment track factor): the
+// coarse column of fine column b is b >> 1, i.e. index trunc(v) >> 1.
+template <int STORE, bool MOMENTS, int TPL, int U, class HS, int SHIFT = 0>
+__device__ __forceinline__ void seg_batch(const DetView &D, __amdgpu_buffer_rsrc_t rs, const HS &hs,
+                                          int j, const double (&f0)[TPL], float (&sc)[TPL],
+                                          float (&w1c)[TPL], float (&w2c)[TPL], Acc<TPL> &acc) {
+    const unsigned nb = (unsigned)D.n_bins;
+    double h[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) h[k] = hs(j + k);
+    unsigned idx[TPL][U];
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const double x = f0[t] * h[k];
+            const double vv = x + D.cshift;
+            // a negative index wraps to a large unsigned value: out of range, reads 0
+            idx[t][k] = (unsigned)__double2int_rz(vv) >> SHIFT;
+        }
+    float p[TPL][U];
 #pragma unroll
     for (int k = 0; k < U; ++k)
-        p[k] = Store<STORE>::get(rs, (int)idx[k], (j + k) * D.pitch_bytes, cnt);
+#pragma unroll
+        for (int t = 0; t < TPL; ++t)
+            p[t][k] = Store<STORE>::get(rs, (int)idx[t][k], (j + k) * D.pitch_bytes, acc.cnt[t]);
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-        sc = __builtin_fmaf(D.wq[j + k], p[k], sc);
-        const bool inb = (idx[k] - 1u) < nb;
-        nin += inb ? 1 : 0;
-        if (WEIGHTED) {
-            const float wj = inb ? D.w[j + k] : 0.0f;
-            w1c += wj;
-            w2c = __builtin_fmaf(wj, wj, w2c);
+        const float wq = D.wq[j + k];
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+            sc[t] = __builtin_fmaf(wq, p[t][k], sc[t]);
+            if (MOMENTS) {
+                const bool inb = (idx[t][k] - 1u) < nb;
+                acc.nin[t] += inb ? 1 : 0;
+                const float wj = inb ? D.w[j + k] : 0.0f;
+                w1c[t] += wj;
+                w2c[t] = __builtin_fmaf(wj, wj, w2c[t]);
+            }
         }
     }
 }
 
-template <int STORE, bool WEIGHTED>
+// All segments of one detector.
+template <int STORE, bool MOMENTS, int TPL, int U, class HS, int SHIFT = 0>
+__device__ __forceinline__ void accumulate_det(const DetView &D, const HS &hs,
+                                               const double (&f0)[TPL], Acc<TPL> &acc) {
+    // one resource per detector, n_bins + 2 records (a row with its guards);
+    // the row is the instruction's scalar byte offset
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)D.store, Store<STORE>::kBytes, D.n_bins + 2, kBufDword3);
+    int j = 0;
+    for (; j + kChunk <= D.n_seg; j += kChunk) {
+        float sc[TPL], w1c[TPL], w2c[TPL];
+        for (int t = 0; t < TPL; ++t) sc[t] = w1c[t] = w2c[t] = 0.0f;
+#pragma unroll 1
+        for (int b = 0; b < kChunk; b += U)
+            seg_batch<STORE, MOMENTS, TPL, U, HS, SHIFT>(D, rs, hs, j + b, f0, sc, w1c, w2c, acc);
+        for (int t = 0; t < TPL; ++t) {
+            acc.s[t] += (double)sc[t];
+            if (MOMENTS) {
+                acc.w1[t] += (double)w1c[t];
+                acc.w2[t] += (double)w2c[t];
+            }
+        }
+    }
+    if (j < D.n_seg) {
+        float sc[TPL], w1c[TPL], w2c[TPL];
+        for (int t = 0; t < TPL; ++t) sc[t] = w1c[t] = w2c[t] = 0.0f;
+        for (; j < D.n_seg; ++j)
+            seg_batch<STORE, MOMENTS, TPL, 1, HS, SHIFT>(D, rs, hs, j, f0, sc, w1c, w2c, acc);
+        for (int t = 0; t < TPL; ++t) {
+            acc.s[t] += (double)sc[t];
+            if (MOMENTS) {
+                acc.w1[t] += (double)w1c[t];
+                acc.w2[t] += (double)w2c[t];
+            }
+        }
+    }
+}
+
+// Results of a lane's templates; template index grp*n_f0 + i.
+template <bool MOMENTS, int TPL>
+__device__ __forceinline__ void store_results(const Acc<TPL> &acc, const int (&i)[TPL], int grp,
+                                              int n_f0, double *s, int32_t *c, int32_t *n,
+                                              double *w1, double *w2, float *out_s, int32_t *out_c,
+                                              int32_t *out_n, unsigned long long *in_band_total) {
+    if (MOMENTS) {
+        // in-band total for the roofline's algorithmic bytes (one atomic per wave)
+        unsigned long long nw = 0;
+        for (int t = 0; t < TPL; ++t) nw += (i[t] < n_f0) ? (unsigned long long)acc.nin[t] : 0ull;
+        for (int o = 32; o > 0; o >>= 1) nw += __shfl_xor(nw, o, 64);
+        if (in_band_total) atomicAdd(in_band_total, (threadIdx.x & 63) == 0 ? nw : 0ull);
+    }
+    for (int t = 0; t < TPL; ++t) {
+        if (i[t] >= n_f0) continue;
+        const int64_t q = (int64_t)grp * n_f0 + i[t];
+        s[q] = acc.s[t];
+        c[q] = acc.cnt[t];
+        if (out_s) out_s[q] = (float)acc.s[t];
+        if (out_c) out_c[q] = acc.cnt[t];
+        if (MOMENTS) {
+            n[q] = acc.nin[t];
+            w1[q] = acc.w1[t];
+            w2[q] = acc.w2[t];
+            if (out_n) out_n[q] = acc.nin[t];
+        }
+    }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Block w runs on XCD w % 8; it is given the (f0 tile, group) pair
+// number start(x) + w / 8 in tile-major order (group fastest), where XCD x
+// owns a contiguous range of pairs.  So the blocks resident on one XCD at a
+// time cover one f0 tile of many neighbouring (tau, n, sky) groups: their
+// tracks start at the same bins and stay close for similar tau and n, so
+// their reads of each row overlap in that XCD's L2.  (Group-major order, one
+// group's successive f0 tiles side by side, reads disjoint bins and measured
+// slower.)
+constexpr int kXcds = 8;
+__device__ inline void xcd_tile_group(int w, int n_blocks, int n_tiles, int &tile, int &grp) {
+    const int x = w % kXcds, k = w / kXcds;
+    const int base = n_blocks / kXcds, extra = n_blocks % kXcds;
+    const int start = x * base + (x < extra ? x : extra);
+    const int p = start + k;
+    const int n_groups = n_blocks / n_tiles;
+    tile = p / n_groups;
+    grp = p % n_groups;
+}
+
+template <int STORE, bool MOMENTS, int TPL, int U>
 __global__ __launch_bounds__(256) void eval_kernel(const EvalArgs a) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int grp = blockIdx.y;
-    const double f0 = a.f0_min + (double)i * a.f0_step;
-    double s = 0.0, w1 = 0.0, w2 = 0.0;
-    int cnt = 0, nin = 0;
+    const int n_tiles = (a.n_f0 + 256 * TPL - 1) / (256 * TPL);
+    int tile, grp;
+    xcd_tile_group(blockIdx.x, gridDim.x, n_tiles, tile, grp);
+    int i[TPL];
+    double f0[TPL];
+    for (int t = 0; t < TPL; ++t) {
+        i[t] = tile * 256 * TPL + t * 256 + threadIdx.x;
+        f0[t] = a.f0_min + (double)i[t] * a.f0_step;
+    }
+    Acc<TPL> acc;
+    acc.zero();
     for (int d = 0; d < a.n_det; ++d) {
         const DetView D = a.det[d];
-        const double *__restrict__ H = D.H + (int64_t)grp * D.n_seg;
-        // one resource for the whole store; the row is the instruction's scalar offset
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)D.store, Store<STORE>::kBytes, D.store_elems, kBufDword3);
-        int j = 0;
-        for (; j + kChunk <= D.n_seg; j += kChunk) {
-            float sc = 0.0f, w1c = 0.0f, w2c = 0.0f;
-#pragma unroll 1
-            for (int b = 0; b < kChunk; b += kBatch)
-                seg_batch<STORE, WEIGHTED, kBatch>(D, rs, H, j + b, f0, sc, w1c, w2c, cnt, nin);
-            s += (double)sc;
-            if (WEIGHTED) {
-                w1 += (double)w1c;
-                w2 += (double)w2c;
-            }
-        }
-        if (j < D.n_seg) {
-            float sc = 0.0f, w1c = 0.0f, w2c = 0.0f;
-            for (; j < D.n_seg; ++j) seg_batch<STORE, WEIGHTED, 1>(D, rs, H, j, f0, sc, w1c, w2c, cnt, nin);
-            s += (double)sc;
-            if (WEIGHTED) {
-                w1 += (double)w1c;
-                w2 += (double)w2c;
-            }
-        }
+        accumulate_det<STORE, MOMENTS, TPL, U>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc);
     }
-    if (!WEIGHTED) {
-        const double wu = (double)a.w_uniform;
-        w1 = (double)nin * wu;
-        w2 = (double)nin * (wu * wu);
-    }
-    // in-band total for the roofline's algorithmic bytes (one atomic per wave)
-    unsigned long long nw = (i < a.n_f0) ? (unsigned long long)nin : 0ull;
-    for (int o = 32; o > 0; o >>= 1) nw += __shfl_xor(nw, o, 64);
-    if ((threadIdx.x & 63) == 0 && a.in_band_total) atomicAdd(a.in_band_total, nw);
-    if (i >= a.n_f0) return;
-    const int64_t t = (int64_t)grp * a.n_f0 + i;
-    a.s[t] = s;
-    a.c[t] = cnt;
-    a.n[t] = nin;
-    a.w1[t] = w1;
-    a.w2[t] = w2;
-    if (a.out_s) a.out_s[t] = (float)s;
-    if (a.out_c) a.out_c[t] = cnt;
-    if (a.out_n) a.out_n[t] = nin;
+    store_results<MOMENTS, TPL>(acc, i, grp, a.n_f0, a.s, a.c, a.n, a.w1, a.w2, a.out_s, a.out_c,
+                                a.out_n, a.in_band_total);
 }
 
-template <int STORE>
-static hipError_t launch_eval_s(bool weighted, const EvalArgs &a, hipStream_t st) {
-    dim3 grid((a.n_f0 + 255) / 256, a.n_groups), block(256);
-    if (weighted)
-        hipLaunchKernelGGL((eval_kernel<STORE, true>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((eval_kernel<STORE, false>), grid, block, 0, st, a);
+// Tile shapes: (templates per lane, segments per gather batch).
+constexpr int kVariantTpl[kNumVariants] = {1, 1, 2, 2};
+
+int variant_templates_per_block(int variant) { return 256 * kVariantTpl[variant]; }
+
+template <int STORE, bool MOMENTS, int TPL, int U>
+static hipError_t launch_eval_v(const EvalArgs &a, hipStream_t st) {
+    const int64_t blocks = (int64_t)((a.n_f0 + 256 * TPL - 1) / (256 * TPL)) * a.n_groups;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((eval_kernel<STORE, MOMENTS, TPL, U>), dim3((unsigned)blocks), dim3(256), 0,
+                       st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_eval(int store, bool weighted, const EvalArgs &a, hipStream_t st) {
-    if (store == LTGW_STORE_F32) return launch_eval_s<LTGW_STORE_F32>(weighted, a, st);
-    if (store == LTGW_STORE_BF16) return launch_eval_s<LTGW_STORE_BF16>(weighted, a, st);
-    return launch_eval_s<LTGW_STORE_FP8>(weighted, a, st);
+template <int STORE, bool MOMENTS>
+static hipError_t launch_eval_m(int variant, const EvalArgs &a, hipStream_t st) {
+    switch (variant) {
+        case 0: return launch_eval_v<STORE, MOMENTS, 1, 8>(a, st);
+        case 1: return launch_eval_v<STORE, MOMENTS, 1, 16>(a, st);
+        case 2: return launch_eval_v<STORE, MOMENTS, 2, 8>(a, st);
+        default: return launch_eval_v<STORE, MOMENTS, 2, 16>(a, st);
+    }
+}
+
+template <int STORE>
+static hipError_t launch_eval_s(bool moments, int variant, const EvalArgs &a, hipStream_t st) {
+    return moments ? launch_eval_m<STORE, true>(variant, a, st)
+                   : launch_eval_m<STORE, false>(variant, a, st);
+}
+
+hipError_t launch_eval(int store, bool moments, int variant, const EvalArgs &a, hipStream_t st) {
+    if (store == LTGW_STORE_F32) return launch_eval_s<LTGW_STORE_F32>(moments, variant, a, st);
+    if (store == LTGW_STORE_BF16) return launch_eval_s<LTGW_STORE_BF16>(moments, variant, a, st);
+    return launch_eval_s<LTGW_STORE_FP8>(moments, variant, a, st);
+}
+
+// A value that is the same in every lane, moved to scalar registers word by
+// word (lets the compiler treat descriptors read from memory as uniform).
+template <class T>
+__device__ __forceinline__ T uniform(const T &x) {
+    static_assert(sizeof(T) % 4 == 0, "whole words only");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &x, sizeof(T));
+#pragma unroll
+    for (unsigned k = 0; k < sizeof(T) / 4; ++k) w[k] = __builtin_amdgcn_readfirstlane(w[k]);
+    T y;
+    __builtin_memcpy(&y, w, sizeof(T));
+    return y;
+}
+
+// ---------------------------------------------------------------------------
+// Many searches in one persistent launch.  Tiles (search, group, 64 x TPL
+// consecutive f0) are listed largest search first; every resident wavefront
+// takes the next tile from an atomic counter until the list is exhausted (the
+// loop ends for every wave once the counter passes the tile count).  The wave
+// that finishes a search's last tile stamps the search's completion time.
+template <int STORE, bool MOMENTS, int TPL, int U>
+__global__ __launch_bounds__(256) void batch_kernel(const BatchArgs a) {
+    // Work is pulled per wavefront.  The loop body has no lane-divergent
+    // branch around the tile hand-out: every lane issues the atomic (lane 0
+    // adds 1, the others 0) and the wave takes lane 0's ticket as a scalar, so
+    // the compiler keeps one wave-uniform loop (a lane-0-only branch there let
+    // it split the loop, parking lane 0 while the other lanes re-read a stale
+    // ticket forever).  No barrier is used.
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0 && a.t_start) atomicMin(a.t_start, (unsigned long long)wall_clock64());
+    for (;;) {
+        const unsigned ticket = atomicAdd(a.counter, lane == 0 ? 1u : 0u);
+        const int tt = __builtin_amdgcn_readfirstlane((int)ticket);
+        if (tt >= a.n_tiles) break;
+        // descriptors are read into scalar registers (uniform loop bounds, buffer
+        // resources and table pointers)
+        const BatchTile T = uniform(a.tiles[tt]);
+        const BatchSearch *Sp = a.searches + T.search;
+        const int n_det = uniform(Sp->n_det), n_f0 = uniform(Sp->n_f0), n_tn = uniform(Sp->n_tn);
+        const double f0_min = uniform(Sp->f0_min), f0_step = uniform(Sp->f0_step);
+        int i[TPL];
+        double f0[TPL];
+        for (int t = 0; t < TPL; ++t) {
+            i[t] = T.tile * 64 * TPL + t * 64 + lane;
+            f0[t] = f0_min + (double)i[t] * f0_step;
+        }
+        const int tn = T.grp % n_tn, sky = T.grp / n_tn;
+        Acc<TPL> acc;
+        acc.zero();
+        for (int d = 0; d < n_det; ++d) {
+            const DetView D = uniform(Sp->det[d]);
+            const HFromGD hs{D.g + (int64_t)tn * D.n_seg, D.D + (int64_t)sky * D.n_seg, D.t_sft};
+            accumulate_det<STORE, MOMENTS, TPL, U>(D, hs, f0, acc);
+        }
+        store_results<MOMENTS, TPL>(acc, i, T.grp, n_f0, uniform(Sp->s), uniform(Sp->c), uniform(Sp->n),
+                                    uniform(Sp->w1), uniform(Sp->w2), nullptr, nullptr, nullptr,
+                                    a.in_band_total);
+        __threadfence();
+        unsigned *const tiles_done = uniform(Sp->tiles_done);
+        unsigned long long *const t_done = uniform(Sp->t_done);
+        const unsigned done = (unsigned)__builtin_amdgcn_readfirstlane(
+                                  (int)atomicAdd(tiles_done, lane == 0 ? 1u : 0u)) + 1u;
+        if (done == (unsigned)uniform(Sp->n_tiles) && t_done) *t_done = wall_clock64();  // same value, every lane
+    }
+}
+
+template <int STORE, bool MOMENTS, int TPL, int U>
+static hipError_t launch_batch_v(const BatchArgs &a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((batch_kernel<STORE, MOMENTS, TPL, U>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int STORE, bool MOMENTS>
+static hipError_t launch_batch_m(int variant, const BatchArgs &a, int grid, hipStream_t st) {
+    switch (variant) {
+        case 0: return launch_batch_v<STORE, MOMENTS, 1, 8>(a, grid, st);
+        case 1: return launch_batch_v<STORE, MOMENTS, 1, 16>(a, grid, st);
+        case 2: return launch_batch_v<STORE, MOMENTS, 2, 8>(a, grid, st);
+        default: return launch_batch_v<STORE, MOMENTS, 2, 16>(a, grid, st);
+    }
+}
+
+hipError_t launch_batch(int store, bool moments, int variant, const BatchArgs &a, int grid,
+                        hipStream_t st) {
+    if (store == LTGW_STORE_F32)
+        return moments ? launch_batch_m<LTGW_STORE_F32, true>(variant, a, grid, st)
+                       : launch_batch_m<LTGW_STORE_F32, false>(variant, a, grid, st);
+    if (store == LTGW_STORE_BF16)
+        return moments ? launch_batch_m<LTGW_STORE_BF16, true>(variant, a, grid, st)
+                       : launch_batch_m<LTGW_STORE_BF16, false>(variant, a, grid, st);
+    return moments ? launch_batch_m<LTGW_STORE_FP8, true>(variant, a, grid, st)
+                   : launch_batch_m<LTGW_STORE_FP8, false>(variant, a, grid, st);
+}
+
+int batch_blocks_per_cu(int store, bool moments, int variant) {
+    int n = 0;
+    hipError_t e = hipSuccess;
+#define LTGW_OCC(S, M, T, U)                                                                    \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<S, M, T, U>, 256, 0)
+#define LTGW_OCC_V(S, M)                            \
+    switch (variant) {                              \
+        case 0: LTGW_OCC(S, M, 1, 8); break;        \
+        case 1: LTGW_OCC(S, M, 1, 16); break;       \
+        case 2: LTGW_OCC(S, M, 2, 8); break;        \
+        default: LTGW_OCC(S, M, 2, 16); break;      \
+    }
+    if (store == LTGW_STORE_F32) {
+        if (moments) { LTGW_OCC_V(LTGW_STORE_F32, true) } else { LTGW_OCC_V(LTGW_STORE_F32, false) }
+    } else if (store == LTGW_STORE_BF16) {
+        if (moments) { LTGW_OCC_V(LTGW_STORE_BF16, true) } else { LTGW_OCC_V(LTGW_STORE_BF16, false) }
+    } else {
+        if (moments) { LTGW_OCC_V(LTGW_STORE_FP8, true) } else { LTGW_OCC_V(LTGW_STORE_FP8, false) }
+    }
+#undef LTGW_OCC_V
+#undef LTGW_OCC
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n < 1 ? 1 : n;
+}
+
+// Eq. 2 table for batched searches: D[sky][j] = 1 + ((vx nx + vy ny) + vz nz)/c.
+__global__ __launch_bounds__(256) void doppler_kernel(const double *__restrict__ v, int n_seg,
+                                                      const double *__restrict__ sky,
+                                                      double *__restrict__ D) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int s = blockIdx.y;
+    if (j >= n_seg) return;
+    const double a = v[3 * j + 0] * sky[3 * s + 0];
+    const double b = v[3 * j + 1] * sky[3 * s + 1];
+    const double z = v[3 * j + 2] * sky[3 * s + 2];
+    const double vn = (a + b) + z;
+    const double r = vn / kC;
+    D[(int64_t)s * n_seg + j] = 1.0 + r;
+}
+
+hipError_t launch_doppler(const double *v, int32_t n_seg, const double *sky, int32_t n_sky,
+                          double *D, hipStream_t st) {
+    hipLaunchKernelGGL(doppler_kernel, dim3((n_seg + 255) / 256, n_sky), dim3(256), 0, st, v, n_seg,
+                       sky, D);
+    return hipGetLastError();
+}
+
+__global__ void fill_u32_kernel(unsigned *p, int n, unsigned v) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
+}
+__global__ void fill_u64_kernel(unsigned long long *p, int n, unsigned long long v) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
+}
+
+hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256),
+                       0, st, p, n, v);
+    return hipGetLastError();
+}
+__global__ void f64_to_f32_kernel(const double *in, float *out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = (float)in[i];
+}
+
+hipError_t launch_f64_to_f32(const double *in, float *out, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(f64_to_f32_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st,
+                       in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256),
+                       0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stacks of realisations (the learned proposer's data): R spectrograms of one
+// geometry, realisation r at byte offset r * stack_bytes of the store and
+// r * stack_rows of the per-row weights.  One launch evaluates every template
+// of a grid on every realisation and writes the power critical ratio
+//     Psi = (s - mu W1) / sqrt(var W2)
+// with the per-pixel noise mean mu and variance var of the store (Exp(1):
+// 1, 1; a 2x2 sum of Exp(1): 4, 4), NaN (or 0 with nan_to_zero) for N = 0.
+template <int STORE, int SHIFT>
+__global__ __launch_bounds__(256) void stack_eval_kernel(const EvalArgs a, int64_t stack_bytes,
+                                                         int64_t stack_rows, double mu, double var,
+                                                         int nan_to_zero, double *__restrict__ out_psi,
+                                                         int32_t *__restrict__ out_c) {
+    const int n_tiles = (a.n_f0 + 255) / 256;
+    int tile, grp;
+    xcd_tile_group(blockIdx.x, gridDim.x, n_tiles, tile, grp);
+    const int r = blockIdx.y;
+    int i[1] = {tile * 256 + (int)threadIdx.x};
+    double f0[1] = {a.f0_min + (double)i[0] * a.f0_step};
+    DetView D = a.det[0];
+    D.store = (const char *)D.store + (int64_t)r * stack_bytes;
+    D.wq += (int64_t)r * stack_rows;
+    D.w += (int64_t)r * stack_rows;
+    Acc<1> acc;
+    acc.zero();
+    accumulate_det<STORE, true, 1, 16, HTable, SHIFT>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc);
+    if (i[0] >= a.n_f0) return;
+    const int64_t t = (int64_t)r * ((int64_t)a.n_groups * a.n_f0) + (int64_t)grp * a.n_f0 + i[0];
+    double psi;
+    if (acc.nin[0] == 0) {
+        psi = nan_to_zero ? 0.0 : __builtin_nan("");
+    } else {
+        const double num = acc.s[0] - mu * acc.w1[0];
+        psi = num / sqrt(var * acc.w2[0]);
+    }
+    out_psi[t] = psi;
+    if (out_c) out_c[t] = acc.cnt[0];
+}
+
+hipError_t launch_stack_eval(int store, int shift, const EvalArgs &a, int R, int64_t stack_bytes,
+                             int64_t stack_rows, double mu, double var, int nan_to_zero,
+                             double *out_psi, int32_t *out_c, hipStream_t st) {
+    const int64_t blocks = (int64_t)((a.n_f0 + 255) / 256) * a.n_groups;
+    if (blocks > 0x7fffffff || R > 65535 || R < 1) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks, (unsigned)R), block(256);
+    if (store == LTGW_STORE_F32 && shift == 0)
+        hipLaunchKernelGGL((stack_eval_kernel<LTGW_STORE_F32, 0>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, nan_to_zero, out_psi, out_c);
+    else if (store == LTGW_STORE_BF16 && shift == 0)
+        hipLaunchKernelGGL((stack_eval_kernel<LTGW_STORE_BF16, 0>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, nan_to_zero, out_psi, out_c);
+    else if (store == LTGW_STORE_BF16 && shift == 1)
+        hipLaunchKernelGGL((stack_eval_kernel<LTGW_STORE_BF16, 1>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, nan_to_zero, out_psi, out_c);
+    else if (store == LTGW_STORE_FP8 && shift == 0)
+        hipLaunchKernelGGL((stack_eval_kernel<LTGW_STORE_FP8, 0>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, nan_to_zero, out_psi, out_c);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// Explicit template lists: lane q of realisation r evaluates template
+// idx[r][q] of the grid (any order; each lane reads its own group's track
+// factors).  Writes the power critical ratio (mu = var = 1) or NaN.
+template <int STORE>
+__global__ __launch_bounds__(256) void list_eval_kernel(const EvalArgs a, int64_t stack_bytes,
+                                                        int64_t stack_rows, const int32_t *__restrict__ idx,
+                                                        int m, const int32_t *__restrict__ rmap,
+                                                        double *__restrict__ out_psi) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int rr = blockIdx.y;                  // row of idx and out_psi
+    const int r = rmap ? rmap[rr] : rr;         // realisation of the stack
+    DetView D = a.det[0];
+    D.store = (const char *)D.store + (int64_t)r * stack_bytes;
+    D.wq += (int64_t)r * stack_rows;
+    D.w += (int64_t)r * stack_rows;
+    const int64_t n_tpl = (int64_t)a.n_groups * a.n_f0;
+    int t = q < m ? idx[(int64_t)rr * m + q] : 0;
+    const bool bad = t < 0 || t >= n_tpl;  // not a template of the grid: NaN
+    if (bad) t = 0;
+    const int i_f0 = t % a.n_f0, grp = t / a.n_f0;
+    const double f0 = a.f0_min + (double)i_f0 * a.f0_step;
+    const double *__restrict__ H = D.H + (int64_t)grp * D.n_seg;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)D.store, Store<STORE>::kBytes, D.n_bins + 2, kBufDword3);
+    const unsigned nb = (unsigned)D.n_bins;
+    double s = 0.0, w1 = 0.0, w2 = 0.0;
+    int cnt = 0, nin = 0;
+    for (int j0 = 0; j0 < D.n_seg; j0 += kChunk) {
+        const int je = min(j0 + kChunk, D.n_seg);
+        float sc = 0.0f, w1c = 0.0f, w2c = 0.0f;
+        for (int j = j0; j < je; ++j) {
+            const double x = f0 * H[j];
+            const double vv = x + D.cshift;
+            const unsigned ix = (unsigned)__double2int_rz(vv);
+            const float p = Store<STORE>::get(rs, (int)ix, j * D.pitch_bytes, cnt);
+            sc = __builtin_fmaf(D.wq[j], p, sc);
+            const bool inb = (ix - 1u) < nb;
+            nin += inb ? 1 : 0;
+            const float wj = inb ? D.w[j] : 0.0f;
+            w1c += wj;
+            w2c = __builtin_fmaf(wj, wj, w2c);
+        }
+        s += (double)sc;
+        w1 += (double)w1c;
+        w2 += (double)w2c;
+    }
+    if (q >= m) return;
+    out_psi[(int64_t)rr * m + q] = (nin && !bad) ? (s - w1) / sqrt(w2) : __builtin_nan("");
+}
+
+hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,
+                            const int32_t *idx, int m, const int32_t *rmap, double *out_psi, hipStream_t st) {
+    if (R > 65535 || R < 1 || m < 1) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((m + 255) / 256), (unsigned)R), block(256);
+    if (store == LTGW_STORE_F32)
+        hipLaunchKernelGGL(list_eval_kernel<LTGW_STORE_F32>, grid, block, 0, st, a, stack_bytes, stack_rows, idx, m, rmap, out_psi);
+    else if (store == LTGW_STORE_BF16)
+        hipLaunchKernelGGL(list_eval_kernel<LTGW_STORE_BF16>, grid, block, 0, st, a, stack_bytes, stack_rows, idx, m, rmap, out_psi);
+    else
+        hipLaunchKernelGGL(list_eval_kernel<LTGW_STORE_FP8>, grid, block, 0, st, a, stack_bytes, stack_rows, idx, m, rmap, out_psi);
+    return hipGetLastError();
+}
+
+// Cells of the network's output (channel ch, position l of L) to fine
+// templates: group ch / 2, f0 index 2 l + ch % 2 (fine n_f0 = 2 L).
+__global__ void cells_to_templates_kernel(const int32_t *cells, int64_t n, int L, int32_t *tpl) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int cell = cells[i];
+    const int ch = cell / L, l = cell % L;
+    tpl[i] = (ch / 2) * (2 * L) + 2 * l + (ch % 2);
+}
+
+hipError_t launch_cells_to_templates(const int32_t *cells, int64_t n, int L, int32_t *tpl, hipStream_t st) {
+    hipLaunchKernelGGL(cells_to_templates_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cells,
+                       n, L, tpl);
+    return hipGetLastError();
+}
+
+// Per realisation: the best listed fine cell, the largest coarse ratio and
+// the fallback rule (coarse max > coarse threshold but no listed cell above
+// the detection threshold).
+__global__ void propose_reduce_kernel(int R, const double *psi_sel, const int32_t *tpl_sel, int M,
+                                      const double *psi_coarse, int nc, double thr, double cthr,
+                                      int32_t *best_idx, double *best_psi, int32_t *fallback) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= R) return;
+    double b = -__builtin_inf();
+    int bi = -1;
+    for (int q = 0; q < M; ++q) {
+        const double v = psi_sel[(int64_t)r * M + q];
+        const int t = tpl_sel[(int64_t)r * M + q];
+        if (v == v && (v > b || (v == b && t < bi))) {
+            b = v;
+            bi = t;
+        }
+    }
+    double cm = -__builtin_inf();
+    for (int q = 0; q < nc; ++q) {
+        const double v = psi_coarse[(int64_t)r * nc + q];
+        if (v == v && v > cm) cm = v;
+    }
+    best_idx[r] = bi;
+    best_psi[r] = b;
+    fallback[r] = (cm > cthr && !(b > thr)) ? 1 : 0;
+}
+
+hipError_t launch_propose_reduce(int R, const double *psi_sel, const int32_t *tpl_sel, int M,
+                                 const double *psi_coarse, int nc, double thr, double cthr,
+                                 int32_t *best_idx, double *best_psi, int32_t *fallback, hipStream_t st) {
+    hipLaunchKernelGGL(propose_reduce_kernel, dim3((R + 255) / 256), dim3(256), 0, st, R, psi_sel, tpl_sel, M,
+                       psi_coarse, nc, thr, cthr, best_idx, best_psi, fallback);
+    return hipGetLastError();
+}
+
+// Best entry of each row of psi[rows][n] (largest finite value, ties to the
+// lowest index; index = position, or idx[row][position] when idx is given):
+// one block per row, strided scan and an LDS tree.  No finite value: -1, -inf.
+__device__ inline bool best_before(double a, int ia, double b, int ib) {
+    return a > b || (a == b && (unsigned)ia < (unsigned)ib);
+}
+
+__global__ __launch_bounds__(256) void row_best_kernel(const double *psi, int64_t n, const int32_t *idx,
+                                                       int32_t *best_idx, double *best_psi) {
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    const int64_t row = blockIdx.x;
+    double b = -__builtin_inf();
+    int bi = -1;
+    for (int64_t q = threadIdx.x; q < n; q += 256) {
+        const double v = psi[row * n + q];
+        const int t = idx ? idx[row * n + q] : (int)q;
+        if (v == v && (bi < 0 || best_before(v, t, b, bi))) {
+            b = v;
+            bi = t;
+        }
+    }
+    sv[threadIdx.x] = b;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double v = sv[threadIdx.x + w];
+            const int t = si[threadIdx.x + w];
+            if (t >= 0 && (si[threadIdx.x] < 0 || best_before(v, t, sv[threadIdx.x], si[threadIdx.x]))) {
+                sv[threadIdx.x] = v;
+                si[threadIdx.x] = t;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        best_idx[row] = si[0];
+        best_psi[row] = si[0] < 0 ? -__builtin_inf() : sv[0];
+    }
+}
+
+hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t *idx, int32_t *best_idx,
+                           double *best_psi, hipStream_t st) {
+    if (rows < 1 || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(row_best_kernel, dim3(rows), dim3(256), 0, st, psi, n, idx, best_idx, best_psi);
+    return hipGetLastError();
+}
+
+// Fine templates to network cells (fine n_f0 = 2 L): template (group g, f0
+// index i) is cell (2 g + i % 2) L + i / 2; -1 where mask[r] == 0 or tpl < 0.
+__global__ void templates_to_cells_kernel(const int32_t *tpl, int n, int L, const int32_t *mask,
+                                          int32_t *cells) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int t = tpl[i];
+    if (t < 0 || (mask && mask[i] == 0)) {
+        cells[i] = -1;
+        return;
+    }
+    const int g = t / (2 * L), f = t % (2 * L);
+    cells[i] = (2 * g + (f & 1)) * L + (f >> 1);
+}
+
+hipError_t launch_templates_to_cells(const int32_t *tpl, int n, int L, const int32_t *mask, int32_t *cells,
+                                     hipStream_t st) {
+    hipLaunchKernelGGL(templates_to_cells_kernel, dim3((n + 255) / 256), dim3(256), 0, st, tpl, n, L, mask, cells);
+    return hipGetLastError();
+}
+
+// Every template index of a grid, once per listed realisation.
+__global__ void iota_rows_kernel(int32_t *idx, int rows, int n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < (int64_t)rows * n) idx[i] = (int32_t)(i % n);
+}
+
+hipError_t launch_iota_rows(int32_t *idx, int rows, int n, hipStream_t st) {
+    const int64_t t = (int64_t)rows * n;
+    hipLaunchKernelGGL(iota_rows_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, idx, rows, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// In-band moments (N, W1, W2) without touching the spectrogram.  For a fixed
+// (group, segment) the column index trunc(f0_i*H + 1.5 - k_lo) is a
+// non-decreasing function of i (every step is monotone), so the in-band
+// templates are the contiguous range [lo, hi) with lo the first i whose
+// index reaches 1 and hi the first whose index passes n_bins.  Both are
+// found by binary search with exactly the statistic kernel's arithmetic.
+__device__ inline int col_index(double f0_min, double f0_step, int i, double H, double cshift) {
+    const double f0 = f0_min + (double)i * f0_step;
+    const double x = f0 * H;
+    const double vv = x + cshift;
+    return __double2int_rz(vv);
+}
+
+// first i in [0, n] with col_index(i) >= target (n if none)
+__device__ inline int first_at_least(double f0_min, double f0_step, int n, double H,
+                                     double cshift, int target) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (col_index(f0_min, f0_step, mid, H, cshift) >= target)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Each lane takes kMomSeg consecutive segments of one group and merges
+// consecutive equal range ends before adding them, so the many segments that
+// share an end (every template in band: lo = 0, hi = n_f0) cost one atomic
+// per lane instead of one per segment.
+constexpr int kMomSeg = 32;
+
+struct RangeRun {
+    int key = -1;
+    unsigned long long v[4] = {0, 0, 0, 0};
+};
+
+__device__ inline void flush_run(RangeRun &r, unsigned long long *base, int64_t stride, int na,
+                                 bool negate) {
+    if (r.key < 0) return;
+    for (int q = 0; q < na; ++q)
+        if (r.v[q]) atomicAdd(base + q * stride + r.key, negate ? (unsigned long long)(-(long long)r.v[q]) : r.v[q]);
+    r.key = -1;
+    for (int q = 0; q < 4; ++q) r.v[q] = 0;
+}
+
+__device__ inline void add_run(RangeRun &r, int key, const unsigned long long *val, int na,
+                               unsigned long long *base, int64_t stride, bool negate) {
+    if (key != r.key) {
+        flush_run(r, base, stride, na, negate);
+        r.key = key;
+    }
+    for (int q = 0; q < na; ++q) r.v[q] += val[q];
+}
+
+__global__ __launch_bounds__(256) void moments_ranges_kernel(const EvalArgs a, int weights,
+                                                             int64_t *__restrict__ diff) {
+    const int d = blockIdx.z;
+    const DetView D = a.det[d];
+    const int row = blockIdx.y;
+    const int j0 = (blockIdx.x * 256 + threadIdx.x) * kMomSeg;
+    const int64_t stride = (int64_t)a.n_groups * (a.n_f0 + 1);
+    unsigned long long *base = (unsigned long long *)diff + (int64_t)row * (a.n_f0 + 1);
+    const int na = weights ? 4 : 1;
+    RangeRun rlo, rhi;
+    unsigned long long inb = 0;
+    const int j1 = min(j0 + kMomSeg, D.n_seg);
+    const int tn = row % a.n_tn, sky = row / a.n_tn;
+    for (int j = j0; j < j1; ++j) {
+        double H;
+        if (D.H) {
+            H = D.H[(int64_t)row * D.n_seg + j];
+        } else {
+            const double h = D.g[(int64_t)tn * D.n_seg + j] * D.D[(int64_t)sky * D.n_seg + j];
+            H = h * D.t_sft;
+        }
+        const int lo = first_at_least(a.f0_min, a.f0_step, a.n_f0, H, D.cshift, 1);
+        const int hi = first_at_least(a.f0_min, a.f0_step, a.n_f0, H, D.cshift, D.n_bins + 1);
+        if (lo >= hi) continue;
+        inb += (unsigned long long)(hi - lo);
+        unsigned long long val[4] = {1ull, 0ull, 0ull, 0ull};
+        if (weights)
+            for (int q = 0; q < 3; ++q) val[q + 1] = (unsigned long long)D.wfix[3 * j + q];
+        add_run(rlo, lo, val, na, base, stride, false);
+        add_run(rhi, hi, val, na, base, stride, true);
+    }
+    flush_run(rlo, base, stride, na, false);
+    flush_run(rhi, base, stride, na, true);
+    for (int o = 32; o > 0; o >>= 1) inb += __shfl_xor(inb, o, 64);
+    if ((threadIdx.x & 63) == 0 && inb && a.in_band_total) atomicAdd(a.in_band_total, inb);
+}
+
+// One block per group: prefix sums of the difference arrays over f0, in tiles
+// of 256 consecutive positions (coalesced), with a running carry.
+__device__ inline int64_t block_inclusive_scan_256(int64_t v, int64_t *sh, int64_t &total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) sh[wv] = v;
+    __syncthreads();
+    int64_t off = 0;
+    for (int k = 0; k < wv; ++k) off += sh[k];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return v + off;
+}
+
+__global__ __launch_bounds__(256) void moments_scan_kernel(const EvalArgs a, int weights, int e0,
+                                                           const int64_t *__restrict__ diff) {
+    __shared__ int64_t sh[4];
+    const int row = blockIdx.x;
+    const int n = a.n_f0;
+    const int64_t stride = (int64_t)a.n_groups * (n + 1);
+    const int64_t *base = diff + (int64_t)row * (n + 1);
+    const int na = weights ? 4 : 1;
+    int64_t carry[4] = {0, 0, 0, 0};
+    const double wu = (double)a.w_uniform;
+    for (int i0 = 0; i0 < n; i0 += 256) {
+        const int i = i0 + threadIdx.x;
+        int64_t run[4] = {0, 0, 0, 0};
+        for (int q = 0; q < na; ++q) {
+            const int64_t v = i < n ? base[q * stride + i] : 0;
+            int64_t tot;
+            run[q] = block_inclusive_scan_256(v, sh, tot) + carry[q];
+            carry[q] += tot;
+        }
+        if (i < n) {
+            const int64_t t = (int64_t)row * n + i;
+            const int nin = (int)run[0];
+            double w1, w2;
+            if (weights) {
+                w1 = ldexp((double)run[1], e0);
+                w2 = ldexp((double)run[2] * 4294967296.0 + (double)run[3], 2 * e0);
+            } else {
+                w1 = (double)nin * wu;
+                w2 = (double)nin * (wu * wu);
+            }
+            a.n[t] = nin;
+            a.w1[t] = w1;
+            a.w2[t] = w2;
+            if (a.out_n) a.out_n[t] = nin;
+        }
+    }
+}
+
+__global__ void zero_i64_kernel(int64_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = 0;
+}
+
+hipError_t launch_moments(const EvalArgs &a, int weights, int e0, int64_t *diff, hipStream_t st) {
+    const int64_t n_entries = (int64_t)(weights ? 4 : 1) * a.n_groups * (a.n_f0 + 1);
+    hipLaunchKernelGGL(zero_i64_kernel, dim3(1024), dim3(256), 0, st, diff, n_entries);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int max_seg = 0;
+    for (int d = 0; d < a.n_det; ++d) max_seg = a.det[d].n_seg > max_seg ? a.det[d].n_seg : max_seg;
+    const int lanes = (max_seg + kMomSeg - 1) / kMomSeg;
+    hipLaunchKernelGGL(moments_ranges_kernel, dim3((lanes + 255) / 256, a.n_groups, a.n_det),
+                       dim3(256), 0, st, a, weights, diff);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(moments_scan_kernel, dim3(a.n_groups), dim3(256), 0, st, a, weights, e0,
+                       (const int64_t *)diff);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -444,6 +1161,10 @@ __global__ __launch_bounds__(256) void topk_level_kernel(
                 bp = sp[wv];
                 bi = si[wv];
             }
+        // block-uniform values from LDS, made scalar so the early exit below
+        // is a uniform branch (barriers inside the loop)
+        bi = ((int64_t)__builtin_amdgcn_readfirstlane((int)(bi >> 32)) << 32) |
+             (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bi);
         __syncthreads();
         if (threadIdx.x == 0) {
             out_psi[(int64_t)blockIdx.x * k + r] = bp;

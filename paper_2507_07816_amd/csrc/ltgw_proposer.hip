@@ -1,0 +1,569 @@
+// Kernels of the learned proposer: synthetic training data (counter-based
+// Exp(1) noise, injected tracks), the 2x2-coarsened BF16 store of the coarse
+// pass, the ranking network (BF16 MFMA, FP32 accumulation) with its backward
+// pass, loss and Adam, and the per-row top-M selection of fine cells.
+#include "ltgw_internal.h"
+#include "ddpow.h"
+
+#pragma clang fp contract(off)
+
+namespace ltgw {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC11): ten rounds of
+//   (c0, c1, c2, c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
+// with the key advanced by the Weyl constants W0, W1 between rounds.
+constexpr uint32_t kPhM0 = 0xD2511F53u, kPhM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhW0 = 0x9E3779B9u, kPhW1 = 0xBB67AE85u;
+
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhM0 * c[0];
+        const uint64_t p1 = (uint64_t)kPhM1 * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        const uint32_t n3 = (uint32_t)p0;
+        c[0] = n0;
+        c[1] = n1;
+        c[2] = n2;
+        c[3] = n3;
+        k0 += kPhW0;
+        k1 += kPhW1;
+    }
+}
+
+// Exp(1) noise: element e of realisation r takes word e % 4 of
+// Philox(counter = (e/4 low, e/4 high, r, stream), key = seed);
+// u = (word + 1/2) 2^-32 in (0, 1) exactly; value RN_32(-log(u)) (FP64 log).
+__global__ __launch_bounds__(256) void noise_kernel(uint64_t seed, uint32_t stream, int r0,
+                                                    int64_t n_per, float *__restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (q * 4 >= n_per) return;
+    uint32_t c[4] = {(uint32_t)q, (uint32_t)((uint64_t)q >> 32), (uint32_t)(r0 + r), stream};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    float *o = out + (int64_t)r * n_per;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t e = q * 4 + i;
+        if (e < n_per) {
+            const double u = ((double)c[i] + 0.5) * 0x1p-32;
+            o[e] = (float)(-log(u));
+        }
+    }
+}
+
+hipError_t launch_noise(uint64_t seed, uint32_t stream, int r0, int R, int64_t n_per, float *out,
+                        hipStream_t st) {
+    if (R < 1 || R > 65535 || n_per < 1) return hipErrorInvalidValue;
+    const int64_t blocks = ((n_per + 3) / 4 + 255) / 256;
+    hipLaunchKernelGGL(noise_kernel, dim3((unsigned)blocks, (unsigned)R), dim3(256), 0, st, seed, stream,
+                       r0, n_per, out);
+    return hipGetLastError();
+}
+
+// Injected tracks into a stack: realisation r gets amp_r * w_j at the bin of
+// template params[r] = (f0, tau, brake, amp) in every in-band segment (amp 0:
+// none); the bin arithmetic is the statistic's.
+__global__ __launch_bounds__(256) void inject_stack_kernel(
+    float *power, int n_seg, int n_bins, int64_t k_lo, double t_sft, const double *t_seg,
+    const double *v, const float *w, const double *params, double sx, double sy, double sz,
+    double t0, unsigned long long *undecided) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (j >= n_seg) return;
+    const double f0 = params[4 * r + 0], tau = params[4 * r + 1], brake = params[4 * r + 2];
+    const float amp = (float)params[4 * r + 3];
+    if (amp == 0.0f) return;
+    const double t = t_seg[j];
+    if (t < t0) return;
+    const double d = t - t0;
+    const double qq = d / tau;
+    const double u = 1.0 + qq;
+    const double e = 1.0 / (1.0 - brake);
+    int und = 0;
+    const double g = pow_cr(u, e, &und);
+    if (und) atomicAdd(undecided, 1ull);
+    const double a = v[3 * j + 0] * sx;
+    const double b = v[3 * j + 1] * sy;
+    const double z = v[3 * j + 2] * sz;
+    const double vn = (a + b) + z;
+    const double D = 1.0 + vn / kC;
+    const double h = g * D;
+    const double H = h * t_sft;
+    const double x = f0 * H;
+    const double y = x + 0.5;
+    const int64_t bin = (int64_t)floor(y) - k_lo;
+    if (bin < 0 || bin >= n_bins) return;
+    float *px = power + ((int64_t)r * n_seg + j) * n_bins + bin;
+    *px = *px + amp * w[j];
+}
+
+hipError_t launch_inject_stack(float *power, int R, int32_t n_seg, int32_t n_bins, int64_t k_lo,
+                               double t_sft, const double *t_seg, const double *v, const float *w,
+                               const double *params, double sx, double sy, double sz, double t0,
+                               unsigned long long *undecided, hipStream_t st) {
+    if (R < 1 || R > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(inject_stack_kernel, dim3((n_seg + 255) / 256, R), dim3(256), 0, st, power,
+                       n_seg, n_bins, k_lo, t_sft, t_seg, v, w, params, sx, sy, sz, t0, undecided);
+    return hipGetLastError();
+}
+
+// 2x2 coarsening into BF16: coarse[r][j'][m + 1] = RN_bf16((P[2j'][2m] + P[2j'][2m+1]) +
+// (P[2j'+1][2m] + P[2j'+1][2m+1])) (FP32 sums), zero guards at 0 and n_bins/2 + 1.
+__device__ inline unsigned short bf16_rne(float x) {  // finite x >= 0
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ __launch_bounds__(256) void coarsen_kernel(const float *__restrict__ in, int n_seg,
+                                                      int n_bins, int64_t pitch2,
+                                                      unsigned short *__restrict__ out) {
+    const int j2 = blockIdx.x, r = blockIdx.y;
+    const int ns2 = n_seg / 2, nb2 = n_bins / 2;
+    const float *r0 = in + ((int64_t)r * n_seg + 2 * j2) * n_bins;
+    const float *r1 = r0 + n_bins;
+    unsigned short *o = out + ((int64_t)r * ns2 + j2) * pitch2;
+    for (int64_t b = threadIdx.x; b < pitch2; b += 256) {
+        unsigned short code = 0;
+        if (b >= 1 && b <= nb2) {
+            const int64_t m = b - 1;
+            const float a = r0[2 * m] + r0[2 * m + 1];
+            const float c = r1[2 * m] + r1[2 * m + 1];
+            code = bf16_rne(a + c);
+        }
+        o[b] = code;
+    }
+}
+
+hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins, int64_t pitch2,
+                          unsigned short *out, hipStream_t st) {
+    if (R < 1 || R > 65535 || n_seg < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(coarsen_kernel, dim3(n_seg / 2, R), dim3(256), 0, st, in, n_seg, n_bins, pitch2, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Ranking network.  Layers (width 32, kernel 5, zero padding 2):
+//   h1 = relu(conv(x; W1, b1)), h2 = relu(conv(h1; W2, b2)), h3 = relu(conv(h2; W3, b3)),
+//   z = conv1(h3; W4, b4)
+// conv(x; W, b)[b][o][l] = b[o] + sum_{c,t} W[o][c][t] x[b][c][l + t - p].
+// Every contraction is a GEMM on v_mfma_f32_16x16x16_bf16 (operands rounded
+// to bfloat16, FP32 accumulation): a wavefront owns a 16 x 16 output tile
+// and walks K in steps of 16.  Lane l of the wavefront holds A[l % 16][4 (l/16) + i],
+// B[4 (l/16) + i][l % 16] (i < 4) and receives C[4 (l/16) + i][l % 16].
+constexpr int kWidth = 32;
+constexpr int kTaps = 5;
+
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ inline short to_bf16(float x) {
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (short)(u >> 16);  // inf/nan kept
+    return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+struct ConvDims {
+    int B, C, L, O, k, p;
+};
+
+// Y = conv(X; W, b) (+ relu).  GEMM rows o, columns n = (b, l), K = (c, t).
+__global__ __launch_bounds__(256) void conv_fwd_kernel(ConvDims d, const float *__restrict__ X,
+                                                       const float *__restrict__ W,
+                                                       const float *__restrict__ bias, int relu,
+                                                       float *__restrict__ Y) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t N = (int64_t)d.B * d.L;
+    const int64_t n0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
+    const int m0 = blockIdx.y * 16;
+    const int K = d.C * d.k;
+    const int row = lane & 15, kq = (lane >> 4) * 4;
+    const int64_t n = n0 + row;  // this lane's B-operand column
+    const int nb = (int)(n / d.L), nl = (int)(n % d.L);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < K; kk += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kidx = kk + kq + i;
+            const int o = m0 + row;
+            float av = 0.f, bv = 0.f;
+            if (kidx < K) {
+                const int c = kidx / d.k, t = kidx % d.k;
+                if (o < d.O) av = W[((int64_t)o * d.C + c) * d.k + t];
+                const int li = nl + t - d.p;
+                if (n < N && li >= 0 && li < d.L) bv = X[((int64_t)nb * d.C + c) * d.L + li];
+            }
+            a[i] = to_bf16(av);
+            b[i] = to_bf16(bv);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    const int64_t nc = n0 + (lane & 15);
+    if (nc >= N) return;
+    const int cb = (int)(nc / d.L), cl = (int)(nc % d.L);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int o = m0 + (lane >> 4) * 4 + i;
+        if (o >= d.O) continue;
+        float y = acc[i] + bias[o];
+        if (relu) y = y > 0.f ? y : 0.f;
+        Y[((int64_t)cb * d.O + o) * d.L + cl] = y;
+    }
+}
+
+// dX = conv^T(dY; W), times the mask (H > 0) of the layer below when H is given.
+// GEMM rows c, columns n = (b, l), K = (o, t): dX[b][c][l] = sum W[o][c][t] dY[b][o][l - t + p].
+__global__ __launch_bounds__(256) void conv_bwd_data_kernel(ConvDims d, const float *__restrict__ dY,
+                                                            const float *__restrict__ W,
+                                                            const float *__restrict__ H,
+                                                            float *__restrict__ dX) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t N = (int64_t)d.B * d.L;
+    const int64_t n0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
+    const int m0 = blockIdx.y * 16;
+    const int K = d.O * d.k;
+    const int row = lane & 15, kq = (lane >> 4) * 4;
+    const int64_t n = n0 + row;
+    const int nb = (int)(n / d.L), nl = (int)(n % d.L);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < K; kk += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kidx = kk + kq + i;
+            const int c = m0 + row;
+            float av = 0.f, bv = 0.f;
+            if (kidx < K) {
+                const int o = kidx / d.k, t = kidx % d.k;
+                if (c < d.C) av = W[((int64_t)o * d.C + c) * d.k + t];
+                const int li = nl - t + d.p;
+                if (n < N && li >= 0 && li < d.L) bv = dY[((int64_t)nb * d.O + o) * d.L + li];
+            }
+            a[i] = to_bf16(av);
+            b[i] = to_bf16(bv);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    const int64_t nc = n0 + (lane & 15);
+    if (nc >= N) return;
+    const int cb = (int)(nc / d.L), cl = (int)(nc % d.L);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = m0 + (lane >> 4) * 4 + i;
+        if (c >= d.C) continue;
+        const int64_t off = ((int64_t)cb * d.C + c) * d.L + cl;
+        float g = acc[i];
+        if (H && !(H[off] > 0.f)) g = 0.f;
+        dX[off] = g;
+    }
+}
+
+// Partial weight gradients over a chunk of columns: GEMM rows o, columns
+// (c, t), K = n = (b, l) in [chunk * kc, (chunk + 1) kc):
+//   part[chunk][o][c][t] = sum_n dY[b][o][l] X[b][c][l + t - p].
+__global__ __launch_bounds__(256) void conv_bwd_weight_kernel(ConvDims d, const float *__restrict__ dY,
+                                                              const float *__restrict__ X, int64_t kc,
+                                                              float *__restrict__ part) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int CK = d.C * d.k;
+    const int j0 = (blockIdx.x * 4 + wv) * 16;  // column tile over (c, t)
+    const int m0 = blockIdx.y * 16;
+    const int64_t N = (int64_t)d.B * d.L;
+    const int64_t k_begin = (int64_t)blockIdx.z * kc;
+    const int64_t k_end = k_begin + kc < N ? k_begin + kc : N;
+    const int row = lane & 15, kq = (lane >> 4) * 4;
+    const int jcol = j0 + row;
+    const int bc = jcol < CK ? jcol / d.k : 0, bt = jcol < CK ? jcol % d.k : 0;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t kk = k_begin; kk < k_end; kk += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t n = kk + kq + i;
+            float av = 0.f, bv = 0.f;
+            if (n < k_end) {
+                const int nb = (int)(n / d.L), nl = (int)(n % d.L);
+                const int o = m0 + row;
+                if (o < d.O) av = dY[((int64_t)nb * d.O + o) * d.L + nl];
+                const int li = nl + bt - d.p;
+                if (jcol < CK && li >= 0 && li < d.L) bv = X[((int64_t)nb * d.C + bc) * d.L + li];
+            }
+            a[i] = to_bf16(av);
+            b[i] = to_bf16(bv);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    const int jc = j0 + (lane & 15);
+    if (jc >= CK) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int o = m0 + (lane >> 4) * 4 + i;
+        if (o < d.O) part[((int64_t)blockIdx.z * d.O + o) * CK + jc] = acc[i];
+    }
+}
+
+// Sum of the chunk partials in chunk order (deterministic) into grad.
+__global__ void sum_chunks_kernel(const float *part, int chunks, int64_t n, float *grad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int q = 0; q < chunks; ++q) s += part[(int64_t)q * n + i];
+    grad[i] = s;
+}
+
+// Bias gradient: db[o] = sum_{b,l} dY[b][o][l], one block per o, fixed order.
+__global__ __launch_bounds__(256) void bias_grad_kernel(const float *dY, int B, int O, int L, float *db) {
+    __shared__ float sh[256];
+    const int o = blockIdx.x;
+    float s = 0.f;
+    for (int64_t n = threadIdx.x; n < (int64_t)B * L; n += 256) {
+        const int b = (int)(n / L), l = (int)(n % L);
+        s += dY[((int64_t)b * O + o) * L + l];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[o] = sh[0];
+}
+
+struct CnnLayout {
+    int64_t off[8];  // W1 b1 W2 b2 W3 b3 W4 b4
+    int64_t total;
+};
+
+__host__ __device__ inline CnnLayout cnn_layout(int c_in, int c_out) {
+    CnnLayout L;
+    const int64_t sz[8] = {(int64_t)kWidth * c_in * kTaps, kWidth, (int64_t)kWidth * kWidth * kTaps, kWidth,
+                           (int64_t)kWidth * kWidth * kTaps, kWidth, (int64_t)c_out * kWidth, c_out};
+    int64_t o = 0;
+    for (int i = 0; i < 8; ++i) {
+        L.off[i] = o;
+        o += sz[i];
+    }
+    L.total = o;
+    return L;
+}
+
+int64_t cnn_n_params(int c_in, int c_out) { return cnn_layout(c_in, c_out).total; }
+
+static hipError_t conv_fwd(const ConvDims &d, const float *X, const float *W, const float *b, int relu,
+                           float *Y, hipStream_t st) {
+    const int64_t N = (int64_t)d.B * d.L;
+    const int64_t tiles = (N + 15) / 16;
+    dim3 grid((unsigned)((tiles + 3) / 4), (unsigned)((d.O + 15) / 16)), block(256);
+    hipLaunchKernelGGL(conv_fwd_kernel, grid, block, 0, st, d, X, W, b, relu, Y);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_forward(const float *params, const float *x, int B, int c_in, int c_out, int L,
+                              float *act, float *logits, hipStream_t st) {
+    const CnnLayout P = cnn_layout(c_in, c_out);
+    const int64_t la = (int64_t)B * kWidth * L;
+    float *h1 = act, *h2 = act + la, *h3 = act + 2 * la;
+    hipError_t e;
+    ConvDims d1{B, c_in, L, kWidth, kTaps, kTaps / 2};
+    if ((e = conv_fwd(d1, x, params + P.off[0], params + P.off[1], 1, h1, st)) != hipSuccess) return e;
+    ConvDims d2{B, kWidth, L, kWidth, kTaps, kTaps / 2};
+    if ((e = conv_fwd(d2, h1, params + P.off[2], params + P.off[3], 1, h2, st)) != hipSuccess) return e;
+    if ((e = conv_fwd(d2, h2, params + P.off[4], params + P.off[5], 1, h3, st)) != hipSuccess) return e;
+    ConvDims d4{B, kWidth, L, c_out, 1, 0};
+    return conv_fwd(d4, h3, params + P.off[6], params + P.off[7], 0, logits, st);
+}
+
+// Work area of the backward pass: two activation-sized gradients plus the
+// weight-gradient chunk partials.
+constexpr int64_t kWgradChunk = 4096;
+static int64_t wgrad_chunks(int B, int L) { return ((int64_t)B * L + kWgradChunk - 1) / kWgradChunk; }
+
+int64_t cnn_work_floats(int B, int c_in, int c_out, int L) {
+    const int64_t la = (int64_t)B * kWidth * L;
+    const int64_t wmax = (int64_t)kWidth * (c_in > kWidth ? c_in : kWidth) * kTaps;
+    const int64_t w4 = (int64_t)c_out * kWidth;
+    return 2 * la + wgrad_chunks(B, L) * (wmax > w4 ? wmax : w4);
+}
+
+static hipError_t weight_grad(const ConvDims &d, const float *dY, const float *X, float *part, float *dW,
+                              float *db, hipStream_t st) {
+    const int CK = d.C * d.k;
+    const int64_t chunks = wgrad_chunks(d.B, d.L);
+    dim3 grid((unsigned)(((CK + 15) / 16 + 3) / 4), (unsigned)((d.O + 15) / 16), (unsigned)chunks);
+    hipLaunchKernelGGL(conv_bwd_weight_kernel, grid, dim3(256), 0, st, d, dY, X, kWgradChunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)d.O * CK;
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part,
+                       (int)chunks, n, dW);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(bias_grad_kernel, dim3(d.O), dim3(256), 0, st, dY, d.B, d.O, d.L, db);
+    return hipGetLastError();
+}
+
+static hipError_t data_grad(const ConvDims &d, const float *dY, const float *W, const float *H, float *dX,
+                            hipStream_t st) {
+    const int64_t N = (int64_t)d.B * d.L;
+    const int64_t tiles = (N + 15) / 16;
+    dim3 grid((unsigned)((tiles + 3) / 4), (unsigned)((d.C + 15) / 16)), block(256);
+    hipLaunchKernelGGL(conv_bwd_data_kernel, grid, block, 0, st, d, dY, W, H, dX);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_backward(const float *params, const float *x, int B, int c_in, int c_out, int L,
+                               const float *act, const float *dlogits, float *work, int64_t work_floats,
+                               float *grads, hipStream_t st) {
+    if (work_floats < cnn_work_floats(B, c_in, c_out, L)) return hipErrorInvalidValue;
+    const CnnLayout P = cnn_layout(c_in, c_out);
+    const int64_t la = (int64_t)B * kWidth * L;
+    const float *h1 = act, *h2 = act + la, *h3 = act + 2 * la;
+    float *ga = work, *gb = work + la, *part = work + 2 * la;
+    hipError_t e;
+    ConvDims d4{B, kWidth, L, c_out, 1, 0};
+    ConvDims d3{B, kWidth, L, kWidth, kTaps, kTaps / 2};
+    ConvDims d1{B, c_in, L, kWidth, kTaps, kTaps / 2};
+    // layer 4: dW4, db4 and dh3 (masked by h3 > 0)
+    if ((e = weight_grad(d4, dlogits, h3, part, grads + P.off[6], grads + P.off[7], st)) != hipSuccess) return e;
+    if ((e = data_grad(d4, dlogits, params + P.off[6], h3, ga, st)) != hipSuccess) return e;
+    // layer 3
+    if ((e = weight_grad(d3, ga, h2, part, grads + P.off[4], grads + P.off[5], st)) != hipSuccess) return e;
+    if ((e = data_grad(d3, ga, params + P.off[4], h2, gb, st)) != hipSuccess) return e;
+    // layer 2
+    if ((e = weight_grad(d3, gb, h1, part, grads + P.off[2], grads + P.off[3], st)) != hipSuccess) return e;
+    if ((e = data_grad(d3, gb, params + P.off[2], h1, ga, st)) != hipSuccess) return e;
+    // layer 1 (no gradient for the input)
+    return weight_grad(d1, ga, x, part, grads + P.off[0], grads + P.off[1], st);
+}
+
+// Softmax cross-entropy per sample over n_cells logits against one target
+// cell (target < 0: loss 0, gradient 0); gradients divided by n_valid.
+__global__ __launch_bounds__(256) void softmax_xent_kernel(const float *logits, int n_cells,
+                                                           const int32_t *target, int n_valid,
+                                                           float *loss, float *dlogits) {
+    __shared__ float sh[256];
+    const int b = blockIdx.x;
+    const float *z = logits + (int64_t)b * n_cells;
+    float *dz = dlogits + (int64_t)b * n_cells;
+    const int tg = target[b];
+    if (tg < 0) {
+        for (int i = threadIdx.x; i < n_cells; i += 256) dz[i] = 0.f;
+        if (threadIdx.x == 0) loss[b] = 0.f;
+        return;
+    }
+    float m = -3.4e38f;
+    for (int i = threadIdx.x; i < n_cells; i += 256) m = fmaxf(m, z[i]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    m = sh[0];
+    __syncthreads();
+    float s = 0.f;
+    for (int i = threadIdx.x; i < n_cells; i += 256) s += expf(z[i] - m);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    s = sh[0];
+    const float inv = 1.0f / ((float)n_valid * s);
+    for (int i = threadIdx.x; i < n_cells; i += 256) {
+        float g = expf(z[i] - m) * inv;
+        if (i == tg) g -= 1.0f / (float)n_valid;
+        dz[i] = g;
+    }
+    if (threadIdx.x == 0) loss[b] = logf(s) + m - z[tg];
+}
+
+hipError_t launch_softmax_xent(const float *logits, int B, int n_cells, const int32_t *target,
+                               int n_valid, float *loss, float *dlogits, hipStream_t st) {
+    if (B < 1 || n_cells < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(softmax_xent_kernel, dim3(B), dim3(256), 0, st, logits, n_cells, target,
+                       n_valid < 1 ? 1 : n_valid, loss, dlogits);
+    return hipGetLastError();
+}
+
+// Adam (Kingma and Ba) on FP32 master weights.
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t st) {
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, g, m, v, n, lr,
+                       b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+// Per row of n scores: indices of the M largest (score desc, index asc; NaN
+// ranks last), by a bitonic sort of (score, index) pairs in LDS.
+constexpr int kSelMax = 8192;
+
+__device__ inline bool sel_before(float a, int ia, float b, int ib) {
+    return a > b || (a == b && ia < ib);
+}
+
+__global__ __launch_bounds__(256) void select_top_kernel(const float *score, int n, int M,
+                                                         int32_t *out) {
+    __shared__ float ks[kSelMax];
+    __shared__ int ki[kSelMax];
+    const int r = blockIdx.x;
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += 256) {
+        float v = -3.4e38f;
+        if (i < n) {
+            v = score[(int64_t)r * n + i];
+            if (!(v == v)) v = -3.4e38f;
+        }
+        ks[i] = v;
+        ki[i] = i < n ? i : 0x7fffffff;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P; i += 256) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool desc = (i & size) == 0;  // first half of each block sorted best-first
+                    const bool swap = desc ? sel_before(ks[j], ki[j], ks[i], ki[i])
+                                           : sel_before(ks[i], ki[i], ks[j], ki[j]);
+                    if (swap) {
+                        const float tv = ks[i];
+                        ks[i] = ks[j];
+                        ks[j] = tv;
+                        const int ti = ki[i];
+                        ki[i] = ki[j];
+                        ki[j] = ti;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < M; i += 256) out[(int64_t)r * M + i] = ki[i];
+}
+
+hipError_t launch_select_top(const float *score, int R, int n, int M, int32_t *out, hipStream_t st) {
+    if (n < 1 || n > kSelMax || M < 1 || M > n || R < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(select_top_kernel, dim3(R), dim3(256), 0, st, score, n, M, out);
+    return hipGetLastError();
+}
+
+}  // namespace ltgw

@@ -32,13 +32,21 @@ LTGW_STAT_POWER = 1
 LTGW_STAT_COUNT = 2
 STATS = {"power": LTGW_STAT_POWER, "count": LTGW_STAT_COUNT}
 
-LTGW_MAX_DET = 4
+LTGW_MAX_DET = 256
+LTGW_MAX_SEARCH_DET = 4
 LTGW_MAX_TOPK = 256
+TILE_SHAPES = {0: (1, 8), 1: (1, 16), 2: (2, 8), 3: (2, 16)}  # (templates per lane, segments per batch)
 
 # every symbol include/ltgw.h declares
 EXPORTS = ("ltgw_create", "ltgw_destroy", "ltgw_last_error", "ltgw_load_spectrogram",
            "ltgw_set_velocity_table", "ltgw_eval_templates", "ltgw_psi",
-           "ltgw_topk_candidates", "ltgw_diagnostics", "ltgw_inject_track", "ltgw_read_store")
+           "ltgw_topk_candidates", "ltgw_diagnostics", "ltgw_inject_track", "ltgw_read_store",
+           "ltgw_eval_batch", "ltgw_batch_results", "ltgw_batch_latency", "ltgw_autotune",
+           "ltgw_set_tile_shape", "ltgw_tune_save", "ltgw_tune_load",
+           "ltgw_generate_noise", "ltgw_inject_stack", "ltgw_load_stack", "ltgw_stack_psi",
+           "ltgw_stack_psi_list", "ltgw_cnn_param_count", "ltgw_cnn_work_floats", "ltgw_cnn_forward",
+           "ltgw_cnn_backward", "ltgw_softmax_xent", "ltgw_adam_step", "ltgw_select_top",
+           "ltgw_propose", "ltgw_stack_features", "ltgw_stack_best", "ltgw_cells_from_templates")
 
 
 class ltgw_spec_desc(C.Structure):
@@ -62,7 +70,26 @@ class ltgw_candidate(C.Structure):
 
 class ltgw_diag(C.Structure):
     _fields_ = [("pow_undecided", C.c_int64), ("templates", C.c_int64), ("evals", C.c_int64),
-                ("in_band", C.c_int64), ("eval_kernel_ms", C.c_double), ("tables_ms", C.c_double)]
+                ("in_band", C.c_int64), ("eval_kernel_ms", C.c_double), ("tables_ms", C.c_double),
+                ("tile_shape", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ltgw_search(C.Structure):
+    _fields_ = [("grid", ltgw_grid), ("dets", C.c_int32 * 4), ("n_dets", C.c_int32)]
+
+
+class ltgw_batch_stats(C.Structure):
+    _fields_ = [("graph_replayed", C.c_int32), ("variant", C.c_int32),
+                ("templates_per_lane", C.c_int32), ("segments_per_batch", C.c_int32),
+                ("workgroups", C.c_int32), ("tiles", C.c_int32), ("templates", C.c_int64),
+                ("evals", C.c_int64), ("in_band", C.c_int64), ("kernel_ms", C.c_double),
+                ("total_ms", C.c_double)]
+
+
+class ltgw_proposer(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("c_in", C.c_int32), ("c_out", C.c_int32), ("L", C.c_int32),
+                ("n_select", C.c_int32), ("psi_threshold", C.c_double),
+                ("coarse_threshold", C.c_double)]
 
 
 class LtgwError(RuntimeError):
@@ -95,6 +122,30 @@ def library():
             "ltgw_diagnostics": (i32, [P, C.POINTER(ltgw_diag)]),
             "ltgw_inject_track": (i32, [P, i32, P, d, d, d, P, d, f]),
             "ltgw_read_store": (i32, [P, i32, P, P]),
+            "ltgw_eval_batch": (i32, [P, P, i32, i32, P, P, P, P, C.POINTER(ltgw_batch_stats)]),
+            "ltgw_batch_results": (i32, [P, i32, P, P, P, P, P]),
+            "ltgw_batch_latency": (i32, [P, P]),
+            "ltgw_autotune": (i32, [P, C.POINTER(ltgw_grid), C.POINTER(i32)]),
+            "ltgw_set_tile_shape": (i32, [P, i32]),
+            "ltgw_tune_save": (i32, [P, C.c_char_p]),
+            "ltgw_tune_load": (i32, [P, C.c_char_p]),
+            "ltgw_generate_noise": (i32, [P, C.c_uint64, u32, i32, i32, C.c_int64, P]),
+            "ltgw_inject_stack": (i32, [P, i32, P, i32, P, P, d]),
+            "ltgw_load_stack": (i32, [P, i32, i32, P, i32, i32]),
+            "ltgw_stack_psi": (i32, [P, C.POINTER(ltgw_grid), i32, i32, P]),
+            "ltgw_stack_psi_list": (i32, [P, C.POINTER(ltgw_grid), P, i32, P]),
+            "ltgw_cnn_param_count": (C.c_int64, [i32, i32]),
+            "ltgw_cnn_work_floats": (C.c_int64, [i32, i32, i32, i32]),
+            "ltgw_cnn_forward": (i32, [P, P, P, i32, i32, i32, i32, P, P]),
+            "ltgw_cnn_backward": (i32, [P, P, P, i32, i32, i32, i32, P, P, P, C.c_int64, P]),
+            "ltgw_softmax_xent": (i32, [P, P, i32, i32, P, i32, P, P]),
+            "ltgw_adam_step": (i32, [P, P, P, P, P, C.c_int64, f, f, f, f, i32]),
+            "ltgw_select_top": (i32, [P, P, i32, i32, i32, P]),
+            "ltgw_stack_features": (i32, [P, C.POINTER(ltgw_grid), P]),
+            "ltgw_stack_best": (i32, [P, C.POINTER(ltgw_grid), P, P]),
+            "ltgw_cells_from_templates": (i32, [P, P, i32, i32, P, P]),
+            "ltgw_propose": (i32, [P, C.POINTER(ltgw_grid), C.POINTER(ltgw_grid), C.POINTER(ltgw_proposer),
+                                   P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -217,6 +268,191 @@ def ltgw_read_store(ctx, det, n_seg, n_bins, store):
     return out, sc
 
 
+def ltgw_eval_batch(ctx, searches, k):
+    """searches: list of (make_grid(...) result, detector slot list).  Returns
+    (top_power, top_count, stats): per-search lists of candidate dicts and a dict."""
+    n = len(searches)
+    arr = (ltgw_search * n)()
+    keep = []
+    for i, ((g, kg), dets) in enumerate(searches):
+        keep.append(kg)
+        arr[i].grid = g
+        if not 1 <= len(dets) <= LTGW_MAX_SEARCH_DET:
+            raise ValueError("a search sums 1..4 detectors")
+        for q, d in enumerate(dets):
+            arr[i].dets[q] = int(d)
+        arr[i].n_dets = len(dets)
+    tp = (ltgw_candidate * (n * k))()
+    tc = (ltgw_candidate * (n * k))()
+    npw = (C.c_int32 * n)()
+    nct = (C.c_int32 * n)()
+    st = ltgw_batch_stats()
+    _check(ctx, library().ltgw_eval_batch(ctx, C.cast(arr, C.c_void_p), n, int(k), C.cast(tp, C.c_void_p),
+                                          C.cast(tc, C.c_void_p), C.cast(npw, C.c_void_p),
+                                          C.cast(nct, C.c_void_p), C.byref(st)))
+    rec = lambda a, j: {f: getattr(a[j], f) for f, _ in ltgw_candidate._fields_}
+    top_p = [[rec(tp, i * k + r) for r in range(npw[i])] for i in range(n)]
+    top_c = [[rec(tc, i * k + r) for r in range(nct[i])] for i in range(n)]
+    return top_p, top_c, {f: getattr(st, f) for f, _ in ltgw_batch_stats._fields_}
+
+
+def ltgw_batch_results(ctx, i, out_s=None, out_c=None, out_n=None, psi_power=None, psi_count=None):
+    a = [_addr(x)[0] for x in (out_s, out_c, out_n, psi_power, psi_count)]
+    _check(ctx, library().ltgw_batch_results(ctx, int(i), *a))
+
+
+def ltgw_batch_latency(ctx, n):
+    out = np.empty(n, np.float64)
+    _check(ctx, library().ltgw_batch_latency(ctx, out.ctypes.data))
+    return out
+
+
+def ltgw_autotune(ctx, grid):
+    v = C.c_int32()
+    _check(ctx, library().ltgw_autotune(ctx, C.byref(grid), C.byref(v)))
+    return v.value
+
+
+def ltgw_set_tile_shape(ctx, variant):
+    _check(ctx, library().ltgw_set_tile_shape(ctx, int(variant)))
+
+
+def ltgw_tune_save(ctx, path):
+    _check(ctx, library().ltgw_tune_save(ctx, str(path).encode()))
+
+
+def ltgw_tune_load(ctx, path):
+    _check(ctx, library().ltgw_tune_load(ctx, str(path).encode()))
+
+
+# ---- learned proposer ------------------------------------------------------
+def _dev(x, dtype):
+    """Address of a contiguous device tensor of the given torch dtype."""
+    if not hasattr(x, "data_ptr") or not x.is_cuda:
+        raise TypeError("expected a device tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return x.data_ptr()
+
+
+def ltgw_generate_noise(ctx, seed, stream, r0, out):
+    """Exp(1) noise into the device float32 tensor out[R][...] (realisations r0..)."""
+    import torch
+    R = int(out.shape[0])
+    n = out.numel() // R
+    _check(ctx, library().ltgw_generate_noise(ctx, int(seed), int(stream), int(r0), R, n,
+                                              _dev(out, torch.float32)))
+
+
+def ltgw_inject_stack(ctx, det, stack, params, sky, t0=0.0):
+    """Add tracks params[r] = (f0, tau, brake, amp) to the device stack [R][n_seg][n_bins]."""
+    import torch
+    params = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, 4)
+    sky = np.ascontiguousarray(sky, dtype=np.float64).reshape(3)
+    _check(ctx, library().ltgw_inject_stack(ctx, int(det), _dev(stack, torch.float32), len(params),
+                                            params.ctypes.data, sky.ctypes.data, float(t0)))
+
+
+def ltgw_load_stack(ctx, det, stack, store="f32", coarse=True):
+    import torch
+    _check(ctx, library().ltgw_load_stack(ctx, int(det), int(stack.shape[0]), _dev(stack, torch.float32),
+                                          STORES[store] if isinstance(store, str) else int(store),
+                                          1 if coarse else 0))
+
+
+def ltgw_stack_psi(ctx, grid, level, out_psi, nan_to_zero=False):
+    import torch
+    _check(ctx, library().ltgw_stack_psi(ctx, C.byref(grid), int(level), 1 if nan_to_zero else 0,
+                                         _dev(out_psi, torch.float64)))
+
+
+def ltgw_stack_psi_list(ctx, grid, idx, out_psi):
+    import torch
+    _check(ctx, library().ltgw_stack_psi_list(ctx, C.byref(grid), _dev(idx, torch.int32), int(idx.shape[1]),
+                                              _dev(out_psi, torch.float64)))
+
+
+def ltgw_stack_features(ctx, grid, x):
+    import torch
+    _check(ctx, library().ltgw_stack_features(ctx, C.byref(grid), _dev(x, torch.float32)))
+
+
+def ltgw_stack_best(ctx, grid, best_index, best_psi):
+    import torch
+    _check(ctx, library().ltgw_stack_best(ctx, C.byref(grid), _dev(best_index, torch.int32),
+                                          _dev(best_psi, torch.float64)))
+
+
+def ltgw_cells_from_templates(ctx, tpl, L, cells, mask=None):
+    import torch
+    _check(ctx, library().ltgw_cells_from_templates(ctx, _dev(tpl, torch.int32), tpl.numel(), int(L),
+                                                    None if mask is None else _dev(mask, torch.int32),
+                                                    _dev(cells, torch.int32)))
+
+
+def ltgw_cnn_param_count(c_in, c_out):
+    return int(library().ltgw_cnn_param_count(int(c_in), int(c_out)))
+
+
+def ltgw_cnn_work_floats(B, c_in, c_out, L):
+    return int(library().ltgw_cnn_work_floats(int(B), int(c_in), int(c_out), int(L)))
+
+
+def ltgw_cnn_forward(ctx, params, x, c_out, act, logits):
+    import torch
+    B, c_in, L = (int(v) for v in x.shape)
+    f = torch.float32
+    _check(ctx, library().ltgw_cnn_forward(ctx, _dev(params, f), _dev(x, f), B, c_in, int(c_out), L,
+                                           _dev(act, f), _dev(logits, f)))
+
+
+def ltgw_cnn_backward(ctx, params, x, c_out, act, dlogits, work, grads):
+    import torch
+    B, c_in, L = (int(v) for v in x.shape)
+    f = torch.float32
+    _check(ctx, library().ltgw_cnn_backward(ctx, _dev(params, f), _dev(x, f), B, c_in, int(c_out), L,
+                                            _dev(act, f), _dev(dlogits, f), _dev(work, f), work.numel(),
+                                            _dev(grads, f)))
+
+
+def ltgw_softmax_xent(ctx, logits, target, n_valid, loss, dlogits):
+    import torch
+    B = int(logits.shape[0])
+    _check(ctx, library().ltgw_softmax_xent(ctx, _dev(logits, torch.float32), B, logits.numel() // B,
+                                            _dev(target, torch.int32), int(n_valid),
+                                            _dev(loss, torch.float32), _dev(dlogits, torch.float32)))
+
+
+def ltgw_adam_step(ctx, params, grads, m, v, lr, beta1, beta2, eps, step):
+    import torch
+    f = torch.float32
+    _check(ctx, library().ltgw_adam_step(ctx, _dev(params, f), _dev(grads, f), _dev(m, f), _dev(v, f),
+                                         params.numel(), float(lr), float(beta1), float(beta2), float(eps),
+                                         int(step)))
+
+
+def ltgw_select_top(ctx, score, M, out_idx):
+    import torch
+    R = int(score.shape[0])
+    _check(ctx, library().ltgw_select_top(ctx, _dev(score, torch.float32), R, score.numel() // R, int(M),
+                                          _dev(out_idx, torch.int32)))
+
+
+def ltgw_propose(ctx, fine, coarse, params, c_in, c_out, L, n_select, psi_threshold, coarse_threshold, R):
+    """(best_index[R], best_psi[R], fallback[R]) numpy arrays."""
+    import torch
+    p = ltgw_proposer(_dev(params, torch.float32), int(c_in), int(c_out), int(L), int(n_select),
+                      float(psi_threshold), float(coarse_threshold))
+    bi = np.empty(R, np.int32)
+    bp = np.empty(R, np.float64)
+    fb = np.empty(R, np.int32)
+    _check(ctx, library().ltgw_propose(ctx, C.byref(fine), C.byref(coarse), C.byref(p), bi.ctypes.data,
+                                       bp.ctypes.data, fb.ctypes.data))
+    return bi, bp, fb
+
+
 # ---------------------------------------------------------------------------
 class Context:
     """Convenience wrapper: one ltgw context bound to a torch device and stream."""
@@ -284,3 +520,36 @@ class Context:
     def read_store(self, det):
         n_seg, n_bins, store = self.shapes[det]
         return ltgw_read_store(self.h, det, n_seg, n_bins, store)
+
+    def eval_batch(self, searches, k=10):
+        """searches: list of dicts with f0_min, f0_step, n_f0, tau, brake, sky, t0, dets."""
+        specs = [(make_grid(s["f0_min"], s["f0_step"], s["n_f0"], s["tau"], s["brake"], s["sky"],
+                            s.get("t0", 0.0)), s["dets"]) for s in searches]
+        self._batch = specs
+        return ltgw_eval_batch(self.h, specs, k)
+
+    def batch_results(self, i, n_templates):
+        T = self.torch
+        s = T.empty(n_templates, dtype=T.float32, device=self.device)
+        c = T.empty(n_templates, dtype=T.int32, device=self.device)
+        N = T.empty(n_templates, dtype=T.int32, device=self.device)
+        pp = T.empty(n_templates, dtype=T.float64, device=self.device)
+        pc = T.empty(n_templates, dtype=T.float64, device=self.device)
+        ltgw_batch_results(self.h, i, s, c, N, pp, pc)
+        return s, c, N, pp, pc
+
+    def batch_latency(self, n):
+        return ltgw_batch_latency(self.h, n)
+
+    def autotune(self, f0_min, f0_step, n_f0, tau, brake, sky, t0=0.0, det_mask=0):
+        g, keep = make_grid(f0_min, f0_step, n_f0, tau, brake, sky, t0, det_mask)
+        return ltgw_autotune(self.h, g)
+
+    def set_tile_shape(self, variant):
+        ltgw_set_tile_shape(self.h, variant)
+
+    def tune_save(self, path):
+        ltgw_tune_save(self.h, path)
+
+    def tune_load(self, path):
+        ltgw_tune_load(self.h, path)

@@ -1,0 +1,219 @@
+"""Learned proposer for the template bank: training on device-generated
+realisations and inference, driven over the ltgw C-ABI.
+
+The method evaluates every template of a cubic lattice bank (Sec. 2); its
+detection rule flags a template whose critical ratio (Eq. 4) exceeds the
+largest value reached on noise alone (Sec. 3).  The proposer is a system
+pattern layered on that rule, not part of the paper: a small convolutional
+network reads the coarse critical-ratio map of a realisation (2x2-coarsened
+BF16 store, a coarse grid with half the f0 points and fewer (tau, n) groups)
+and ranks the fine cells; the n_select best are evaluated exactly on the
+fine store, and realisations whose coarse map is loud while no selected cell
+passes the threshold fall back to the exhaustive fine search.
+
+Every step runs in the library's kernels: noise (Philox4x32-10), injections,
+stores, coarse and fine ratios, labels (the exhaustive search's best cell),
+the network's passes, the loss and Adam.  This module only draws injection
+parameters on the host, keeps the device buffers and orders the calls.
+"""
+import math
+
+import numpy as np
+
+from . import ltgw
+
+WIDTH, TAPS = 32, 5
+
+
+def init_params(c_in, c_out, seed):
+    """He-uniform weights, zero biases; flat FP32 in the order W1 b1 W2 b2 W3 b3 W4 b4."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    shapes = [(WIDTH, c_in, TAPS), (WIDTH,), (WIDTH, WIDTH, TAPS), (WIDTH,), (WIDTH, WIDTH, TAPS), (WIDTH,),
+              (c_out, WIDTH, 1), (c_out,)]
+    parts = []
+    for s in shapes:
+        if len(s) == 3:
+            lim = math.sqrt(6.0 / (s[1] * s[2]))
+            parts.append(r.uniform(-lim, lim, s).ravel())
+        else:
+            parts.append(np.zeros(s))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def coarse_grid_for(fine, tau, brake):
+    """Coarse grid over the fine one: positions l cover fine f0 indices 2l, 2l+1
+    (centre f0), with its own (tau, n) lists."""
+    return dict(f0_min=fine["f0_min"] + 0.5 * fine["f0_step"], f0_step=2.0 * fine["f0_step"],
+                n_f0=fine["n_f0"] // 2, tau=np.asarray(tau, np.float64), brake=np.asarray(brake, np.float64),
+                sky=np.asarray(fine["sky"], np.float64).reshape(-1, 3), t0=fine.get("t0", 0.0))
+
+
+def _grid(d):
+    return ltgw.make_grid(d["f0_min"], d["f0_step"], d["n_f0"], d["tau"], d["brake"], d["sky"], d.get("t0", 0.0))
+
+
+def _n_groups(d):
+    return len(d["tau"]) * len(d["brake"]) * len(np.asarray(d["sky"]).reshape(-1, 3))
+
+
+class Proposer:
+    """Training and inference state on one ltgw.Context whose detector slot
+    `det` holds the geometry (segment times, weights, velocities)."""
+
+    def __init__(self, ctx, det, shape, fine, coarse, seed=0, select_frac=0.05, store="f32"):
+        import torch
+
+        if fine["n_f0"] % 2:
+            raise ValueError("the fine grid needs an even number of f0 points")
+        if len(np.asarray(fine["sky"]).reshape(-1, 3)) != 1:
+            raise ValueError("the proposer serves directed searches (one sky position)")
+        self.torch, self.ctx, self.det = torch, ctx, det
+        self.n_seg, self.n_bins = shape
+        self.fine, self.coarse = fine, coarse
+        self.L = fine["n_f0"] // 2
+        self.c_in = _n_groups(coarse)
+        self.c_out = 2 * _n_groups(fine)
+        self.n_cells = self.c_out * self.L
+        self.n_select = max(1, int(round(select_frac * self.n_cells)))
+        self.store = store
+        self.seed = seed
+        self.rng = np.random.Generator(np.random.PCG64(seed))
+        dev = ctx.device
+        self.params = torch.from_numpy(init_params(self.c_in, self.c_out, seed)).to(dev)
+        n = self.params.numel()
+        assert n == ltgw.ltgw_cnn_param_count(self.c_in, self.c_out)
+        self.m = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.grads = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.step = 0
+        self._bufs = {}
+        self._fg, self._fg_keep = _grid(fine)
+        self._cg, self._cg_keep = _grid(coarse)
+
+    # -- device buffers, sized once per batch size --------------------------------
+    def _buf(self, R):
+        T = self.torch
+        if R not in self._bufs:
+            dev = self.ctx.device
+            f32 = dict(dtype=T.float32, device=dev)
+            i32 = dict(dtype=T.int32, device=dev)
+            self._bufs = {R: dict(
+                stack=T.empty((R, self.n_seg, self.n_bins), **f32),
+                x=T.empty((R, self.c_in, self.L), **f32),
+                act=T.empty((3, R, WIDTH, self.L), **f32),
+                logits=T.empty((R, self.c_out, self.L), **f32),
+                dlogits=T.empty((R, self.c_out, self.L), **f32),
+                loss=T.empty(R, **f32),
+                work=T.empty(ltgw.ltgw_cnn_work_floats(R, self.c_in, self.c_out, self.L), **f32),
+                best=T.empty(R, **i32),
+                best_psi=T.empty(R, dtype=T.float64, device=dev),
+                mask=T.empty(R, **i32),
+                target=T.empty(R, **i32))}
+        return self._bufs[R]
+
+    def draw_injections(self, R, p_signal, amp_range):
+        """Host draw of (f0, tau, n, amp) per realisation: f0 uniform over the fine
+        band, tau log-uniform and n uniform over the fine grid's ranges."""
+        f = self.fine
+        f_lo = f["f0_min"]
+        f_hi = f["f0_min"] + (f["n_f0"] - 1) * f["f0_step"]
+        tau, brake = np.asarray(f["tau"]), np.asarray(f["brake"])
+        r = self.rng
+        sig = r.uniform(size=R) < p_signal
+        out = np.zeros((R, 4))
+        out[:, 0] = r.uniform(f_lo, f_hi, R)
+        out[:, 1] = np.exp(r.uniform(math.log(tau.min()), math.log(tau.max()), R))
+        out[:, 2] = r.uniform(brake.min(), brake.max(), R)
+        out[:, 3] = np.where(sig, r.uniform(amp_range[0], amp_range[1], R), 0.0)
+        return out, sig
+
+    def make_batch(self, R, stream, r0, inj, with_labels=True):
+        """Noise + injections -> stack stores -> coarse features (and labels)."""
+        b = self._buf(R)
+        h = self.ctx.h
+        ltgw.ltgw_generate_noise(h, self.seed, stream, r0, b["stack"])
+        ltgw.ltgw_inject_stack(h, self.det, b["stack"], inj, np.asarray(self.fine["sky"]).reshape(3),
+                               self.fine.get("t0", 0.0))
+        ltgw.ltgw_load_stack(h, self.det, b["stack"], self.store, coarse=True)
+        ltgw.ltgw_stack_features(h, self._cg, b["x"])
+        if with_labels:
+            ltgw.ltgw_stack_best(h, self._fg, b["best"], b["best_psi"])
+        return b
+
+    def train_step(self, R, p_signal=0.9, amp_range=(1.0, 3.0), lr=1e-3, stream=1):
+        """One Adam step on a fresh batch; returns the batch's mean loss (host float)."""
+        T = self.torch
+        inj, sig = self.draw_injections(R, p_signal, amp_range)
+        b = self.make_batch(R, stream, self.step * R, inj)
+        h = self.ctx.h
+        b["mask"].copy_(T.from_numpy(sig.astype(np.int32)))
+        ltgw.ltgw_cells_from_templates(h, b["best"], self.L, b["target"], mask=b["mask"])
+        n_valid = int(sig.sum())
+        ltgw.ltgw_cnn_forward(h, self.params, b["x"], self.c_out, b["act"], b["logits"])
+        ltgw.ltgw_softmax_xent(h, b["logits"], b["target"], max(n_valid, 1), b["loss"], b["dlogits"])
+        ltgw.ltgw_cnn_backward(h, self.params, b["x"], self.c_out, b["act"], b["dlogits"], b["work"], self.grads)
+        self.step += 1
+        ltgw.ltgw_adam_step(h, self.params, self.grads, self.m, self.v, lr, 0.9, 0.999, 1e-8, self.step)
+        return float(b["loss"].cpu().numpy().astype(np.float64).sum()) / max(n_valid, 1)
+
+    def propose(self, psi_threshold, coarse_threshold, R):
+        """ltgw_propose on the loaded stack: (best_index, best_psi, fallback)."""
+        return ltgw.ltgw_propose(self.ctx.h, self._fg, self._cg, self.params, self.c_in, self.c_out, self.L,
+                                 self.n_select, psi_threshold, coarse_threshold, R)
+
+    def exhaustive(self, R):
+        """Exhaustive fine search of the loaded stack: host (best_index, best_psi)."""
+        b = self._buf(R)
+        ltgw.ltgw_stack_best(self.ctx.h, self._fg, b["best"], b["best_psi"])
+        return b["best"].cpu().numpy().copy(), b["best_psi"].cpu().numpy().copy()
+
+    def evaluate(self, R_noise=256, R_signal=256, amp_range=(1.0, 3.0), fine_store="bf16", reps=3):
+        """Recall and speed against the exhaustive search.
+
+        Thresholds: psi_threshold is the largest exhaustive fine ratio over
+        R_noise noise-only realisations (the detection rule of Sec. 3);
+        coarse_threshold is the largest coarse ratio over the same
+        realisations.  On R_signal realisations with injections, an injection
+        is detectable when the exhaustive FP32 search passes psi_threshold,
+        and recalled when the proposer (coarse BF16 map, network, n_select
+        exact cells on the `fine_store` store, fallback) passes it too.
+        Times: exhaustive FP32 search (ltgw_stack_best) and ltgw_propose on
+        the same realisations, HIP events on the context's stream, best of
+        `reps`."""
+        T = self.torch
+        h = self.ctx.h
+        zeros = np.zeros((R_noise, 4))
+        b = self.make_batch(R_noise, 2, 0, zeros, with_labels=False)
+        _, noise_best = self.exhaustive(R_noise)
+        psi_thr = float(np.max(noise_best))
+        coarse_thr = float(b["x"].cpu().numpy().reshape(R_noise, -1).max())
+        inj, sig = self.draw_injections(R_signal, 1.0, amp_range)
+        b = self.make_batch(R_signal, 3, 0, inj, with_labels=False)
+        ev0, ev1 = T.cuda.Event(enable_timing=True), T.cuda.Event(enable_timing=True)
+        t_ex = []
+        ltgw.ltgw_load_stack(h, self.det, b["stack"], "f32", coarse=False)
+        for _ in range(reps):
+            ev0.record()
+            ltgw.ltgw_stack_best(h, self._fg, b["best"], b["best_psi"])
+            ev1.record()
+            ev1.synchronize()
+            t_ex.append(ev0.elapsed_time(ev1))
+        ex_idx = b["best"].cpu().numpy().copy()
+        ex_psi = b["best_psi"].cpu().numpy().copy()
+        ltgw.ltgw_load_stack(h, self.det, b["stack"], fine_store, coarse=True)
+        t_pr = []
+        for _ in range(reps):
+            ev0.record()
+            pi, pp, fb = self.propose(psi_thr, coarse_thr, R_signal)
+            ev1.record()
+            ev1.synchronize()
+            t_pr.append(ev0.elapsed_time(ev1))
+        det_ex = ex_psi > psi_thr
+        det_pr = pp > psi_thr
+        n_det = int(det_ex.sum())
+        recall = float((det_ex & det_pr).sum() / n_det) if n_det else float("nan")
+        same = float((pi[det_ex] == ex_idx[det_ex]).mean()) if n_det else float("nan")
+        return dict(recall=recall, detectable=n_det, realisations=R_signal, same_template=same,
+                    fallback_frac=float(fb.mean()), psi_threshold=psi_thr, coarse_threshold=coarse_thr,
+                    exhaustive_ms=min(t_ex), propose_ms=min(t_pr), speedup=min(t_ex) / min(t_pr),
+                    n_select=self.n_select, n_cells=self.n_cells, fine_store=fine_store)

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
     L = ltgw.library()
     declared = _declared()
-    assert len(declared) >= 11
+    assert len(declared) >= 18
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(ltgw.EXPORTS) == declared
@@ -62,8 +62,13 @@ int main(void) {
   printf("ltgw_candidate %zu\n", sizeof(ltgw_candidate));
   F(ltgw_candidate, f0); F(ltgw_candidate, sky); F(ltgw_candidate, n_valid);
   F(ltgw_candidate, stat); F(ltgw_candidate, psi);
+  printf("ltgw_search %zu\n", sizeof(ltgw_search));
+  F(ltgw_search, dets); F(ltgw_search, n_dets);
+  printf("ltgw_batch_stats %zu\n", sizeof(ltgw_batch_stats));
+  F(ltgw_batch_stats, templates); F(ltgw_batch_stats, kernel_ms); F(ltgw_batch_stats, total_ms);
   printf("ltgw_diag %zu\n", sizeof(ltgw_diag));
   F(ltgw_diag, in_band); F(ltgw_diag, eval_kernel_ms); F(ltgw_diag, tables_ms);
+  F(ltgw_diag, tile_shape);
   return 0;
 }
 ''')
@@ -72,7 +77,8 @@ int main(void) {
                    check=True)
     got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
                                                          check=True).stdout.splitlines())
-    for name in ("ltgw_spec_desc", "ltgw_grid", "ltgw_candidate", "ltgw_diag"):
+    for name in ("ltgw_spec_desc", "ltgw_grid", "ltgw_candidate", "ltgw_diag", "ltgw_search",
+                 "ltgw_batch_stats"):
         cls = getattr(ltgw, name)
         assert int(got[name]) == C.sizeof(cls), name
         for key, val in got.items():

@@ -84,25 +84,33 @@ def test_tiny_bin_checksum_exact():
 
 
 def _small(seed, n_seg, n_bins, k_lo=1900, t_sft=4.0, vmag=3.0e5, spacing=300.0, weights=True):
+    """weights: True = U[0.5, 2]; 'wide' = 2^U[-6, 6] (beyond the fixed-point
+    moment range, so the statistic kernel accumulates W1, W2 itself)."""
     rng = np.random.default_rng(seed)
     t_seg = np.arange(n_seg) * spacing + 2.0
     v = rng.normal(size=(n_seg, 3))
     v = v / np.linalg.norm(v, axis=1, keepdims=True) * vmag
     rho = rng.exponential(size=(n_seg, n_bins)).astype(np.float32)
-    w = rng.uniform(0.5, 2.0, n_seg).astype(np.float32) if weights else None
+    if weights == "wide":
+        w = np.exp2(rng.uniform(-6.0, 6.0, n_seg)).astype(np.float32)
+    else:
+        w = rng.uniform(0.5, 2.0, n_seg).astype(np.float32) if weights else None
     return oracle.Detector(rho, t_seg, v, k_lo, t_sft, weights=w)
 
 
-@pytest.mark.parametrize("n_seg,n_bins,n_f0,t0", [
-    (1, 1, 1, 0.0),           # degenerate: one segment, one bin, one template
-    (77, 33, 300, 0.0),       # ragged everywhere (segments not a multiple of 8/32, f0 not of 256)
-    (5, 800, 257, 0.0),
-    (40, 256, 513, 700.0),    # T0 inside the data: the first 19 segments are masked
-    (129, 97, 64, 0.0),
+@pytest.mark.parametrize("n_seg,n_bins,n_f0,t0,weights", [
+    (1, 1, 1, 0.0, True),           # degenerate: one segment, one bin, one template
+    (77, 33, 300, 0.0, True),       # ragged everywhere (segments not a multiple of 8/32, f0 not of 256)
+    (5, 800, 257, 0.0, True),
+    (40, 256, 513, 700.0, True),    # T0 inside the data: the first 19 segments are masked
+    (129, 97, 64, 0.0, True),
+    (129, 97, 300, 0.0, "wide"),    # weights over 12 binades: moments accumulated in the kernel
+    (77, 120, 257, 0.0, False),     # unit weights
 ])
-def test_ragged_shapes_weighted(n_seg, n_bins, n_f0, t0):
-    print(f"case: ragged n_seg={n_seg} n_bins={n_bins} n_f0={n_f0} t0={t0}", flush=True)
-    det = _small(n_seg + n_bins, n_seg, n_bins, k_lo=1990 - n_bins // 4, spacing=37.0)
+def test_ragged_shapes_weighted(n_seg, n_bins, n_f0, t0, weights):
+    print(f"case: ragged n_seg={n_seg} n_bins={n_bins} n_f0={n_f0} t0={t0} w={weights}", flush=True)
+    det = _small(n_seg + n_bins, n_seg, n_bins, k_lo=1990 - n_bins // 4, spacing=37.0,
+                 weights=weights)
     grid = oracle.Grid(490.0 + 0.03 * n_bins, 0.25, n_f0, [512.0, 5000.0, 35000.0], [2.5, 5.0],
                        [[0.6, 0.0, 0.8], [0.0, -1.0, 0.0]], t0)
     ref = oracle.evaluate(det, grid)
@@ -110,6 +118,10 @@ def test_ragged_shapes_weighted(n_seg, n_bins, n_f0, t0):
     assert np.array_equal(gpu["N"], ref["N"])
     assert np.array_equal(gpu["c"], ref["c"])
     assert_sums_close(gpu["s"], ref["s"])
+    pp = oracle.psi_power(ref)
+    ok = ~np.isnan(pp)
+    assert np.array_equal(np.isnan(gpu["psi_power"]), ~ok)
+    assert np.all(np.abs(gpu["psi_power"][ok] - pp[ok]) <= psi_tolerance(ref)[ok] + 1e-9)
     if (ref["N"] > 0).sum() >= 7:
         assert_topk_count(gpu["top_count"], ref, 7)
         assert_topk_power(gpu["top_power"], ref, 7)
@@ -274,7 +286,7 @@ def test_error_paths_leave_context_usable():
     for args, code in [((0, bad, det.k_lo, 4.0, det.t_seg), ltgw.LTGW_E_INVALID_ARG),
                        ((0, p, 1, 4.0, det.t_seg), ltgw.LTGW_E_INVALID_ARG),
                        ((0, p, det.k_lo, 0.0, det.t_seg), ltgw.LTGW_E_INVALID_ARG),
-                       ((7, p, det.k_lo, 4.0, det.t_seg), ltgw.LTGW_E_INVALID_ARG)]:
+                       ((ltgw.LTGW_MAX_DET, p, det.k_lo, 4.0, det.t_seg), ltgw.LTGW_E_INVALID_ARG)]:
         with pytest.raises(E) as ei:
             ctx.load_spectrogram(*args)
         assert ei.value.code == code, args
