@@ -61,6 +61,95 @@ def cpu_baseline(wl, rho, target_s=15.0):
                       f"({idx.size * n_seg:.3g} evals, {dt:.1f} s, FP64, incl. its Eq. 1 table)"}
 
 
+def proposer_leg(torch, ltgw, realisations=50000, batch=256, eval_signal=2048, eval_noise=1024, seed=7):
+    """The learned proposer on the small workload's shape (1024 segments x 800
+    bins, 4800 fine templates): trained on `realisations` device-generated
+    noise + injection realisations (amplitudes U[0.3, 3]), then recall and
+    speed against the plain FP32 exhaustive search.  Returns the JSON object."""
+    import synth
+    from paper_2507_07816_amd.proposer import Proposer, coarse_grid_for
+
+    wl = synth.tiny(with_noise=False)
+    d, g = wl.dets[0], wl.grid
+    ctx = ltgw.Context(0)
+    dev = torch.device("cuda", 0)
+    ctx.load_spectrogram(0, torch.zeros(d["rho"].shape, dtype=torch.float32, device=dev), d["k_lo"],
+                         d["t_sft"], d["t_seg"], weights=d["weights"])
+    ctx.set_velocity_table(0, d["v"])
+    fine = dict(g)
+    tau, brake = np.asarray(g["tau"]), np.asarray(g["brake"])
+    # 2x coarser in f0, tau and n: pair means (geometric for tau)
+    ctau = np.sqrt(tau[0::2] * tau[1::2])
+    cbrake = np.array([(brake[0] + brake[1]) / 2, (brake[-2] + brake[-1]) / 2])
+    coarse = coarse_grid_for(fine, ctau, cbrake)
+    pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=0.05, store="f32")
+    steps = max(1, realisations // batch)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    losses = [pr.train_step(batch, p_signal=0.9, amp_range=(0.3, 3.0), lr=2e-3) for _ in range(steps)]
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    ev = pr.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16")
+    untrained = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed + 1, select_frac=0.05, store="f32")
+    ev0 = untrained.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
+                             reps=1)
+    ctx.close()
+    out = {"workload": "tiny-1024seg-800bin-4800tpl realisations", "realisations": steps * batch,
+           "train_s": train_s, "loss_first": float(np.mean(losses[:5])), "loss_last": float(np.mean(losses[-5:])),
+           "coarse_grid": f"{coarse['n_f0']} f0 x {len(ctau)} tau x {len(cbrake)} n", "network": "4-layer CNN, BF16 MFMA",
+           "untrained_recall_no_fallback": ev0["recall_no_fallback"], "untrained_fallback_frac": ev0["fallback_frac"]}
+    out.update(ev)
+    return out
+
+
+def batch_leg(torch, ltgw, reps=2, seed=5):
+    """The batch of 64 uneven searches (two detectors each, sky patches of 16 to
+    1024 points, 1.76e13 template x segment evaluations) in one persistent,
+    graph-captured launch: aggregate evals/s, in-band fraction, % of the HBM
+    roofline of the persistent statistic launch, and per-search latency.
+    The power (Exp(1)) is generated on the device by the library."""
+    import synth
+
+    searches = synth.batch_searches(seed)
+    ctx = ltgw.Context(0)
+    dev = torch.device("cuda", 0)
+    specs = []
+    slot = 0
+    for i, srch in enumerate(searches):
+        dets = []
+        for d in srch["dets"]:
+            p = torch.empty((d["n_seg"], d["n_bins"]), dtype=torch.float32, device=dev)
+            ltgw.ltgw_generate_noise(ctx.h, 1000003 + seed, 7, slot, p.view(1, -1))
+            ctx.load_spectrogram(slot, p, d["k_lo"], d["t_sft"], d["t_seg"], store="f32")
+            ctx.set_velocity_table(slot, d["v"])
+            del p
+            dets.append(slot)
+            slot += 1
+        specs.append(dict(srch["grid"], dets=dets))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    top_p, top_c, st0 = ctx.eval_batch(specs, k=10)       # tunes the tile shape, captures the graph
+    build_s = time.perf_counter() - t
+    runs = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        top_p, top_c, st = ctx.eval_batch(specs, k=10)     # replays the graph
+        runs.append((time.perf_counter() - t, st))
+    wall, st = min(runs, key=lambda x: x[0])
+    lat = ctx.batch_latency(len(specs))
+    ctx.close()
+    evals = st["evals"]
+    achieved = st["in_band"] * 4 / (st["kernel_ms"] * 1e-3) / 1e9
+    return {"workload": f"{len(specs)} searches, 2 detectors each, sky 16-1024 points, seed {seed}",
+            "searches": len(specs), "templates": int(st["templates"]), "evals": int(evals),
+            "in_band_fraction": st["in_band"] / evals, "value": evals / wall, "unit": "template·segment evals/s",
+            "wall_s": wall, "kernel_ms": st["kernel_ms"], "graph_ms": st["total_ms"], "graph_replayed": st["graph_replayed"],
+            "first_call_s": build_s, "tile_shape": int(st["variant"]), "workgroups": int(st["workgroups"]),
+            "tiles": int(st["tiles"]), "roofline_frac": achieved / HBM_PEAK_GBS, "achieved_gbs": achieved,
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+            "latency_ms_max": float(lat.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +159,9 @@ def main():
     ap.add_argument("--workload", choices=["realistic", "tiny"], default="realistic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-proposer", action="store_true", help="skip the learned-proposer leg")
+    ap.add_argument("--batch", action="store_true", help="add the 64-search batch leg")
+    ap.add_argument("--proposer-realisations", type=int, default=50000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 1 GiB device-to-device copies (HBM counter calibration)")
     args = ap.parse_args()
@@ -161,6 +253,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }
+    if args.batch:
+        print("[bench] batch of 64 searches", file=sys.stderr, flush=True)
+        out["batch"] = batch_leg(torch, ltgw)
+        print(f"[bench] batch: {json.dumps(out['batch'])}", file=sys.stderr, flush=True)
+    if not args.no_proposer:
+        print("[bench] learned proposer: training and evaluation", file=sys.stderr, flush=True)
+        out["proposer"] = proposer_leg(torch, ltgw, realisations=args.proposer_realisations)
+        print(f"[bench] proposer: {json.dumps(out['proposer'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "realistic":
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, power.cpu().numpy(), args.cpu_seconds)

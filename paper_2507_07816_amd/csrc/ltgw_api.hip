@@ -542,7 +542,7 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     }
     HIP_TRY(c, hipEventRecord(c->ev_h2d, c->stream), "event record");
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream), "event record");
-    HIP_TRY(c, launch_eval(P.store, moments_in_loop, variant, a, c->stream), "eval launch");
+    HIP_TRY(c, launch_eval(P.store, moments_in_loop, variant, a, c->cu_count, c->stream), "eval launch");
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream), "event record");
     c->have_eval = true;
     c->last_variant = variant;

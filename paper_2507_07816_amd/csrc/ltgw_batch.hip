@@ -372,16 +372,16 @@ int build(ltgw_ctx *c, const ltgw_search *S, int n, int k) {
     const auto it = c->tune.find(key);
     int variant = 1;
     if (c->forced_variant >= 0) {
-        variant = c->forced_variant;
+        variant = c->forced_variant & 3;  // the persistent launch is one generation already
     } else if (it != c->tune.end()) {
-        variant = it->second;
+        variant = it->second & 3;
     } else {
         float best = 0.0f;
         int best_v = -1;
         int64_t tiles1 = 0;  // tiles of the one-template-per-lane shapes
         for (int i = 0; i < n; ++i) tiles1 += ((B.plans[i].n_f0 + 63) / 64) * B.plans[i].n_groups;
         const int64_t lead = std::min<int64_t>(tiles1, std::max<int64_t>((int64_t)c->cu_count * 64, tiles1 / 10));
-        for (int v = 0; v < kNumVariants; ++v) {
+        for (int v = 0; v < kNumShapes; ++v) {
             if ((rc = upload_tiles(c, B, v)) != LTGW_OK) return rc;
             // the first lead/TPL tiles cover (nearly) the same templates for every shape
             const int lim = (int)std::max<int64_t>(1, lead / tpl_of(v));

@@ -62,11 +62,15 @@ hipError_t launch_track_factor(const double *g, int32_t n_tn, const double *v, i
                                hipStream_t st);
 // Statistic kernel.  moments_in_loop: also accumulate N, W1, W2 per segment
 // (used when the weights have no exact fixed-point form); otherwise only s
-// and c, with N, W1, W2 from launch_moments.  variant: tile shape
-// (templates per lane, segments per gather batch) = (1,8), (1,16), (2,8), (2,16).
-constexpr int kNumVariants = 4;
+// and c, with N, W1, W2 from launch_moments.  variant & 3: tile shape
+// (templates per lane, segments per gather batch) = (1,8), (1,16), (2,8),
+// (2,16); variant & 4: the grid is launched in generations of the blocks the
+// device holds at once (cu_count x resident blocks per CU), so that the
+// blocks of a launch walk the segments together and share rows in L2.
+constexpr int kNumShapes = 4;
+constexpr int kNumVariants = 8;
 int variant_templates_per_block(int variant);
-hipError_t launch_eval(int store, bool moments_in_loop, int variant, const EvalArgs &a,
+hipError_t launch_eval(int store, bool moments_in_loop, int variant, const EvalArgs &a, int cu_count,
                        hipStream_t st);
 
 // Batched searches (device-resident descriptors).

@@ -386,22 +386,25 @@ __device__ __forceinline__ void store_results(const Acc<TPL> &acc, const int (&i
 // their reads of each row overlap in that XCD's L2.  (Group-major order, one
 // group's successive f0 tiles side by side, reads disjoint bins and measured
 // slower.)
+// A launch may cover a slice [first, first + gridDim.x) of the pairs (a
+// generation of the grid); the XCD ranges are taken within the slice.
 constexpr int kXcds = 8;
-__device__ inline void xcd_tile_group(int w, int n_blocks, int n_tiles, int &tile, int &grp) {
+__device__ inline void xcd_tile_group(int w, int n_blocks, int n_tiles, int &tile, int &grp,
+                                      int first = 0, int total = -1) {
     const int x = w % kXcds, k = w / kXcds;
     const int base = n_blocks / kXcds, extra = n_blocks % kXcds;
     const int start = x * base + (x < extra ? x : extra);
-    const int p = start + k;
-    const int n_groups = n_blocks / n_tiles;
+    const int p = first + start + k;
+    const int n_groups = (total < 0 ? n_blocks : total) / n_tiles;
     tile = p / n_groups;
     grp = p % n_groups;
 }
 
 template <int STORE, bool MOMENTS, int TPL, int U>
-__global__ __launch_bounds__(256) void eval_kernel(const EvalArgs a) {
+__global__ __launch_bounds__(256) void eval_kernel(const EvalArgs a, int first, int total) {
     const int n_tiles = (a.n_f0 + 256 * TPL - 1) / (256 * TPL);
     int tile, grp;
-    xcd_tile_group(blockIdx.x, gridDim.x, n_tiles, tile, grp);
+    xcd_tile_group(blockIdx.x, gridDim.x, n_tiles, tile, grp, first, total);
     int i[TPL];
     double f0[TPL];
     for (int t = 0; t < TPL; ++t) {
@@ -419,39 +422,56 @@ __global__ __launch_bounds__(256) void eval_kernel(const EvalArgs a) {
 }
 
 // Tile shapes: (templates per lane, segments per gather batch).
-constexpr int kVariantTpl[kNumVariants] = {1, 1, 2, 2};
+constexpr int kVariantTpl[kNumShapes] = {1, 1, 2, 2};
 
-int variant_templates_per_block(int variant) { return 256 * kVariantTpl[variant]; }
+int variant_templates_per_block(int variant) { return 256 * kVariantTpl[variant & 3]; }
 
 template <int STORE, bool MOMENTS, int TPL, int U>
-static hipError_t launch_eval_v(const EvalArgs &a, hipStream_t st) {
+static hipError_t launch_eval_v(const EvalArgs &a, bool generations, int cu_count, hipStream_t st) {
     const int64_t blocks = (int64_t)((a.n_f0 + 256 * TPL - 1) / (256 * TPL)) * a.n_groups;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((eval_kernel<STORE, MOMENTS, TPL, U>), dim3((unsigned)blocks), dim3(256), 0,
-                       st, a);
-    return hipGetLastError();
+    int64_t step = blocks;
+    if (generations) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, eval_kernel<STORE, MOMENTS, TPL, U>, 256, 0) !=
+                hipSuccess || per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        step = (int64_t)cu_count * per_cu;
+    }
+    for (int64_t first = 0; first < blocks; first += step) {
+        const int64_t n = blocks - first < step ? blocks - first : step;
+        hipLaunchKernelGGL((eval_kernel<STORE, MOMENTS, TPL, U>), dim3((unsigned)n), dim3(256), 0, st, a,
+                           (int)first, (int)blocks);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int STORE, bool MOMENTS>
-static hipError_t launch_eval_m(int variant, const EvalArgs &a, hipStream_t st) {
-    switch (variant) {
-        case 0: return launch_eval_v<STORE, MOMENTS, 1, 8>(a, st);
-        case 1: return launch_eval_v<STORE, MOMENTS, 1, 16>(a, st);
-        case 2: return launch_eval_v<STORE, MOMENTS, 2, 8>(a, st);
-        default: return launch_eval_v<STORE, MOMENTS, 2, 16>(a, st);
+static hipError_t launch_eval_m(int variant, const EvalArgs &a, int cu_count, hipStream_t st) {
+    const bool gen = (variant & 4) != 0;
+    switch (variant & 3) {
+        case 0: return launch_eval_v<STORE, MOMENTS, 1, 8>(a, gen, cu_count, st);
+        case 1: return launch_eval_v<STORE, MOMENTS, 1, 16>(a, gen, cu_count, st);
+        case 2: return launch_eval_v<STORE, MOMENTS, 2, 8>(a, gen, cu_count, st);
+        default: return launch_eval_v<STORE, MOMENTS, 2, 16>(a, gen, cu_count, st);
     }
 }
 
 template <int STORE>
-static hipError_t launch_eval_s(bool moments, int variant, const EvalArgs &a, hipStream_t st) {
-    return moments ? launch_eval_m<STORE, true>(variant, a, st)
-                   : launch_eval_m<STORE, false>(variant, a, st);
+static hipError_t launch_eval_s(bool moments, int variant, const EvalArgs &a, int cu_count, hipStream_t st) {
+    return moments ? launch_eval_m<STORE, true>(variant, a, cu_count, st)
+                   : launch_eval_m<STORE, false>(variant, a, cu_count, st);
 }
 
-hipError_t launch_eval(int store, bool moments, int variant, const EvalArgs &a, hipStream_t st) {
-    if (store == LTGW_STORE_F32) return launch_eval_s<LTGW_STORE_F32>(moments, variant, a, st);
-    if (store == LTGW_STORE_BF16) return launch_eval_s<LTGW_STORE_BF16>(moments, variant, a, st);
-    return launch_eval_s<LTGW_STORE_FP8>(moments, variant, a, st);
+hipError_t launch_eval(int store, bool moments, int variant, const EvalArgs &a, int cu_count, hipStream_t st) {
+    if (variant < 0 || variant >= kNumVariants) return hipErrorInvalidValue;
+    if (store == LTGW_STORE_F32) return launch_eval_s<LTGW_STORE_F32>(moments, variant, a, cu_count, st);
+    if (store == LTGW_STORE_BF16) return launch_eval_s<LTGW_STORE_BF16>(moments, variant, a, cu_count, st);
+    return launch_eval_s<LTGW_STORE_FP8>(moments, variant, a, cu_count, st);
 }
 
 // A value that is the same in every lane, moved to scalar registers word by
@@ -528,7 +548,7 @@ static hipError_t launch_batch_v(const BatchArgs &a, int grid, hipStream_t st) {
 
 template <int STORE, bool MOMENTS>
 static hipError_t launch_batch_m(int variant, const BatchArgs &a, int grid, hipStream_t st) {
-    switch (variant) {
+    switch (variant & 3) {
         case 0: return launch_batch_v<STORE, MOMENTS, 1, 8>(a, grid, st);
         case 1: return launch_batch_v<STORE, MOMENTS, 1, 16>(a, grid, st);
         case 2: return launch_batch_v<STORE, MOMENTS, 2, 8>(a, grid, st);
@@ -554,7 +574,7 @@ int batch_blocks_per_cu(int store, bool moments, int variant) {
 #define LTGW_OCC(S, M, T, U)                                                                    \
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<S, M, T, U>, 256, 0)
 #define LTGW_OCC_V(S, M)                            \
-    switch (variant) {                              \
+    switch (variant & 3) {                          \
         case 0: LTGW_OCC(S, M, 1, 8); break;        \
         case 1: LTGW_OCC(S, M, 1, 16); break;       \
         case 2: LTGW_OCC(S, M, 2, 8); break;        \

@@ -167,26 +167,29 @@ class Proposer:
         ltgw.ltgw_stack_best(self.ctx.h, self._fg, b["best"], b["best_psi"])
         return b["best"].cpu().numpy().copy(), b["best_psi"].cpu().numpy().copy()
 
-    def evaluate(self, R_noise=256, R_signal=256, amp_range=(1.0, 3.0), fine_store="bf16", reps=3):
+    def evaluate(self, R_noise=256, R_signal=256, amp_range=(1.0, 3.0), fine_store="bf16", reps=3,
+                 coarse_quantile=1.0):
         """Recall and speed against the exhaustive search.
 
         Thresholds: psi_threshold is the largest exhaustive fine ratio over
         R_noise noise-only realisations (the detection rule of Sec. 3);
-        coarse_threshold is the largest coarse ratio over the same
-        realisations.  On R_signal realisations with injections, an injection
-        is detectable when the exhaustive FP32 search passes psi_threshold,
-        and recalled when the proposer (coarse BF16 map, network, n_select
-        exact cells on the `fine_store` store, fallback) passes it too.
-        Times: exhaustive FP32 search (ltgw_stack_best) and ltgw_propose on
-        the same realisations, HIP events on the context's stream, best of
-        `reps`."""
+        coarse_threshold is the coarse_quantile quantile of the largest coarse
+        ratio of each noise realisation (1.0: their maximum).  On R_signal
+        realisations with injections, an injection is detectable when the
+        exhaustive FP32 search passes psi_threshold, and recalled when the
+        proposer (coarse BF16 map, network, n_select exact cells on the
+        `fine_store` store, fallback) passes it too; recall_no_fallback is the
+        same with the fallback switched off.  Times: exhaustive FP32 search
+        (ltgw_stack_best) and ltgw_propose on the same realisations, HIP
+        events on the context's stream, best of `reps`."""
         T = self.torch
         h = self.ctx.h
         zeros = np.zeros((R_noise, 4))
         b = self.make_batch(R_noise, 2, 0, zeros, with_labels=False)
         _, noise_best = self.exhaustive(R_noise)
         psi_thr = float(np.max(noise_best))
-        coarse_thr = float(b["x"].cpu().numpy().reshape(R_noise, -1).max())
+        coarse_max = b["x"].cpu().numpy().reshape(R_noise, -1).max(axis=1)
+        coarse_thr = float(np.quantile(coarse_max, coarse_quantile))
         inj, sig = self.draw_injections(R_signal, 1.0, amp_range)
         b = self.make_batch(R_signal, 3, 0, inj, with_labels=False)
         ev0, ev1 = T.cuda.Event(enable_timing=True), T.cuda.Event(enable_timing=True)
@@ -208,12 +211,15 @@ class Proposer:
             ev1.record()
             ev1.synchronize()
             t_pr.append(ev0.elapsed_time(ev1))
+        _, pp_nf, _ = self.propose(psi_thr, float("inf"), R_signal)
         det_ex = ex_psi > psi_thr
-        det_pr = pp > psi_thr
         n_det = int(det_ex.sum())
-        recall = float((det_ex & det_pr).sum() / n_det) if n_det else float("nan")
+        rec = lambda p: float((det_ex & (p > psi_thr)).sum() / n_det) if n_det else float("nan")
         same = float((pi[det_ex] == ex_idx[det_ex]).mean()) if n_det else float("nan")
-        return dict(recall=recall, detectable=n_det, realisations=R_signal, same_template=same,
-                    fallback_frac=float(fb.mean()), psi_threshold=psi_thr, coarse_threshold=coarse_thr,
+        amp = inj[:, 3]
+        return dict(recall=rec(pp), recall_no_fallback=rec(pp_nf), detectable=n_det, realisations=R_signal,
+                    detectable_min_amp=float(amp[det_ex].min()) if n_det else float("nan"),
+                    same_template=same, fallback_frac=float(fb.mean()), psi_threshold=psi_thr,
+                    coarse_threshold=coarse_thr, coarse_quantile=coarse_quantile,
                     exhaustive_ms=min(t_ex), propose_ms=min(t_pr), speedup=min(t_ex) / min(t_pr),
                     n_select=self.n_select, n_cells=self.n_cells, fine_store=fine_store)

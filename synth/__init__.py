@@ -152,3 +152,33 @@ def realistic(seed=2, weight_seed=3, inj_seed=4, n_seg=10800, n_bins=8000, n_f0=
         brake = r.uniform(3.0, 7.0)
         inj.append(dict(f0=f0, tau=tau, brake=brake, sky=sky[0], amp=amp))
     return Workload(f"realistic-{n_seg}seg-{n_bins}bin-{grid['n_f0'] * 288}tpl", [det], grid, inj)
+
+
+def batch_searches(seed=5, n_searches=64, t_sft=8.0):
+    """The batch of uneven searches: T_obs ~ U[2 h, 48 h] (whole segments of
+    8 s), band width ~ U[100, 1000] Hz placed in 500-3000 Hz on the 0.125-Hz
+    grid, two detectors (the H and L site rotations), a sky patch of N_sky ~
+    log-uniform integer [16, 1024] Fibonacci points in a 10-degree cap around a
+    random centre, and a lattice of f0 at every bin of the band x tau {3500,
+    7000, 14000, 35000} x n {3, 5, 7} from the data start.  Returns a list of
+    dicts (geometry and grid; the power itself is generated on the device)."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_searches):
+        t_obs = r.uniform(2 * 3600.0, 48 * 3600.0)
+        n_seg = max(1, int(round(t_obs / t_sft)))
+        width = r.uniform(100.0, 1000.0)
+        n_bins = int(round(width / 0.125))
+        f_lo = 500.0 + 0.125 * int(r.integers(0, int((3000.0 - 500.0 - n_bins * 0.125) / 0.125) + 1))
+        k_lo = int(round(f_lo * t_sft))
+        n_sky = int(round(math.exp(r.uniform(math.log(16.0), math.log(1024.0)))))
+        centre = sky_vector(r.uniform(0.0, 2.0 * math.pi), math.asin(r.uniform(-1.0, 1.0)))
+        sky = fibonacci_cap(n_sky, centre, math.radians(10.0))
+        t_seg = segment_times(n_seg, t_sft)
+        dets = [dict(t_seg=t_seg, v=velocity(t_seg, *site), k_lo=k_lo, t_sft=t_sft, n_seg=n_seg, n_bins=n_bins)
+                for site in (SITE_H, SITE_L)]
+        grid = dict(f0_min=f_lo, f0_step=0.125, n_f0=n_bins, tau=np.array([3500.0, 7000.0, 14000.0, 35000.0]),
+                    brake=np.array([3.0, 5.0, 7.0]), sky=sky, t0=0.0)
+        out.append(dict(dets=dets, grid=grid, n_templates=n_bins * 12 * n_sky,
+                        n_evals=n_bins * 12 * n_sky * 2 * n_seg))
+    return out

@@ -156,13 +156,13 @@ def test_tile_shapes_are_bit_identical():
     ctx = ltgw.Context(0)
     dets, searches = _setup(ctx)
     ref_single, ref_batch = None, None
-    for v in range(4):
+    for v in range(8):
         print(f"case: tile shape {v}", flush=True)
         ctx.set_tile_shape(v)
         single = _single(ctx, searches[1])
         assert ctx.diagnostics()["tile_shape"] == v
         _, _, st = ctx.eval_batch(searches, k=5)
-        assert st["variant"] == v
+        assert st["variant"] == v % 4
         batch = [_batch(ctx, i, s) for i, s in enumerate(searches)]
         if ref_single is None:
             ref_single, ref_batch = single, batch
@@ -180,7 +180,7 @@ def test_autotune_and_cache_roundtrip(tmp_path):
     s = searches[2]
     best = ctx.autotune(s["f0_min"], s["f0_step"], s["n_f0"], s["tau"], s["brake"], s["sky"], s["t0"],
                         det_mask=1 << s["dets"][0])
-    assert 0 <= best <= 3
+    assert 0 <= best <= 7
     _single(ctx, s)
     assert ctx.diagnostics()["tile_shape"] == best
     _, _, st = ctx.eval_batch(searches, k=5)
@@ -188,7 +188,7 @@ def test_autotune_and_cache_roundtrip(tmp_path):
     ctx.tune_save(str(path))
     cache = json.loads(path.read_text())["ltgw_tune"]
     assert any(k.startswith("eval/") for k in cache) and any(k.startswith("batch/") for k in cache)
-    assert set(cache.values()) <= {0, 1, 2, 3}
+    assert set(cache.values()) <= set(range(8))
     ctx.close()
     # a fresh context takes the shapes from the file
     ctx2 = ltgw.Context(0)
@@ -199,7 +199,7 @@ def test_autotune_and_cache_roundtrip(tmp_path):
     _, _, st2 = ctx2.eval_batch(searches, k=5)
     assert st2["variant"] == st["variant"]
     bad = tmp_path / "bad.json"
-    bad.write_text('{"ltgw_tune": {"eval/x": 9}}')
+    bad.write_text('{"ltgw_tune": {"eval/x": 9}}')   # no such variant
     with pytest.raises(ltgw.LtgwError):
         ctx2.tune_load(str(bad))
     with pytest.raises(ltgw.LtgwError):
