@@ -32,6 +32,36 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
 
 
+KERNEL_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_kernels.hip", "paper_2507_07816_amd/csrc/ddpow.h",
+                  "paper_2507_07816_amd/csrc/ltgw_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, store, variant):
+    """HBM-side bytes of one step's statistic launches from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE runs, each scaled by
+    what the same counter reads for a device copy of known size), or None
+    when the summary is for another workload, store, variant or kernel source."""
+    path = os.path.join(ROOT, "profiles", "eval_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if (t.get("source_sha256") != kernel_source_hash() or t.get("workload") != workload
+            or t.get("store") != store or t.get("variant") != variant):
+        return None
+    return (t["fetch_kib_per_step"] * t["fetch_scale"] + t["write_kib_per_step"] * t["write_scale"]) * 1024.0
+
+
 def cpu_baseline(wl, rho, target_s=15.0):
     """Oracle throughput on this host over a bounded sample of the workload:
     whole (tau, n) groups of all f0, all segments.  Returns the JSON object."""
@@ -161,6 +191,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-proposer", action="store_true", help="skip the learned-proposer leg")
     ap.add_argument("--batch", action="store_true", help="add the 64-search batch leg")
+    ap.add_argument("--tile-shape", type=int, default=-1,
+                    help="force the statistic kernel's variant (0..7) instead of autotuning (profiling runs)")
     ap.add_argument("--proposer-realisations", type=int, default=50000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 1 GiB device-to-device copies (HBM counter calibration)")
@@ -218,7 +250,10 @@ def main():
     # search on the device (cached for every later step)
     ctx.load_spectrogram(0, power, d["k_lo"], d["t_sft"], t_seg, weights=w, store=args.store)
     ctx.set_velocity_table(0, v)
-    shape = ctx.autotune(g["f0_min"], g["f0_step"], g["n_f0"], g["tau"], g["brake"], g["sky"], g["t0"])
+    if args.tile_shape >= 0:
+        ctx.set_tile_shape(args.tile_shape)
+    else:
+        ctx.autotune(g["f0_min"], g["f0_step"], g["n_f0"], g["tau"], g["brake"], g["sky"], g["t0"])
     for i in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -251,7 +286,8 @@ def main():
                    "in_band_fraction": in_band / evals, "eval_kernel_ms": kms,
                    "tile_shape": int(dg["tile_shape"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(wl.name, args.store, int(dg["tile_shape"]))},
     }
     if args.batch:
         print("[bench] batch of 64 searches", file=sys.stderr, flush=True)

@@ -171,6 +171,7 @@ struct ConvDims {
 };
 
 // Y = conv(X; W, b) (+ relu).  GEMM rows o, columns n = (b, l), K = (c, t).
+template <int KT>  // taps (1 or 5), zero padding KT / 2
 __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvDims d, const float *__restrict__ X,
                                                        const float *__restrict__ W,
                                                        const float *__restrict__ bias, int relu,
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvDims d, const float *
     const int64_t N = (int64_t)d.B * d.L;
     const int64_t n0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
     const int m0 = blockIdx.y * 16;
-    const int K = d.C * d.k;
+    const int K = d.C * KT;
     const int row = lane & 15, kq = (lane >> 4) * 4;
     const int64_t n = n0 + row;  // this lane's B-operand column
     const int nb = (int)(n / d.L), nl = (int)(n % d.L);
@@ -192,9 +193,9 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvDims d, const float *
             const int o = m0 + row;
             float av = 0.f, bv = 0.f;
             if (kidx < K) {
-                const int c = kidx / d.k, t = kidx % d.k;
-                if (o < d.O) av = W[((int64_t)o * d.C + c) * d.k + t];
-                const int li = nl + t - d.p;
+                const int c = kidx / KT, t = kidx % KT;
+                if (o < d.O) av = W[((int64_t)o * d.C + c) * KT + t];
+                const int li = nl + t - (KT / 2);
                 if (n < N && li >= 0 && li < d.L) bv = X[((int64_t)nb * d.C + c) * d.L + li];
             }
             a[i] = to_bf16(av);
@@ -217,6 +218,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvDims d, const float *
 
 // dX = conv^T(dY; W), times the mask (H > 0) of the layer below when H is given.
 // GEMM rows c, columns n = (b, l), K = (o, t): dX[b][c][l] = sum W[o][c][t] dY[b][o][l - t + p].
+template <int KT>  // taps (1 or 5), zero padding KT / 2
 __global__ __launch_bounds__(256) void conv_bwd_data_kernel(ConvDims d, const float *__restrict__ dY,
                                                             const float *__restrict__ W,
                                                             const float *__restrict__ H,
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(ConvDims d, const fl
     const int64_t N = (int64_t)d.B * d.L;
     const int64_t n0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
     const int m0 = blockIdx.y * 16;
-    const int K = d.O * d.k;
+    const int K = d.O * KT;
     const int row = lane & 15, kq = (lane >> 4) * 4;
     const int64_t n = n0 + row;
     const int nb = (int)(n / d.L), nl = (int)(n % d.L);
@@ -238,9 +240,9 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(ConvDims d, const fl
             const int c = m0 + row;
             float av = 0.f, bv = 0.f;
             if (kidx < K) {
-                const int o = kidx / d.k, t = kidx % d.k;
-                if (c < d.C) av = W[((int64_t)o * d.C + c) * d.k + t];
-                const int li = nl - t + d.p;
+                const int o = kidx / KT, t = kidx % KT;
+                if (c < d.C) av = W[((int64_t)o * d.C + c) * KT + t];
+                const int li = nl - t + (KT / 2);
                 if (n < N && li >= 0 && li < d.L) bv = dY[((int64_t)nb * d.O + o) * d.L + li];
             }
             a[i] = to_bf16(av);
@@ -265,11 +267,12 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(ConvDims d, const fl
 // Partial weight gradients over a chunk of columns: GEMM rows o, columns
 // (c, t), K = n = (b, l) in [chunk * kc, (chunk + 1) kc):
 //   part[chunk][o][c][t] = sum_n dY[b][o][l] X[b][c][l + t - p].
+template <int KT>  // taps (1 or 5), zero padding KT / 2
 __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(ConvDims d, const float *__restrict__ dY,
                                                               const float *__restrict__ X, int64_t kc,
                                                               float *__restrict__ part) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int CK = d.C * d.k;
+    const int CK = d.C * KT;
     const int j0 = (blockIdx.x * 4 + wv) * 16;  // column tile over (c, t)
     const int m0 = blockIdx.y * 16;
     const int64_t N = (int64_t)d.B * d.L;
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(ConvDims d, const 
     const int64_t k_end = k_begin + kc < N ? k_begin + kc : N;
     const int row = lane & 15, kq = (lane >> 4) * 4;
     const int jcol = j0 + row;
-    const int bc = jcol < CK ? jcol / d.k : 0, bt = jcol < CK ? jcol % d.k : 0;
+    const int bc = jcol < CK ? jcol / KT : 0, bt = jcol < CK ? jcol % KT : 0;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int64_t kk = k_begin; kk < k_end; kk += 16) {
         bf16x4 a, b;
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(ConvDims d, const 
                 const int nb = (int)(n / d.L), nl = (int)(n % d.L);
                 const int o = m0 + row;
                 if (o < d.O) av = dY[((int64_t)nb * d.O + o) * d.L + nl];
-                const int li = nl + bt - d.p;
+                const int li = nl + bt - (KT / 2);
                 if (jcol < CK && li >= 0 && li < d.L) bv = X[((int64_t)nb * d.C + bc) * d.L + li];
             }
             a[i] = to_bf16(av);
@@ -358,7 +361,10 @@ static hipError_t conv_fwd(const ConvDims &d, const float *X, const float *W, co
     const int64_t N = (int64_t)d.B * d.L;
     const int64_t tiles = (N + 15) / 16;
     dim3 grid((unsigned)((tiles + 3) / 4), (unsigned)((d.O + 15) / 16)), block(256);
-    hipLaunchKernelGGL(conv_fwd_kernel, grid, block, 0, st, d, X, W, b, relu, Y);
+    if (d.k == kTaps)
+        hipLaunchKernelGGL(conv_fwd_kernel<kTaps>, grid, block, 0, st, d, X, W, b, relu, Y);
+    else
+        hipLaunchKernelGGL(conv_fwd_kernel<1>, grid, block, 0, st, d, X, W, b, relu, Y);
     return hipGetLastError();
 }
 
@@ -394,7 +400,10 @@ static hipError_t weight_grad(const ConvDims &d, const float *dY, const float *X
     const int CK = d.C * d.k;
     const int64_t chunks = wgrad_chunks(d.B, d.L);
     dim3 grid((unsigned)(((CK + 15) / 16 + 3) / 4), (unsigned)((d.O + 15) / 16), (unsigned)chunks);
-    hipLaunchKernelGGL(conv_bwd_weight_kernel, grid, dim3(256), 0, st, d, dY, X, kWgradChunk, part);
+    if (d.k == kTaps)
+        hipLaunchKernelGGL(conv_bwd_weight_kernel<kTaps>, grid, dim3(256), 0, st, d, dY, X, kWgradChunk, part);
+    else
+        hipLaunchKernelGGL(conv_bwd_weight_kernel<1>, grid, dim3(256), 0, st, d, dY, X, kWgradChunk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)d.O * CK;
@@ -410,7 +419,10 @@ static hipError_t data_grad(const ConvDims &d, const float *dY, const float *W, 
     const int64_t N = (int64_t)d.B * d.L;
     const int64_t tiles = (N + 15) / 16;
     dim3 grid((unsigned)((tiles + 3) / 4), (unsigned)((d.C + 15) / 16)), block(256);
-    hipLaunchKernelGGL(conv_bwd_data_kernel, grid, block, 0, st, d, dY, W, H, dX);
+    if (d.k == kTaps)
+        hipLaunchKernelGGL(conv_bwd_data_kernel<kTaps>, grid, block, 0, st, d, dY, W, H, dX);
+    else
+        hipLaunchKernelGGL(conv_bwd_data_kernel<1>, grid, block, 0, st, d, dY, W, H, dX);
     return hipGetLastError();
 }
 

@@ -69,6 +69,9 @@ int main(void) {
   printf("ltgw_diag %zu\n", sizeof(ltgw_diag));
   F(ltgw_diag, in_band); F(ltgw_diag, eval_kernel_ms); F(ltgw_diag, tables_ms);
   F(ltgw_diag, tile_shape);
+  printf("ltgw_proposer %zu\n", sizeof(ltgw_proposer));
+  F(ltgw_proposer, c_in); F(ltgw_proposer, n_select); F(ltgw_proposer, psi_threshold);
+  F(ltgw_proposer, coarse_threshold);
   return 0;
 }
 ''')
@@ -78,7 +81,7 @@ int main(void) {
     got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
                                                          check=True).stdout.splitlines())
     for name in ("ltgw_spec_desc", "ltgw_grid", "ltgw_candidate", "ltgw_diag", "ltgw_search",
-                 "ltgw_batch_stats"):
+                 "ltgw_batch_stats", "ltgw_proposer"):
         cls = getattr(ltgw, name)
         assert int(got[name]) == C.sizeof(cls), name
         for key, val in got.items():
@@ -112,3 +115,42 @@ def test_create_without_gpu_reports_error():
         ltgw.ltgw_create(0)
     assert ei.value.code in (ltgw.LTGW_E_DEVICE, ltgw.LTGW_E_INVALID_ARG)
     assert ltgw.ltgw_last_error(None)
+
+
+def test_cnn_sizes_without_gpu():
+    """Parameter and work-area sizes are host arithmetic (no device needed)."""
+    from paper_2507_07816_amd import ltgw
+    from oracle import cnn
+
+    for c_in, c_out in ((1, 2), (4, 24), (8, 24)):
+        assert ltgw.ltgw_cnn_param_count(c_in, c_out) == cnn.n_params(c_in, c_out)
+    assert ltgw.ltgw_cnn_param_count(0, 4) < 0
+    assert ltgw.ltgw_cnn_work_floats(2, 4, 24, 200) >= 2 * 2 * 32 * 200
+    assert ltgw.ltgw_cnn_work_floats(0, 4, 24, 200) < 0
+
+
+def test_batch_workload_recipe():
+    """The 64-search batch follows its recipe: T_obs 2-48 h, bands 100-1000 Hz
+    inside 500-3000 Hz on the 0.125-Hz grid, 16-1024 sky points in a 10-degree
+    cap, two detectors; deterministic for a seed."""
+    import math
+
+    import numpy as np
+    import synth
+
+    a = synth.batch_searches(5)
+    b = synth.batch_searches(5)
+    assert len(a) == 64
+    for s, t in zip(a, b):
+        g, d = s["grid"], s["dets"]
+        assert len(d) == 2 and np.array_equal(g["sky"], t["grid"]["sky"])
+        assert 900 <= d[0]["n_seg"] <= 21600
+        assert 800 <= g["n_f0"] <= 8000 and g["f0_step"] == 0.125
+        assert g["f0_min"] >= 500.0 and g["f0_min"] + g["n_f0"] * 0.125 <= 3000.0 + 1e-9
+        assert d[0]["k_lo"] == round(g["f0_min"] * 8)
+        assert 16 <= len(g["sky"]) <= 1024
+        centre = g["sky"].mean(axis=0)
+        centre /= np.linalg.norm(centre)
+        assert np.all(g["sky"] @ centre >= math.cos(math.radians(10.0)) - 1e-9)
+        assert not np.array_equal(d[0]["v"], d[1]["v"])
+    assert 1.5e13 < sum(s["n_evals"] for s in a) < 2.1e13
