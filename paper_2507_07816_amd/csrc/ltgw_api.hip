@@ -187,7 +187,7 @@ void ltgw_destroy(ltgw_ctx *c) {
     free_stack(c->stack);
     for (auto &d : c->det) {
         release(d.store_buf); release(d.t_seg); release(d.w); release(d.wq);
-        release(d.scale); release(d.v); release(d.g); release(d.H); release(d.wfix);
+        release(d.scale); release(d.v); release(d.g); release(d.H); release(d.wfix); release(d.win);
     }
     DevBuf *all[] = {&c->staging, &c->counters, &c->tau_d, &c->brake_d, &c->sky_d,
                      &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2, &c->diff,
@@ -506,6 +506,14 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
                 return rc;
             V.wfix = (const int64_t *)D.wfix.p;
         }
+        // in-band segment windows of every (group, run of 64 f0)
+        V.win_blocks = (g->n_f0 + 63) / 64;
+        if ((rc = ensure(c, D.win, (size_t)P.n_groups * V.win_blocks * sizeof(int2), "segment windows")) != LTGW_OK)
+            return rc;
+        V.win = (const int2 *)D.win.p;
+        HIP_TRY(c, launch_windows(V, (int)P.n_groups, P.n_tn, g->f0_min, g->f0_step, g->n_f0, (int2 *)D.win.p,
+                                  c->stream),
+                "window launch");
     }
     const int64_t n_tpl = P.n_tpl;
     if ((rc = ensure(c, c->res_s, n_tpl * 8, "results s")) != LTGW_OK) return rc;

@@ -23,7 +23,7 @@ void free_batch(BatchState &B) {
     if (B.ev0) (void)hipEventDestroy(B.ev0);
     if (B.ev1) (void)hipEventDestroy(B.ev1);
     DevBuf *all[] = {&B.searches, &B.tiles, &B.ctr, &B.tiles_done, &B.t_done, &B.t_start,
-                     &B.in_band, &B.s, &B.c, &B.n_res, &B.w1, &B.w2, &B.gtab, &B.dtab,
+                     &B.in_band, &B.s, &B.c, &B.n_res, &B.w1, &B.w2, &B.gtab, &B.dtab, &B.win,
                      &B.tau, &B.brake, &B.sky, &B.cand, &B.n_out, &B.diff, &B.pa, &B.ia,
                      &B.pb, &B.ib};
     for (DevBuf *b : all) release(*b);
@@ -144,6 +144,9 @@ int enqueue(ltgw_ctx *c, BatchState &B, hipStream_t st, int variant, bool with_t
             HIP_TRY(c, launch_doppler((const double *)D.v.p, D.n_seg, (const double *)B.sky.p + B.sky_off[i],
                                       P.n_sky, (double *)V.D, st),
                     "batch Doppler launch");
+            HIP_TRY(c, launch_windows(V, (int)P.n_groups, P.n_tn, B.hsearch[i].f0_min, B.hsearch[i].f0_step, P.n_f0,
+                                      (int2 *)V.win, st),
+                    "batch window launch");
         }
     }
     if (!B.moments_in_loop)
@@ -229,7 +232,8 @@ int build(ltgw_ctx *c, const ltgw_search *S, int n, int k) {
     B.sky_off.resize(n);
     B.g_off.assign((size_t)n * LTGW_MAX_SEARCH_DET, 0);
     B.d_off.assign((size_t)n * LTGW_MAX_SEARCH_DET, 0);
-    int64_t tpl = 0, gtot = 0, dtot = 0, ntau = 0, nbrake = 0, nsky = 0, diff_max = 0, topk_max = 0;
+    B.win_off.assign((size_t)n * LTGW_MAX_SEARCH_DET, 0);
+    int64_t tpl = 0, gtot = 0, dtot = 0, wtot = 0, ntau = 0, nbrake = 0, nsky = 0, diff_max = 0, topk_max = 0;
     std::vector<double> htau, hbrake, hsky;
     for (int i = 0; i < n; ++i) {
         const SearchPlan &P = B.plans[i];
@@ -251,8 +255,10 @@ int build(ltgw_ctx *c, const ltgw_search *S, int n, int k) {
             const Det &D = c->det[P.sel[q]];
             B.g_off[(size_t)i * LTGW_MAX_SEARCH_DET + q] = gtot;
             B.d_off[(size_t)i * LTGW_MAX_SEARCH_DET + q] = dtot;
+            B.win_off[(size_t)i * LTGW_MAX_SEARCH_DET + q] = wtot;
             gtot += (int64_t)P.n_tn * D.n_seg;
             dtot += (int64_t)P.n_sky * D.n_seg;
+            wtot += P.n_groups * (int64_t)((P.n_f0 + 63) / 64);
         }
         diff_max = std::max(diff_max, (int64_t)(B.mom[i].mode ? 4 : 1) * P.n_groups * (P.n_f0 + 1));
         topk_max = std::max(topk_max, topk_scratch_entries(P.n_tpl, k));
@@ -269,6 +275,7 @@ int build(ltgw_ctx *c, const ltgw_search *S, int n, int k) {
         {&B.n_res, (size_t)tpl * 4, "batch N"},      {&B.w1, (size_t)tpl * 8, "batch W1"},
         {&B.w2, (size_t)tpl * 8, "batch W2"},        {&B.gtab, (size_t)gtot * 8, "batch spin-factor tables"},
         {&B.dtab, (size_t)dtot * 8, "batch Doppler tables"},
+        {&B.win, (size_t)wtot * sizeof(int2), "batch segment windows"},
         {&B.tau, (size_t)ntau * 8, "batch tau"},     {&B.brake, (size_t)nbrake * 8, "batch brake"},
         {&B.sky, (size_t)nsky * 8, "batch sky"},
         {&B.cand, (size_t)n * 2 * k * sizeof(ltgw_candidate), "batch candidates"},
@@ -318,6 +325,8 @@ int build(ltgw_ctx *c, const ltgw_search *S, int n, int k) {
             V.cshift = 1.5 - (double)D.k_lo;
             V.n_seg = D.n_seg;
             V.n_bins = D.n_bins;
+            V.win = (const int2 *)B.win.p + B.win_off[(size_t)i * LTGW_MAX_SEARCH_DET + q];
+            V.win_blocks = (P.n_f0 + 63) / 64;
             H.det[q] = V;
             a.det[q] = V;
         }

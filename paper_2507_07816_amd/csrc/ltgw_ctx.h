@@ -29,7 +29,7 @@ struct Det {
     std::vector<double> h_t;      // segment times as loaded
     std::vector<double> h_v;      // velocity table as set
     std::vector<int64_t> h_wfix;  // [n_seg][3] fixed-point w, w^2 high, w^2 low
-    DevBuf store_buf, t_seg, w, wq, scale, v, g, H, wfix;
+    DevBuf store_buf, t_seg, w, wq, scale, v, g, H, wfix, win;
 };
 
 // How the in-band moments W1, W2 are formed for a set of detectors.
@@ -69,7 +69,8 @@ struct BatchState {
     std::vector<BatchSearch> hsearch;     // host copy of the device descriptors
     std::vector<int64_t> g_off, d_off;    // per (search, det) offsets into the g and D tables
     DevBuf searches, tiles, ctr, tiles_done, t_done, t_start, in_band;
-    DevBuf s, c, n_res, w1, w2, gtab, dtab, tau, brake, sky, cand, n_out, diff;
+    DevBuf s, c, n_res, w1, w2, gtab, dtab, tau, brake, sky, cand, n_out, diff, win;
+    std::vector<int64_t> win_off;         // per (search, det) offsets into the window table
     DevBuf pa, ia, pb, ib;
     int64_t topk_cap = 0, diff_entries = 0;
     hipStream_t cap_stream = nullptr;
@@ -81,6 +82,8 @@ struct BatchState {
 // Grid axes and track-factor tables of one level of a stack.
 struct StackLevel {
     std::vector<double> h_tau, h_brake, h_sky;  // host copies of the last upload
+    double t0 = 0.0;
+    bool tables = false;                        // g and H hold the last upload's tables
     DevBuf tau, brake, sky, g, H;
 };
 

@@ -25,6 +25,9 @@ struct DetView {
     double cshift;          // 1.5 - k_lo
     int32_t n_seg;
     int32_t n_bins;
+    const int2 *win;        // [n_groups][win_blocks] first and last segment where a run of 64 f0
+                            // has a lane in band ({n_seg, -1}: none), or NULL: every segment
+    int32_t win_blocks;     // runs of 64 f0 per group
 };
 
 struct EvalArgs {
@@ -103,6 +106,9 @@ struct BatchArgs {
 hipError_t launch_batch(int store, bool moments_in_loop, int variant, const BatchArgs &a, int grid,
                         hipStream_t st);
 int batch_blocks_per_cu(int store, bool moments_in_loop, int variant);
+// In-band segment windows of every (group, run of 64 f0) of one detector.
+hipError_t launch_windows(const DetView &D, int n_groups, int n_tn, double f0_min, double f0_step, int n_f0,
+                          int2 *win, hipStream_t st);
 hipError_t launch_doppler(const double *v, int32_t n_seg, const double *sky, int32_t n_sky,
                           double *D, hipStream_t st);
 hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t st);

@@ -311,15 +311,42 @@ __device__ __forceinline__ void seg_batch(const DetView &D, __amdgpu_buffer_rsrc
 }
 
 // All segments of one detector.
+// Segments [jb, je) of detector D to visit for the runs [blk0, blk1) of 64 f0
+// of group grp: the in-band window widened to whole chunks (chunks outside
+// add exact zeros, so skipping them leaves every sum bit-identical); all
+// segments when D has no windows.  Wave-uniform.
+__device__ __forceinline__ void seg_window(const DetView &D, int grp, int blk0, int blk1, int &jb, int &je) {
+    jb = 0;
+    je = D.n_seg;
+    if (!D.win) return;
+    int lo = D.n_seg, hi = -1;
+    const int end = blk1 < D.win_blocks ? blk1 : D.win_blocks;
+    for (int b = blk0; b < end; ++b) {
+        const int2 w = D.win[(int64_t)grp * D.win_blocks + b];
+        lo = min(lo, w.x);
+        hi = max(hi, w.y);
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    if (hi < lo) {
+        je = 0;
+        return;
+    }
+    jb = (lo / kChunk) * kChunk;
+    je = min(D.n_seg, (hi / kChunk + 1) * kChunk);
+}
+
 template <int STORE, bool MOMENTS, int TPL, int U, class HS, int SHIFT = 0>
 __device__ __forceinline__ void accumulate_det(const DetView &D, const HS &hs,
-                                               const double (&f0)[TPL], Acc<TPL> &acc) {
+                                               const double (&f0)[TPL], Acc<TPL> &acc, int jb = 0,
+                                               int je = -1) {
+    if (je < 0) je = D.n_seg;
     // one resource per detector, n_bins + 2 records (a row with its guards);
     // the row is the instruction's scalar byte offset
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)D.store, Store<STORE>::kBytes, D.n_bins + 2, kBufDword3);
-    int j = 0;
-    for (; j + kChunk <= D.n_seg; j += kChunk) {
+    int j = jb;
+    for (; j + kChunk <= je; j += kChunk) {
         float sc[TPL], w1c[TPL], w2c[TPL];
         for (int t = 0; t < TPL; ++t) sc[t] = w1c[t] = w2c[t] = 0.0f;
 #pragma unroll 1
@@ -333,10 +360,10 @@ __device__ __forceinline__ void accumulate_det(const DetView &D, const HS &hs,
             }
         }
     }
-    if (j < D.n_seg) {
+    if (j < je) {
         float sc[TPL], w1c[TPL], w2c[TPL];
         for (int t = 0; t < TPL; ++t) sc[t] = w1c[t] = w2c[t] = 0.0f;
-        for (; j < D.n_seg; ++j)
+        for (; j < je; ++j)
             seg_batch<STORE, MOMENTS, TPL, 1, HS, SHIFT>(D, rs, hs, j, f0, sc, w1c, w2c, acc);
         for (int t = 0; t < TPL; ++t) {
             acc.s[t] += (double)sc[t];
@@ -415,7 +442,9 @@ __global__ __launch_bounds__(256) void eval_kernel(const EvalArgs a, int first, 
     acc.zero();
     for (int d = 0; d < a.n_det; ++d) {
         const DetView D = a.det[d];
-        accumulate_det<STORE, MOMENTS, TPL, U>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc);
+        int jb, je;
+        seg_window(D, grp, tile * 4 * TPL, (tile + 1) * 4 * TPL, jb, je);
+        accumulate_det<STORE, MOMENTS, TPL, U>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc, jb, je);
     }
     store_results<MOMENTS, TPL>(acc, i, grp, a.n_f0, a.s, a.c, a.n, a.w1, a.w2, a.out_s, a.out_c,
                                 a.out_n, a.in_band_total);
@@ -526,7 +555,9 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchArgs a) {
         for (int d = 0; d < n_det; ++d) {
             const DetView D = uniform(Sp->det[d]);
             const HFromGD hs{D.g + (int64_t)tn * D.n_seg, D.D + (int64_t)sky * D.n_seg, D.t_sft};
-            accumulate_det<STORE, MOMENTS, TPL, U>(D, hs, f0, acc);
+            int jb, je;
+            seg_window(D, T.grp, T.tile * TPL, (T.tile + 1) * TPL, jb, je);
+            accumulate_det<STORE, MOMENTS, TPL, U>(D, hs, f0, acc, jb, je);
         }
         store_results<MOMENTS, TPL>(acc, i, T.grp, n_f0, uniform(Sp->s), uniform(Sp->c), uniform(Sp->n),
                                     uniform(Sp->w1), uniform(Sp->w2), nullptr, nullptr, nullptr,
@@ -609,6 +640,55 @@ __global__ __launch_bounds__(256) void doppler_kernel(const double *__restrict__
     const double vn = (a + b) + z;
     const double r = vn / kC;
     D[(int64_t)s * n_seg + j] = 1.0 + r;
+}
+
+// In-band segment windows.  For a segment, the column index trunc(f0 h +
+// 1.5 - k_lo) is non-decreasing in f0, so a run of 64 consecutive f0 has a
+// lane in band exactly when its last f0 reaches column 1 and its first f0 is
+// at most column n_bins (the statistic kernel's arithmetic).  One wavefront
+// per (group, run): lanes stride over the segments, then min / max.
+__global__ __launch_bounds__(256) void window_kernel(const DetView D, int n_groups, int n_tn, double f0_min,
+                                                     double f0_step, int n_f0, int2 *__restrict__ win) {
+    const int lane = threadIdx.x & 63;
+    const int per_group = (D.win_blocks + 3) / 4;
+    const int grp = blockIdx.x / per_group;
+    const int blk = (blockIdx.x % per_group) * 4 + (threadIdx.x >> 6);
+    if (blk >= D.win_blocks) return;
+    const int ia = blk * 64;
+    const int ib = min(ia + 63, n_f0 - 1);
+    const double fa = f0_min + (double)ia * f0_step;
+    const double fb = f0_min + (double)ib * f0_step;
+    const int tn = grp % n_tn, sky = grp / n_tn;
+    int lo = D.n_seg, hi = -1;
+    for (int j = lane; j < D.n_seg; j += 64) {
+        double h;
+        if (D.H) {
+            h = D.H[(int64_t)grp * D.n_seg + j];
+        } else {
+            const double hg = D.g[(int64_t)tn * D.n_seg + j] * D.D[(int64_t)sky * D.n_seg + j];
+            h = hg * D.t_sft;
+        }
+        const double xa = fa * h, xb = fb * h;
+        const int ca = __double2int_rz(xa + D.cshift), cb = __double2int_rz(xb + D.cshift);
+        if (cb >= 1 && ca <= D.n_bins) {
+            lo = min(lo, j);
+            hi = max(hi, j);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, 64));
+        hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    if (lane == 0) win[(int64_t)grp * D.win_blocks + blk] = make_int2(lo, hi);
+}
+
+hipError_t launch_windows(const DetView &D, int n_groups, int n_tn, double f0_min, double f0_step, int n_f0,
+                          int2 *win, hipStream_t st) {
+    const int64_t blocks = (int64_t)((D.win_blocks + 3) / 4) * n_groups;
+    if (n_groups < 1 || D.win_blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(window_kernel, dim3((unsigned)blocks), dim3(256), 0, st, D, n_groups, n_tn, f0_min, f0_step,
+                       n_f0, win);
+    return hipGetLastError();
 }
 
 hipError_t launch_doppler(const double *v, int32_t n_seg, const double *sky, int32_t n_sky,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -64,6 +65,14 @@ int stack_tables(ltgw_ctx *c, const ltgw_grid *g, int level, SearchPlan &P) {
     if (D.n_seg != S.n_seg || D.n_bins != S.n_bins || D.k_lo != S.k_lo || D.t_sft != S.t_sft)
         return fail(c, LTGW_E_STATE, "detector slot %d changed shape since the stack was loaded", slot);
     StackLevel &L = S.lv[level];
+    // the same axes and T0 as the last call on this level: the tables stand
+    if (L.tables && L.t0 == g->t0 && L.h_tau.size() == (size_t)g->n_tau &&
+        L.h_brake.size() == (size_t)g->n_brake && L.h_sky.size() == 3 * (size_t)g->n_sky &&
+        std::equal(L.h_tau.begin(), L.h_tau.end(), g->tau) &&
+        std::equal(L.h_brake.begin(), L.h_brake.end(), g->brake) &&
+        std::equal(L.h_sky.begin(), L.h_sky.end(), g->sky))
+        return LTGW_OK;
+    L.tables = false;
     HIP_TRY(c, hipEventSynchronize(S.ev_h2d), "previous grid upload");
     L.h_tau.assign(g->tau, g->tau + g->n_tau);
     L.h_brake.assign(g->brake, g->brake + g->n_brake);
@@ -85,6 +94,8 @@ int stack_tables(ltgw_ctx *c, const ltgw_grid *g, int level, SearchPlan &P) {
     HIP_TRY(c, launch_track_factor((const double *)L.g.p, P.n_tn, (const double *)(level ? S.v2.p : S.v.p), ns,
                                    (const double *)L.sky.p, g->n_sky, S.t_sft, (double *)L.H.p, c->stream),
             "track-factor launch");
+    L.t0 = g->t0;
+    L.tables = true;
     return LTGW_OK;
 }
 
@@ -227,6 +238,7 @@ int32_t ltgw_load_stack(ltgw_ctx *c, int32_t det, int32_t R, const float *stack,
     Enter en(c);
     StackState &S = c->stack;
     S.valid = false;
+    S.lv[0].tables = S.lv[1].tables = false;
     if (det < 0 || det >= LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "detector %d out of range", det);
     const Det &D = c->det[det];
     if (!D.loaded || !D.has_v) return fail(c, LTGW_E_STATE, "detector %d needs a spectrogram and a velocity table", det);
@@ -291,6 +303,7 @@ int32_t ltgw_load_stack(ltgw_ctx *c, int32_t det, int32_t R, const float *stack,
     unsigned long long bad = 0;
     if ((rc = read_counter(c, kCntBad, &bad)) != LTGW_OK) return rc;  // synchronises: host vectors may go
     if (bad) return fail(c, LTGW_E_INVALID_ARG, "%llu stack values are negative or not finite", bad);
+    S.lv[0].tables = S.lv[1].tables = false;  // new geometry (segment times, velocities)
     S.det = det;
     S.R = R;
     S.store = store;

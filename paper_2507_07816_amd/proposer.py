@@ -211,7 +211,7 @@ class Proposer:
             ev1.record()
             ev1.synchronize()
             t_pr.append(ev0.elapsed_time(ev1))
-        _, pp_nf, _ = self.propose(psi_thr, float("inf"), R_signal)
+        _, pp_nf, _ = self.propose(psi_thr, 1e300, R_signal)      # fallback never taken
         det_ex = ex_psi > psi_thr
         n_det = int(det_ex.sum())
         rec = lambda p: float((det_ex & (p > psi_thr)).sum() / n_det) if n_det else float("nan")
