@@ -91,7 +91,7 @@ def cpu_baseline(wl, rho, target_s=15.0):
                       f"({idx.size * n_seg:.3g} evals, {dt:.1f} s, FP64, incl. its Eq. 1 table)"}
 
 
-def proposer_leg(torch, ltgw, realisations=50000, batch=256, eval_signal=2048, eval_noise=1024, seed=7):
+def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=8, eval_signal=2048, eval_noise=1024, seed=7):
     """The learned proposer on the small workload's shape (1024 segments x 800
     bins, 4800 fine templates): trained on `realisations` device-generated
     noise + injection realisations (amplitudes U[0.3, 3]), then recall and
@@ -116,7 +116,8 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, eval_signal=2048, e
     steps = max(1, realisations // batch)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    losses = [pr.train_step(batch, p_signal=0.9, amp_range=(0.3, 3.0), lr=2e-3) for _ in range(steps)]
+    losses = pr.train(steps * batch, batch=batch, epochs=epochs, p_signal=0.9, amp_range=(0.3, 3.0), lr=2e-3,
+                      label_psi=4.5)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t
     ev = pr.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16")
@@ -124,7 +125,8 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, eval_signal=2048, e
     ev0 = untrained.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
                              reps=1)
     ctx.close()
-    out = {"workload": "tiny-1024seg-800bin-4800tpl realisations", "realisations": steps * batch,
+    out = {"workload": "tiny-1024seg-800bin-4800tpl realisations", "train_realisations": steps * batch,
+           "epochs": epochs, "label_psi": 4.5,
            "train_s": train_s, "loss_first": float(np.mean(losses[:5])), "loss_last": float(np.mean(losses[-5:])),
            "coarse_grid": f"{coarse['n_f0']} f0 x {len(ctau)} tau x {len(cbrake)} n", "network": "4-layer CNN, BF16 MFMA",
            "untrained_recall_no_fallback": ev0["recall_no_fallback"], "untrained_fallback_frac": ev0["fallback_frac"]}
@@ -194,6 +196,7 @@ def main():
     ap.add_argument("--tile-shape", type=int, default=-1,
                     help="force the statistic kernel's variant (0..7) instead of autotuning (profiling runs)")
     ap.add_argument("--proposer-realisations", type=int, default=50000)
+    ap.add_argument("--proposer-epochs", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 1 GiB device-to-device copies (HBM counter calibration)")
     args = ap.parse_args()
@@ -295,7 +298,8 @@ def main():
         print(f"[bench] batch: {json.dumps(out['batch'])}", file=sys.stderr, flush=True)
     if not args.no_proposer:
         print("[bench] learned proposer: training and evaluation", file=sys.stderr, flush=True)
-        out["proposer"] = proposer_leg(torch, ltgw, realisations=args.proposer_realisations)
+        out["proposer"] = proposer_leg(torch, ltgw, realisations=args.proposer_realisations,
+                                       epochs=args.proposer_epochs)
         print(f"[bench] proposer: {json.dumps(out['proposer'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "realistic":
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)

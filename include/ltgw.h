@@ -364,10 +364,11 @@ int32_t ltgw_stack_features(ltgw_ctx *ctx, const ltgw_grid *g, float *x);
 int32_t ltgw_stack_best(ltgw_ctx *ctx, const ltgw_grid *g, int32_t *best_index, double *best_psi);
 
 /* ltgw_cells_from_templates: fine template t (group g, f0 index i, with fine
- * n_f0 = 2 L) -> network cell (2 g + i % 2) L + i / 2; -1 where t < 0 or
- * mask[k] == 0 (mask may be NULL).  Device arrays of n; asynchronous. */
+ * n_f0 = 2 L) -> network cell (2 g + i % 2) L + i / 2; -1 where t < 0,
+ * mask[k] == 0 (mask may be NULL) or psi[k] is not above min_psi (psi may be
+ * NULL).  Device arrays of n; asynchronous. */
 int32_t ltgw_cells_from_templates(ltgw_ctx *ctx, const int32_t *tpl, int32_t n, int32_t L, const int32_t *mask,
-                                  int32_t *cells);
+                                  const double *psi, double min_psi, int32_t *cells);
 
 /* The ranking network: x[B][c_in][L] -> logits[B][c_out][L] through three
  * width-32, kernel-5 convolutions with ReLU and a kernel-1 output
@@ -392,7 +393,8 @@ int32_t ltgw_softmax_xent(ltgw_ctx *ctx, const float *logits, int32_t B, int32_t
 /* One Adam step (Kingma and Ba) on FP32 master weights; step counts from 1. */
 int32_t ltgw_adam_step(ltgw_ctx *ctx, float *params, const float *grads, float *m, float *v, int64_t n,
                        float lr, float beta1, float beta2, float eps, int32_t step);
-/* Per row of n scores (n <= 8192): the M best indices (score desc, index asc). */
+/* Per row of n scores (n <= 8192): the indices of the M best scores (ties go
+ * to the lower index, NaN ranks last), written in ascending index order. */
 int32_t ltgw_select_top(ltgw_ctx *ctx, const float *score, int32_t R, int32_t n, int32_t M,
                         int32_t *out_idx);
 

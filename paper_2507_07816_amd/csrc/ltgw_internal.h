@@ -121,14 +121,14 @@ hipError_t launch_stack_eval(int store, int shift, const EvalArgs &a, int R, int
 hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,
                             const int32_t *idx, int m, const int32_t *rmap, double *out_psi, hipStream_t st);
 hipError_t launch_cells_to_templates(const int32_t *cells, int64_t n, int L, int32_t *tpl, hipStream_t st);
-hipError_t launch_propose_reduce(int R, const double *psi_sel, const int32_t *tpl_sel, int M,
-                                 const double *psi_coarse, int nc, double thr, double cthr,
-                                 int32_t *best_idx, double *best_psi, int32_t *fallback, hipStream_t st);
+hipError_t launch_sort_rows(int32_t *idx, int rows, int m, hipStream_t st);
+hipError_t launch_fallback(int R, const double *psi_coarse, int nc, const double *best_psi, double thr,
+                           double cthr, int32_t *fallback, hipStream_t st);
 hipError_t launch_iota_rows(int32_t *idx, int rows, int n, hipStream_t st);
 hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t *idx, int32_t *best_idx,
                            double *best_psi, hipStream_t st);
-hipError_t launch_templates_to_cells(const int32_t *tpl, int n, int L, const int32_t *mask, int32_t *cells,
-                                     hipStream_t st);
+hipError_t launch_templates_to_cells(const int32_t *tpl, int n, int L, const int32_t *mask, const double *psi,
+                                     double min_psi, int32_t *cells, hipStream_t st);
 hipError_t launch_noise(uint64_t seed, uint32_t stream, int r0, int R, int64_t n_per, float *out,
                         hipStream_t st);
 hipError_t launch_inject_stack(float *power, int R, int32_t n_seg, int32_t n_bins, int64_t k_lo,

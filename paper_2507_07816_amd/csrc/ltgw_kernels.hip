@@ -819,7 +819,31 @@ __global__ __launch_bounds__(256) void list_eval_kernel(const EvalArgs a, int64_
     for (int j0 = 0; j0 < D.n_seg; j0 += kChunk) {
         const int je = min(j0 + kChunk, D.n_seg);
         float sc = 0.0f, w1c = 0.0f, w2c = 0.0f;
-        for (int j = j0; j < je; ++j) {
+        int j = j0;
+        // batches of 8 segments: the track factors, then the gathers, then the
+        // sums in segment order (the same sums as one segment at a time)
+        for (; j + 8 <= je; j += 8) {
+            unsigned ix[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const double x = f0 * H[j + k];
+                const double vv = x + D.cshift;
+                ix[k] = (unsigned)__double2int_rz(vv);
+            }
+            float p[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) p[k] = Store<STORE>::get(rs, (int)ix[k], (j + k) * D.pitch_bytes, cnt);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                sc = __builtin_fmaf(D.wq[j + k], p[k], sc);
+                const bool inb = (ix[k] - 1u) < nb;
+                nin += inb ? 1 : 0;
+                const float wj = inb ? D.w[j + k] : 0.0f;
+                w1c += wj;
+                w2c = __builtin_fmaf(wj, wj, w2c);
+            }
+        }
+        for (; j < je; ++j) {
             const double x = f0 * H[j];
             const double vv = x + D.cshift;
             const unsigned ix = (unsigned)__double2int_rz(vv);
@@ -868,39 +892,68 @@ hipError_t launch_cells_to_templates(const int32_t *cells, int64_t n, int L, int
     return hipGetLastError();
 }
 
-// Per realisation: the best listed fine cell, the largest coarse ratio and
-// the fallback rule (coarse max > coarse threshold but no listed cell above
-// the detection threshold).
-__global__ void propose_reduce_kernel(int R, const double *psi_sel, const int32_t *tpl_sel, int M,
-                                      const double *psi_coarse, int nc, double thr, double cthr,
-                                      int32_t *best_idx, double *best_psi, int32_t *fallback) {
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= R) return;
-    double b = -__builtin_inf();
-    int bi = -1;
-    for (int q = 0; q < M; ++q) {
-        const double v = psi_sel[(int64_t)r * M + q];
-        const int t = tpl_sel[(int64_t)r * M + q];
-        if (v == v && (v > b || (v == b && t < bi))) {
-            b = v;
-            bi = t;
+// Each row of m template indices into ascending order (bitonic sort in LDS,
+// one workgroup per row): neighbouring lanes of the listed evaluation then
+// take neighbouring f0 wherever the selection is contiguous, so their gathers
+// share cache lines.
+constexpr int kSortMax = 8192;
+__global__ __launch_bounds__(256) void sort_rows_kernel(int32_t *idx, int m) {
+    __shared__ int32_t v[kSortMax];
+    int32_t *row = idx + (int64_t)blockIdx.x * m;
+    int P = 1;
+    while (P < m) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += 256) v[i] = i < m ? row[i] : 0x7fffffff;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P; i += 256) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const int32_t a = v[i], b = v[j];
+                    if (up ? a > b : a < b) {
+                        v[i] = b;
+                        v[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
         }
     }
-    double cm = -__builtin_inf();
-    for (int q = 0; q < nc; ++q) {
-        const double v = psi_coarse[(int64_t)r * nc + q];
-        if (v == v && v > cm) cm = v;
-    }
-    best_idx[r] = bi;
-    best_psi[r] = b;
-    fallback[r] = (cm > cthr && !(b > thr)) ? 1 : 0;
+    for (int i = threadIdx.x; i < m; i += 256) row[i] = v[i];
 }
 
-hipError_t launch_propose_reduce(int R, const double *psi_sel, const int32_t *tpl_sel, int M,
-                                 const double *psi_coarse, int nc, double thr, double cthr,
-                                 int32_t *best_idx, double *best_psi, int32_t *fallback, hipStream_t st) {
-    hipLaunchKernelGGL(propose_reduce_kernel, dim3((R + 255) / 256), dim3(256), 0, st, R, psi_sel, tpl_sel, M,
-                       psi_coarse, nc, thr, cthr, best_idx, best_psi, fallback);
+hipError_t launch_sort_rows(int32_t *idx, int rows, int m, hipStream_t st) {
+    if (rows < 1 || m < 1 || m > kSortMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sort_rows_kernel, dim3(rows), dim3(256), 0, st, idx, m);
+    return hipGetLastError();
+}
+
+// The fallback rule per realisation (one workgroup per row): the largest
+// coarse ratio above cthr while the best listed fine ratio does not pass thr.
+__global__ __launch_bounds__(256) void fallback_kernel(const double *psi_coarse, int nc, const double *best_psi,
+                                                       double thr, double cthr, int32_t *fallback) {
+    __shared__ double sh[4];
+    const int64_t r = blockIdx.x;
+    double cm = -__builtin_inf();
+    for (int q = threadIdx.x; q < nc; q += 256) {
+        const double v = psi_coarse[r * nc + q];
+        if (v == v && v > cm) cm = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) cm = fmax(cm, __shfl_xor(cm, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cm = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+        const double b = best_psi[r];
+        fallback[r] = (cm > cthr && !(b > thr)) ? 1 : 0;
+    }
+}
+
+hipError_t launch_fallback(int R, const double *psi_coarse, int nc, const double *best_psi, double thr,
+                           double cthr, int32_t *fallback, hipStream_t st) {
+    if (R < 1 || nc < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fallback_kernel, dim3(R), dim3(256), 0, st, psi_coarse, nc, best_psi, thr, cthr, fallback);
     return hipGetLastError();
 }
 
@@ -954,13 +1007,14 @@ hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t
 }
 
 // Fine templates to network cells (fine n_f0 = 2 L): template (group g, f0
-// index i) is cell (2 g + i % 2) L + i / 2; -1 where mask[r] == 0 or tpl < 0.
+// index i) is cell (2 g + i % 2) L + i / 2; -1 where mask[r] == 0, tpl < 0,
+// or psi (when given) is not above min_psi.
 __global__ void templates_to_cells_kernel(const int32_t *tpl, int n, int L, const int32_t *mask,
-                                          int32_t *cells) {
+                                          const double *psi, double min_psi, int32_t *cells) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int t = tpl[i];
-    if (t < 0 || (mask && mask[i] == 0)) {
+    if (t < 0 || (mask && mask[i] == 0) || (psi && !(psi[i] > min_psi))) {
         cells[i] = -1;
         return;
     }
@@ -968,9 +1022,10 @@ __global__ void templates_to_cells_kernel(const int32_t *tpl, int n, int L, cons
     cells[i] = (2 * g + (f & 1)) * L + (f >> 1);
 }
 
-hipError_t launch_templates_to_cells(const int32_t *tpl, int n, int L, const int32_t *mask, int32_t *cells,
-                                     hipStream_t st) {
-    hipLaunchKernelGGL(templates_to_cells_kernel, dim3((n + 255) / 256), dim3(256), 0, st, tpl, n, L, mask, cells);
+hipError_t launch_templates_to_cells(const int32_t *tpl, int n, int L, const int32_t *mask, const double *psi,
+                                     double min_psi, int32_t *cells, hipStream_t st) {
+    hipLaunchKernelGGL(templates_to_cells_kernel, dim3((n + 255) / 256), dim3(256), 0, st, tpl, n, L, mask, psi,
+                       min_psi, cells);
     return hipGetLastError();
 }
 

@@ -216,6 +216,70 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvDims d, const float *
     }
 }
 
+// The same product staged through LDS (the inference path).  A workgroup
+// owns one sample b, 64 positions l0 .. l0+63 and 32 output channels: it
+// converts the 32 weight rows and the im2col tile of x (k = (c, t) fastest
+// in each column) to bfloat16 in LDS once, then each wavefront computes two
+// 16 x 16 output tiles, reading its A and B fragments as 8-byte LDS words.
+// Rows are padded to Kpad + 4 halves (Kpad = K rounded up to 16).
+template <int KT>
+__global__ __launch_bounds__(256) void conv_fwd_lds_kernel(ConvDims d, const float *__restrict__ X,
+                                                           const float *__restrict__ W,
+                                                           const float *__restrict__ bias, int relu,
+                                                           float *__restrict__ Y, int Kpad) {
+    extern __shared__ short lds[];
+    const int S = Kpad + 4;
+    short *wt = lds;           // [32][S]
+    short *xt = lds + 32 * S;  // [64][S]
+    const int tiles_l = (d.L + 63) / 64;
+    const int b = blockIdx.x / tiles_l, l0 = (blockIdx.x % tiles_l) * 64;
+    const int o0 = blockIdx.y * 32;
+    const int K = d.C * KT;
+    for (int e = threadIdx.x; e < 32 * Kpad; e += 256) {
+        const int r = e / Kpad, k = e % Kpad;
+        const int o = o0 + r;
+        float v = 0.f;
+        if (o < d.O && k < K) v = W[(int64_t)o * K + k];
+        wt[r * S + k] = to_bf16(v);
+    }
+    for (int e = threadIdx.x; e < Kpad * 64; e += 256) {
+        const int k = e / 64, col = e % 64;
+        float v = 0.f;
+        if (k < K) {
+            const int c = k / KT, t = k % KT;
+            const int l = l0 + col + t - KT / 2;
+            if (l0 + col < d.L && l >= 0 && l < d.L) v = X[((int64_t)b * d.C + c) * d.L + l];
+        }
+        xt[col * S + k] = to_bf16(v);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r0 = (wv & 1) * 16, c0 = (wv >> 1) * 32;
+    const int row = lane & 15, kq = (lane >> 4) * 4;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < Kpad; kk += 16) {
+        const bf16x4 a = *(const bf16x4 *)&wt[(r0 + row) * S + kk + kq];
+        const bf16x4 b0 = *(const bf16x4 *)&xt[(c0 + row) * S + kk + kq];
+        const bf16x4 b1 = *(const bf16x4 *)&xt[(c0 + 16 + row) * S + kk + kq];
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1, acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const f32x4 acc = h ? acc1 : acc0;
+        const int l = l0 + c0 + h * 16 + (lane & 15);
+        if (l >= d.L) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = o0 + r0 + kq + i;
+            if (o >= d.O) continue;
+            float y = acc[i] + bias[o];
+            if (relu) y = y > 0.f ? y : 0.f;
+            Y[((int64_t)b * d.O + o) * d.L + l] = y;
+        }
+    }
+}
+
 // dX = conv^T(dY; W), times the mask (H > 0) of the layer below when H is given.
 // GEMM rows c, columns n = (b, l), K = (o, t): dX[b][c][l] = sum W[o][c][t] dY[b][o][l - t + p].
 template <int KT>  // taps (1 or 5), zero padding KT / 2
@@ -358,6 +422,17 @@ int64_t cnn_n_params(int c_in, int c_out) { return cnn_layout(c_in, c_out).total
 
 static hipError_t conv_fwd(const ConvDims &d, const float *X, const float *W, const float *b, int relu,
                            float *Y, hipStream_t st) {
+    const int Kpad = (d.C * d.k + 15) / 16 * 16;
+    const size_t lds = (size_t)(32 + 64) * (Kpad + 4) * sizeof(short);
+    const int64_t ltiles = (int64_t)d.B * ((d.L + 63) / 64);
+    if (lds <= 48 * 1024 && ltiles <= 0x7fffffff) {
+        dim3 grid((unsigned)ltiles, (unsigned)((d.O + 31) / 32)), block(256);
+        if (d.k == kTaps)
+            hipLaunchKernelGGL(conv_fwd_lds_kernel<kTaps>, grid, block, lds, st, d, X, W, b, relu, Y, Kpad);
+        else
+            hipLaunchKernelGGL(conv_fwd_lds_kernel<1>, grid, block, lds, st, d, X, W, b, relu, Y, Kpad);
+        return hipGetLastError();
+    }
     const int64_t N = (int64_t)d.B * d.L;
     const int64_t tiles = (N + 15) / 16;
     dim3 grid((unsigned)((tiles + 3) / 4), (unsigned)((d.O + 15) / 16)), block(256);
@@ -523,53 +598,107 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, 
     return hipGetLastError();
 }
 
-// Per row of n scores: indices of the M largest (score desc, index asc; NaN
-// ranks last), by a bitonic sort of (score, index) pairs in LDS.
+// Per row of n scores: the indices of the M largest (ties to the lower index;
+// NaN ranks below everything), written in ascending index order.  One
+// workgroup per row.  Scores become order-preserving 32-bit keys; the M-th
+// largest key is found bit by bit from the top (32 rounds of a block-wide
+// count), then every key above it and the first (in index order) keys equal
+// to it are written through a block-wide prefix sum.  Thread k holds the
+// contiguous indices [k q, k q + q), q = ceil(n / 256) <= 32.
 constexpr int kSelMax = 8192;
+constexpr int kSelPer = kSelMax / 256;
 
-__device__ inline bool sel_before(float a, int ia, float b, int ib) {
-    return a > b || (a == b && ia < ib);
+__device__ inline uint32_t order_key(float v) {
+    if (!(v == v)) return 0u;  // NaN: below every number
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__global__ __launch_bounds__(256) void select_top_kernel(const float *score, int n, int M,
-                                                         int32_t *out) {
-    __shared__ float ks[kSelMax];
-    __shared__ int ki[kSelMax];
-    const int r = blockIdx.x;
-    int P = 1;
-    while (P < n) P <<= 1;
-    for (int i = threadIdx.x; i < P; i += 256) {
-        float v = -3.4e38f;
-        if (i < n) {
-            v = score[(int64_t)r * n + i];
-            if (!(v == v)) v = -3.4e38f;
-        }
-        ks[i] = v;
-        ki[i] = i < n ? i : 0x7fffffff;
+// Block-wide sum of v (256 threads); every thread receives it.
+__device__ inline int block_sum(int v, int *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Exclusive prefix over the block of v in thread order; also the total.
+__device__ inline int block_exclusive(int v, int *sh, int &total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
     __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < P; i += 256) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    const bool desc = (i & size) == 0;  // first half of each block sorted best-first
-                    const bool swap = desc ? sel_before(ks[j], ki[j], ks[i], ki[i])
-                                           : sel_before(ks[i], ki[i], ks[j], ki[j]);
-                    if (swap) {
-                        const float tv = ks[i];
-                        ks[i] = ks[j];
-                        ks[j] = tv;
-                        const int ti = ki[i];
-                        ki[i] = ki[j];
-                        ki[j] = ti;
-                    }
-                }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    int off = 0;
+    for (int k = 0; k < wv; ++k) off += sh[k];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    return off + x - v;
+}
+
+__global__ __launch_bounds__(256) void select_top_kernel(const float *score, int n, int M, int32_t *out) {
+    __shared__ int sh[4];
+    const float *row = score + (int64_t)blockIdx.x * n;
+    const int q = (n + 255) / 256;
+    const int i0 = threadIdx.x * q;
+    uint32_t key[kSelPer];
+#pragma unroll
+    for (int r = 0; r < kSelPer; ++r) key[r] = (r < q && i0 + r < n) ? order_key(row[i0 + r]) : 0u;
+    // the largest T with #(key >= T) >= M (keys of padding are 0 and are never
+    // written: T >= 1 whenever M <= n counts only real entries, see below)
+    uint32_t T = 0u;
+    for (int bit = 31; bit >= 0; --bit) {
+        const uint32_t cand = T | (1u << bit);
+        int cnt = 0;
+#pragma unroll
+        for (int r = 0; r < kSelPer; ++r) cnt += (r < q && i0 + r < n && key[r] >= cand) ? 1 : 0;
+        if (block_sum(cnt, sh) >= M) T = cand;
+    }
+    int gt = 0, eq = 0;
+#pragma unroll
+    for (int r = 0; r < kSelPer; ++r) {
+        const bool real = r < q && i0 + r < n;
+        gt += (real && key[r] > T) ? 1 : 0;
+        eq += (real && key[r] == T) ? 1 : 0;
+    }
+    int n_gt = 0, n_eq = 0;
+    const int eq_before = block_exclusive(eq, sh, n_eq);
+    const int gt_before = block_exclusive(gt, sh, n_gt);
+    (void)n_eq;
+    const int take_eq = M - n_gt;  // keys equal to T taken, lowest indices first
+    // position of this thread's first output: selected entries of lower threads
+    int sel = 0;
+    {
+        int e = 0;
+#pragma unroll
+        for (int r = 0; r < kSelPer; ++r) {
+            const bool real = r < q && i0 + r < n;
+            if (real && key[r] > T) ++sel;
+            if (real && key[r] == T) {
+                if (eq_before + e < take_eq) ++sel;
+                ++e;
             }
-            __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < M; i += 256) out[(int64_t)r * M + i] = ki[i];
+    int total = 0;
+    int pos = block_exclusive(sel, sh, total);
+    (void)gt_before;
+    int e = 0;
+    int32_t *o = out + (int64_t)blockIdx.x * M;
+#pragma unroll
+    for (int r = 0; r < kSelPer; ++r) {
+        const bool real = r < q && i0 + r < n;
+        bool take = real && key[r] > T;
+        if (real && key[r] == T) {
+            take = eq_before + e < take_eq;
+            ++e;
+        }
+        if (take && pos < M) o[pos++] = i0 + r;
+    }
 }
 
 hipError_t launch_select_top(const float *score, int R, int n, int M, int32_t *out, hipStream_t st) {

@@ -459,7 +459,7 @@ int32_t ltgw_stack_best(ltgw_ctx *c, const ltgw_grid *g, int32_t *best_index, do
 }
 
 int32_t ltgw_cells_from_templates(ltgw_ctx *c, const int32_t *tpl, int32_t n, int32_t L, const int32_t *mask,
-                                  int32_t *cells) {
+                                  const double *psi, double min_psi, int32_t *cells) {
     if (!c) return LTGW_E_INVALID_ARG;
     Enter en(c);
     if (n < 1 || L < 1) return fail(c, LTGW_E_INVALID_ARG, "n and L must be >= 1");
@@ -467,7 +467,8 @@ int32_t ltgw_cells_from_templates(ltgw_ctx *c, const int32_t *tpl, int32_t n, in
     if ((rc = need_device(c, tpl, "tpl")) != LTGW_OK) return rc;
     if ((rc = need_device(c, cells, "cells")) != LTGW_OK) return rc;
     if (mask && (rc = need_device(c, mask, "mask")) != LTGW_OK) return rc;
-    HIP_TRY(c, launch_templates_to_cells(tpl, n, L, mask, cells, c->stream), "cell mapping launch");
+    if (psi && (rc = need_device(c, psi, "psi")) != LTGW_OK) return rc;
+    HIP_TRY(c, launch_templates_to_cells(tpl, n, L, mask, psi, min_psi, cells, c->stream), "cell mapping launch");
     return LTGW_OK;
 }
 
@@ -519,13 +520,16 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
     HIP_TRY(c, launch_cells_to_templates((const int32_t *)S.cells.p, (int64_t)R * M, L, (int32_t *)S.tpl.p,
                                          c->stream),
             "cell mapping launch");
+    HIP_TRY(c, launch_sort_rows((int32_t *)S.tpl.p, R, M, c->stream), "template sort launch");
     SearchPlan P;
     if ((rc = list_psi_impl(c, fine, (const int32_t *)S.tpl.p, R, M, nullptr, (double *)S.psi_sel.p, &P)) != LTGW_OK)
         return rc;
-    HIP_TRY(c, launch_propose_reduce(R, (const double *)S.psi_sel.p, (const int32_t *)S.tpl.p, M,
-                                     (const double *)S.psi_c.p, (int)nc, p->psi_threshold, p->coarse_threshold,
-                                     (int32_t *)S.best_idx.p, (double *)S.best_psi.p, (int32_t *)S.fb.p, c->stream),
+    HIP_TRY(c, launch_row_best((const double *)S.psi_sel.p, R, M, (const int32_t *)S.tpl.p, (int32_t *)S.best_idx.p,
+                               (double *)S.best_psi.p, c->stream),
             "reduction launch");
+    HIP_TRY(c, launch_fallback(R, (const double *)S.psi_c.p, (int)nc, (const double *)S.best_psi.p, p->psi_threshold,
+                               p->coarse_threshold, (int32_t *)S.fb.p, c->stream),
+            "fallback launch");
     HIP_TRY(c, hipMemcpyAsync(best_index, S.best_idx.p, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipMemcpyAsync(best_psi, S.best_psi.p, (size_t)R * 8, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipMemcpyAsync(fallback, S.fb.p, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");

@@ -143,7 +143,7 @@ def library():
             "ltgw_select_top": (i32, [P, P, i32, i32, i32, P]),
             "ltgw_stack_features": (i32, [P, C.POINTER(ltgw_grid), P]),
             "ltgw_stack_best": (i32, [P, C.POINTER(ltgw_grid), P, P]),
-            "ltgw_cells_from_templates": (i32, [P, P, i32, i32, P, P]),
+            "ltgw_cells_from_templates": (i32, [P, P, i32, i32, P, P, d, P]),
             "ltgw_propose": (i32, [P, C.POINTER(ltgw_grid), C.POINTER(ltgw_grid), C.POINTER(ltgw_proposer),
                                    P, P, P]),
         }
@@ -385,11 +385,12 @@ def ltgw_stack_best(ctx, grid, best_index, best_psi):
                                           _dev(best_psi, torch.float64)))
 
 
-def ltgw_cells_from_templates(ctx, tpl, L, cells, mask=None):
+def ltgw_cells_from_templates(ctx, tpl, L, cells, mask=None, psi=None, min_psi=0.0):
     import torch
     _check(ctx, library().ltgw_cells_from_templates(ctx, _dev(tpl, torch.int32), tpl.numel(), int(L),
                                                     None if mask is None else _dev(mask, torch.int32),
-                                                    _dev(cells, torch.int32)))
+                                                    None if psi is None else _dev(psi, torch.float64),
+                                                    float(min_psi), _dev(cells, torch.int32)))
 
 
 def ltgw_cnn_param_count(c_in, c_out):

@@ -140,21 +140,49 @@ class Proposer:
             ltgw.ltgw_stack_best(h, self._fg, b["best"], b["best_psi"])
         return b
 
-    def train_step(self, R, p_signal=0.9, amp_range=(1.0, 3.0), lr=1e-3, stream=1):
-        """One Adam step on a fresh batch; returns the batch's mean loss (host float)."""
+    def train_step(self, R, p_signal=0.9, amp_range=(1.0, 3.0), lr=1e-3, stream=1, inj=None, r0=None,
+                   label_psi=None):
+        """One Adam step on a batch of R realisations (fresh ones unless inj and
+        r0 name a stored batch); the label of an injected realisation is the
+        exhaustive search's best cell, dropped when that best ratio is not above
+        label_psi.  Returns the batch's mean loss (host float)."""
         T = self.torch
-        inj, sig = self.draw_injections(R, p_signal, amp_range)
-        b = self.make_batch(R, stream, self.step * R, inj)
+        if inj is None:
+            inj, _ = self.draw_injections(R, p_signal, amp_range)
+        sig = inj[:, 3] > 0
+        b = self.make_batch(R, stream, self.step * R if r0 is None else r0, inj)
         h = self.ctx.h
         b["mask"].copy_(T.from_numpy(sig.astype(np.int32)))
-        ltgw.ltgw_cells_from_templates(h, b["best"], self.L, b["target"], mask=b["mask"])
-        n_valid = int(sig.sum())
+        ltgw.ltgw_cells_from_templates(h, b["best"], self.L, b["target"], mask=b["mask"],
+                                       psi=None if label_psi is None else b["best_psi"],
+                                       min_psi=0.0 if label_psi is None else label_psi)
+        n_valid = int((b["target"].cpu().numpy() >= 0).sum())
         ltgw.ltgw_cnn_forward(h, self.params, b["x"], self.c_out, b["act"], b["logits"])
         ltgw.ltgw_softmax_xent(h, b["logits"], b["target"], max(n_valid, 1), b["loss"], b["dlogits"])
         ltgw.ltgw_cnn_backward(h, self.params, b["x"], self.c_out, b["act"], b["dlogits"], b["work"], self.grads)
         self.step += 1
         ltgw.ltgw_adam_step(h, self.params, self.grads, self.m, self.v, lr, 0.9, 0.999, 1e-8, self.step)
         return float(b["loss"].cpu().numpy().astype(np.float64).sum()) / max(n_valid, 1)
+
+    def train(self, realisations, batch=256, epochs=1, p_signal=0.9, amp_range=(1.0, 3.0), lr=2e-3,
+              label_psi=None, stream=1):
+        """Several passes over one fixed set of `realisations` realisations
+        (Philox stream `stream`, realisation indices 0 .. realisations-1; the
+        injection parameters are drawn once), batches in a new order each
+        epoch, learning rate on a cosine from lr to lr / 20.  Returns the
+        per-step losses."""
+        steps_per_epoch = max(1, realisations // batch)
+        inj, _ = self.draw_injections(steps_per_epoch * batch, p_signal, amp_range)
+        total = steps_per_epoch * epochs
+        losses = []
+        for e in range(epochs):
+            for k in self.rng.permutation(steps_per_epoch):
+                t = len(losses) / max(total - 1, 1)
+                lr_t = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * t)))
+                sl = slice(int(k) * batch, (int(k) + 1) * batch)
+                losses.append(self.train_step(batch, inj=inj[sl], r0=int(k) * batch, lr=lr_t, stream=stream,
+                                              label_psi=label_psi))
+        return losses
 
     def propose(self, psi_threshold, coarse_threshold, R):
         """ltgw_propose on the loaded stack: (best_index, best_psi, fallback)."""
