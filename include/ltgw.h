@@ -287,11 +287,13 @@ int32_t ltgw_batch_latency(ltgw_ctx *ctx, double *out_ms);
 /* ---- autotuner -----------------------------------------------------------
  * Tile shapes (templates per lane, segments per gather batch):
  *   0 = (1, 8)   1 = (1, 16)   2 = (2, 8)   3 = (2, 16)
- * and, for the single-search statistic kernel, 4..7 = the same shapes
+ and, for the single-search statistic kernel, bit 4 = the same shape
  * launched in generations of as many workgroups as the device holds at once
  * (the workgroups of a generation walk the segments together and share the
- * spectrogram rows in L2).  A batch uses shape (value & 3): its persistent
- * launch is one generation already.
+ * spectrogram rows in L2) and bit 8 = one search detector's segments walked
+ * in slabs of 1024, one launch per slab (results bit-identical to one pass).
+ * Variants 0..15.  A batch uses shape (value & 3): its persistent launch is
+ * one generation already.
  * Keys describe the work (single search or batch, store, moment mode and
  * size classes); values are the fastest variant measured on this device.
  * ltgw_autotune times every variant on the given grid (single search) and
@@ -299,7 +301,7 @@ int32_t ltgw_batch_latency(ltgw_ctx *ctx, double *out_ms);
  * ltgw_tune_save / ltgw_tune_load write and read the cache as JSON text
  * ({"ltgw_tune": {"<key>": <variant>, ...}}). */
 int32_t ltgw_autotune(ltgw_ctx *ctx, const ltgw_grid *g, int32_t *best_variant);
-/* ltgw_set_tile_shape: use variant `variant` (0..7) for every later
+/* ltgw_set_tile_shape: use variant `variant` (0..15) for every later
  * evaluation, or -1 to return to the autotuner.  Drops a captured batch. */
 int32_t ltgw_set_tile_shape(ltgw_ctx *ctx, int32_t variant);
 int32_t ltgw_tune_save(ltgw_ctx *ctx, const char *path);

@@ -507,7 +507,8 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
             V.wfix = (const int64_t *)D.wfix.p;
         }
         // in-band segment windows of every (group, run of 64 f0)
-        V.win_blocks = (g->n_f0 + 63) / 64;
+        V.win_run = 256;  // the statistic kernel's tiles are whole multiples of 256 f0
+        V.win_blocks = (g->n_f0 + 255) / 256;
         if ((rc = ensure(c, D.win, (size_t)P.n_groups * V.win_blocks * sizeof(int2), "segment windows")) != LTGW_OK)
             return rc;
         V.win = (const int2 *)D.win.p;

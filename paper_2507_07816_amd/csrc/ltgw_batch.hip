@@ -326,6 +326,7 @@ int build(ltgw_ctx *c, const ltgw_search *S, int n, int k) {
             V.n_seg = D.n_seg;
             V.n_bins = D.n_bins;
             V.win = (const int2 *)B.win.p + B.win_off[(size_t)i * LTGW_MAX_SEARCH_DET + q];
+            V.win_run = 64;
             V.win_blocks = (P.n_f0 + 63) / 64;
             H.det[q] = V;
             a.det[q] = V;

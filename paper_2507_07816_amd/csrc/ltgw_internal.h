@@ -25,9 +25,10 @@ struct DetView {
     double cshift;          // 1.5 - k_lo
     int32_t n_seg;
     int32_t n_bins;
-    const int2 *win;        // [n_groups][win_blocks] first and last segment where a run of 64 f0
-                            // has a lane in band ({n_seg, -1}: none), or NULL: every segment
-    int32_t win_blocks;     // runs of 64 f0 per group
+    const int2 *win;        // [n_groups][win_blocks] first and last segment where a run of win_run
+                            // f0 has a lane in band ({n_seg, -1}: none), or NULL: every segment
+    int32_t win_blocks;     // runs per group
+    int32_t win_run;        // f0 per run (64: batch tiles; 256: single-search tiles)
 };
 
 struct EvalArgs {
@@ -69,9 +70,11 @@ hipError_t launch_track_factor(const double *g, int32_t n_tn, const double *v, i
 // (templates per lane, segments per gather batch) = (1,8), (1,16), (2,8),
 // (2,16); variant & 4: the grid is launched in generations of the blocks the
 // device holds at once (cu_count x resident blocks per CU), so that the
-// blocks of a launch walk the segments together and share rows in L2.
+// blocks of a launch walk the segments together and share rows in L2;
+// variant & 8 (one detector): the segments are walked in slabs of 1024, one
+// launch per slab, so that the blocks of a launch stay within a slab.
 constexpr int kNumShapes = 4;
-constexpr int kNumVariants = 8;
+constexpr int kNumVariants = 16;
 int variant_templates_per_block(int variant);
 hipError_t launch_eval(int store, bool moments_in_loop, int variant, const EvalArgs &a, int cu_count,
                        hipStream_t st);
@@ -106,7 +109,7 @@ struct BatchArgs {
 hipError_t launch_batch(int store, bool moments_in_loop, int variant, const BatchArgs &a, int grid,
                         hipStream_t st);
 int batch_blocks_per_cu(int store, bool moments_in_loop, int variant);
-// In-band segment windows of every (group, run of 64 f0) of one detector.
+// In-band segment windows of every (group, run of win_run f0) of one detector.
 hipError_t launch_windows(const DetView &D, int n_groups, int n_tn, double f0_min, double f0_step, int n_f0,
                           int2 *win, hipStream_t st);
 hipError_t launch_doppler(const double *v, int32_t n_seg, const double *sky, int32_t n_sky,

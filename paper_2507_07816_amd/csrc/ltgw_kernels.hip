@@ -427,8 +427,13 @@ __device__ inline void xcd_tile_group(int w, int n_blocks, int n_tiles, int &til
     grp = p % n_groups;
 }
 
+// A launch covers the segments [j_lo, j_hi) (a slab; multiples of the chunk
+// except a final j_hi = n_seg): a slab after the first resumes from the sums
+// the previous slab stored (the same operations in the same order as one
+// pass), and only the last slab writes the caller's outputs.
 template <int STORE, bool MOMENTS, int TPL, int U>
-__global__ __launch_bounds__(256) void eval_kernel(const EvalArgs a, int first, int total) {
+__global__ __launch_bounds__(256) void eval_kernel(const EvalArgs a, int first, int total, int j_lo, int j_hi,
+                                                   int last) {
     const int n_tiles = (a.n_f0 + 256 * TPL - 1) / (256 * TPL);
     int tile, grp;
     xcd_tile_group(blockIdx.x, gridDim.x, n_tiles, tile, grp, first, total);
@@ -440,14 +445,31 @@ __global__ __launch_bounds__(256) void eval_kernel(const EvalArgs a, int first, 
     }
     Acc<TPL> acc;
     acc.zero();
+    if (j_lo > 0)
+        for (int t = 0; t < TPL; ++t) {
+            if (i[t] >= a.n_f0) continue;
+            const int64_t q = (int64_t)grp * a.n_f0 + i[t];
+            acc.s[t] = a.s[q];
+            acc.cnt[t] = a.c[q];
+            if (MOMENTS) {
+                acc.nin[t] = a.n[q];
+                acc.w1[t] = a.w1[q];
+                acc.w2[t] = a.w2[q];
+            }
+        }
     for (int d = 0; d < a.n_det; ++d) {
         const DetView D = a.det[d];
         int jb, je;
-        seg_window(D, grp, tile * 4 * TPL, (tile + 1) * 4 * TPL, jb, je);
-        accumulate_det<STORE, MOMENTS, TPL, U>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc, jb, je);
+        const int runs = D.win ? 256 * TPL / D.win_run : 1;
+        seg_window(D, grp, tile * runs, (tile + 1) * runs, jb, je);
+        jb = jb > j_lo ? jb : j_lo;
+        je = je < j_hi ? je : j_hi;
+        if (jb < je)
+            accumulate_det<STORE, MOMENTS, TPL, U>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc, jb, je);
     }
-    store_results<MOMENTS, TPL>(acc, i, grp, a.n_f0, a.s, a.c, a.n, a.w1, a.w2, a.out_s, a.out_c,
-                                a.out_n, a.in_band_total);
+    store_results<MOMENTS, TPL>(acc, i, grp, a.n_f0, a.s, a.c, a.n, a.w1, a.w2, last ? a.out_s : nullptr,
+                                last ? a.out_c : nullptr, last ? a.out_n : nullptr,
+                                last ? a.in_band_total : nullptr);
 }
 
 // Tile shapes: (templates per lane, segments per gather batch).
@@ -455,8 +477,11 @@ constexpr int kVariantTpl[kNumShapes] = {1, 1, 2, 2};
 
 int variant_templates_per_block(int variant) { return 256 * kVariantTpl[variant & 3]; }
 
+// Segments per slab (variant & 8); a multiple of the chunk.
+constexpr int kSlab = 1024;
+
 template <int STORE, bool MOMENTS, int TPL, int U>
-static hipError_t launch_eval_v(const EvalArgs &a, bool generations, int cu_count, hipStream_t st) {
+static hipError_t launch_eval_v(const EvalArgs &a, bool generations, bool slabs, int cu_count, hipStream_t st) {
     const int64_t blocks = (int64_t)((a.n_f0 + 256 * TPL - 1) / (256 * TPL)) * a.n_groups;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     int64_t step = blocks;
@@ -469,24 +494,32 @@ static hipError_t launch_eval_v(const EvalArgs &a, bool generations, int cu_coun
         }
         step = (int64_t)cu_count * per_cu;
     }
-    for (int64_t first = 0; first < blocks; first += step) {
-        const int64_t n = blocks - first < step ? blocks - first : step;
-        hipLaunchKernelGGL((eval_kernel<STORE, MOMENTS, TPL, U>), dim3((unsigned)n), dim3(256), 0, st, a,
-                           (int)first, (int)blocks);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    // slabs only for one detector (one segment axis)
+    const int n_seg = a.det[0].n_seg;
+    const int slab = (slabs && a.n_det == 1) ? kSlab : 0x7fffffff;
+    for (int j_lo = 0; j_lo == 0 || j_lo < n_seg; j_lo += slab) {
+        const int j_hi = (a.n_det > 1 || slab == 0x7fffffff || j_lo + slab >= n_seg) ? 0x7fffffff : j_lo + slab;
+        const int last = j_hi == 0x7fffffff ? 1 : 0;
+        for (int64_t first = 0; first < blocks; first += step) {
+            const int64_t n = blocks - first < step ? blocks - first : step;
+            hipLaunchKernelGGL((eval_kernel<STORE, MOMENTS, TPL, U>), dim3((unsigned)n), dim3(256), 0, st, a,
+                               (int)first, (int)blocks, j_lo, j_hi, last);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (last) break;
     }
     return hipSuccess;
 }
 
 template <int STORE, bool MOMENTS>
 static hipError_t launch_eval_m(int variant, const EvalArgs &a, int cu_count, hipStream_t st) {
-    const bool gen = (variant & 4) != 0;
+    const bool gen = (variant & 4) != 0, slabs = (variant & 8) != 0;
     switch (variant & 3) {
-        case 0: return launch_eval_v<STORE, MOMENTS, 1, 8>(a, gen, cu_count, st);
-        case 1: return launch_eval_v<STORE, MOMENTS, 1, 16>(a, gen, cu_count, st);
-        case 2: return launch_eval_v<STORE, MOMENTS, 2, 8>(a, gen, cu_count, st);
-        default: return launch_eval_v<STORE, MOMENTS, 2, 16>(a, gen, cu_count, st);
+        case 0: return launch_eval_v<STORE, MOMENTS, 1, 8>(a, gen, slabs, cu_count, st);
+        case 1: return launch_eval_v<STORE, MOMENTS, 1, 16>(a, gen, slabs, cu_count, st);
+        case 2: return launch_eval_v<STORE, MOMENTS, 2, 8>(a, gen, slabs, cu_count, st);
+        default: return launch_eval_v<STORE, MOMENTS, 2, 16>(a, gen, slabs, cu_count, st);
     }
 }
 
@@ -556,7 +589,8 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchArgs a) {
             const DetView D = uniform(Sp->det[d]);
             const HFromGD hs{D.g + (int64_t)tn * D.n_seg, D.D + (int64_t)sky * D.n_seg, D.t_sft};
             int jb, je;
-            seg_window(D, T.grp, T.tile * TPL, (T.tile + 1) * TPL, jb, je);
+            const int runs = D.win ? 64 * TPL / D.win_run : 1;  // the batch's windows are per 64 f0
+            seg_window(D, T.grp, T.tile * runs, (T.tile + 1) * runs, jb, je);
             accumulate_det<STORE, MOMENTS, TPL, U>(D, hs, f0, acc, jb, je);
         }
         store_results<MOMENTS, TPL>(acc, i, T.grp, n_f0, uniform(Sp->s), uniform(Sp->c), uniform(Sp->n),
@@ -643,10 +677,10 @@ __global__ __launch_bounds__(256) void doppler_kernel(const double *__restrict__
 }
 
 // In-band segment windows.  For a segment, the column index trunc(f0 h +
-// 1.5 - k_lo) is non-decreasing in f0, so a run of 64 consecutive f0 has a
-// lane in band exactly when its last f0 reaches column 1 and its first f0 is
-// at most column n_bins (the statistic kernel's arithmetic).  One wavefront
-// per (group, run): lanes stride over the segments, then min / max.
+// 1.5 - k_lo) is non-decreasing in f0, so a run of consecutive f0 has a lane
+// in band exactly when its last f0 reaches column 1 and its first f0 is at
+// most column n_bins (the statistic kernel's arithmetic).  One wavefront per
+// (group, run): lanes stride over the segments, then min / max.
 __global__ __launch_bounds__(256) void window_kernel(const DetView D, int n_groups, int n_tn, double f0_min,
                                                      double f0_step, int n_f0, int2 *__restrict__ win) {
     const int lane = threadIdx.x & 63;
@@ -654,8 +688,8 @@ __global__ __launch_bounds__(256) void window_kernel(const DetView D, int n_grou
     const int grp = blockIdx.x / per_group;
     const int blk = (blockIdx.x % per_group) * 4 + (threadIdx.x >> 6);
     if (blk >= D.win_blocks) return;
-    const int ia = blk * 64;
-    const int ib = min(ia + 63, n_f0 - 1);
+    const int ia = blk * D.win_run;
+    const int ib = min(ia + D.win_run - 1, n_f0 - 1);
     const double fa = f0_min + (double)ia * f0_step;
     const double fb = f0_min + (double)ib * f0_step;
     const int tn = grp % n_tn, sky = grp / n_tn;
