@@ -112,7 +112,8 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=8, eval_sign
     ctau = np.sqrt(tau[0::2] * tau[1::2])
     cbrake = np.array([(brake[0] + brake[1]) / 2, (brake[-2] + brake[-1]) / 2])
     coarse = coarse_grid_for(fine, ctau, cbrake)
-    pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=0.05, store="f32")
+    pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=0.05, store="f32", block=16,
+                  select2_frac=0.05)
     steps = max(1, realisations // batch)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -120,8 +121,10 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=8, eval_sign
                       label_psi=4.5)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t
-    ev = pr.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16")
-    untrained = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed + 1, select_frac=0.05, store="f32")
+    ev = pr.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
+                     coarse_quantiles=(1.0, 0.9, 0.7, 0.5, 0.3))
+    untrained = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed + 1, select_frac=0.05, store="f32",
+                         block=16, select2_frac=0.05)
     ev0 = untrained.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
                              reps=1)
     ctx.close()

@@ -404,6 +404,10 @@ typedef struct {
     const float *params;      /* network parameters (device)                      */
     int32_t c_in, c_out, L;   /* network shape                                    */
     int32_t n_select;         /* fine cells evaluated exactly per realisation     */
+    int32_t block;            /* cells are taken in blocks of this many
+                                 consecutive f0 of one fine group (1 .. 64)       */
+    int32_t n_select2;        /* second tier: further cells for the realisations
+                                 with no cell above psi_threshold (0: none)       */
     double psi_threshold;     /* detection threshold on Psi (largest noise value)  */
     double coarse_threshold;  /* fallback when the coarse map exceeds this but no
                                  selected cell passes psi_threshold               */
@@ -411,13 +415,17 @@ typedef struct {
 
 /* ltgw_propose: on the loaded stack, for every realisation: coarse critical
  * ratios on the coarse grid (channels = its (tau, n) groups, positions = its
- * f0) -> network logits over the fine cells -> the n_select best cells ->
- * exact fine critical ratios of those cells -> the best of them; realisations
- * that trip the fallback rule are evaluated exhaustively on the fine grid.
- * Cell (channel ch, position l) is fine template ((ch / 2) group, f0 index
- * 2 l + ch % 2): the fine grid has twice the coarse positions in f0 and
- * c_out / 2 (tau, n) groups.  Outputs (host, [R]): best template index and
- * Psi, fallback flag.  Synchronous. */
+ * f0) -> network logits over the fine cells -> blocks of `block` consecutive
+ * fine f0 of one group, scored by their largest logit -> the
+ * ceil(n_select / block) best blocks -> exact fine critical ratios of their
+ * templates -> the best.  Realisations with no template above psi_threshold
+ * then get the next ceil(n_select2 / block) blocks; those still below it
+ * whose largest coarse ratio exceeds coarse_threshold are evaluated
+ * exhaustively on the fine grid (the fallback).  Cell (channel ch, position
+ * l) is fine template ((ch / 2) group, f0 index 2 l + ch % 2): the fine grid
+ * has twice the coarse positions in f0 and c_out / 2 (tau, n) groups.
+ * Outputs (host, [R]): best template index and Psi (ties to the lower index),
+ * fallback flag.  Synchronous. */
 int32_t ltgw_propose(ltgw_ctx *ctx, const ltgw_grid *fine, const ltgw_grid *coarse,
                      const ltgw_proposer *p, int32_t *best_index, double *best_psi, int32_t *fallback);
 

@@ -99,6 +99,7 @@ struct StackState {
     StackLevel lv[2];
     hipEvent_t ev_h2d = nullptr;  // after the last grid upload
     DevBuf psi_c, x, act, logits, cells, tpl, psi_sel, best_idx, best_psi, fb, rmap, idx_all, psi_all;
+    DevBuf bscore, blk, blk2, tpl2, psi2, cm_idx, cm;
 };
 
 }  // namespace ltgw

@@ -125,6 +125,11 @@ hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_b
                             const int32_t *idx, int m, const int32_t *rmap, double *out_psi, hipStream_t st);
 hipError_t launch_cells_to_templates(const int32_t *cells, int64_t n, int L, int32_t *tpl, hipStream_t st);
 hipError_t launch_sort_rows(int32_t *idx, int rows, int m, hipStream_t st);
+hipError_t launch_block_scores(const float *logits, int R, int c_out, int L, int W, int nbg, float *score,
+                               hipStream_t st);
+hipError_t launch_mask_blocks(float *score, const int32_t *blk, int R, int K, int nb, hipStream_t st);
+hipError_t launch_expand_blocks(const int32_t *blk, int K, int W, int two_L, int nbg, const int32_t *rmap, int rows,
+                                int32_t *tpl, hipStream_t st);
 hipError_t launch_fallback(int R, const double *psi_coarse, int nc, const double *best_psi, double thr,
                            double cthr, int32_t *fallback, hipStream_t st);
 hipError_t launch_iota_rows(int32_t *idx, int rows, int n, hipStream_t st);

@@ -926,6 +926,76 @@ hipError_t launch_cells_to_templates(const int32_t *cells, int64_t n, int L, int
     return hipGetLastError();
 }
 
+// Proposal blocks: runs of W consecutive fine f0 of one fine group (block k
+// of group g covers f0 indices [k W, k W + W) of the 2 L).  The score of a
+// block is the largest network logit of its cells (cell of fine (g, i):
+// (2 g + i % 2) L + i / 2).  One thread per (realisation, block).
+__global__ void block_scores_kernel(const float *logits, int64_t total, int c_out, int L, int W, int nbg,
+                                    float *score) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int G = c_out / 2;
+    const int64_t r = e / ((int64_t)G * nbg);
+    const int rem = (int)(e % ((int64_t)G * nbg));
+    const int g = rem / nbg, k = rem % nbg;
+    const float *z = logits + r * (int64_t)c_out * L;
+    float m = -__builtin_inff();
+    for (int j = 0; j < W; ++j) {
+        const int i = k * W + j;
+        if (i >= 2 * L) break;
+        const float v = z[(2 * g + (i & 1)) * L + (i >> 1)];
+        m = v > m ? v : m;
+    }
+    score[e] = m;
+}
+
+hipError_t launch_block_scores(const float *logits, int R, int c_out, int L, int W, int nbg, float *score,
+                               hipStream_t st) {
+    const int64_t total = (int64_t)R * (c_out / 2) * nbg;
+    hipLaunchKernelGGL(block_scores_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, logits, total,
+                       c_out, L, W, nbg, score);
+    return hipGetLastError();
+}
+
+// Scores of the blocks already taken (blk[r][0..K)) become NaN, which ranks last.
+__global__ void mask_blocks_kernel(float *score, const int32_t *blk, int64_t total, int K, int nb) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int64_t r = e / K;
+    const int b = blk[e];
+    if (b >= 0 && b < nb) score[r * nb + b] = __builtin_nanf("");
+}
+
+hipError_t launch_mask_blocks(float *score, const int32_t *blk, int R, int K, int nb, hipStream_t st) {
+    const int64_t total = (int64_t)R * K;
+    hipLaunchKernelGGL(mask_blocks_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, score, blk, total,
+                       K, nb);
+    return hipGetLastError();
+}
+
+// Templates of the selected blocks: row q (realisation rmap[q], or q)
+// lists blk[r][0..K) expanded to W consecutive f0 each (-1 past the grid).
+__global__ void expand_blocks_kernel(const int32_t *blk, int K, int W, int two_L, int nbg, const int32_t *rmap,
+                                     int64_t total, int32_t *tpl) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int64_t row = e / ((int64_t)K * W);
+    const int rem = (int)(e % ((int64_t)K * W));
+    const int q = rem / W, j = rem % W;
+    const int64_t r = rmap ? rmap[row] : row;
+    const int b = blk[r * K + q];
+    const int g = b / nbg, i = (b % nbg) * W + j;
+    tpl[e] = (b >= 0 && i < two_L) ? g * two_L + i : -1;
+}
+
+hipError_t launch_expand_blocks(const int32_t *blk, int K, int W, int two_L, int nbg, const int32_t *rmap, int rows,
+                                int32_t *tpl, hipStream_t st) {
+    const int64_t total = (int64_t)rows * K * W;
+    hipLaunchKernelGGL(expand_blocks_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, blk, K, W,
+                       two_L, nbg, rmap, total, tpl);
+    return hipGetLastError();
+}
+
 // Each row of m template indices into ascending order (bitonic sort in LDS,
 // one workgroup per row): neighbouring lanes of the listed evaluation then
 // take neighbouring f0 wherever the selection is contiguous, so their gathers

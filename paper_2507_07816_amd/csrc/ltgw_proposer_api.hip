@@ -19,7 +19,8 @@ void free_stack(StackState &S) {
     DevBuf *all[] = {&S.fine,   &S.crs,      &S.w,        &S.wq,    &S.scale,  &S.w2,     &S.t,
                      &S.v,      &S.t2,       &S.v2,       &S.params, &S.psi_c, &S.x,      &S.act,
                      &S.logits, &S.cells,    &S.tpl,      &S.psi_sel, &S.best_idx, &S.best_psi, &S.fb,
-                     &S.rmap,   &S.idx_all,  &S.psi_all};
+                     &S.rmap,   &S.idx_all,  &S.psi_all, &S.bscore, &S.blk, &S.blk2, &S.tpl2, &S.psi2,
+                     &S.cm_idx, &S.cm};
     for (DevBuf *b : all) release(*b);
     for (StackLevel &L : S.lv) {
         release(L.tau);
@@ -492,52 +493,105 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
         return fail(c, LTGW_E_INVALID_ARG, "network channels must be (coarse groups, 2 x fine groups) = (%lld, %lld)",
                     (long long)g_c, (long long)(2 * g_f));
     if ((rc = cnn_shape_ok(c, R, p->c_in, p->c_out, L)) != LTGW_OK) return rc;
-    const int64_t n_cells = (int64_t)p->c_out * L;
-    const int M = p->n_select;
-    if (n_cells > 8192 || M < 1 || M > n_cells)
-        return fail(c, LTGW_E_INVALID_ARG, "need 1 <= n_select <= c_out L <= 8192");
+    const int W = p->block;
+    if (W < 1 || W > 64) return fail(c, LTGW_E_INVALID_ARG, "block must be in 1 .. 64");
+    const int nbg = (2 * L + W - 1) / W;          // blocks per fine group
+    const int64_t nb = g_f * nbg;                  // blocks per realisation
+    const int K1 = (p->n_select + W - 1) / W, K2 = p->n_select2 > 0 ? (p->n_select2 + W - 1) / W : 0;
+    if (nb > 8192 || p->n_select < 1 || p->n_select2 < 0 || K1 + K2 > nb)
+        return fail(c, LTGW_E_INVALID_ARG, "need 1 <= n_select, 0 <= n_select2, blocks of both <= %lld <= 8192",
+                    (long long)nb);
     if (!fin(p->psi_threshold) || !fin(p->coarse_threshold))
         return fail(c, LTGW_E_INVALID_ARG, "thresholds must be finite");
-    const int64_t nc = g_c * L;
-    if ((rc = ensure(c, S.psi_c, (size_t)(R * nc) * 8, "coarse ratios")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.x, (size_t)(R * nc) * 4, "network input")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.act, (size_t)R * 3 * 32 * L * 4, "activations")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.logits, (size_t)(R * n_cells) * 4, "logits")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.cells, (size_t)R * M * 4, "selected cells")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.tpl, (size_t)R * M * 4, "selected templates")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.psi_sel, (size_t)R * M * 8, "selected ratios")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.best_idx, (size_t)R * 4, "best index")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.best_psi, (size_t)R * 8, "best ratio")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.fb, (size_t)R * 4, "fallback flags")) != LTGW_OK) return rc;
-    // coarse map -> network -> the n_select best cells -> exact fine ratios of those
+    const int64_t nc = g_c * L, n_cells = (int64_t)p->c_out * L;
+    const int M1 = K1 * W, M2 = K2 * W;
+    struct {
+        DevBuf *b;
+        size_t bytes;
+    } need[] = {{&S.psi_c, (size_t)(R * nc) * 8},       {&S.x, (size_t)(R * nc) * 4},
+                {&S.act, (size_t)R * 3 * 32 * L * 4},    {&S.logits, (size_t)(R * n_cells) * 4},
+                {&S.bscore, (size_t)(R * nb) * 4},       {&S.blk, (size_t)R * K1 * 4},
+                {&S.tpl, (size_t)R * M1 * 4},            {&S.psi_sel, (size_t)R * M1 * 8},
+                {&S.best_idx, (size_t)R * 4},            {&S.best_psi, (size_t)R * 8},
+                {&S.cm_idx, (size_t)R * 4},              {&S.cm, (size_t)R * 8}};
+    for (auto &n : need)
+        if ((rc = ensure(c, *n.b, n.bytes, "proposer buffers")) != LTGW_OK) return rc;
+    // 1. coarse map -> network -> block scores -> the K1 best blocks -> their exact fine ratios
     if ((rc = stack_psi_impl(c, coarse, 1, 1, (double *)S.psi_c.p)) != LTGW_OK) return rc;
     HIP_TRY(c, launch_f64_to_f32((const double *)S.psi_c.p, (float *)S.x.p, R * nc, c->stream), "input convert");
     HIP_TRY(c, launch_cnn_forward(p->params, (const float *)S.x.p, R, p->c_in, p->c_out, L, (float *)S.act.p,
                                   (float *)S.logits.p, c->stream),
             "network forward");
-    HIP_TRY(c, launch_select_top((const float *)S.logits.p, R, (int)n_cells, M, (int32_t *)S.cells.p, c->stream),
+    HIP_TRY(c, launch_block_scores((const float *)S.logits.p, R, p->c_out, L, W, nbg, (float *)S.bscore.p, c->stream),
+            "block score launch");
+    HIP_TRY(c, launch_select_top((const float *)S.bscore.p, R, (int)nb, K1, (int32_t *)S.blk.p, c->stream),
             "selection launch");
-    HIP_TRY(c, launch_cells_to_templates((const int32_t *)S.cells.p, (int64_t)R * M, L, (int32_t *)S.tpl.p,
-                                         c->stream),
-            "cell mapping launch");
-    HIP_TRY(c, launch_sort_rows((int32_t *)S.tpl.p, R, M, c->stream), "template sort launch");
+    HIP_TRY(c, launch_expand_blocks((const int32_t *)S.blk.p, K1, W, 2 * L, nbg, nullptr, R, (int32_t *)S.tpl.p,
+                                    c->stream),
+            "block expansion launch");
     SearchPlan P;
-    if ((rc = list_psi_impl(c, fine, (const int32_t *)S.tpl.p, R, M, nullptr, (double *)S.psi_sel.p, &P)) != LTGW_OK)
+    if ((rc = list_psi_impl(c, fine, (const int32_t *)S.tpl.p, R, M1, nullptr, (double *)S.psi_sel.p, &P)) != LTGW_OK)
         return rc;
-    HIP_TRY(c, launch_row_best((const double *)S.psi_sel.p, R, M, (const int32_t *)S.tpl.p, (int32_t *)S.best_idx.p,
+    HIP_TRY(c, launch_row_best((const double *)S.psi_sel.p, R, M1, (const int32_t *)S.tpl.p, (int32_t *)S.best_idx.p,
                                (double *)S.best_psi.p, c->stream),
             "reduction launch");
-    HIP_TRY(c, launch_fallback(R, (const double *)S.psi_c.p, (int)nc, (const double *)S.best_psi.p, p->psi_threshold,
-                               p->coarse_threshold, (int32_t *)S.fb.p, c->stream),
-            "fallback launch");
+    HIP_TRY(c, launch_row_best((const double *)S.psi_c.p, R, nc, nullptr, (int32_t *)S.cm_idx.p, (double *)S.cm.p,
+                               c->stream),
+            "coarse maximum launch");
+    std::vector<double> cm((size_t)R);
     HIP_TRY(c, hipMemcpyAsync(best_index, S.best_idx.p, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipMemcpyAsync(best_psi, S.best_psi.p, (size_t)R * 8, hipMemcpyDeviceToHost, c->stream), "copy");
-    HIP_TRY(c, hipMemcpyAsync(fallback, S.fb.p, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");
+    HIP_TRY(c, hipMemcpyAsync(cm.data(), S.cm.p, (size_t)R * 8, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "propose");
-    // exhaustive fine evaluation of the realisations that tripped the fallback
+    const double thr = p->psi_threshold;
+    // merge a later result into the best so far (larger ratio; ties to the lower index)
+    auto merge = [&](int r, int32_t i, double v) {
+        if (i < 0 || !(v == v)) return;
+        if (best_index[r] < 0 || v > best_psi[r] || (v == best_psi[r] && i < best_index[r])) {
+            best_index[r] = i;
+            best_psi[r] = v;
+        }
+    };
+    // 2. realisations with no cell above the threshold: the next K2 blocks
     std::vector<int32_t> rows;
     for (int r = 0; r < R; ++r)
+        if (!(best_psi[r] > thr)) rows.push_back(r);
+    if (K2 > 0 && !rows.empty()) {
+        const int n2 = (int)rows.size();
+        struct {
+            DevBuf *b;
+            size_t bytes;
+        } need2[] = {{&S.blk2, (size_t)R * K2 * 4}, {&S.tpl2, (size_t)n2 * M2 * 4}, {&S.psi2, (size_t)n2 * M2 * 8},
+                     {&S.rmap, (size_t)n2 * 4}};
+        for (auto &n : need2)
+            if ((rc = ensure(c, *n.b, n.bytes, "proposer buffers")) != LTGW_OK) return rc;
+        if ((rc = h2d(c, S.rmap.p, rows.data(), (size_t)n2 * 4, "row upload")) != LTGW_OK) return rc;
+        HIP_TRY(c, launch_mask_blocks((float *)S.bscore.p, (const int32_t *)S.blk.p, R, K1, (int)nb, c->stream),
+                "block mask launch");
+        HIP_TRY(c, launch_select_top((const float *)S.bscore.p, R, (int)nb, K2, (int32_t *)S.blk2.p, c->stream),
+                "selection launch");
+        HIP_TRY(c, launch_expand_blocks((const int32_t *)S.blk2.p, K2, W, 2 * L, nbg, (const int32_t *)S.rmap.p, n2,
+                                        (int32_t *)S.tpl2.p, c->stream),
+                "block expansion launch");
+        if ((rc = list_psi_impl(c, fine, (const int32_t *)S.tpl2.p, n2, M2, (const int32_t *)S.rmap.p,
+                                (double *)S.psi2.p, nullptr)) != LTGW_OK)
+            return rc;
+        HIP_TRY(c, launch_row_best((const double *)S.psi2.p, n2, M2, (const int32_t *)S.tpl2.p,
+                                   (int32_t *)S.best_idx.p, (double *)S.best_psi.p, c->stream),
+                "reduction launch");
+        std::vector<int32_t> bi((size_t)n2);
+        std::vector<double> bp((size_t)n2);
+        HIP_TRY(c, hipMemcpyAsync(bi.data(), S.best_idx.p, (size_t)n2 * 4, hipMemcpyDeviceToHost, c->stream), "copy");
+        HIP_TRY(c, hipMemcpyAsync(bp.data(), S.best_psi.p, (size_t)n2 * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+        HIP_TRY(c, hipStreamSynchronize(c->stream), "propose second tier");
+        for (int q = 0; q < n2; ++q) merge(rows[(size_t)q], bi[(size_t)q], bp[(size_t)q]);
+    }
+    // 3. the fallback rule: a loud coarse map and still no cell above the threshold
+    rows.clear();
+    for (int r = 0; r < R; ++r) {
+        fallback[r] = (cm[(size_t)r] > p->coarse_threshold && !(best_psi[r] > thr)) ? 1 : 0;
         if (fallback[r]) rows.push_back(r);
+    }
     if (rows.empty()) return LTGW_OK;
     const int nf = (int)rows.size();
     const int64_t n_tpl = P.n_tpl;
@@ -560,9 +614,9 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
     HIP_TRY(c, hipMemcpyAsync(bi.data(), S.best_idx.p, (size_t)nf * 4, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipMemcpyAsync(bp.data(), S.best_psi.p, (size_t)nf * 8, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "propose fallback");
-    for (int q = 0; q < nf; ++q) {
-        best_index[rows[q]] = bi[(size_t)q];
-        best_psi[rows[q]] = bp[(size_t)q];
+    for (int q = 0; q < nf; ++q) {  // the exhaustive best of the realisation
+        best_index[rows[(size_t)q]] = bi[(size_t)q];
+        best_psi[rows[(size_t)q]] = bp[(size_t)q];
     }
     return LTGW_OK;
 }

@@ -88,8 +88,8 @@ class ltgw_batch_stats(C.Structure):
 
 class ltgw_proposer(C.Structure):
     _fields_ = [("params", C.c_void_p), ("c_in", C.c_int32), ("c_out", C.c_int32), ("L", C.c_int32),
-                ("n_select", C.c_int32), ("psi_threshold", C.c_double),
-                ("coarse_threshold", C.c_double)]
+                ("n_select", C.c_int32), ("block", C.c_int32), ("n_select2", C.c_int32),
+                ("psi_threshold", C.c_double), ("coarse_threshold", C.c_double)]
 
 
 class LtgwError(RuntimeError):
@@ -441,11 +441,12 @@ def ltgw_select_top(ctx, score, M, out_idx):
                                           _dev(out_idx, torch.int32)))
 
 
-def ltgw_propose(ctx, fine, coarse, params, c_in, c_out, L, n_select, psi_threshold, coarse_threshold, R):
+def ltgw_propose(ctx, fine, coarse, params, c_in, c_out, L, n_select, psi_threshold, coarse_threshold, R,
+                 block=1, n_select2=0):
     """(best_index[R], best_psi[R], fallback[R]) numpy arrays."""
     import torch
-    p = ltgw_proposer(_dev(params, torch.float32), int(c_in), int(c_out), int(L), int(n_select),
-                      float(psi_threshold), float(coarse_threshold))
+    p = ltgw_proposer(_dev(params, torch.float32), int(c_in), int(c_out), int(L), int(n_select), int(block),
+                      int(n_select2), float(psi_threshold), float(coarse_threshold))
     bi = np.empty(R, np.int32)
     bp = np.empty(R, np.float64)
     fb = np.empty(R, np.int32)

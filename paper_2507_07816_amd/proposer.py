@@ -60,7 +60,8 @@ class Proposer:
     """Training and inference state on one ltgw.Context whose detector slot
     `det` holds the geometry (segment times, weights, velocities)."""
 
-    def __init__(self, ctx, det, shape, fine, coarse, seed=0, select_frac=0.05, store="f32"):
+    def __init__(self, ctx, det, shape, fine, coarse, seed=0, select_frac=0.05, store="f32", block=1,
+                 select2_frac=0.0):
         import torch
 
         if fine["n_f0"] % 2:
@@ -75,6 +76,8 @@ class Proposer:
         self.c_out = 2 * _n_groups(fine)
         self.n_cells = self.c_out * self.L
         self.n_select = max(1, int(round(select_frac * self.n_cells)))
+        self.n_select2 = int(round(select2_frac * self.n_cells))
+        self.block = int(block)
         self.store = store
         self.seed = seed
         self.rng = np.random.Generator(np.random.PCG64(seed))
@@ -187,7 +190,8 @@ class Proposer:
     def propose(self, psi_threshold, coarse_threshold, R):
         """ltgw_propose on the loaded stack: (best_index, best_psi, fallback)."""
         return ltgw.ltgw_propose(self.ctx.h, self._fg, self._cg, self.params, self.c_in, self.c_out, self.L,
-                                 self.n_select, psi_threshold, coarse_threshold, R)
+                                 self.n_select, psi_threshold, coarse_threshold, R, block=self.block,
+                                 n_select2=self.n_select2)
 
     def exhaustive(self, R):
         """Exhaustive fine search of the loaded stack: host (best_index, best_psi)."""
@@ -196,20 +200,23 @@ class Proposer:
         return b["best"].cpu().numpy().copy(), b["best_psi"].cpu().numpy().copy()
 
     def evaluate(self, R_noise=256, R_signal=256, amp_range=(1.0, 3.0), fine_store="bf16", reps=3,
-                 coarse_quantile=1.0):
+                 coarse_quantiles=(1.0,), target_recall=0.99):
         """Recall and speed against the exhaustive search.
 
         Thresholds: psi_threshold is the largest exhaustive fine ratio over
-        R_noise noise-only realisations (the detection rule of Sec. 3);
-        coarse_threshold is the coarse_quantile quantile of the largest coarse
-        ratio of each noise realisation (1.0: their maximum).  On R_signal
-        realisations with injections, an injection is detectable when the
-        exhaustive FP32 search passes psi_threshold, and recalled when the
-        proposer (coarse BF16 map, network, n_select exact cells on the
-        `fine_store` store, fallback) passes it too; recall_no_fallback is the
-        same with the fallback switched off.  Times: exhaustive FP32 search
-        (ltgw_stack_best) and ltgw_propose on the same realisations, HIP
-        events on the context's stream, best of `reps`."""
+        R_noise noise-only realisations (the detection rule of Sec. 3); for
+        each q in coarse_quantiles the fallback's coarse threshold is the q
+        quantile of the largest coarse ratio of each noise realisation (1.0:
+        their maximum).  On R_signal realisations with injections, an
+        injection is detectable when the exhaustive FP32 search passes
+        psi_threshold, and recalled when the proposer (coarse BF16 map,
+        network, n_select exact cells on the `fine_store` store, fallback)
+        passes it too; recall_no_fallback is the same with the fallback off.
+        Times: exhaustive FP32 search (ltgw_stack_best) and ltgw_propose on
+        the same realisations, HIP events on the context's stream, best of
+        `reps`.  The operating point reported at the top level is the fastest
+        quantile whose recall reaches target_recall, else the best recall;
+        every quantile's figures are under "points"."""
         T = self.torch
         h = self.ctx.h
         zeros = np.zeros((R_noise, 4))
@@ -217,7 +224,6 @@ class Proposer:
         _, noise_best = self.exhaustive(R_noise)
         psi_thr = float(np.max(noise_best))
         coarse_max = b["x"].cpu().numpy().reshape(R_noise, -1).max(axis=1)
-        coarse_thr = float(np.quantile(coarse_max, coarse_quantile))
         inj, sig = self.draw_injections(R_signal, 1.0, amp_range)
         b = self.make_batch(R_signal, 3, 0, inj, with_labels=False)
         ev0, ev1 = T.cuda.Event(enable_timing=True), T.cuda.Event(enable_timing=True)
@@ -232,22 +238,31 @@ class Proposer:
         ex_idx = b["best"].cpu().numpy().copy()
         ex_psi = b["best_psi"].cpu().numpy().copy()
         ltgw.ltgw_load_stack(h, self.det, b["stack"], fine_store, coarse=True)
-        t_pr = []
-        for _ in range(reps):
-            ev0.record()
-            pi, pp, fb = self.propose(psi_thr, coarse_thr, R_signal)
-            ev1.record()
-            ev1.synchronize()
-            t_pr.append(ev0.elapsed_time(ev1))
-        _, pp_nf, _ = self.propose(psi_thr, 1e300, R_signal)      # fallback never taken
         det_ex = ex_psi > psi_thr
         n_det = int(det_ex.sum())
         rec = lambda p: float((det_ex & (p > psi_thr)).sum() / n_det) if n_det else float("nan")
-        same = float((pi[det_ex] == ex_idx[det_ex]).mean()) if n_det else float("nan")
+        _, pp_nf, _ = self.propose(psi_thr, 1e300, R_signal)      # fallback never taken
+        points = []
+        for q in coarse_quantiles:
+            coarse_thr = float(np.quantile(coarse_max, q))
+            t_pr = []
+            for _ in range(reps):
+                ev0.record()
+                pi, pp, fb = self.propose(psi_thr, coarse_thr, R_signal)
+                ev1.record()
+                ev1.synchronize()
+                t_pr.append(ev0.elapsed_time(ev1))
+            points.append(dict(coarse_quantile=q, coarse_threshold=coarse_thr, recall=rec(pp),
+                               fallback_frac=float(fb.mean()), propose_ms=min(t_pr),
+                               speedup=min(t_ex) / min(t_pr),
+                               same_template=float((pi[det_ex] == ex_idx[det_ex]).mean()) if n_det else float("nan")))
+        ok = [p for p in points if p["recall"] >= target_recall]
+        best = max(ok, key=lambda p: p["speedup"]) if ok else max(points, key=lambda p: (p["recall"], p["speedup"]))
         amp = inj[:, 3]
-        return dict(recall=rec(pp), recall_no_fallback=rec(pp_nf), detectable=n_det, realisations=R_signal,
-                    detectable_min_amp=float(amp[det_ex].min()) if n_det else float("nan"),
-                    same_template=same, fallback_frac=float(fb.mean()), psi_threshold=psi_thr,
-                    coarse_threshold=coarse_thr, coarse_quantile=coarse_quantile,
-                    exhaustive_ms=min(t_ex), propose_ms=min(t_pr), speedup=min(t_ex) / min(t_pr),
-                    n_select=self.n_select, n_cells=self.n_cells, fine_store=fine_store)
+        out = dict(best)
+        out.update(recall_no_fallback=rec(pp_nf), detectable=n_det, realisations=R_signal,
+                   detectable_min_amp=float(amp[det_ex].min()) if n_det else float("nan"),
+                   psi_threshold=psi_thr, exhaustive_ms=min(t_ex), n_select=self.n_select,
+                   n_select2=self.n_select2, block=self.block, n_cells=self.n_cells,
+                   fine_store=fine_store, target_recall=target_recall, points=points)
+        return out

@@ -335,6 +335,18 @@ def test_propose_all_cells_finds_the_exhaustive_best():
     bi2, bp2, fb2 = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, 4, 1e9, -1e9, R)
     assert np.all(fb2 == 1)
     assert np.array_equal(bi2, bi) and np.array_equal(bp2, bp)
+    # blocks of 16 f0 (the last of each group ragged: 48 = 3 x 16 is not, so use 20):
+    # all blocks at once, or half of them and the other half as the second tier
+    # (no cell passes the threshold, so every realisation takes it), cover the grid
+    for W in (16, 20):
+        nb = 4 * ((2 * L + W - 1) // W)
+        print(f"case: propose blocks of {W}", flush=True)
+        bi3, bp3, fb3 = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, nb * W, 1e9, 1e9, R, block=W)
+        assert np.all(fb3 == 0) and np.array_equal(bi3, bi) and np.array_equal(bp3, bp)
+        h = nb // 2
+        bi4, bp4, fb4 = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, h * W, 1e9, 1e9, R, block=W,
+                                          n_select2=(nb - h) * W)
+        assert np.all(fb4 == 0) and np.array_equal(bi4, bi) and np.array_equal(bp4, bp)
     ctx.close()
 
 
