@@ -32,8 +32,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
 
 
-KERNEL_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_kernels.hip", "paper_2507_07816_amd/csrc/ddpow.h",
-                  "paper_2507_07816_amd/csrc/ltgw_internal.h")
+# the statistic kernel's code: a change to any of these voids the committed counters
+KERNEL_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_kernels.hip", "paper_2507_07816_amd/csrc/ltgw_gather.h",
+                  "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_internal.h")
 
 
 def kernel_source_hash():
