@@ -1,0 +1,49 @@
+// Internal interface of the learned proposer's kernels (ltgw_stack.hip,
+// ltgw_proposer.hip) for its C-ABI layer (ltgw_proposer_api.hip).  Not part
+// of the public boundary.
+#pragma once
+#include "ltgw_internal.h"
+
+namespace ltgw {
+
+hipError_t launch_stack_eval(int store, int shift, const EvalArgs &a, int R, int64_t stack_bytes,
+                             int64_t stack_rows, double mu, double var, int nan_to_zero,
+                             double *out_psi, int32_t *out_c, hipStream_t st);
+hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,
+                            const int32_t *idx, int m, const int32_t *rmap, double *out_psi, hipStream_t st);
+hipError_t launch_cells_to_templates(const int32_t *cells, int64_t n, int L, int32_t *tpl, hipStream_t st);
+hipError_t launch_sort_rows(int32_t *idx, int rows, int m, hipStream_t st);
+hipError_t launch_block_scores(const float *logits, int R, int c_out, int L, int W, int nbg, float *score,
+                               hipStream_t st);
+hipError_t launch_mask_blocks(float *score, const int32_t *blk, int R, int K, int nb, hipStream_t st);
+hipError_t launch_expand_blocks(const int32_t *blk, int K, int W, int two_L, int nbg, const int32_t *rmap, int rows,
+                                int32_t *tpl, hipStream_t st);
+hipError_t launch_fallback(int R, const double *psi_coarse, int nc, const double *best_psi, double thr,
+                           double cthr, int32_t *fallback, hipStream_t st);
+hipError_t launch_iota_rows(int32_t *idx, int rows, int n, hipStream_t st);
+hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t *idx, int32_t *best_idx,
+                           double *best_psi, hipStream_t st);
+hipError_t launch_templates_to_cells(const int32_t *tpl, int n, int L, const int32_t *mask, const double *psi,
+                                     double min_psi, int32_t *cells, hipStream_t st);
+hipError_t launch_noise(uint64_t seed, uint32_t stream, int r0, int R, int64_t n_per, float *out,
+                        hipStream_t st);
+hipError_t launch_inject_stack(float *power, int R, int32_t n_seg, int32_t n_bins, int64_t k_lo,
+                               double t_sft, const double *t_seg, const double *v, const float *w,
+                               const double *params, double sx, double sy, double sz, double t0,
+                               unsigned long long *undecided, hipStream_t st);
+hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins, int64_t pitch2,
+                          unsigned short *out, hipStream_t st);
+hipError_t launch_cnn_forward(const float *params, const float *x, int B, int c_in, int c_out, int L,
+                              float *act /* [3][B][32][L] */, float *logits, hipStream_t st);
+hipError_t launch_cnn_backward(const float *params, const float *x, int B, int c_in, int c_out, int L,
+                               const float *act, const float *dlogits, float *work, int64_t work_floats,
+                               float *grads, hipStream_t st);
+int64_t cnn_work_floats(int B, int c_in, int c_out, int L);
+int64_t cnn_n_params(int c_in, int c_out);
+hipError_t launch_softmax_xent(const float *logits, int B, int n_cells, const int32_t *target,
+                               int n_valid, float *loss, float *dlogits, hipStream_t st);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t st);
+hipError_t launch_select_top(const float *score, int R, int n, int M, int32_t *out_idx, hipStream_t st);
+
+}  // namespace ltgw

@@ -2,7 +2,7 @@
 // Exp(1) noise, injected tracks), the 2x2-coarsened BF16 store of the coarse
 // pass, the ranking network (BF16 MFMA, FP32 accumulation) with its backward
 // pass, loss and Adam, and the per-row top-M selection of fine cells.
-#include "ltgw_internal.h"
+#include "ltgw_proposer.h"
 #include "ddpow.h"
 
 #pragma clang fp contract(off)

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "ltgw_ctx.h"
+#include "ltgw_proposer.h"
 
 using namespace ltgw;
 

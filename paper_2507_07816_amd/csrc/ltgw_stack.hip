@@ -3,6 +3,7 @@
 // the selection of proposal blocks, per-row best entries and the fallback
 // rule.  They use the statistic's gather and accumulation (ltgw_gather.h).
 #include "ltgw_gather.h"
+#include "ltgw_proposer.h"
 
 #pragma clang fp contract(off)
 
