@@ -92,7 +92,8 @@ def cpu_baseline(wl, rho, target_s=15.0):
                       f"({idx.size * n_seg:.3g} evals, {dt:.1f} s, FP64, incl. its Eq. 1 table)"}
 
 
-def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=8, eval_signal=2048, eval_noise=1024, seed=7):
+def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=8, eval_signal=2048, eval_noise=1024, seed=7,
+                 coarse_segments=2, select2_frac=0.05, block=16):
     """The learned proposer on the small workload's shape (1024 segments x 800
     bins, 4800 fine templates): trained on `realisations` device-generated
     noise + injection realisations (amplitudes U[0.3, 3]), then recall and
@@ -113,8 +114,8 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=8, eval_sign
     ctau = np.sqrt(tau[0::2] * tau[1::2])
     cbrake = np.array([(brake[0] + brake[1]) / 2, (brake[-2] + brake[-1]) / 2])
     coarse = coarse_grid_for(fine, ctau, cbrake)
-    pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=0.05, store="f32", block=16,
-                  select2_frac=0.05)
+    pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=0.05, store="f32", block=block,
+                  select2_frac=select2_frac, coarse_segments=coarse_segments)
     steps = max(1, realisations // batch)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -125,7 +126,7 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=8, eval_sign
     ev = pr.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
                      coarse_quantiles=(1.0, 0.9, 0.7, 0.5, 0.3))
     untrained = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed + 1, select_frac=0.05, store="f32",
-                         block=16, select2_frac=0.05)
+                         block=block, select2_frac=select2_frac, coarse_segments=coarse_segments)
     ev0 = untrained.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
                              reps=1)
     ctx.close()

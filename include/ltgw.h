@@ -333,17 +333,19 @@ int32_t ltgw_inject_stack(ltgw_ctx *ctx, int32_t det, float *stack, int32_t R, c
 /* ltgw_load_stack: R realisations of detector slot det's geometry (its
  * segment times, weights and velocity table are used for all): a fine store
  * of format `store` from the device FP32 stack [R][n_seg][n_bins], and with
- * coarse != 0 a 2x2-coarsened BF16 store (sums over pairs of segments and of
- * bins; n_seg and n_bins must be even).  The stack data must be finite and
- * >= 0.  Synchronous.  Errors: STATE (slot not loaded), INVALID_ARG, NOMEM. */
+ * coarse = S (2 or 4; 1 means 2) a coarsened BF16 store: sums over groups of
+ * S consecutive segments and pairs of bins (n_seg a multiple of S, n_bins
+ * even); a group's weight is the mean of its S weights.  coarse = 0: none.
+ * The stack data must be finite and >= 0.  Synchronous.  Errors: STATE (slot
+ * not loaded), INVALID_ARG, NOMEM. */
 int32_t ltgw_load_stack(ltgw_ctx *ctx, int32_t det, int32_t R, const float *stack, int32_t store,
                         int32_t coarse);
 
 /* ltgw_stack_psi: power critical ratio of every template of grid g on every
  * realisation of the loaded stack into the device array out_psi[R][n_templates].
  * level 0: fine store (Exp(1) pixels: mean 1, variance 1); level 1: coarse
- * store, the track's column halved at the first segment of each pair (pixels
- * are sums of 4 Exp(1): mean 4, variance 4).  N = 0 gives NaN, or 0 with
+ * store, the track's column halved at the first segment of each group
+ * (pixels are sums of 2 S Exp(1): mean 2 S, variance 2 S).  N = 0 gives NaN, or 0 with
  * nan_to_zero.  Asynchronous.  Errors: STATE (no stack / no coarse store). */
 int32_t ltgw_stack_psi(ltgw_ctx *ctx, const ltgw_grid *g, int32_t level, int32_t nan_to_zero,
                        double *out_psi);

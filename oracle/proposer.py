@@ -1,15 +1,16 @@
 """Reference definitions of the learned proposer's data path (test
 infrastructure only: the product never imports this module).
 
-- coarse_power: the 2x2-coarsened map.  Pixel (j', m) is the FP32 sum
-  (P[2j'][2m] + P[2j'][2m+1]) + (P[2j'+1][2m] + P[2j'+1][2m+1]), rounded to
-  bfloat16; under noise alone it is a sum of four Exp(1) values (mean 4,
-  variance 4).
+- coarse_power: the coarsened map over S consecutive segments and 2 bins
+  (S = 2 by default).  Pixel (j', m) is the FP32 sum, segment by segment in
+  order, of the segments' bin-pair sums P[S j' + s][2m] + P[S j' + s][2m+1],
+  rounded to bfloat16; under noise alone it is a sum of 2 S Exp(1) values
+  (mean 2 S, variance 2 S).
 - coarse_psi: the power critical ratio (Eq. 4 with that mean and variance)
-  of a template on the coarse map.  The template's column in segment pair
-  j' is its fine column (Eqs. 1-2 and the bin rule of Sec. 2) at the pair's
-  first segment, halved (floor); the pair's weight is the FP32 mean of its
-  two segments' weights.
+  of a template on the coarse map.  The template's column in segment group
+  j' is its fine column (Eqs. 1-2 and the bin rule of Sec. 2) at the group's
+  first segment, halved (floor); the group's weight is the FP32 sum of its S
+  weights (in order) times 1/S.
 - cells and templates: network output cell (channel ch, position l) is fine
   template (group ch // 2, f0 index 2 l + ch % 2).
 - best_template: the largest Psi of a list (ties: lowest template index),
@@ -20,32 +21,37 @@ import numpy as np
 import oracle
 
 
-def coarse_power(P):
-    """P: FP32 [n_seg][n_bins] (both even) -> FP64 values of the BF16 coarse map."""
+def coarse_power(P, S=2):
+    """P: FP32 [n_seg][n_bins] (n_seg a multiple of S, n_bins even) -> FP64
+    values of the BF16 coarse map [n_seg / S][n_bins / 2]."""
     P = np.asarray(P, dtype=np.float32)
-    a = P[0::2, 0::2] + P[0::2, 1::2]
-    b = P[1::2, 0::2] + P[1::2, 1::2]
-    s = (a + b).astype(np.float32)
-    codes = oracle.bf16_rne(s).astype(np.uint32) << 16
+    s = P[0::S, 0::2] + P[0::S, 1::2]
+    for k in range(1, S):
+        s = (s + (P[k::S, 0::2] + P[k::S, 1::2])).astype(np.float32)
+    codes = oracle.bf16_rne(s.astype(np.float32)).astype(np.uint32) << 16
     return codes.view(np.float32).astype(np.float64)
 
 
-def coarse_weights(w, n_seg):
+def coarse_weights(w, n_seg, S=2):
     w = np.ones(n_seg, np.float32) if w is None else np.asarray(w, np.float32)
-    return ((w[0::2] + w[1::2]) * np.float32(0.5)).astype(np.float32)
+    s = w[0::S].copy()
+    for k in range(1, S):
+        s = (s + w[k::S]).astype(np.float32)
+    return (s * np.float32(1.0 / S)).astype(np.float32)
 
 
-def coarse_psi(det: "oracle.Detector", grid: "oracle.Grid", P, nan_to_zero=False):
+def coarse_psi(det: "oracle.Detector", grid: "oracle.Grid", P, nan_to_zero=False, S=2):
     """Coarse power critical ratio of every template of grid on det's geometry
     with fine power P (FP32 [n_seg][n_bins]); FP64 [n_templates]."""
-    C = coarse_power(P)
-    w2 = coarse_weights(det.w, det.n_seg).astype(np.float64)
+    C = coarse_power(P, S)
+    w2 = coarse_weights(det.w, det.n_seg, S).astype(np.float64)
     nb2 = det.n_bins // 2
+    mu = 2.0 * S
     out = np.empty(grid.n_templates)
     for t in range(grid.n_templates):
         f0, tau, brake, i_sky = grid.params(t)
         b = oracle.track_bins(det, float(f0), float(tau), float(brake), grid.sky[int(i_sky)], grid.t0)
-        b = b[0::2]
+        b = b[0::S]
         m = np.where(b == np.iinfo(np.int64).min, -1, b // 2)
         inb = (m >= 0) & (m < nb2)
         j = np.nonzero(inb)[0]
@@ -55,7 +61,7 @@ def coarse_psi(det: "oracle.Detector", grid: "oracle.Grid", P, nan_to_zero=False
         s = np.sum(w2[j] * C[j, m[j]])
         W1 = np.sum(w2[j])
         W2 = np.sum(w2[j] ** 2)
-        out[t] = (s - 4.0 * W1) / np.sqrt(4.0 * W2)
+        out[t] = (s - mu * W1) / np.sqrt(mu * W2)
     return out
 
 

@@ -93,6 +93,7 @@ struct StackLevel {
 struct StackState {
     bool valid = false, coarse = false;
     int det = 0, R = 0, store = 0, n_seg = 0, n_bins = 0;
+    int S = 2;                    // segments per coarse row
     int64_t k_lo = 0, pitch = 0, pitch2 = 0;
     double t_sft = 0.0;
     DevBuf fine, crs, w, wq, scale, w2, t, v, t2, v2, params;

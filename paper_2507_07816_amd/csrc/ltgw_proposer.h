@@ -31,7 +31,7 @@ hipError_t launch_inject_stack(float *power, int R, int32_t n_seg, int32_t n_bin
                                double t_sft, const double *t_seg, const double *v, const float *w,
                                const double *params, double sx, double sy, double sz, double t0,
                                unsigned long long *undecided, hipStream_t st);
-hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins, int64_t pitch2,
+hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins, int S, int64_t pitch2,
                           unsigned short *out, hipStream_t st);
 hipError_t launch_cnn_forward(const float *params, const float *x, int B, int c_in, int c_out, int L,
                               float *act /* [3][B][32][L] */, float *logits, hipStream_t st);

@@ -111,37 +111,38 @@ hipError_t launch_inject_stack(float *power, int R, int32_t n_seg, int32_t n_bin
     return hipGetLastError();
 }
 
-// 2x2 coarsening into BF16: coarse[r][j'][m + 1] = RN_bf16((P[2j'][2m] + P[2j'][2m+1]) +
-// (P[2j'+1][2m] + P[2j'+1][2m+1])) (FP32 sums), zero guards at 0 and n_bins/2 + 1.
+// Coarsening into BF16 over S consecutive segments and 2 bins:
+// coarse[r][j'][m + 1] = RN_bf16(sum over s < S, in order, of
+// (P[S j' + s][2m] + P[S j' + s][2m+1])) (FP32 sums), zero guards at 0 and
+// n_bins/2 + 1.
 __device__ inline unsigned short bf16_rne(float x) {  // finite x >= 0
     const unsigned u = __float_as_uint(x);
     return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
 __global__ __launch_bounds__(256) void coarsen_kernel(const float *__restrict__ in, int n_seg,
-                                                      int n_bins, int64_t pitch2,
+                                                      int n_bins, int S, int64_t pitch2,
                                                       unsigned short *__restrict__ out) {
     const int j2 = blockIdx.x, r = blockIdx.y;
-    const int ns2 = n_seg / 2, nb2 = n_bins / 2;
-    const float *r0 = in + ((int64_t)r * n_seg + 2 * j2) * n_bins;
-    const float *r1 = r0 + n_bins;
+    const int ns2 = n_seg / S, nb2 = n_bins / 2;
+    const float *row = in + ((int64_t)r * n_seg + (int64_t)S * j2) * n_bins;
     unsigned short *o = out + ((int64_t)r * ns2 + j2) * pitch2;
     for (int64_t b = threadIdx.x; b < pitch2; b += 256) {
         unsigned short code = 0;
         if (b >= 1 && b <= nb2) {
             const int64_t m = b - 1;
-            const float a = r0[2 * m] + r0[2 * m + 1];
-            const float c = r1[2 * m] + r1[2 * m + 1];
-            code = bf16_rne(a + c);
+            float acc = row[2 * m] + row[2 * m + 1];
+            for (int k = 1; k < S; ++k) acc = acc + (row[(int64_t)k * n_bins + 2 * m] + row[(int64_t)k * n_bins + 2 * m + 1]);
+            code = bf16_rne(acc);
         }
         o[b] = code;
     }
 }
 
-hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins, int64_t pitch2,
+hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins, int S, int64_t pitch2,
                           unsigned short *out, hipStream_t st) {
-    if (R < 1 || R > 65535 || n_seg < 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(coarsen_kernel, dim3(n_seg / 2, R), dim3(256), 0, st, in, n_seg, n_bins, pitch2, out);
+    if (R < 1 || R > 65535 || S < 1 || n_seg < S) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(coarsen_kernel, dim3(n_seg / S, R), dim3(256), 0, st, in, n_seg, n_bins, S, pitch2, out);
     return hipGetLastError();
 }
 
@@ -274,6 +275,74 @@ __global__ __launch_bounds__(256) void conv_fwd_lds_kernel(ConvDims d, const flo
             const int o = o0 + r0 + kq + i;
             if (o >= d.O) continue;
             float y = acc[i] + bias[o];
+            if (relu) y = y > 0.f ? y : 0.f;
+            Y[((int64_t)b * d.O + o) * d.L + l] = y;
+        }
+    }
+}
+
+// The product with K ordered (t, c) instead of (c, t), so that the B fragment
+// (4 consecutive k) is 4 consecutive channels at one tap: the LDS holds the
+// raw input window [position][channel] once (no im2col copies) and every
+// fragment is one 8-byte read.  A workgroup owns one sample, 256 positions
+// and 32 output channels; each wavefront computes 8 of the 16 x 16 tiles.
+// Cp = channels rounded up to 4; K = KT Cp rounded up to 16 (zero fragments
+// past KT Cp).
+template <int KT>
+__global__ __launch_bounds__(256) void conv_fwd_win_kernel(ConvDims d, const float *__restrict__ X,
+                                                           const float *__restrict__ W,
+                                                           const float *__restrict__ bias, int relu,
+                                                           float *__restrict__ Y, int Cp, int Kpad) {
+    extern __shared__ short lds[];
+    constexpr int kPos = 256;
+    const int SW = Kpad + 4, SX = Cp + 4;
+    const int P = kPos + KT - 1;
+    short *wt = lds;            // [32][SW]
+    short *xw = lds + 32 * SW;  // [P][SX]
+    const int tiles_l = (d.L + kPos - 1) / kPos;
+    const int b = blockIdx.x / tiles_l, l0 = (blockIdx.x % tiles_l) * kPos;
+    const int o0 = blockIdx.y * 32;
+    for (int e = threadIdx.x; e < 32 * Kpad; e += 256) {
+        const int r = e / Kpad, k = e % Kpad;
+        const int t = k / Cp, c = k % Cp, o = o0 + r;
+        float v = 0.f;
+        if (o < d.O && t < KT && c < d.C) v = W[((int64_t)o * d.C + c) * KT + t];
+        wt[r * SW + k] = to_bf16(v);
+    }
+    for (int e = threadIdx.x; e < Cp * P; e += 256) {
+        const int c = e / P, pos = e % P;
+        const int l = l0 + pos - KT / 2;
+        float v = 0.f;
+        if (c < d.C && l >= 0 && l < d.L) v = X[((int64_t)b * d.C + c) * d.L + l];
+        xw[pos * SX + c] = to_bf16(v);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r0 = (wv & 1) * 16, c0 = (wv >> 1) * 128;
+    const int row = lane & 15, kq = (lane >> 4) * 4;
+    f32x4 acc[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) acc[h] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < Kpad; kk += 16) {
+        const int k = kk + kq;
+        const int t = k / Cp, c = k % Cp;
+        const bf16x4 a = *(const bf16x4 *)&wt[(r0 + row) * SW + k];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            bf16x4 bv = {0, 0, 0, 0};
+            if (t < KT) bv = *(const bf16x4 *)&xw[(c0 + h * 16 + row + t) * SX + c];
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[h], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+        const int l = l0 + c0 + h * 16 + (lane & 15);
+        if (l >= d.L) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = o0 + r0 + kq + i;
+            if (o >= d.O) continue;
+            float y = acc[h][i] + bias[o];
             if (relu) y = y > 0.f ? y : 0.f;
             Y[((int64_t)b * d.O + o) * d.L + l] = y;
         }
@@ -422,6 +491,20 @@ int64_t cnn_n_params(int c_in, int c_out) { return cnn_layout(c_in, c_out).total
 
 static hipError_t conv_fwd(const ConvDims &d, const float *X, const float *W, const float *b, int relu,
                            float *Y, hipStream_t st) {
+    {
+        const int Cp = (d.C + 3) / 4 * 4;
+        const int Kw = (d.k * Cp + 15) / 16 * 16;
+        const size_t lds = ((size_t)32 * (Kw + 4) + (size_t)(256 + d.k - 1) * (Cp + 4)) * sizeof(short);
+        const int64_t ltiles = (int64_t)d.B * ((d.L + 255) / 256);
+        if (lds <= 48 * 1024 && ltiles <= 0x7fffffff) {
+            dim3 grid((unsigned)ltiles, (unsigned)((d.O + 31) / 32)), block(256);
+            if (d.k == kTaps)
+                hipLaunchKernelGGL(conv_fwd_win_kernel<kTaps>, grid, block, lds, st, d, X, W, b, relu, Y, Cp, Kw);
+            else
+                hipLaunchKernelGGL(conv_fwd_win_kernel<1>, grid, block, lds, st, d, X, W, b, relu, Y, Cp, Kw);
+            return hipGetLastError();
+        }
+    }
     const int Kpad = (d.C * d.k + 15) / 16 * 16;
     const size_t lds = (size_t)(32 + 64) * (Kpad + 4) * sizeof(short);
     const int64_t ltiles = (int64_t)d.B * ((d.L + 63) / 64);

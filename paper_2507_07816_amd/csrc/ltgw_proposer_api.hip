@@ -79,7 +79,7 @@ int stack_tables(ltgw_ctx *c, const ltgw_grid *g, int level, SearchPlan &P) {
     L.h_tau.assign(g->tau, g->tau + g->n_tau);
     L.h_brake.assign(g->brake, g->brake + g->n_brake);
     L.h_sky.assign(g->sky, g->sky + 3 * (size_t)g->n_sky);
-    const int ns = level ? S.n_seg / 2 : S.n_seg;
+    const int ns = level ? S.n_seg / S.S : S.n_seg;
     if ((rc = ensure(c, L.tau, L.h_tau.size() * 8, "tau")) != LTGW_OK) return rc;
     if ((rc = ensure(c, L.brake, L.h_brake.size() * 8, "brake")) != LTGW_OK) return rc;
     if ((rc = ensure(c, L.sky, L.h_sky.size() * 8, "sky")) != LTGW_OK) return rc;
@@ -126,10 +126,10 @@ EvalArgs stack_args(const StackState &S, int level, const ltgw_grid *g, const Se
         V.wq = (const float *)S.w2.p;
         V.w = (const float *)S.w2.p;
         V.cshift = 2.5 - (double)S.k_lo;
-        V.n_seg = S.n_seg / 2;
+        V.n_seg = S.n_seg / S.S;
         V.n_bins = S.n_bins / 2;
-        stack_bytes = (int64_t)(S.n_seg / 2) * S.pitch2 * 2;
-        stack_rows = S.n_seg / 2;
+        stack_bytes = (int64_t)(S.n_seg / S.S) * S.pitch2 * 2;
+        stack_rows = S.n_seg / S.S;
     }
     V.H = (const double *)L.H.p;
     V.g = (const double *)L.g.p;
@@ -157,7 +157,7 @@ int stack_psi_impl(ltgw_ctx *c, const ltgw_grid *g, int level, int nan_to_zero, 
     const EvalArgs a = stack_args(c->stack, level, g, P, sb, sr);
     const int shift = level;
     const int store = level ? LTGW_STORE_BF16 : c->stack.store;
-    const double mu = level ? 4.0 : 1.0;
+    const double mu = level ? 2.0 * c->stack.S : 1.0;  // a coarse pixel sums 2 S Exp(1) values
     HIP_TRY(c, launch_stack_eval(store, shift, a, c->stack.R, sb, sr, mu, mu, nan_to_zero, out_psi, nullptr,
                                  c->stream),
             "stack evaluation launch");
@@ -250,9 +250,12 @@ int32_t ltgw_load_stack(ltgw_ctx *c, int32_t det, int32_t R, const float *stack,
     int rc = need_device(c, stack, "stack");
     if (rc != LTGW_OK) return rc;
     const int64_t ns = D.n_seg, nb = D.n_bins;
-    if (coarse && ((ns & 1) || (nb & 1)))
-        return fail(c, LTGW_E_INVALID_ARG, "a coarse store needs even n_seg and n_bins (have %lld, %lld)",
-                    (long long)ns, (long long)nb);
+    const int Sg = coarse == 1 ? 2 : coarse;  // segments per coarse row
+    if (coarse < 0 || (coarse > 0 && Sg != 2 && Sg != 4))
+        return fail(c, LTGW_E_INVALID_ARG, "coarse must be 0 (none), 1 or 2 (pairs of segments) or 4");
+    if (coarse && ((ns % Sg) || (nb & 1)))
+        return fail(c, LTGW_E_INVALID_ARG, "a coarse store needs n_seg a multiple of %d and even n_bins (have %lld, %lld)",
+                    Sg, (long long)ns, (long long)nb);
     if ((int64_t)R * ns >= ((int64_t)1 << 31)) return fail(c, LTGW_E_UNSUPPORTED, "R * n_seg exceeds 2^31 rows");
     const int64_t pitch = ((nb + 2 + 63) / 64) * 64;
     if (ns * pitch * esize(store) >= ((int64_t)1 << 31))
@@ -280,26 +283,30 @@ int32_t ltgw_load_stack(ltgw_ctx *c, int32_t det, int32_t R, const float *stack,
     std::vector<double> ht2, hv2;
     int64_t pitch2 = 0;
     if (coarse) {
-        const int64_t ns2 = ns / 2, nb2 = nb / 2;
+        const int64_t ns2 = ns / Sg, nb2 = nb / 2;
         pitch2 = ((nb2 + 2 + 63) / 64) * 64;
         if ((rc = ensure(c, S.crs, (size_t)(R * ns2 * pitch2 * 2), "coarse store")) != LTGW_OK) return rc;
         if ((rc = ensure(c, S.w2, (size_t)(R * ns2) * 4, "coarse weights")) != LTGW_OK) return rc;
         if ((rc = ensure(c, S.t2, (size_t)ns2 * 8, "coarse segment times")) != LTGW_OK) return rc;
         if ((rc = ensure(c, S.v2, (size_t)ns2 * 24, "coarse velocities")) != LTGW_OK) return rc;
-        // a pair's weight is the mean of its two segments' weights (FP32)
+        // a group's weight: its S weights summed in order, times 1/S (FP32)
         hw2.resize((size_t)(R * ns2));
-        for (int64_t j = 0; j < ns2; ++j) hw2[(size_t)j] = (D.h_w[2 * j] + D.h_w[2 * j + 1]) * 0.5f;
+        for (int64_t j = 0; j < ns2; ++j) {
+            float acc = D.h_w[(size_t)(Sg * j)];
+            for (int k = 1; k < Sg; ++k) acc = acc + D.h_w[(size_t)(Sg * j + k)];
+            hw2[(size_t)j] = acc * (1.0f / (float)Sg);
+        }
         for (int64_t r = 1; r < R; ++r) std::memcpy(&hw2[(size_t)(r * ns2)], hw2.data(), (size_t)ns2 * 4);
         ht2.resize((size_t)ns2);
         hv2.resize((size_t)ns2 * 3);
         for (int64_t j = 0; j < ns2; ++j) {
-            ht2[(size_t)j] = D.h_t[2 * j];
-            for (int k = 0; k < 3; ++k) hv2[3 * (size_t)j + k] = D.h_v[3 * (size_t)(2 * j) + k];
+            ht2[(size_t)j] = D.h_t[(size_t)(Sg * j)];
+            for (int k = 0; k < 3; ++k) hv2[3 * (size_t)j + k] = D.h_v[3 * (size_t)(Sg * j) + k];
         }
         if ((rc = h2d(c, S.w2.p, hw2.data(), hw2.size() * 4, "coarse weights upload")) != LTGW_OK) return rc;
         if ((rc = h2d(c, S.t2.p, ht2.data(), ht2.size() * 8, "coarse times upload")) != LTGW_OK) return rc;
         if ((rc = h2d(c, S.v2.p, hv2.data(), hv2.size() * 8, "coarse velocity upload")) != LTGW_OK) return rc;
-        HIP_TRY(c, launch_coarsen(stack, R, (int32_t)ns, (int32_t)nb, pitch2, (unsigned short *)S.crs.p, c->stream),
+        HIP_TRY(c, launch_coarsen(stack, R, (int32_t)ns, (int32_t)nb, Sg, pitch2, (unsigned short *)S.crs.p, c->stream),
                 "coarsen launch");
     }
     unsigned long long bad = 0;
@@ -316,6 +323,7 @@ int32_t ltgw_load_stack(ltgw_ctx *c, int32_t det, int32_t R, const float *stack,
     S.pitch = pitch;
     S.pitch2 = pitch2;
     S.coarse = coarse != 0;
+    S.S = coarse ? Sg : 2;
     S.valid = true;
     return LTGW_OK;
 }

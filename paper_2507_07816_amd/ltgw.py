@@ -356,10 +356,11 @@ def ltgw_inject_stack(ctx, det, stack, params, sky, t0=0.0):
 
 
 def ltgw_load_stack(ctx, det, stack, store="f32", coarse=True):
+    """coarse: False (none), True (pairs of segments) or the segments per coarse row (2, 4)."""
     import torch
+    cs = int(coarse) if not isinstance(coarse, bool) else (1 if coarse else 0)
     _check(ctx, library().ltgw_load_stack(ctx, int(det), int(stack.shape[0]), _dev(stack, torch.float32),
-                                          STORES[store] if isinstance(store, str) else int(store),
-                                          1 if coarse else 0))
+                                          STORES[store] if isinstance(store, str) else int(store), cs))
 
 
 def ltgw_stack_psi(ctx, grid, level, out_psi, nan_to_zero=False):

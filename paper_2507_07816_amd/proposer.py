@@ -61,7 +61,7 @@ class Proposer:
     `det` holds the geometry (segment times, weights, velocities)."""
 
     def __init__(self, ctx, det, shape, fine, coarse, seed=0, select_frac=0.05, store="f32", block=1,
-                 select2_frac=0.0):
+                 select2_frac=0.0, coarse_segments=2):
         import torch
 
         if fine["n_f0"] % 2:
@@ -78,6 +78,7 @@ class Proposer:
         self.n_select = max(1, int(round(select_frac * self.n_cells)))
         self.n_select2 = int(round(select2_frac * self.n_cells))
         self.block = int(block)
+        self.coarse_segments = int(coarse_segments)
         self.store = store
         self.seed = seed
         self.rng = np.random.Generator(np.random.PCG64(seed))
@@ -137,7 +138,7 @@ class Proposer:
         ltgw.ltgw_generate_noise(h, self.seed, stream, r0, b["stack"])
         ltgw.ltgw_inject_stack(h, self.det, b["stack"], inj, np.asarray(self.fine["sky"]).reshape(3),
                                self.fine.get("t0", 0.0))
-        ltgw.ltgw_load_stack(h, self.det, b["stack"], self.store, coarse=True)
+        ltgw.ltgw_load_stack(h, self.det, b["stack"], self.store, coarse=self.coarse_segments)
         ltgw.ltgw_stack_features(h, self._cg, b["x"])
         if with_labels:
             ltgw.ltgw_stack_best(h, self._fg, b["best"], b["best_psi"])
@@ -237,7 +238,7 @@ class Proposer:
             t_ex.append(ev0.elapsed_time(ev1))
         ex_idx = b["best"].cpu().numpy().copy()
         ex_psi = b["best_psi"].cpu().numpy().copy()
-        ltgw.ltgw_load_stack(h, self.det, b["stack"], fine_store, coarse=True)
+        ltgw.ltgw_load_stack(h, self.det, b["stack"], fine_store, coarse=self.coarse_segments)
         det_ex = ex_psi > psi_thr
         n_det = int(det_ex.sum())
         rec = lambda p: float((det_ex & (p > psi_thr)).sum() / n_det) if n_det else float("nan")
@@ -263,6 +264,7 @@ class Proposer:
         out.update(recall_no_fallback=rec(pp_nf), detectable=n_det, realisations=R_signal,
                    detectable_min_amp=float(amp[det_ex].min()) if n_det else float("nan"),
                    psi_threshold=psi_thr, exhaustive_ms=min(t_ex), n_select=self.n_select,
-                   n_select2=self.n_select2, block=self.block, n_cells=self.n_cells,
+                   n_select2=self.n_select2, block=self.block, coarse_segments=self.coarse_segments,
+                   n_cells=self.n_cells,
                    fine_store=fine_store, target_recall=target_recall, points=points)
         return out

@@ -130,21 +130,21 @@ def test_inject_stack_matches_oracle_bins():
     ctx.close()
 
 
-@pytest.mark.parametrize("weights", [True, False])
-def test_stack_psi_fine_and_coarse_vs_oracle(weights):
+@pytest.mark.parametrize("weights,S", [(True, 2), (False, 2), (True, 4)])
+def test_stack_psi_fine_and_coarse_vs_oracle(weights, S):
     import torch
     from paper_2507_07816_amd import ltgw
 
     ctx, t, v, w = _ctx(weights)
     R = len(INJ)
-    print(f"case: stack psi weights={weights}", flush=True)
+    print(f"case: stack psi weights={weights} coarse segments {S}", flush=True)
     st = _stack(ctx, R, INJ)
     ref_stack = _oracle_stack(R, INJ, t, v, w)
     host = st.cpu().numpy()
     for r in range(R):   # the device stack is the oracle's up to the last bit of a logarithm
         d = np.abs(host[r].view(np.int32).astype(np.int64) - ref_stack[r].view(np.int32).astype(np.int64))
         assert d.max() <= 1
-    ltgw.ltgw_load_stack(ctx.h, 0, st, "f32", coarse=True)
+    ltgw.ltgw_load_stack(ctx.h, 0, st, "f32", coarse=S)
     fg, keep_f = _grid(FINE)
     cg, keep_c = _grid(COARSE)
     n_f, n_c = _ogrid(FINE).n_templates, _ogrid(COARSE).n_templates
@@ -160,7 +160,7 @@ def test_stack_psi_fine_and_coarse_vs_oracle(weights):
         ok = np.isfinite(psi)
         assert np.array_equal(ok, np.isfinite(pf[r]))
         assert np.all(np.abs(pf[r][ok] - psi[ok]) <= psi_tolerance(ref)[ok])
-        cref = op.coarse_psi(det, _ogrid(COARSE), ref_stack[r])
+        cref = op.coarse_psi(det, _ogrid(COARSE), ref_stack[r], S=S)
         okc = np.isfinite(cref)
         assert np.array_equal(okc, np.isfinite(pc[r]))
         assert np.allclose(pc[r][okc], cref[okc], rtol=0, atol=2e-5 * (1 + np.abs(cref[okc])))

@@ -1,10 +1,11 @@
 """Pins of the proposer's reference definitions (oracle/proposer.py, oracle/cnn.py
 operand rounding and Adam).
 
-- the coarse map is the 2x2 block sum, rounded to bfloat16 (hand values, a tie);
-- the coarse critical ratio against the fine oracle: with each segment pair
-  sharing one time and velocity and power constant on 2x2 blocks, the coarse
-  ratio is sqrt(2) times the fine one (s halves, W1 and W2 double);
+- the coarse map is the S x 2 block sum, rounded to bfloat16 (hand values, a
+  tie, groups of 2 and of 4 segments);
+- the coarse critical ratio against the fine oracle: with each group of S
+  segments sharing one time and velocity and power constant on S x 2 blocks,
+  the coarse ratio is sqrt(2) times the fine one, for S = 2 and 4;
 - only the first segment of a pair places the coarse column;
 - noise-free constant power gives Psi = 0 on every in-band template;
 - cells <-> templates is a bijection; best_template's tie rule;
@@ -14,6 +15,7 @@ operand rounding and Adam).
 import math
 
 import numpy as np
+import pytest
 
 import oracle
 from oracle import cnn
@@ -40,6 +42,15 @@ def _grid():
                        GRID["sky"], GRID["t0"])
 
 
+def test_coarse_power_groups_of_four_segments():
+    P = np.zeros((8, 4), np.float32)
+    P[0:4, 0:2] = 1.0          # 8 ones in the first coarse pixel
+    P[4, 2], P[7, 3] = 127.5, 1.5
+    C = op.coarse_power(P, S=4)
+    assert C.shape == (2, 2) and C[0, 0] == 8.0 and C[1, 1] == 129.0 and C[0, 1] == 0.0
+    assert np.allclose(op.coarse_weights(np.array([1, 2, 3, 4, 1, 1, 1, 1], np.float32), 8, 4), [2.5, 1.0])
+
+
 def test_coarse_power_block_sums_and_bf16_tie():
     P = np.zeros((4, 6), np.float32)
     P[0, 0], P[0, 1], P[1, 0], P[1, 1] = 1.0, 2.0, 3.0, 4.0
@@ -51,17 +62,25 @@ def test_coarse_power_block_sums_and_bf16_tie():
     assert C[0, 1] == 0.0 and C[0, 2] == 0.0 and C[1, 0] == 0.0
 
 
-def test_coarse_psi_is_sqrt2_times_fine_on_duplicated_pairs():
+@pytest.mark.parametrize("S", [2, 4])
+def test_coarse_psi_is_sqrt2_times_fine_on_duplicated_groups(S):
+    """Each group of S segments shares one time and velocity, the weights are
+    equal within a group and the power is constant on S x 2 blocks: the fine
+    sum is S w q per group, the coarse one 2 S w q, so the coarse ratio is
+    sqrt(2) times the fine one for every S."""
     n_seg, n_bins, k_lo, t_sft = 64, 96, 1900, 4.0
-    t, v = _geometry(n_seg, dup=True)
+    t, v = _geometry(n_seg)
+    for k in range(1, S):
+        t[k::S] = t[0::S]
+        v[k::S] = v[0::S]
     r = np.random.default_rng(3)
-    q = r.integers(0, 6, size=(n_seg // 2, n_bins // 2)).astype(np.float32)
-    P = np.repeat(np.repeat(q, 2, axis=0), 2, axis=1)        # constant on 2x2 blocks
-    w = np.repeat(r.uniform(0.5, 2.0, n_seg // 2).astype(np.float32), 2)  # equal within a pair
+    q = r.integers(0, 6, size=(n_seg // S, n_bins // 2)).astype(np.float32)
+    P = np.repeat(np.repeat(q, S, axis=0), 2, axis=1)        # constant on S x 2 blocks
+    w = np.repeat(r.uniform(0.5, 2.0, n_seg // S).astype(np.float32), S)  # equal within a group
     det = oracle.Detector(P, t, v, k_lo, t_sft, weights=w)
     g = _grid()
     fine = oracle.psi_power(oracle.evaluate(det, g))
-    coarse = op.coarse_psi(det, g, P)
+    coarse = op.coarse_psi(det, g, P, S=S)
     ok = np.isfinite(fine)
     assert ok.sum() > 50
     assert np.array_equal(ok, np.isfinite(coarse))
