@@ -199,7 +199,7 @@ def main():
     ap.add_argument("--no-proposer", action="store_true", help="skip the learned-proposer leg")
     ap.add_argument("--batch", action="store_true", help="add the 64-search batch leg")
     ap.add_argument("--tile-shape", type=int, default=-1,
-                    help="force the statistic kernel's variant (0..7) instead of autotuning (profiling runs)")
+                    help="force the statistic kernel's variant (0..15) instead of autotuning (profiling runs)")
     ap.add_argument("--proposer-realisations", type=int, default=50000)
     ap.add_argument("--proposer-epochs", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",

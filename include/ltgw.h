@@ -413,6 +413,15 @@ typedef struct {
     double psi_threshold;     /* detection threshold on Psi (largest noise value)  */
     double coarse_threshold;  /* fallback when the coarse map exceeds this but no
                                  selected cell passes psi_threshold               */
+    int32_t *blocks;          /* optional host output (NULL: none), [R][K1 + K2]
+                                 with K1 = ceil(n_select / block), K2 =
+                                 ceil(n_select2 / block): the blocks evaluated
+                                 exactly, tier 1 in ascending order, then tier 2
+                                 (-1 where the realisation did not take it).
+                                 Block b covers fine group b / nbg, f0 indices
+                                 (b % nbg) block .. + block - 1 (below 2 L),
+                                 nbg = ceil(2 L / block).  A fallback
+                                 realisation evaluated every template.        */
 } ltgw_proposer;
 
 /* ltgw_propose: on the loaded stack, for every realisation: coarse critical

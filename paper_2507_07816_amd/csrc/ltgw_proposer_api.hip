@@ -551,7 +551,16 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
     HIP_TRY(c, hipMemcpyAsync(best_index, S.best_idx.p, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipMemcpyAsync(best_psi, S.best_psi.p, (size_t)R * 8, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipMemcpyAsync(cm.data(), S.cm.p, (size_t)R * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+    const int KB = K1 + K2;
+    std::vector<int32_t> hb1(p->blocks ? (size_t)R * K1 : 0);
+    if (p->blocks)
+        HIP_TRY(c, hipMemcpyAsync(hb1.data(), S.blk.p, hb1.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "propose");
+    if (p->blocks)
+        for (int r = 0; r < R; ++r) {
+            std::copy(hb1.begin() + (size_t)r * K1, hb1.begin() + (size_t)(r + 1) * K1, p->blocks + (size_t)r * KB);
+            std::fill(p->blocks + (size_t)r * KB + K1, p->blocks + (size_t)(r + 1) * KB, -1);
+        }
     const double thr = p->psi_threshold;
     // merge a later result into the best so far (larger ratio; ties to the lower index)
     auto merge = [&](int r, int32_t i, double v) {
@@ -590,10 +599,17 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
                 "reduction launch");
         std::vector<int32_t> bi((size_t)n2);
         std::vector<double> bp((size_t)n2);
+        std::vector<int32_t> hb2(p->blocks ? (size_t)R * K2 : 0);
         HIP_TRY(c, hipMemcpyAsync(bi.data(), S.best_idx.p, (size_t)n2 * 4, hipMemcpyDeviceToHost, c->stream), "copy");
         HIP_TRY(c, hipMemcpyAsync(bp.data(), S.best_psi.p, (size_t)n2 * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+        if (p->blocks)
+            HIP_TRY(c, hipMemcpyAsync(hb2.data(), S.blk2.p, hb2.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy");
         HIP_TRY(c, hipStreamSynchronize(c->stream), "propose second tier");
         for (int q = 0; q < n2; ++q) merge(rows[(size_t)q], bi[(size_t)q], bp[(size_t)q]);
+        if (p->blocks)
+            for (int32_t r : rows)
+                std::copy(hb2.begin() + (size_t)r * K2, hb2.begin() + (size_t)(r + 1) * K2,
+                          p->blocks + (size_t)r * KB + K1);
     }
     // 3. the fallback rule: a loud coarse map and still no cell above the threshold
     rows.clear();

@@ -89,7 +89,7 @@ class ltgw_batch_stats(C.Structure):
 class ltgw_proposer(C.Structure):
     _fields_ = [("params", C.c_void_p), ("c_in", C.c_int32), ("c_out", C.c_int32), ("L", C.c_int32),
                 ("n_select", C.c_int32), ("block", C.c_int32), ("n_select2", C.c_int32),
-                ("psi_threshold", C.c_double), ("coarse_threshold", C.c_double)]
+                ("psi_threshold", C.c_double), ("coarse_threshold", C.c_double), ("blocks", C.c_void_p)]
 
 
 class LtgwError(RuntimeError):
@@ -442,18 +442,27 @@ def ltgw_select_top(ctx, score, M, out_idx):
                                           _dev(out_idx, torch.int32)))
 
 
+def propose_block_counts(n_select, n_select2, block):
+    """(K1, K2): blocks of the first and second tier."""
+    return -(-int(n_select) // int(block)), (-(-int(n_select2) // int(block)) if n_select2 > 0 else 0)
+
+
 def ltgw_propose(ctx, fine, coarse, params, c_in, c_out, L, n_select, psi_threshold, coarse_threshold, R,
-                 block=1, n_select2=0):
-    """(best_index[R], best_psi[R], fallback[R]) numpy arrays."""
+                 block=1, n_select2=0, return_blocks=False):
+    """(best_index[R], best_psi[R], fallback[R]) numpy arrays, and with
+    return_blocks the evaluated blocks [R][K1 + K2] (-1: tier not taken)."""
     import torch
+    K1, K2 = propose_block_counts(n_select, n_select2, block)
+    blocks = np.empty((R, K1 + K2), np.int32) if return_blocks else None
     p = ltgw_proposer(_dev(params, torch.float32), int(c_in), int(c_out), int(L), int(n_select), int(block),
-                      int(n_select2), float(psi_threshold), float(coarse_threshold))
+                      int(n_select2), float(psi_threshold), float(coarse_threshold),
+                      blocks.ctypes.data if return_blocks else None)
     bi = np.empty(R, np.int32)
     bp = np.empty(R, np.float64)
     fb = np.empty(R, np.int32)
     _check(ctx, library().ltgw_propose(ctx, C.byref(fine), C.byref(coarse), C.byref(p), bi.ctypes.data,
                                        bp.ctypes.data, fb.ctypes.data))
-    return bi, bp, fb
+    return (bi, bp, fb, blocks) if return_blocks else (bi, bp, fb)
 
 
 # ---------------------------------------------------------------------------

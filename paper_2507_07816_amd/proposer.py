@@ -56,6 +56,35 @@ def _n_groups(d):
     return len(d["tau"]) * len(d["brake"]) * len(np.asarray(d["sky"]).reshape(-1, 3))
 
 
+def close_region(fine, inj, df=2, dg=1):
+    """Fine templates close to each injection (rows of inj: f0, tau, n): f0
+    index within df of the nearest fine f0, tau and n indices within dg of
+    the nearest (tau nearest in log, the lattice being geometric).
+    [R][(2 df + 1)(2 dg + 1)^2] template indices (order sky, n, tau, f0
+    fastest) in ascending order, -1 outside the grid."""
+    n_f0 = int(fine["n_f0"])
+    tau, brake = np.asarray(fine["tau"], np.float64), np.asarray(fine["brake"], np.float64)
+    inj = np.asarray(inj, np.float64)
+    i0 = np.rint((inj[:, 0] - fine["f0_min"]) / fine["f0_step"]).astype(np.int64)
+    j0 = np.argmin(np.abs(np.log(inj[:, 1])[:, None] - np.log(tau)[None, :]), axis=1)
+    k0 = np.argmin(np.abs(inj[:, 2][:, None] - brake[None, :]), axis=1)
+    d_g, d_f = np.arange(-dg, dg + 1), np.arange(-df, df + 1)
+    K, J, I = (a.ravel() for a in np.meshgrid(d_g, d_g, d_f, indexing="ij"))
+    i, j, k = i0[:, None] + I, j0[:, None] + J, k0[:, None] + K
+    ok = (i >= 0) & (i < n_f0) & (j >= 0) & (j < len(tau)) & (k >= 0) & (k < len(brake))
+    return np.where(ok, (k * len(tau) + j) * n_f0 + i, -1)
+
+
+def evaluated(blocks, fallback, tpl, L, block):
+    """Whether fine template tpl[r] (fine n_f0 = 2 L) was among the cells that
+    realisation r evaluated exactly: its block (group, f0 index // block) in
+    the row's tier lists blocks[r] (-1: unused), or the row fell back."""
+    nbg = -(-2 * L // block)
+    tpl = np.asarray(tpl, np.int64)
+    blk = (tpl // (2 * L)) * nbg + (tpl % (2 * L)) // block
+    return (np.asarray(fallback) != 0) | (np.asarray(blocks) == blk[:, None]).any(axis=1)
+
+
 class Proposer:
     """Training and inference state on one ltgw.Context whose detector slot
     `det` holds the geometry (segment times, weights, velocities)."""
@@ -92,6 +121,7 @@ class Proposer:
         self.step = 0
         self._bufs = {}
         self._fg, self._fg_keep = _grid(fine)
+        self._fg_keep_n = _n_groups(fine) * int(fine["n_f0"])
         self._cg, self._cg_keep = _grid(coarse)
 
     # -- device buffers, sized once per batch size --------------------------------
@@ -188,11 +218,17 @@ class Proposer:
                                               label_psi=label_psi))
         return losses
 
-    def propose(self, psi_threshold, coarse_threshold, R):
-        """ltgw_propose on the loaded stack: (best_index, best_psi, fallback)."""
+    def propose(self, psi_threshold, coarse_threshold, R, return_blocks=False):
+        """ltgw_propose on the loaded stack: (best_index, best_psi, fallback[, blocks])."""
         return ltgw.ltgw_propose(self.ctx.h, self._fg, self._cg, self.params, self.c_in, self.c_out, self.L,
                                  self.n_select, psi_threshold, coarse_threshold, R, block=self.block,
-                                 n_select2=self.n_select2)
+                                 n_select2=self.n_select2, return_blocks=return_blocks)
+
+    def close_region(self, inj, df=2, dg=1):
+        return close_region(self.fine, inj, df, dg)
+
+    def evaluated(self, blocks, fallback, tpl):
+        return evaluated(blocks, fallback, tpl, self.L, self.block)
 
     def exhaustive(self, R):
         """Exhaustive fine search of the loaded stack: host (best_index, best_psi)."""
@@ -213,6 +249,14 @@ class Proposer:
         psi_threshold, and recalled when the proposer (coarse BF16 map,
         network, n_select exact cells on the `fine_store` store, fallback)
         passes it too; recall_no_fallback is the same with the fallback off.
+        Recall follows the detection rule with "close to the injection" read
+        as the neighbourhood of close_region: an injection is detectable when
+        the exhaustive FP32 search's best template of that neighbourhood
+        passes psi_threshold, and recalled when the proposer evaluated that
+        template exactly and its ratio there (on the `fine_store` store)
+        passes the threshold too.  recall_best is the looser figure over the
+        realisation's overall best (exhaustive best above the threshold;
+        proposer best above it).
         Times: exhaustive FP32 search (ltgw_stack_best) and ltgw_propose on
         the same realisations, HIP events on the context's stream, best of
         `reps`.  The operating point reported at the top level is the fastest
@@ -238,22 +282,45 @@ class Proposer:
             t_ex.append(ev0.elapsed_time(ev1))
         ex_idx = b["best"].cpu().numpy().copy()
         ex_psi = b["best_psi"].cpu().numpy().copy()
+        # the exhaustive search's best template close to each injection
+        psi_map = T.empty((R_signal, self._fg_keep_n), dtype=T.float64, device=self.ctx.device)
+        ltgw.ltgw_stack_psi(h, self._fg, 0, psi_map)
+        region = self.close_region(inj)
+        vals = np.take_along_axis(psi_map.cpu().numpy(), np.maximum(region, 0), axis=1)
+        vals = np.where((region >= 0) & np.isfinite(vals), vals, -np.inf)
+        k = np.argmax(vals, axis=1)                                  # first maximum: the lowest index
+        near_tpl = region[np.arange(R_signal), k].astype(np.int32)
+        near_psi = vals[np.arange(R_signal), k]
+        del psi_map
         ltgw.ltgw_load_stack(h, self.det, b["stack"], fine_store, coarse=self.coarse_segments)
+        near_prop = T.empty((R_signal, 1), dtype=T.float64, device=self.ctx.device)
+        ltgw.ltgw_stack_psi_list(h, self._fg, T.from_numpy(near_tpl.reshape(-1, 1)).to(self.ctx.device), near_prop)
+        near_prop = near_prop.cpu().numpy().ravel()
+        det_near = near_psi > psi_thr
+        n_near = int(det_near.sum())
         det_ex = ex_psi > psi_thr
         n_det = int(det_ex.sum())
-        rec = lambda p: float((det_ex & (p > psi_thr)).sum() / n_det) if n_det else float("nan")
-        _, pp_nf, _ = self.propose(psi_thr, 1e300, R_signal)      # fallback never taken
+        frac = lambda hit, of, n: float((of & hit).sum() / n) if n else float("nan")
+
+        def recalls(pp, fb, blocks):
+            hit = self.evaluated(blocks, fb, near_tpl) & (near_prop > psi_thr)
+            return frac(hit, det_near, n_near), frac(pp > psi_thr, det_ex, n_det)
+
+        _, pp_nf, fb_nf, bl_nf = self.propose(psi_thr, 1e300, R_signal, return_blocks=True)   # fallback never taken
+        rec_nf, rec_best_nf = recalls(pp_nf, fb_nf, bl_nf)
         points = []
         for q in coarse_quantiles:
             coarse_thr = float(np.quantile(coarse_max, q))
             t_pr = []
             for _ in range(reps):
                 ev0.record()
-                pi, pp, fb = self.propose(psi_thr, coarse_thr, R_signal)
+                self.propose(psi_thr, coarse_thr, R_signal)
                 ev1.record()
                 ev1.synchronize()
                 t_pr.append(ev0.elapsed_time(ev1))
-            points.append(dict(coarse_quantile=q, coarse_threshold=coarse_thr, recall=rec(pp),
+            pi, pp, fb, bl = self.propose(psi_thr, coarse_thr, R_signal, return_blocks=True)
+            rec, rec_best = recalls(pp, fb, bl)
+            points.append(dict(coarse_quantile=q, coarse_threshold=coarse_thr, recall=rec, recall_best=rec_best,
                                fallback_frac=float(fb.mean()), propose_ms=min(t_pr),
                                speedup=min(t_ex) / min(t_pr),
                                same_template=float((pi[det_ex] == ex_idx[det_ex]).mean()) if n_det else float("nan")))
@@ -261,8 +328,9 @@ class Proposer:
         best = max(ok, key=lambda p: p["speedup"]) if ok else max(points, key=lambda p: (p["recall"], p["speedup"]))
         amp = inj[:, 3]
         out = dict(best)
-        out.update(recall_no_fallback=rec(pp_nf), detectable=n_det, realisations=R_signal,
-                   detectable_min_amp=float(amp[det_ex].min()) if n_det else float("nan"),
+        out.update(recall_no_fallback=rec_nf, recall_best_no_fallback=rec_best_nf, detectable=n_near,
+                   detectable_best=n_det, realisations=R_signal,
+                   detectable_min_amp=float(amp[det_near].min()) if n_near else float("nan"),
                    psi_threshold=psi_thr, exhaustive_ms=min(t_ex), n_select=self.n_select,
                    n_select2=self.n_select2, block=self.block, coarse_segments=self.coarse_segments,
                    n_cells=self.n_cells,

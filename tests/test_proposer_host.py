@@ -1,0 +1,61 @@
+"""Host-side logic of the proposer's evaluation (no GPU): the neighbourhood
+of an injection that the detection rule (Sec. 3) reads as "close to it", and
+which templates a proposal evaluated.  Both are checked against brute force
+over every template of the small lattice."""
+import math
+
+import numpy as np
+
+from paper_2507_07816_amd.proposer import close_region, evaluated
+
+FINE = dict(f0_min=500.0, f0_step=0.25, n_f0=400, tau=[3500.0, 7000.0, 14000.0, 35000.0],
+            brake=[3.0, 5.0, 7.0], sky=[[0.0, 0.0, 1.0]])
+
+
+def _params(t):
+    n_f0, n_tau = FINE["n_f0"], len(FINE["tau"])
+    return t % n_f0, (t // n_f0) % n_tau, t // (n_f0 * n_tau)
+
+
+def test_close_region_is_the_brute_force_neighbourhood():
+    r = np.random.default_rng(11)
+    R = 40
+    inj = np.stack([r.uniform(499.0, 601.0, R), np.exp(r.uniform(math.log(3000), math.log(40000), R)),
+                    r.uniform(2.5, 7.5, R)], axis=1)
+    inj[0] = [500.0, 3500.0, 3.0]            # corner of the lattice
+    inj[1] = [599.75, 35000.0, 7.0]          # opposite corner
+    reg = close_region(FINE, inj)
+    assert reg.shape == (R, 45)
+    f0s = FINE["f0_min"] + FINE["f0_step"] * np.arange(FINE["n_f0"])
+    for q in range(R):
+        i0 = int(np.argmin(np.abs(f0s - inj[q, 0])))
+        j0 = int(np.argmin([abs(math.log(inj[q, 1] / t)) for t in FINE["tau"]]))
+        k0 = int(np.argmin([abs(inj[q, 2] - b) for b in FINE["brake"]]))
+        want = [t for t in range(FINE["n_f0"] * 12)
+                if abs(_params(t)[0] - i0) <= 2 and abs(_params(t)[1] - j0) <= 1 and abs(_params(t)[2] - k0) <= 1]
+        got = reg[q][reg[q] >= 0].tolist()
+        assert got == want                    # same set, ascending
+    assert (reg[0] >= 0).sum() == 3 * 2 * 2 and (reg[1] >= 0).sum() == 3 * 2 * 2
+
+
+def test_evaluated_matches_expanded_blocks():
+    L, W = 200, 16
+    nbg = -(-2 * L // W)
+    r = np.random.default_rng(12)
+    R = 30
+    blocks = np.stack([np.sort(r.choice(12 * nbg, 5, replace=False)) for _ in range(R)]).astype(np.int32)
+    blocks[::3, -2:] = -1                     # rows without a second tier
+    fb = (r.uniform(size=R) < 0.2).astype(np.int32)
+    tpl = r.integers(0, 12 * 2 * L, R)
+    tpl[1] = (blocks[1, 0] // nbg) * 2 * L + (blocks[1, 0] % nbg) * W + W - 1   # last cell of a block
+    fb[1] = 0
+    got = evaluated(blocks, fb, tpl, L, W)
+    for q in range(R):
+        cells = set()
+        for b in blocks[q]:
+            if b < 0:
+                continue
+            g, k = divmod(int(b), nbg)
+            cells |= {g * 2 * L + i for i in range(k * W, min(k * W + W, 2 * L))}
+        assert got[q] == (bool(fb[q]) or int(tpl[q]) in cells)
+    assert got[1]
