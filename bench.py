@@ -92,8 +92,8 @@ def cpu_baseline(wl, rho, target_s=15.0):
                       f"({idx.size * n_seg:.3g} evals, {dt:.1f} s, FP64, incl. its Eq. 1 table)"}
 
 
-def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=8, eval_signal=2048, eval_noise=1024, seed=7,
-                 coarse_segments=2, select2_frac=0.05, block=16):
+def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_signal=2048, eval_noise=1024, seed=7,
+                 coarse_segments=4, select2_frac=0.10, block=16, label="near", select_frac=0.05):
     """The learned proposer on the small workload's shape (1024 segments x 800
     bins, 4800 fine templates): trained on `realisations` device-generated
     noise + injection realisations (amplitudes U[0.3, 3]), then recall and
@@ -114,24 +114,24 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=8, eval_sign
     ctau = np.sqrt(tau[0::2] * tau[1::2])
     cbrake = np.array([(brake[0] + brake[1]) / 2, (brake[-2] + brake[-1]) / 2])
     coarse = coarse_grid_for(fine, ctau, cbrake)
-    pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=0.05, store="f32", block=block,
+    pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=select_frac, store="f32", block=block,
                   select2_frac=select2_frac, coarse_segments=coarse_segments)
     steps = max(1, realisations // batch)
     torch.cuda.synchronize()
     t = time.perf_counter()
     losses = pr.train(steps * batch, batch=batch, epochs=epochs, p_signal=0.9, amp_range=(0.3, 3.0), lr=2e-3,
-                      label_psi=4.5)
+                      label_psi=4.5, label=label)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t
     ev = pr.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
                      coarse_quantiles=(1.0, 0.9, 0.7, 0.5, 0.3))
-    untrained = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed + 1, select_frac=0.05, store="f32",
+    untrained = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed + 1, select_frac=select_frac, store="f32",
                          block=block, select2_frac=select2_frac, coarse_segments=coarse_segments)
     ev0 = untrained.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
                              reps=1)
     ctx.close()
     out = {"workload": "tiny-1024seg-800bin-4800tpl realisations", "train_realisations": steps * batch,
-           "epochs": epochs, "label_psi": 4.5,
+           "epochs": epochs, "label_psi": 4.5, "label": label,
            "train_s": train_s, "loss_first": float(np.mean(losses[:5])), "loss_last": float(np.mean(losses[-5:])),
            "coarse_grid": f"{coarse['n_f0']} f0 x {len(ctau)} tau x {len(cbrake)} n", "network": "4-layer CNN, BF16 MFMA",
            "untrained_recall_no_fallback": ev0["recall_no_fallback"], "untrained_fallback_frac": ev0["fallback_frac"]}
@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--tile-shape", type=int, default=-1,
                     help="force the statistic kernel's variant (0..15) instead of autotuning (profiling runs)")
     ap.add_argument("--proposer-realisations", type=int, default=50000)
-    ap.add_argument("--proposer-epochs", type=int, default=8)
+    ap.add_argument("--proposer-epochs", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 1 GiB device-to-device copies (HBM counter calibration)")
     args = ap.parse_args()

@@ -85,6 +85,12 @@ struct StackLevel {
     double t0 = 0.0;
     bool tables = false;                        // g and H hold the last upload's tables
     DevBuf tau, brake, sky, g, H;
+    // per-template moments (W1, W2, N) of the level's weights on the lattice
+    // (m_f0_min, m_f0_step, m_n_f0) of the current tables
+    bool mom = false;
+    double m_f0_min = 0.0, m_f0_step = 0.0;
+    int m_n_f0 = 0;
+    DevBuf mw1, mw2, mn;
 };
 
 // A stack of realisations sharing one detector slot's geometry (the learned
@@ -99,8 +105,11 @@ struct StackState {
     DevBuf fine, crs, w, wq, scale, w2, t, v, t2, v2, params;
     StackLevel lv[2];
     hipEvent_t ev_h2d = nullptr;  // after the last grid upload
-    DevBuf psi_c, x, act, logits, cells, tpl, psi_sel, best_idx, best_psi, fb, rmap, idx_all, psi_all;
+    DevBuf psi_c, x, act, logits, cells, tpl, psi_sel, best_idx, best_psi, fb, rmap, psi_all;
     DevBuf bscore, blk, blk2, tpl2, psi2, cm_idx, cm;
+    // per-realisation step lists of a proposal: rows and flags of the second
+    // tier and of the fallback, their counts, the later bests, the block output
+    DevBuf rows2, flag2, bi2, bp2, counts, blocks;
 };
 
 }  // namespace ltgw

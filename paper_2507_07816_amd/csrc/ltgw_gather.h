@@ -116,6 +116,13 @@ __device__ __forceinline__ void seg_batch(const DetView &D, __amdgpu_buffer_rsrc
 #pragma unroll
         for (int t = 0; t < TPL; ++t)
             p[t][k] = Store<STORE>::get(rs, (int)idx[t][k], (j + k) * D.pitch_bytes, acc.cnt[t]);
+    // the weights are read unconditionally (wave-uniform loads, selected per
+    // lane): a load guarded by the lane's in-band test would become a branch
+    float wv[U];
+    if (MOMENTS) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) wv[k] = D.w[j + k];
+    }
 #pragma unroll
     for (int k = 0; k < U; ++k) {
         const float wq = D.wq[j + k];
@@ -125,7 +132,7 @@ __device__ __forceinline__ void seg_batch(const DetView &D, __amdgpu_buffer_rsrc
             if (MOMENTS) {
                 const bool inb = (idx[t][k] - 1u) < nb;
                 acc.nin[t] += inb ? 1 : 0;
-                const float wj = inb ? D.w[j + k] : 0.0f;
+                const float wj = inb ? wv[k] : 0.0f;
                 w1c[t] += wj;
                 w2c[t] = __builtin_fmaf(wj, wj, w2c[t]);
             }

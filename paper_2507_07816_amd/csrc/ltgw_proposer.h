@@ -6,23 +6,41 @@
 
 namespace ltgw {
 
+// Per-template moments of a stack level (the weights are the same for every
+// realisation): W1 = sum of in-band weights, W2 = sum of their squares, N =
+// in-band segments, each in the statistic's own summation order.
+struct StackMoments {
+    const double *w1, *w2;
+    const int32_t *n;
+};
+
+hipError_t launch_stack_moments(int shift, const EvalArgs &a, double *w1, double *w2, int32_t *n, hipStream_t st);
+
 hipError_t launch_stack_eval(int store, int shift, const EvalArgs &a, int R, int64_t stack_bytes,
-                             int64_t stack_rows, double mu, double var, int nan_to_zero,
-                             double *out_psi, int32_t *out_c, hipStream_t st);
+                             int64_t stack_rows, double mu, double var, int nan_to_zero, const int32_t *rmap,
+                             const int32_t *n_rows, StackMoments m, double *out_psi, hipStream_t st);
 hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,
-                            const int32_t *idx, int m, const int32_t *rmap, double *out_psi, hipStream_t st);
+                            const int32_t *idx, int m, const int32_t *rmap, const int32_t *n_rows, StackMoments mom,
+                            double *out_psi, hipStream_t st);
+// Whether launch_block_eval takes blocks of W templates.
+bool block_eval_supported(int W);
+hipError_t launch_block_eval(int store, int W, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,
+                             const int32_t *blk, int K, int nbg, const int32_t *rmap, const int32_t *n_rows,
+                             StackMoments mom, int32_t *out_tpl, double *out_psi, hipStream_t st);
 hipError_t launch_cells_to_templates(const int32_t *cells, int64_t n, int L, int32_t *tpl, hipStream_t st);
-hipError_t launch_sort_rows(int32_t *idx, int rows, int m, hipStream_t st);
 hipError_t launch_block_scores(const float *logits, int R, int c_out, int L, int W, int nbg, float *score,
                                hipStream_t st);
 hipError_t launch_mask_blocks(float *score, const int32_t *blk, int R, int K, int nb, hipStream_t st);
-hipError_t launch_expand_blocks(const int32_t *blk, int K, int W, int two_L, int nbg, const int32_t *rmap, int rows,
-                                int32_t *tpl, hipStream_t st);
-hipError_t launch_fallback(int R, const double *psi_coarse, int nc, const double *best_psi, double thr,
-                           double cthr, int32_t *fallback, hipStream_t st);
-hipError_t launch_iota_rows(int32_t *idx, int rows, int n, hipStream_t st);
-hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t *idx, int32_t *best_idx,
-                           double *best_psi, hipStream_t st);
+hipError_t launch_expand_blocks(const int32_t *blk, int K, int W, int two_L, int nbg, const int32_t *rmap,
+                                const int32_t *n_rows, int rows, int32_t *tpl, hipStream_t st);
+hipError_t launch_take_rows(int R, const double *best_psi, double thr, const double *cm, double cthr, int32_t *rows,
+                            int32_t *count, int32_t *flag, hipStream_t st);
+hipError_t launch_merge_rows(int R, const int32_t *rows, const int32_t *count, const int32_t *bi, const double *bp,
+                             int32_t *best_idx, double *best_psi, hipStream_t st);
+hipError_t launch_blocks_out(int R, const int32_t *blk1, int K1, const int32_t *blk2, int K2, const int32_t *flag2,
+                             int32_t *out, hipStream_t st);
+hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t *idx, const int32_t *n_rows,
+                           int32_t *best_idx, double *best_psi, hipStream_t st);
 hipError_t launch_templates_to_cells(const int32_t *tpl, int n, int L, const int32_t *mask, const double *psi,
                                      double min_psi, int32_t *cells, hipStream_t st);
 hipError_t launch_noise(uint64_t seed, uint32_t stream, int r0, int R, int64_t n_per, float *out,

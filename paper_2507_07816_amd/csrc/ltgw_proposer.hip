@@ -784,9 +784,72 @@ __global__ __launch_bounds__(256) void select_top_kernel(const float *score, int
     }
 }
 
+// The same selection with one wavefront per row, for n <= 64 Q: entry i sits
+// in slot i / 64 of lane i % 64.  Counts are ballots, so the threshold search
+// runs on wave-uniform values with no barrier; the output position of an
+// entry is the number of entries taken in lower slots plus those of lower
+// lanes in its own slot (mbcnt), which lists them in ascending index order.
+__device__ inline int lanes_below(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void select_top_wave_kernel(const float *score, int R, int n, int M,
+                                                              int32_t *out) {
+    const int row = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (row >= R) return;  // whole wavefronts; the kernel has no barrier
+    const int lane = threadIdx.x & 63;
+    const float *s = score + (int64_t)row * n;
+    uint32_t key[Q];
+    bool real[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        real[q] = q * 64 + lane < n;
+        key[q] = real[q] ? order_key(s[q * 64 + lane]) : 0u;
+    }
+    uint32_t T = 0u;  // the largest T with #(key >= T) >= M over the real entries
+    for (int bit = 31; bit >= 0; --bit) {
+        const uint32_t cand = T | (1u << bit);
+        int cnt = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) cnt += __popcll(__ballot(real[q] && key[q] >= cand));
+        if (cnt >= M) T = cand;
+    }
+    int n_gt = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) n_gt += __popcll(__ballot(real[q] && key[q] > T));
+    const int take_eq = M - n_gt;  // keys equal to T taken, lowest indices first
+    int32_t *o = out + (int64_t)row * M;
+    int pos = 0, eq_seen = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const bool eq = real[q] && key[q] == T;
+        const unsigned long long eqm = __ballot(eq);
+        const bool take = (real[q] && key[q] > T) || (eq && eq_seen + lanes_below(eqm) < take_eq);
+        const unsigned long long tm = __ballot(take);
+        const int at = pos + lanes_below(tm);
+        if (take && at < M) o[at] = q * 64 + lane;
+        pos += __popcll(tm);
+        eq_seen += __popcll(eqm);
+    }
+}
+
 hipError_t launch_select_top(const float *score, int R, int n, int M, int32_t *out, hipStream_t st) {
     if (n < 1 || n > kSelMax || M < 1 || M > n || R < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(select_top_kernel, dim3(R), dim3(256), 0, st, score, n, M, out);
+    const int q = (n + 63) / 64;
+    const dim3 wg((unsigned)((R + 3) / 4)), b(256);
+    if (q <= 1)
+        hipLaunchKernelGGL(select_top_wave_kernel<1>, wg, b, 0, st, score, R, n, M, out);
+    else if (q <= 2)
+        hipLaunchKernelGGL(select_top_wave_kernel<2>, wg, b, 0, st, score, R, n, M, out);
+    else if (q <= 4)
+        hipLaunchKernelGGL(select_top_wave_kernel<4>, wg, b, 0, st, score, R, n, M, out);
+    else if (q <= 8)
+        hipLaunchKernelGGL(select_top_wave_kernel<8>, wg, b, 0, st, score, R, n, M, out);
+    else if (q <= 16)
+        hipLaunchKernelGGL(select_top_wave_kernel<16>, wg, b, 0, st, score, R, n, M, out);
+    else
+        hipLaunchKernelGGL(select_top_kernel, dim3(R), dim3(256), 0, st, score, n, M, out);
     return hipGetLastError();
 }
 

@@ -20,8 +20,8 @@ void free_stack(StackState &S) {
     DevBuf *all[] = {&S.fine,   &S.crs,      &S.w,        &S.wq,    &S.scale,  &S.w2,     &S.t,
                      &S.v,      &S.t2,       &S.v2,       &S.params, &S.psi_c, &S.x,      &S.act,
                      &S.logits, &S.cells,    &S.tpl,      &S.psi_sel, &S.best_idx, &S.best_psi, &S.fb,
-                     &S.rmap,   &S.idx_all,  &S.psi_all, &S.bscore, &S.blk, &S.blk2, &S.tpl2, &S.psi2,
-                     &S.cm_idx, &S.cm};
+                     &S.rmap,   &S.psi_all, &S.bscore, &S.blk, &S.blk2, &S.tpl2, &S.psi2,
+                     &S.cm_idx, &S.cm,      &S.rows2,   &S.flag2, &S.bi2,  &S.bp2,   &S.counts, &S.blocks};
     for (DevBuf *b : all) release(*b);
     for (StackLevel &L : S.lv) {
         release(L.tau);
@@ -29,6 +29,9 @@ void free_stack(StackState &S) {
         release(L.sky);
         release(L.g);
         release(L.H);
+        release(L.mw1);
+        release(L.mw2);
+        release(L.mn);
     }
     if (S.ev_h2d) (void)hipEventDestroy(S.ev_h2d);
     S = StackState();
@@ -54,6 +57,37 @@ int need_stack(ltgw_ctx *c, int level) {
     return LTGW_OK;
 }
 
+EvalArgs stack_args(const StackState &S, int level, const ltgw_grid *g, const SearchPlan &P,
+                    int64_t &stack_bytes, int64_t &stack_rows);
+
+// The per-template moments of a level on g's lattice, formed once per set of
+// tables and lattice (the weights are those of every realisation).
+int stack_moments(ltgw_ctx *c, const ltgw_grid *g, int level, const SearchPlan &P) {
+    StackState &S = c->stack;
+    StackLevel &L = S.lv[level];
+    if (L.mom && L.m_f0_min == g->f0_min && L.m_f0_step == g->f0_step && L.m_n_f0 == g->n_f0) return LTGW_OK;
+    L.mom = false;
+    const int64_t n = P.n_tpl;
+    int rc;
+    if ((rc = ensure(c, L.mw1, (size_t)n * 8, "moments")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, L.mw2, (size_t)n * 8, "moments")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, L.mn, (size_t)n * 4, "moments")) != LTGW_OK) return rc;
+    int64_t sb = 0, sr = 0;
+    const EvalArgs a = stack_args(S, level, g, P, sb, sr);
+    HIP_TRY(c, launch_stack_moments(level, a, (double *)L.mw1.p, (double *)L.mw2.p, (int32_t *)L.mn.p, c->stream),
+            "moments launch");
+    L.m_f0_min = g->f0_min;
+    L.m_f0_step = g->f0_step;
+    L.m_n_f0 = g->n_f0;
+    L.mom = true;
+    return LTGW_OK;
+}
+
+StackMoments level_moments(const StackState &S, int level) {
+    const StackLevel &L = S.lv[level];
+    return StackMoments{(const double *)L.mw1.p, (const double *)L.mw2.p, (const int32_t *)L.mn.p};
+}
+
 // Validate grid g against the stack's detector slot, upload its axes for
 // stack level `level` and form the spin-down (Eq. 1) and track-factor
 // (Eqs. 1-2) tables at the level's segment times and velocities: level 0
@@ -73,8 +107,9 @@ int stack_tables(ltgw_ctx *c, const ltgw_grid *g, int level, SearchPlan &P) {
         std::equal(L.h_tau.begin(), L.h_tau.end(), g->tau) &&
         std::equal(L.h_brake.begin(), L.h_brake.end(), g->brake) &&
         std::equal(L.h_sky.begin(), L.h_sky.end(), g->sky))
-        return LTGW_OK;
+        return stack_moments(c, g, level, P);
     L.tables = false;
+    L.mom = false;
     HIP_TRY(c, hipEventSynchronize(S.ev_h2d), "previous grid upload");
     L.h_tau.assign(g->tau, g->tau + g->n_tau);
     L.h_brake.assign(g->brake, g->brake + g->n_brake);
@@ -98,7 +133,7 @@ int stack_tables(ltgw_ctx *c, const ltgw_grid *g, int level, SearchPlan &P) {
             "track-factor launch");
     L.t0 = g->t0;
     L.tables = true;
-    return LTGW_OK;
+    return stack_moments(c, g, level, P);
 }
 
 // The evaluation arguments of a stack level (realisation 0; the kernels
@@ -158,20 +193,21 @@ int stack_psi_impl(ltgw_ctx *c, const ltgw_grid *g, int level, int nan_to_zero, 
     const int shift = level;
     const int store = level ? LTGW_STORE_BF16 : c->stack.store;
     const double mu = level ? 2.0 * c->stack.S : 1.0;  // a coarse pixel sums 2 S Exp(1) values
-    HIP_TRY(c, launch_stack_eval(store, shift, a, c->stack.R, sb, sr, mu, mu, nan_to_zero, out_psi, nullptr,
-                                 c->stream),
+    HIP_TRY(c, launch_stack_eval(store, shift, a, c->stack.R, sb, sr, mu, mu, nan_to_zero, nullptr, nullptr,
+                                 level_moments(c->stack, level), out_psi, c->stream),
             "stack evaluation launch");
     return LTGW_OK;
 }
 
 int list_psi_impl(ltgw_ctx *c, const ltgw_grid *g, const int32_t *idx, int rows, int32_t m,
-                  const int32_t *rmap, double *out_psi, SearchPlan *plan_out) {
+                  const int32_t *rmap, const int32_t *n_rows, double *out_psi, SearchPlan *plan_out) {
     SearchPlan P;
     int rc = stack_tables(c, g, 0, P);
     if (rc != LTGW_OK) return rc;
     int64_t sb = 0, sr = 0;
     const EvalArgs a = stack_args(c->stack, 0, g, P, sb, sr);
-    HIP_TRY(c, launch_list_eval(c->stack.store, a, rows, sb, sr, idx, m, rmap, out_psi, c->stream),
+    HIP_TRY(c, launch_list_eval(c->stack.store, a, rows, sb, sr, idx, m, rmap, n_rows, level_moments(c->stack, 0),
+                                out_psi, c->stream),
             "listed evaluation launch");
     if (plan_out) *plan_out = P;
     return LTGW_OK;
@@ -342,7 +378,7 @@ int32_t ltgw_stack_psi_list(ltgw_ctx *c, const ltgw_grid *g, const int32_t *idx,
     if (m < 1) return fail(c, LTGW_E_INVALID_ARG, "m must be >= 1");
     if ((rc = need_device(c, idx, "idx")) != LTGW_OK) return rc;
     if ((rc = need_device(c, out_psi, "out_psi")) != LTGW_OK) return rc;
-    return list_psi_impl(c, g, idx, c->stack.R, m, nullptr, out_psi, nullptr);
+    return list_psi_impl(c, g, idx, c->stack.R, m, nullptr, nullptr, out_psi, nullptr);
 }
 
 int64_t ltgw_cnn_param_count(int32_t c_in, int32_t c_out) {
@@ -463,7 +499,8 @@ int32_t ltgw_stack_best(ltgw_ctx *c, const ltgw_grid *g, int32_t *best_index, do
     if (n < 1) return fail(c, LTGW_E_INVALID_ARG, "empty grid");
     if ((rc = ensure(c, S.psi_all, (size_t)(S.R * n) * 8, "fine ratios")) != LTGW_OK) return rc;
     if ((rc = stack_psi_impl(c, g, 0, 0, (double *)S.psi_all.p)) != LTGW_OK) return rc;
-    HIP_TRY(c, launch_row_best((const double *)S.psi_all.p, S.R, n, nullptr, best_index, best_psi, c->stream),
+    HIP_TRY(c, launch_row_best((const double *)S.psi_all.p, S.R, n, nullptr, nullptr, best_index, best_psi,
+                               c->stream),
             "reduction launch");
     return LTGW_OK;
 }
@@ -525,6 +562,7 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
                 {&S.cm_idx, (size_t)R * 4},              {&S.cm, (size_t)R * 8}};
     for (auto &n : need)
         if ((rc = ensure(c, *n.b, n.bytes, "proposer buffers")) != LTGW_OK) return rc;
+    // Every step is queued on the stream; the host waits once, for the outputs.
     // 1. coarse map -> network -> block scores -> the K1 best blocks -> their exact fine ratios
     if ((rc = stack_psi_impl(c, coarse, 1, 1, (double *)S.psi_c.p)) != LTGW_OK) return rc;
     HIP_TRY(c, launch_f64_to_f32((const double *)S.psi_c.p, (float *)S.x.p, R * nc, c->stream), "input convert");
@@ -535,114 +573,105 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
             "block score launch");
     HIP_TRY(c, launch_select_top((const float *)S.bscore.p, R, (int)nb, K1, (int32_t *)S.blk.p, c->stream),
             "selection launch");
-    HIP_TRY(c, launch_expand_blocks((const int32_t *)S.blk.p, K1, W, 2 * L, nbg, nullptr, R, (int32_t *)S.tpl.p,
-                                    c->stream),
-            "block expansion launch");
     SearchPlan P;
-    if ((rc = list_psi_impl(c, fine, (const int32_t *)S.tpl.p, R, M1, nullptr, (double *)S.psi_sel.p, &P)) != LTGW_OK)
-        return rc;
-    HIP_TRY(c, launch_row_best((const double *)S.psi_sel.p, R, M1, (const int32_t *)S.tpl.p, (int32_t *)S.best_idx.p,
-                               (double *)S.best_psi.p, c->stream),
-            "reduction launch");
-    HIP_TRY(c, launch_row_best((const double *)S.psi_c.p, R, nc, nullptr, (int32_t *)S.cm_idx.p, (double *)S.cm.p,
-                               c->stream),
-            "coarse maximum launch");
-    std::vector<double> cm((size_t)R);
-    HIP_TRY(c, hipMemcpyAsync(best_index, S.best_idx.p, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");
-    HIP_TRY(c, hipMemcpyAsync(best_psi, S.best_psi.p, (size_t)R * 8, hipMemcpyDeviceToHost, c->stream), "copy");
-    HIP_TRY(c, hipMemcpyAsync(cm.data(), S.cm.p, (size_t)R * 8, hipMemcpyDeviceToHost, c->stream), "copy");
-    const int KB = K1 + K2;
-    std::vector<int32_t> hb1(p->blocks ? (size_t)R * K1 : 0);
-    if (p->blocks)
-        HIP_TRY(c, hipMemcpyAsync(hb1.data(), S.blk.p, hb1.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy");
-    HIP_TRY(c, hipStreamSynchronize(c->stream), "propose");
-    if (p->blocks)
-        for (int r = 0; r < R; ++r) {
-            std::copy(hb1.begin() + (size_t)r * K1, hb1.begin() + (size_t)(r + 1) * K1, p->blocks + (size_t)r * KB);
-            std::fill(p->blocks + (size_t)r * KB + K1, p->blocks + (size_t)(r + 1) * KB, -1);
+    if ((rc = stack_tables(c, fine, 0, P)) != LTGW_OK) return rc;
+    int64_t sb = 0, sr = 0;
+    const EvalArgs fa = stack_args(S, 0, fine, P, sb, sr);
+    const StackMoments fm = level_moments(S, 0);
+    // the templates of the chosen blocks and their exact ratios: in place for
+    // blocks of 16, 32 or 64, else through an expanded list
+    auto eval_blocks = [&](const int32_t *blk, int K, const int32_t *rmap, const int32_t *n_rows, int32_t *tpl,
+                           double *psi) -> int {
+        if (block_eval_supported(W)) {
+            HIP_TRY(c, launch_block_eval(S.store, W, fa, R, sb, sr, blk, K, nbg, rmap, n_rows, fm, tpl, psi, c->stream),
+                    "block evaluation launch");
+            return LTGW_OK;
         }
-    const double thr = p->psi_threshold;
-    // merge a later result into the best so far (larger ratio; ties to the lower index)
-    auto merge = [&](int r, int32_t i, double v) {
-        if (i < 0 || !(v == v)) return;
-        if (best_index[r] < 0 || v > best_psi[r] || (v == best_psi[r] && i < best_index[r])) {
-            best_index[r] = i;
-            best_psi[r] = v;
-        }
+        HIP_TRY(c, launch_expand_blocks(blk, K, W, 2 * L, nbg, rmap, n_rows, R, tpl, c->stream),
+                "block expansion launch");
+        HIP_TRY(c, launch_list_eval(S.store, fa, R, sb, sr, tpl, K * W, rmap, n_rows, fm, psi, c->stream),
+                "listed evaluation launch");
+        return LTGW_OK;
     };
-    // 2. realisations with no cell above the threshold: the next K2 blocks
-    std::vector<int32_t> rows;
-    for (int r = 0; r < R; ++r)
-        if (!(best_psi[r] > thr)) rows.push_back(r);
-    if (K2 > 0 && !rows.empty()) {
-        const int n2 = (int)rows.size();
+    if ((rc = eval_blocks((const int32_t *)S.blk.p, K1, nullptr, nullptr, (int32_t *)S.tpl.p,
+                          (double *)S.psi_sel.p)) != LTGW_OK)
+        return rc;
+    int32_t *best_i = (int32_t *)S.best_idx.p;
+    double *best_p = (double *)S.best_psi.p;
+    HIP_TRY(c, launch_row_best((const double *)S.psi_sel.p, R, M1, (const int32_t *)S.tpl.p, nullptr, best_i, best_p,
+                               c->stream),
+            "reduction launch");
+    HIP_TRY(c, launch_row_best((const double *)S.psi_c.p, R, nc, nullptr, nullptr, (int32_t *)S.cm_idx.p,
+                               (double *)S.cm.p, c->stream),
+            "coarse maximum launch");
+    const double thr = p->psi_threshold;
+    const int64_t n_tpl = P.n_tpl;
+    if ((int64_t)R * n_tpl > ((int64_t)1 << 31))
+        return fail(c, LTGW_E_UNSUPPORTED, "fallback ratios of %d realisations x %lld templates too large", R,
+                    (long long)n_tpl);
+    struct {
+        DevBuf *b;
+        size_t bytes;
+    } need2[] = {{&S.rmap, (size_t)R * 4}, {&S.fb, (size_t)R * 4},        {&S.bi2, (size_t)R * 4},
+                 {&S.bp2, (size_t)R * 8},  {&S.counts, 2 * sizeof(int32_t)}, {&S.psi_all, (size_t)(R * n_tpl) * 8}};
+    for (auto &n : need2)
+        if ((rc = ensure(c, *n.b, n.bytes, "proposer buffers")) != LTGW_OK) return rc;
+    int32_t *counts = (int32_t *)S.counts.p;
+    // 2. realisations with no template above the threshold (listed on the device): the next K2 blocks
+    if (K2 > 0) {
         struct {
             DevBuf *b;
             size_t bytes;
-        } need2[] = {{&S.blk2, (size_t)R * K2 * 4}, {&S.tpl2, (size_t)n2 * M2 * 4}, {&S.psi2, (size_t)n2 * M2 * 8},
-                     {&S.rmap, (size_t)n2 * 4}};
-        for (auto &n : need2)
+        } need3[] = {{&S.blk2, (size_t)R * K2 * 4}, {&S.tpl2, (size_t)R * M2 * 4}, {&S.psi2, (size_t)R * M2 * 8},
+                     {&S.rows2, (size_t)R * 4},     {&S.flag2, (size_t)R * 4}};
+        for (auto &n : need3)
             if ((rc = ensure(c, *n.b, n.bytes, "proposer buffers")) != LTGW_OK) return rc;
-        if ((rc = h2d(c, S.rmap.p, rows.data(), (size_t)n2 * 4, "row upload")) != LTGW_OK) return rc;
+        const int32_t *rows2 = (const int32_t *)S.rows2.p;
+        HIP_TRY(c, launch_take_rows(R, best_p, thr, nullptr, 0.0, (int32_t *)S.rows2.p, counts, (int32_t *)S.flag2.p,
+                                    c->stream),
+                "second-tier rows launch");
         HIP_TRY(c, launch_mask_blocks((float *)S.bscore.p, (const int32_t *)S.blk.p, R, K1, (int)nb, c->stream),
                 "block mask launch");
         HIP_TRY(c, launch_select_top((const float *)S.bscore.p, R, (int)nb, K2, (int32_t *)S.blk2.p, c->stream),
                 "selection launch");
-        HIP_TRY(c, launch_expand_blocks((const int32_t *)S.blk2.p, K2, W, 2 * L, nbg, (const int32_t *)S.rmap.p, n2,
-                                        (int32_t *)S.tpl2.p, c->stream),
-                "block expansion launch");
-        if ((rc = list_psi_impl(c, fine, (const int32_t *)S.tpl2.p, n2, M2, (const int32_t *)S.rmap.p,
-                                (double *)S.psi2.p, nullptr)) != LTGW_OK)
+        if ((rc = eval_blocks((const int32_t *)S.blk2.p, K2, rows2, counts, (int32_t *)S.tpl2.p,
+                              (double *)S.psi2.p)) != LTGW_OK)
             return rc;
-        HIP_TRY(c, launch_row_best((const double *)S.psi2.p, n2, M2, (const int32_t *)S.tpl2.p,
-                                   (int32_t *)S.best_idx.p, (double *)S.best_psi.p, c->stream),
+        HIP_TRY(c, launch_row_best((const double *)S.psi2.p, R, M2, (const int32_t *)S.tpl2.p, counts,
+                                   (int32_t *)S.bi2.p, (double *)S.bp2.p, c->stream),
                 "reduction launch");
-        std::vector<int32_t> bi((size_t)n2);
-        std::vector<double> bp((size_t)n2);
-        std::vector<int32_t> hb2(p->blocks ? (size_t)R * K2 : 0);
-        HIP_TRY(c, hipMemcpyAsync(bi.data(), S.best_idx.p, (size_t)n2 * 4, hipMemcpyDeviceToHost, c->stream), "copy");
-        HIP_TRY(c, hipMemcpyAsync(bp.data(), S.best_psi.p, (size_t)n2 * 8, hipMemcpyDeviceToHost, c->stream), "copy");
-        if (p->blocks)
-            HIP_TRY(c, hipMemcpyAsync(hb2.data(), S.blk2.p, hb2.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy");
-        HIP_TRY(c, hipStreamSynchronize(c->stream), "propose second tier");
-        for (int q = 0; q < n2; ++q) merge(rows[(size_t)q], bi[(size_t)q], bp[(size_t)q]);
-        if (p->blocks)
-            for (int32_t r : rows)
-                std::copy(hb2.begin() + (size_t)r * K2, hb2.begin() + (size_t)(r + 1) * K2,
-                          p->blocks + (size_t)r * KB + K1);
+        HIP_TRY(c, launch_merge_rows(R, rows2, counts, (const int32_t *)S.bi2.p, (const double *)S.bp2.p, best_i,
+                                     best_p, c->stream),
+                "merge launch");
     }
-    // 3. the fallback rule: a loud coarse map and still no cell above the threshold
-    rows.clear();
-    for (int r = 0; r < R; ++r) {
-        fallback[r] = (cm[(size_t)r] > p->coarse_threshold && !(best_psi[r] > thr)) ? 1 : 0;
-        if (fallback[r]) rows.push_back(r);
-    }
-    if (rows.empty()) return LTGW_OK;
-    const int nf = (int)rows.size();
-    const int64_t n_tpl = P.n_tpl;
-    if ((int64_t)nf * n_tpl >= ((int64_t)1 << 31))
-        return fail(c, LTGW_E_UNSUPPORTED, "fallback of %d realisations x %lld templates too large", nf,
-                    (long long)n_tpl);
-    if ((rc = ensure(c, S.rmap, (size_t)nf * 4, "fallback rows")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.idx_all, (size_t)(nf * n_tpl) * 4, "fallback templates")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, S.psi_all, (size_t)(nf * n_tpl) * 8, "fallback ratios")) != LTGW_OK) return rc;
-    if ((rc = h2d(c, S.rmap.p, rows.data(), (size_t)nf * 4, "fallback rows upload")) != LTGW_OK) return rc;
-    HIP_TRY(c, launch_iota_rows((int32_t *)S.idx_all.p, nf, (int)n_tpl, c->stream), "template list launch");
-    if ((rc = list_psi_impl(c, fine, (const int32_t *)S.idx_all.p, nf, (int32_t)n_tpl, (const int32_t *)S.rmap.p,
-                            (double *)S.psi_all.p, nullptr)) != LTGW_OK)
-        return rc;
-    HIP_TRY(c, launch_row_best((const double *)S.psi_all.p, nf, n_tpl, nullptr, (int32_t *)S.best_idx.p,
-                               (double *)S.best_psi.p, c->stream),
+    // 3. the fallback rule: a loud coarse map and still no template above the
+    // threshold -> the exhaustive fine search of those realisations (the same
+    // sums as a list of every template)
+    HIP_TRY(c, launch_take_rows(R, best_p, thr, (const double *)S.cm.p, p->coarse_threshold, (int32_t *)S.rmap.p,
+                                counts + 1, (int32_t *)S.fb.p, c->stream),
+            "fallback rows launch");
+    HIP_TRY(c, launch_stack_eval(S.store, 0, fa, R, sb, sr, 1.0, 1.0, 0, (const int32_t *)S.rmap.p, counts + 1, fm,
+                                 (double *)S.psi_all.p, c->stream),
+            "fallback evaluation launch");
+    HIP_TRY(c, launch_row_best((const double *)S.psi_all.p, R, n_tpl, nullptr, counts + 1, (int32_t *)S.bi2.p,
+                               (double *)S.bp2.p, c->stream),
             "reduction launch");
-    std::vector<int32_t> bi((size_t)nf);
-    std::vector<double> bp((size_t)nf);
-    HIP_TRY(c, hipMemcpyAsync(bi.data(), S.best_idx.p, (size_t)nf * 4, hipMemcpyDeviceToHost, c->stream), "copy");
-    HIP_TRY(c, hipMemcpyAsync(bp.data(), S.best_psi.p, (size_t)nf * 8, hipMemcpyDeviceToHost, c->stream), "copy");
-    HIP_TRY(c, hipStreamSynchronize(c->stream), "propose fallback");
-    for (int q = 0; q < nf; ++q) {  // the exhaustive best of the realisation
-        best_index[rows[(size_t)q]] = bi[(size_t)q];
-        best_psi[rows[(size_t)q]] = bp[(size_t)q];
+    HIP_TRY(c, launch_merge_rows(R, (const int32_t *)S.rmap.p, counts + 1, (const int32_t *)S.bi2.p,
+                                 (const double *)S.bp2.p, best_i, best_p, c->stream),
+            "merge launch");
+    const int KB = K1 + K2;
+    if (p->blocks) {
+        if ((rc = ensure(c, S.blocks, (size_t)R * KB * 4, "proposer buffers")) != LTGW_OK) return rc;
+        HIP_TRY(c, launch_blocks_out(R, (const int32_t *)S.blk.p, K1, (const int32_t *)S.blk2.p, K2,
+                                     (const int32_t *)S.flag2.p, (int32_t *)S.blocks.p, c->stream),
+                "block output launch");
+        HIP_TRY(c, hipMemcpyAsync(p->blocks, S.blocks.p, (size_t)R * KB * 4, hipMemcpyDeviceToHost, c->stream),
+                "copy");
     }
+    HIP_TRY(c, hipMemcpyAsync(best_index, best_i, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");
+    HIP_TRY(c, hipMemcpyAsync(best_psi, best_p, (size_t)R * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+    HIP_TRY(c, hipMemcpyAsync(fallback, S.fb.p, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "propose");
     return LTGW_OK;
 }
 

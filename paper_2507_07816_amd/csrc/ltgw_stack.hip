@@ -12,20 +12,83 @@ namespace ltgw {
 // ---------------------------------------------------------------------------
 // Stacks of realisations (the learned proposer's data): R spectrograms of one
 // geometry, realisation r at byte offset r * stack_bytes of the store and
-// r * stack_rows of the per-row weights.  One launch evaluates every template
-// of a grid on every realisation and writes the power critical ratio
+// r * stack_rows of the per-row weights.  The weights are the same for every
+// realisation, so each template's moments W1, W2, N are formed once per
+// lattice (stack_moments_kernel) in the order the in-loop sums would take:
+// FP32 over chunks of 32 segments, carried in FP64.
+template <int SHIFT>
+__global__ __launch_bounds__(256) void stack_moments_kernel(const EvalArgs a, double *__restrict__ w1,
+                                                            double *__restrict__ w2, int32_t *__restrict__ n) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)a.n_groups * a.n_f0) return;
+    const int grp = (int)(t / a.n_f0), i = (int)(t % a.n_f0);
+    const DetView &D = a.det[0];
+    const double f0 = a.f0_min + (double)i * a.f0_step;
+    const double *__restrict__ H = D.H + (int64_t)grp * D.n_seg;
+    const unsigned nb = (unsigned)D.n_bins;
+    double W1 = 0.0, W2 = 0.0;
+    int N = 0;
+    for (int j0 = 0; j0 < D.n_seg; j0 += kChunk) {
+        const int je = min(j0 + kChunk, D.n_seg);
+        float c1 = 0.0f, c2 = 0.0f;
+        for (int j = j0; j < je; ++j) {
+            const double x = f0 * H[j];
+            const double vv = x + D.cshift;
+            const unsigned idx = (unsigned)__double2int_rz(vv) >> SHIFT;
+            const bool inb = (idx - 1u) < nb;
+            N += inb ? 1 : 0;
+            const float wv = D.w[j];
+            const float wj = inb ? wv : 0.0f;
+            c1 += wj;
+            c2 = __builtin_fmaf(wj, wj, c2);
+        }
+        W1 += (double)c1;
+        W2 += (double)c2;
+    }
+    w1[t] = W1;
+    w2[t] = W2;
+    n[t] = N;
+}
+
+hipError_t launch_stack_moments(int shift, const EvalArgs &a, double *w1, double *w2, int32_t *n, hipStream_t st) {
+    const int64_t t = (int64_t)a.n_groups * a.n_f0;
+    if (t < 1 || t > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((t + 255) / 256)), block(256);
+    if (shift == 0)
+        hipLaunchKernelGGL(stack_moments_kernel<0>, grid, block, 0, st, a, w1, w2, n);
+    else
+        hipLaunchKernelGGL(stack_moments_kernel<1>, grid, block, 0, st, a, w1, w2, n);
+    return hipGetLastError();
+}
+
+// The critical ratio of template tt from its power sum s and the moments:
 //     Psi = (s - mu W1) / sqrt(var W2)
 // with the per-pixel noise mean mu and variance var of the store (Exp(1):
-// 1, 1; a 2x2 sum of Exp(1): 4, 4), NaN (or 0 with nan_to_zero) for N = 0.
+// 1, 1; a sum of m Exp(1): m, m); N = 0 gives NaN (or 0 with nan_to_zero).
+__device__ inline double stack_ratio(double s, const StackMoments &m, int64_t tt, double mu, double var,
+                                     int nan_to_zero) {
+    if (m.n[tt] == 0) return nan_to_zero ? 0.0 : __builtin_nan("");
+    const double num = s - mu * m.w1[tt];
+    return num / sqrt(var * m.w2[tt]);
+}
+
+// Every template of a grid on every realisation: the power critical ratio.
+// Output row rr holds realisation rmap[rr] (rr without a map); with a device
+// row count n_rows, rows rr >= *n_rows are skipped.
 template <int STORE, int SHIFT>
 __global__ __launch_bounds__(256) void stack_eval_kernel(const EvalArgs a, int64_t stack_bytes,
                                                          int64_t stack_rows, double mu, double var,
-                                                         int nan_to_zero, double *__restrict__ out_psi,
-                                                         int32_t *__restrict__ out_c) {
+                                                         int nan_to_zero, const int32_t *__restrict__ rmap,
+                                                         const int32_t *__restrict__ n_rows, const StackMoments m,
+                                                         double *__restrict__ out_psi) {
+    if (n_rows && (int)blockIdx.y >= *n_rows) return;
     const int n_tiles = (a.n_f0 + 255) / 256;
     int tile, grp;
     xcd_tile_group(blockIdx.x, gridDim.x, n_tiles, tile, grp);
-    const int r = blockIdx.y;
+    // a wave whose 64 f0 all lie past the grid has nothing to do (no barrier follows)
+    if (tile * 256 + (int)(threadIdx.x & ~63u) >= a.n_f0) return;
+    const int rr = blockIdx.y;
+    const int r = rmap ? rmap[rr] : rr;
     int i[1] = {tile * 256 + (int)threadIdx.x};
     double f0[1] = {a.f0_min + (double)i[0] * a.f0_step};
     DetView D = a.det[0];
@@ -34,54 +97,52 @@ __global__ __launch_bounds__(256) void stack_eval_kernel(const EvalArgs a, int64
     D.w += (int64_t)r * stack_rows;
     Acc<1> acc;
     acc.zero();
-    accumulate_det<STORE, true, 1, 16, HTable, SHIFT>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc);
+    accumulate_det<STORE, false, 1, 16, HTable, SHIFT>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc);
     if (i[0] >= a.n_f0) return;
-    const int64_t t = (int64_t)r * ((int64_t)a.n_groups * a.n_f0) + (int64_t)grp * a.n_f0 + i[0];
-    double psi;
-    if (acc.nin[0] == 0) {
-        psi = nan_to_zero ? 0.0 : __builtin_nan("");
-    } else {
-        const double num = acc.s[0] - mu * acc.w1[0];
-        psi = num / sqrt(var * acc.w2[0]);
-    }
-    out_psi[t] = psi;
-    if (out_c) out_c[t] = acc.cnt[0];
+    const int64_t tt = (int64_t)grp * a.n_f0 + i[0];
+    out_psi[(int64_t)rr * ((int64_t)a.n_groups * a.n_f0) + tt] = stack_ratio(acc.s[0], m, tt, mu, var, nan_to_zero);
 }
 
 hipError_t launch_stack_eval(int store, int shift, const EvalArgs &a, int R, int64_t stack_bytes,
-                             int64_t stack_rows, double mu, double var, int nan_to_zero,
-                             double *out_psi, int32_t *out_c, hipStream_t st) {
+                             int64_t stack_rows, double mu, double var, int nan_to_zero, const int32_t *rmap,
+                             const int32_t *n_rows, StackMoments m, double *out_psi, hipStream_t st) {
     const int64_t blocks = (int64_t)((a.n_f0 + 255) / 256) * a.n_groups;
     if (blocks > 0x7fffffff || R > 65535 || R < 1) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks, (unsigned)R), block(256);
+#define LTGW_STACK_EVAL(S, SH)                                                                                   \
+    hipLaunchKernelGGL((stack_eval_kernel<S, SH>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, \
+                       nan_to_zero, rmap, n_rows, m, out_psi)
     if (store == LTGW_STORE_F32 && shift == 0)
-        hipLaunchKernelGGL((stack_eval_kernel<LTGW_STORE_F32, 0>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, nan_to_zero, out_psi, out_c);
+        LTGW_STACK_EVAL(LTGW_STORE_F32, 0);
     else if (store == LTGW_STORE_BF16 && shift == 0)
-        hipLaunchKernelGGL((stack_eval_kernel<LTGW_STORE_BF16, 0>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, nan_to_zero, out_psi, out_c);
+        LTGW_STACK_EVAL(LTGW_STORE_BF16, 0);
     else if (store == LTGW_STORE_BF16 && shift == 1)
-        hipLaunchKernelGGL((stack_eval_kernel<LTGW_STORE_BF16, 1>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, nan_to_zero, out_psi, out_c);
+        LTGW_STACK_EVAL(LTGW_STORE_BF16, 1);
     else if (store == LTGW_STORE_FP8 && shift == 0)
-        hipLaunchKernelGGL((stack_eval_kernel<LTGW_STORE_FP8, 0>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, nan_to_zero, out_psi, out_c);
+        LTGW_STACK_EVAL(LTGW_STORE_FP8, 0);
     else
         return hipErrorInvalidValue;
+#undef LTGW_STACK_EVAL
     return hipGetLastError();
 }
 
 // Explicit template lists: lane q of realisation r evaluates template
 // idx[r][q] of the grid (any order; each lane reads its own group's track
-// factors).  Writes the power critical ratio (mu = var = 1) or NaN.
+// factors).  Writes the power critical ratio (mu = var = 1) or NaN.  Rows
+// rr >= *n_rows are skipped when the device count n_rows is given.
 template <int STORE>
 __global__ __launch_bounds__(256) void list_eval_kernel(const EvalArgs a, int64_t stack_bytes,
                                                         int64_t stack_rows, const int32_t *__restrict__ idx,
                                                         int m, const int32_t *__restrict__ rmap,
+                                                        const int32_t *__restrict__ n_rows, const StackMoments mom,
                                                         double *__restrict__ out_psi) {
     const int q = blockIdx.x * 256 + threadIdx.x;
     const int rr = blockIdx.y;                  // row of idx and out_psi
+    if (n_rows && rr >= *n_rows) return;
     const int r = rmap ? rmap[rr] : rr;         // realisation of the stack
     DetView D = a.det[0];
     D.store = (const char *)D.store + (int64_t)r * stack_bytes;
     D.wq += (int64_t)r * stack_rows;
-    D.w += (int64_t)r * stack_rows;
     const int64_t n_tpl = (int64_t)a.n_groups * a.n_f0;
     int t = q < m ? idx[(int64_t)rr * m + q] : 0;
     const bool bad = t < 0 || t >= n_tpl;  // not a template of the grid: NaN
@@ -91,12 +152,11 @@ __global__ __launch_bounds__(256) void list_eval_kernel(const EvalArgs a, int64_
     const double *__restrict__ H = D.H + (int64_t)grp * D.n_seg;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)D.store, Store<STORE>::kBytes, D.n_bins + 2, kBufDword3);
-    const unsigned nb = (unsigned)D.n_bins;
-    double s = 0.0, w1 = 0.0, w2 = 0.0;
-    int cnt = 0, nin = 0;
+    double s = 0.0;
+    int cnt = 0;
     for (int j0 = 0; j0 < D.n_seg; j0 += kChunk) {
         const int je = min(j0 + kChunk, D.n_seg);
-        float sc = 0.0f, w1c = 0.0f, w2c = 0.0f;
+        float sc = 0.0f;
         int j = j0;
         // batches of 8 segments: the track factors, then the gathers, then the
         // sums in segment order (the same sums as one segment at a time)
@@ -112,45 +172,141 @@ __global__ __launch_bounds__(256) void list_eval_kernel(const EvalArgs a, int64_
 #pragma unroll
             for (int k = 0; k < 8; ++k) p[k] = Store<STORE>::get(rs, (int)ix[k], (j + k) * D.pitch_bytes, cnt);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                sc = __builtin_fmaf(D.wq[j + k], p[k], sc);
-                const bool inb = (ix[k] - 1u) < nb;
-                nin += inb ? 1 : 0;
-                const float wj = inb ? D.w[j + k] : 0.0f;
-                w1c += wj;
-                w2c = __builtin_fmaf(wj, wj, w2c);
-            }
+            for (int k = 0; k < 8; ++k) sc = __builtin_fmaf(D.wq[j + k], p[k], sc);
         }
         for (; j < je; ++j) {
             const double x = f0 * H[j];
             const double vv = x + D.cshift;
             const unsigned ix = (unsigned)__double2int_rz(vv);
-            const float p = Store<STORE>::get(rs, (int)ix, j * D.pitch_bytes, cnt);
-            sc = __builtin_fmaf(D.wq[j], p, sc);
-            const bool inb = (ix - 1u) < nb;
-            nin += inb ? 1 : 0;
-            const float wj = inb ? D.w[j] : 0.0f;
-            w1c += wj;
-            w2c = __builtin_fmaf(wj, wj, w2c);
+            sc = __builtin_fmaf(D.wq[j], Store<STORE>::get(rs, (int)ix, j * D.pitch_bytes, cnt), sc);
         }
         s += (double)sc;
-        w1 += (double)w1c;
-        w2 += (double)w2c;
     }
     if (q >= m) return;
-    out_psi[(int64_t)rr * m + q] = (nin && !bad) ? (s - w1) / sqrt(w2) : __builtin_nan("");
+    out_psi[(int64_t)rr * m + q] = bad ? __builtin_nan("") : stack_ratio(s, mom, t, 1.0, 1.0, 0);
 }
 
 hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,
-                            const int32_t *idx, int m, const int32_t *rmap, double *out_psi, hipStream_t st) {
+                            const int32_t *idx, int m, const int32_t *rmap, const int32_t *n_rows, StackMoments mom,
+                            double *out_psi, hipStream_t st) {
     if (R > 65535 || R < 1 || m < 1) return hipErrorInvalidValue;
     dim3 grid((unsigned)((m + 255) / 256), (unsigned)R), block(256);
     if (store == LTGW_STORE_F32)
-        hipLaunchKernelGGL(list_eval_kernel<LTGW_STORE_F32>, grid, block, 0, st, a, stack_bytes, stack_rows, idx, m, rmap, out_psi);
+        hipLaunchKernelGGL(list_eval_kernel<LTGW_STORE_F32>, grid, block, 0, st, a, stack_bytes, stack_rows, idx, m, rmap, n_rows, mom, out_psi);
     else if (store == LTGW_STORE_BF16)
-        hipLaunchKernelGGL(list_eval_kernel<LTGW_STORE_BF16>, grid, block, 0, st, a, stack_bytes, stack_rows, idx, m, rmap, out_psi);
+        hipLaunchKernelGGL(list_eval_kernel<LTGW_STORE_BF16>, grid, block, 0, st, a, stack_bytes, stack_rows, idx, m, rmap, n_rows, mom, out_psi);
     else
-        hipLaunchKernelGGL(list_eval_kernel<LTGW_STORE_FP8>, grid, block, 0, st, a, stack_bytes, stack_rows, idx, m, rmap, out_psi);
+        hipLaunchKernelGGL(list_eval_kernel<LTGW_STORE_FP8>, grid, block, 0, st, a, stack_bytes, stack_rows, idx, m, rmap, n_rows, mom, out_psi);
+    return hipGetLastError();
+}
+
+// Proposal blocks evaluated in place: workgroup (x, rr) takes NB = 256 / W
+// blocks blk[r][x NB .. x NB + NB) of realisation r = rmap[rr] (or rr), W
+// lanes per block, lane l on fine f0 index (b % nbg) W + l of group b / nbg.
+// The blocks' track factors are staged in LDS per chunk of 32 segments, so
+// the only vector-memory access per template and segment is the gather; the
+// sums are those of the listed evaluation, in the same order.  Writes the
+// expanded template (-1 past the grid) and its ratio (NaN there).
+template <int STORE, int W>
+__global__ __launch_bounds__(256) void block_eval_kernel(const EvalArgs a, int64_t stack_bytes, int64_t stack_rows,
+                                                         const int32_t *__restrict__ blk, int K, int nbg,
+                                                         const int32_t *__restrict__ rmap,
+                                                         const int32_t *__restrict__ n_rows, const StackMoments mom,
+                                                         int32_t *__restrict__ out_tpl,
+                                                         double *__restrict__ out_psi) {
+    constexpr int NB = 256 / W;
+    __shared__ double sh[NB][kChunk];
+    __shared__ int sg[NB];
+    const int rr = blockIdx.y;
+    if (n_rows && rr >= *n_rows) return;  // the whole workgroup, before any barrier
+    const int r = rmap ? rmap[rr] : rr;
+    const int slot = (int)threadIdx.x / W, lf = (int)threadIdx.x % W;
+    const int q = (int)blockIdx.x * NB + slot;
+    const int b = q < K ? blk[(int64_t)r * K + q] : -1;
+    const int i = (b >= 0 ? (b % nbg) * W : 0) + lf;
+    const bool valid = b >= 0 && i < a.n_f0;
+    const int grp = b >= 0 ? b / nbg : 0;
+    if (lf == 0) sg[slot] = grp;
+    DetView D = a.det[0];
+    D.store = (const char *)D.store + (int64_t)r * stack_bytes;
+    D.wq += (int64_t)r * stack_rows;
+    const double f0 = a.f0_min + (double)(valid ? i : 0) * a.f0_step;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)D.store, Store<STORE>::kBytes, D.n_bins + 2, kBufDword3);
+    const double *hrow = sh[slot];
+    double s = 0.0;
+    int cnt = 0;
+    for (int j0 = 0; j0 < D.n_seg; j0 += kChunk) {
+        const int nj = min(kChunk, D.n_seg - j0);
+        __syncthreads();  // sg is written; the previous chunk's factors are read
+        for (int e = (int)threadIdx.x; e < NB * kChunk; e += 256) {
+            const int sl = e / kChunk, k = e % kChunk;
+            sh[sl][k] = k < nj ? D.H[(int64_t)sg[sl] * D.n_seg + j0 + k] : 0.0;
+        }
+        __syncthreads();
+        float sc = 0.0f;
+        if (nj == kChunk) {
+#pragma unroll 1
+            for (int k0 = 0; k0 < kChunk; k0 += 8) {
+                unsigned ix[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const double x = f0 * hrow[k0 + k];
+                    const double vv = x + D.cshift;
+                    ix[k] = (unsigned)__double2int_rz(vv);
+                }
+                float p[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    p[k] = Store<STORE>::get(rs, (int)ix[k], (j0 + k0 + k) * D.pitch_bytes, cnt);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) sc = __builtin_fmaf(D.wq[j0 + k0 + k], p[k], sc);
+            }
+        } else {
+            for (int k = 0; k < nj; ++k) {
+                const double x = f0 * hrow[k];
+                const double vv = x + D.cshift;
+                const unsigned ix = (unsigned)__double2int_rz(vv);
+                sc = __builtin_fmaf(D.wq[j0 + k], Store<STORE>::get(rs, (int)ix, (j0 + k) * D.pitch_bytes, cnt),
+                                    sc);
+            }
+        }
+        s += (double)sc;
+    }
+    if (q >= K) return;
+    const int64_t o = (int64_t)rr * K * W + (int64_t)q * W + lf;
+    const int64_t tt = (int64_t)grp * a.n_f0 + i;
+    out_tpl[o] = valid ? (int32_t)tt : -1;
+    out_psi[o] = valid ? stack_ratio(s, mom, tt, 1.0, 1.0, 0) : __builtin_nan("");
+}
+
+bool block_eval_supported(int W) { return W == 16 || W == 32 || W == 64; }
+
+hipError_t launch_block_eval(int store, int W, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,
+                             const int32_t *blk, int K, int nbg, const int32_t *rmap, const int32_t *n_rows,
+                             StackMoments mom, int32_t *out_tpl, double *out_psi, hipStream_t st) {
+    if (R > 65535 || R < 1 || K < 1 || !block_eval_supported(W)) return hipErrorInvalidValue;
+    const int NB = 256 / W;
+    const dim3 grid((unsigned)((K + NB - 1) / NB), (unsigned)R), block(256);
+#define LTGW_BLOCK_EVAL(S, WW)                                                                                   \
+    hipLaunchKernelGGL((block_eval_kernel<S, WW>), grid, block, 0, st, a, stack_bytes, stack_rows, blk, K, nbg, \
+                       rmap, n_rows, mom, out_tpl, out_psi)
+#define LTGW_BLOCK_EVAL_W(S)          \
+    if (W == 16)                      \
+        LTGW_BLOCK_EVAL(S, 16);       \
+    else if (W == 32)                 \
+        LTGW_BLOCK_EVAL(S, 32);       \
+    else                              \
+        LTGW_BLOCK_EVAL(S, 64)
+    if (store == LTGW_STORE_F32) {
+        LTGW_BLOCK_EVAL_W(LTGW_STORE_F32);
+    } else if (store == LTGW_STORE_BF16) {
+        LTGW_BLOCK_EVAL_W(LTGW_STORE_BF16);
+    } else {
+        LTGW_BLOCK_EVAL_W(LTGW_STORE_FP8);
+    }
+#undef LTGW_BLOCK_EVAL_W
+#undef LTGW_BLOCK_EVAL
     return hipGetLastError();
 }
 
@@ -218,12 +374,14 @@ hipError_t launch_mask_blocks(float *score, const int32_t *blk, int R, int K, in
 }
 
 // Templates of the selected blocks: row q (realisation rmap[q], or q)
-// lists blk[r][0..K) expanded to W consecutive f0 each (-1 past the grid).
+// lists blk[r][0..K) expanded to W consecutive f0 each (-1 past the grid);
+// rows q >= *n_rows are skipped when the device count is given.
 __global__ void expand_blocks_kernel(const int32_t *blk, int K, int W, int two_L, int nbg, const int32_t *rmap,
-                                     int64_t total, int32_t *tpl) {
+                                     const int32_t *n_rows, int64_t total, int32_t *tpl) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= total) return;
     const int64_t row = e / ((int64_t)K * W);
+    if (n_rows && row >= *n_rows) return;
     const int rem = (int)(e % ((int64_t)K * W));
     const int q = rem / W, j = rem % W;
     const int64_t r = rmap ? rmap[row] : row;
@@ -232,76 +390,11 @@ __global__ void expand_blocks_kernel(const int32_t *blk, int K, int W, int two_L
     tpl[e] = (b >= 0 && i < two_L) ? g * two_L + i : -1;
 }
 
-hipError_t launch_expand_blocks(const int32_t *blk, int K, int W, int two_L, int nbg, const int32_t *rmap, int rows,
-                                int32_t *tpl, hipStream_t st) {
+hipError_t launch_expand_blocks(const int32_t *blk, int K, int W, int two_L, int nbg, const int32_t *rmap,
+                                const int32_t *n_rows, int rows, int32_t *tpl, hipStream_t st) {
     const int64_t total = (int64_t)rows * K * W;
     hipLaunchKernelGGL(expand_blocks_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, blk, K, W,
-                       two_L, nbg, rmap, total, tpl);
-    return hipGetLastError();
-}
-
-// Each row of m template indices into ascending order (bitonic sort in LDS,
-// one workgroup per row): neighbouring lanes of the listed evaluation then
-// take neighbouring f0 wherever the selection is contiguous, so their gathers
-// share cache lines.
-constexpr int kSortMax = 8192;
-__global__ __launch_bounds__(256) void sort_rows_kernel(int32_t *idx, int m) {
-    __shared__ int32_t v[kSortMax];
-    int32_t *row = idx + (int64_t)blockIdx.x * m;
-    int P = 1;
-    while (P < m) P <<= 1;
-    for (int i = threadIdx.x; i < P; i += 256) v[i] = i < m ? row[i] : 0x7fffffff;
-    __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < P; i += 256) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    const bool up = (i & size) == 0;
-                    const int32_t a = v[i], b = v[j];
-                    if (up ? a > b : a < b) {
-                        v[i] = b;
-                        v[j] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int i = threadIdx.x; i < m; i += 256) row[i] = v[i];
-}
-
-hipError_t launch_sort_rows(int32_t *idx, int rows, int m, hipStream_t st) {
-    if (rows < 1 || m < 1 || m > kSortMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(sort_rows_kernel, dim3(rows), dim3(256), 0, st, idx, m);
-    return hipGetLastError();
-}
-
-// The fallback rule per realisation (one workgroup per row): the largest
-// coarse ratio above cthr while the best listed fine ratio does not pass thr.
-__global__ __launch_bounds__(256) void fallback_kernel(const double *psi_coarse, int nc, const double *best_psi,
-                                                       double thr, double cthr, int32_t *fallback) {
-    __shared__ double sh[4];
-    const int64_t r = blockIdx.x;
-    double cm = -__builtin_inf();
-    for (int q = threadIdx.x; q < nc; q += 256) {
-        const double v = psi_coarse[r * nc + q];
-        if (v == v && v > cm) cm = v;
-    }
-    for (int o = 32; o > 0; o >>= 1) cm = fmax(cm, __shfl_xor(cm, o, 64));
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cm;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        cm = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
-        const double b = best_psi[r];
-        fallback[r] = (cm > cthr && !(b > thr)) ? 1 : 0;
-    }
-}
-
-hipError_t launch_fallback(int R, const double *psi_coarse, int nc, const double *best_psi, double thr,
-                           double cthr, int32_t *fallback, hipStream_t st) {
-    if (R < 1 || nc < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fallback_kernel, dim3(R), dim3(256), 0, st, psi_coarse, nc, best_psi, thr, cthr, fallback);
+                       two_L, nbg, rmap, n_rows, total, tpl);
     return hipGetLastError();
 }
 
@@ -313,10 +406,12 @@ __device__ inline bool best_before(double a, int ia, double b, int ib) {
 }
 
 __global__ __launch_bounds__(256) void row_best_kernel(const double *psi, int64_t n, const int32_t *idx,
-                                                       int32_t *best_idx, double *best_psi) {
+                                                       const int32_t *n_rows, int32_t *best_idx,
+                                                       double *best_psi) {
     __shared__ double sv[256];
     __shared__ int si[256];
     const int64_t row = blockIdx.x;
+    if (n_rows && row >= *n_rows) return;  // the whole block: no barrier is skipped by part of it
     double b = -__builtin_inf();
     int bi = -1;
     for (int64_t q = threadIdx.x; q < n; q += 256) {
@@ -347,10 +442,92 @@ __global__ __launch_bounds__(256) void row_best_kernel(const double *psi, int64_
     }
 }
 
-hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t *idx, int32_t *best_idx,
-                           double *best_psi, hipStream_t st) {
+hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t *idx, const int32_t *n_rows,
+                           int32_t *best_idx, double *best_psi, hipStream_t st) {
     if (rows < 1 || n < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(row_best_kernel, dim3(rows), dim3(256), 0, st, psi, n, idx, best_idx, best_psi);
+    hipLaunchKernelGGL(row_best_kernel, dim3(rows), dim3(256), 0, st, psi, n, idx, n_rows, best_idx, best_psi);
+    return hipGetLastError();
+}
+
+// The realisations that take the next step of a proposal, in ascending order,
+// and their count (one workgroup): those whose best ratio does not pass thr
+// and, with cm given (the fallback rule), whose largest coarse ratio exceeds
+// cthr.  flag[r] (when given) receives each decision.
+__global__ __launch_bounds__(256) void take_rows_kernel(int R, const double *best_psi, double thr,
+                                                        const double *cm, double cthr, int32_t *rows,
+                                                        int32_t *count, int32_t *flag) {
+    __shared__ int sh[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int base = 0;
+    for (int r0 = 0; r0 < R; r0 += 256) {  // uniform trip count: every thread meets every barrier
+        const int r = r0 + (int)threadIdx.x;
+        bool take = false;
+        if (r < R) {
+            take = !(best_psi[r] > thr) && (!cm || cm[r] > cthr);
+            if (flag) flag[r] = take ? 1 : 0;
+        }
+        const unsigned long long m = __ballot(take);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) sh[wv] = __popcll(m);
+        __syncthreads();
+        int off = base;
+        for (int k = 0; k < wv; ++k) off += sh[k];
+        if (take) rows[off + before] = r;
+        base += sh[0] + sh[1] + sh[2] + sh[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
+hipError_t launch_take_rows(int R, const double *best_psi, double thr, const double *cm, double cthr, int32_t *rows,
+                            int32_t *count, int32_t *flag, hipStream_t st) {
+    if (R < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(take_rows_kernel, dim3(1), dim3(256), 0, st, R, best_psi, thr, cm, cthr, rows, count, flag);
+    return hipGetLastError();
+}
+
+// Later results (bi[q], bp[q]) for realisation rows[q], q < *count, merged
+// into its best: the larger ratio, ties to the lower index.
+__global__ void merge_rows_kernel(const int32_t *rows, const int32_t *count, const int32_t *bi, const double *bp,
+                                  int32_t *best_idx, double *best_psi) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= *count) return;
+    const int r = rows[q];
+    const int32_t i = bi[q];
+    const double v = bp[q];
+    if (i < 0 || !(v == v)) return;
+    const int32_t i0 = best_idx[r];
+    const double v0 = best_psi[r];
+    if (i0 < 0 || v > v0 || (v == v0 && i < i0)) {
+        best_idx[r] = i;
+        best_psi[r] = v;
+    }
+}
+
+hipError_t launch_merge_rows(int R, const int32_t *rows, const int32_t *count, const int32_t *bi, const double *bp,
+                             int32_t *best_idx, double *best_psi, hipStream_t st) {
+    hipLaunchKernelGGL(merge_rows_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, rows, count, bi, bp,
+                       best_idx, best_psi);
+    return hipGetLastError();
+}
+
+// The evaluated blocks of each realisation: its K1 first-tier blocks, then
+// its K2 second-tier blocks where flag2[r] says it took them, else -1.
+__global__ void blocks_out_kernel(int64_t total, const int32_t *blk1, int K1, const int32_t *blk2, int K2,
+                                  const int32_t *flag2, int32_t *out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int KB = K1 + K2;
+    const int64_t r = e / KB;
+    const int k = (int)(e % KB);
+    out[e] = k < K1 ? blk1[r * K1 + k] : (flag2[r] ? blk2[r * K2 + (k - K1)] : -1);
+}
+
+hipError_t launch_blocks_out(int R, const int32_t *blk1, int K1, const int32_t *blk2, int K2, const int32_t *flag2,
+                             int32_t *out, hipStream_t st) {
+    const int64_t total = (int64_t)R * (K1 + K2);
+    hipLaunchKernelGGL(blocks_out_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, total, blk1, K1,
+                       blk2, K2, flag2, out);
     return hipGetLastError();
 }
 
@@ -374,18 +551,6 @@ hipError_t launch_templates_to_cells(const int32_t *tpl, int n, int L, const int
                                      double min_psi, int32_t *cells, hipStream_t st) {
     hipLaunchKernelGGL(templates_to_cells_kernel, dim3((n + 255) / 256), dim3(256), 0, st, tpl, n, L, mask, psi,
                        min_psi, cells);
-    return hipGetLastError();
-}
-
-// Every template index of a grid, once per listed realisation.
-__global__ void iota_rows_kernel(int32_t *idx, int rows, int n) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < (int64_t)rows * n) idx[i] = (int32_t)(i % n);
-}
-
-hipError_t launch_iota_rows(int32_t *idx, int rows, int n, hipStream_t st) {
-    const int64_t t = (int64_t)rows * n;
-    hipLaunchKernelGGL(iota_rows_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, idx, rows, n);
     return hipGetLastError();
 }
 

@@ -121,7 +121,6 @@ class Proposer:
         self.step = 0
         self._bufs = {}
         self._fg, self._fg_keep = _grid(fine)
-        self._fg_keep_n = _n_groups(fine) * int(fine["n_f0"])
         self._cg, self._cg_keep = _grid(coarse)
 
     # -- device buffers, sized once per batch size --------------------------------
@@ -174,19 +173,41 @@ class Proposer:
             ltgw.ltgw_stack_best(h, self._fg, b["best"], b["best_psi"])
         return b
 
+    def near_best(self, inj):
+        """The exact ratio's best template close to each injection (close_region)
+        on the loaded fine store: (template[R] int32, psi[R]; -1, -inf if none)."""
+        T = self.torch
+        region = close_region(self.fine, inj)
+        R = region.shape[0]
+        out = T.empty(region.shape, dtype=T.float64, device=self.ctx.device)
+        ltgw.ltgw_stack_psi_list(self.ctx.h, self._fg, T.from_numpy(region.astype(np.int32)).to(self.ctx.device), out)
+        vals = out.cpu().numpy()
+        vals = np.where((region >= 0) & np.isfinite(vals), vals, -np.inf)
+        k = np.argmax(vals, axis=1)                     # first maximum: the lowest index
+        tpl = region[np.arange(R), k].astype(np.int32)
+        psi = vals[np.arange(R), k]
+        return np.where(np.isfinite(psi), tpl, -1).astype(np.int32), psi
+
     def train_step(self, R, p_signal=0.9, amp_range=(1.0, 3.0), lr=1e-3, stream=1, inj=None, r0=None,
-                   label_psi=None):
+                   label_psi=None, label="best"):
         """One Adam step on a batch of R realisations (fresh ones unless inj and
-        r0 name a stored batch); the label of an injected realisation is the
-        exhaustive search's best cell, dropped when that best ratio is not above
+        r0 name a stored batch).  The label of an injected realisation is the
+        exhaustive search's best cell (label="best") or the best cell close to
+        the injection (label="near"), dropped when that ratio is not above
         label_psi.  Returns the batch's mean loss (host float)."""
         T = self.torch
         if inj is None:
             inj, _ = self.draw_injections(R, p_signal, amp_range)
         sig = inj[:, 3] > 0
-        b = self.make_batch(R, stream, self.step * R if r0 is None else r0, inj)
+        b = self.make_batch(R, stream, self.step * R if r0 is None else r0, inj, with_labels=(label == "best"))
         h = self.ctx.h
         b["mask"].copy_(T.from_numpy(sig.astype(np.int32)))
+        if label == "near":
+            tpl, psi = self.near_best(inj)
+            b["best"].copy_(T.from_numpy(tpl))
+            b["best_psi"].copy_(T.from_numpy(np.where(np.isfinite(psi), psi, -1e300)))
+        elif label != "best":
+            raise ValueError(f"label must be 'best' or 'near', not {label!r}")
         ltgw.ltgw_cells_from_templates(h, b["best"], self.L, b["target"], mask=b["mask"],
                                        psi=None if label_psi is None else b["best_psi"],
                                        min_psi=0.0 if label_psi is None else label_psi)
@@ -199,7 +220,7 @@ class Proposer:
         return float(b["loss"].cpu().numpy().astype(np.float64).sum()) / max(n_valid, 1)
 
     def train(self, realisations, batch=256, epochs=1, p_signal=0.9, amp_range=(1.0, 3.0), lr=2e-3,
-              label_psi=None, stream=1):
+              label_psi=None, stream=1, label="best"):
         """Several passes over one fixed set of `realisations` realisations
         (Philox stream `stream`, realisation indices 0 .. realisations-1; the
         injection parameters are drawn once), batches in a new order each
@@ -215,7 +236,7 @@ class Proposer:
                 lr_t = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * t)))
                 sl = slice(int(k) * batch, (int(k) + 1) * batch)
                 losses.append(self.train_step(batch, inj=inj[sl], r0=int(k) * batch, lr=lr_t, stream=stream,
-                                              label_psi=label_psi))
+                                              label_psi=label_psi, label=label))
         return losses
 
     def propose(self, psi_threshold, coarse_threshold, R, return_blocks=False):
@@ -282,20 +303,14 @@ class Proposer:
             t_ex.append(ev0.elapsed_time(ev1))
         ex_idx = b["best"].cpu().numpy().copy()
         ex_psi = b["best_psi"].cpu().numpy().copy()
-        # the exhaustive search's best template close to each injection
-        psi_map = T.empty((R_signal, self._fg_keep_n), dtype=T.float64, device=self.ctx.device)
-        ltgw.ltgw_stack_psi(h, self._fg, 0, psi_map)
-        region = self.close_region(inj)
-        vals = np.take_along_axis(psi_map.cpu().numpy(), np.maximum(region, 0), axis=1)
-        vals = np.where((region >= 0) & np.isfinite(vals), vals, -np.inf)
-        k = np.argmax(vals, axis=1)                                  # first maximum: the lowest index
-        near_tpl = region[np.arange(R_signal), k].astype(np.int32)
-        near_psi = vals[np.arange(R_signal), k]
-        del psi_map
+        # the exhaustive search's best template close to each injection (the
+        # listed evaluation gives the exhaustive kernel's sums, bit for bit)
+        near_tpl, near_psi = self.near_best(inj)
         ltgw.ltgw_load_stack(h, self.det, b["stack"], fine_store, coarse=self.coarse_segments)
         near_prop = T.empty((R_signal, 1), dtype=T.float64, device=self.ctx.device)
-        ltgw.ltgw_stack_psi_list(h, self._fg, T.from_numpy(near_tpl.reshape(-1, 1)).to(self.ctx.device), near_prop)
-        near_prop = near_prop.cpu().numpy().ravel()
+        ltgw.ltgw_stack_psi_list(h, self._fg, T.from_numpy(np.maximum(near_tpl, 0).reshape(-1, 1)).to(self.ctx.device),
+                                 near_prop)
+        near_prop = np.where(near_tpl >= 0, near_prop.cpu().numpy().ravel(), -np.inf)
         det_near = near_psi > psi_thr
         n_near = int(det_near.sum())
         det_ex = ex_psi > psi_thr

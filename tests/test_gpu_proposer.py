@@ -281,14 +281,18 @@ def test_softmax_xent_adam_and_select_top():
         ltgw.ltgw_adam_step(ctx.h, pd, gd, md, vd, 1e-3, 0.9, 0.999, 1e-8, step)
         pr, mr, vr = cnn.adam(pr, g.astype(np.float64), mr, vr, 1e-3, 0.9, 0.999, 1e-8, step)
     assert np.allclose(pd.cpu().numpy(), pr, rtol=0, atol=1e-6)
-    # top-M with ties and NaN
-    for n_sc, M in ((1000, 50), (8192, 200), (7, 7)):
-        s = rng.integers(0, 40, size=(4, n_sc)).astype(np.float32)
+    # top-M with ties and NaN: one wavefront per row up to 1024 scores (slots of
+    # 1 .. 16 per lane; 5 rows, so the last workgroup is partly empty), one
+    # workgroup per row above; a row mostly NaN takes NaN entries, lowest first
+    for n_sc, M in ((1000, 50), (8192, 200), (7, 7), (300, 15), (130, 3), (100, 1), (64, 64), (2000, 40),
+                    (600, 400)):
+        s = rng.integers(0, 40, size=(5, n_sc)).astype(np.float32)
         s[0, 3] = np.nan
-        out = torch.empty((4, M), dtype=torch.int32, device="cuda")
+        s[1, : (n_sc * 3) // 4] = np.nan
+        out = torch.empty((5, M), dtype=torch.int32, device="cuda")
         ltgw.ltgw_select_top(ctx.h, T(s), M, out)
         o = out.cpu().numpy()
-        for r in range(4):
+        for r in range(5):
             # the M best (score desc, ties to the lower index, NaN last), in index order
             key = np.where(np.isnan(s[r]), -np.inf, s[r])
             ref = np.sort(np.lexsort((np.arange(n_sc), np.isnan(s[r]), -key))[:M])
@@ -344,9 +348,14 @@ def test_propose_all_cells_finds_the_exhaustive_best():
         bi3, bp3, fb3 = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, nb * W, 1e9, 1e9, R, block=W)
         assert np.all(fb3 == 0) and np.array_equal(bi3, bi) and np.array_equal(bp3, bp)
         h = nb // 2
-        bi4, bp4, fb4 = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, h * W, 1e9, 1e9, R, block=W,
-                                          n_select2=(nb - h) * W)
+        bi4, bp4, fb4, bl4 = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, h * W, 1e9, 1e9, R,
+                                               block=W, n_select2=(nb - h) * W, return_blocks=True)
         assert np.all(fb4 == 0) and np.array_equal(bi4, bi) and np.array_equal(bp4, bp)
+        # the reported blocks: each tier ascending, together every block once
+        assert bl4.shape == (R, nb)
+        for r in range(R):
+            assert np.all(np.diff(bl4[r, :h]) > 0) and np.all(np.diff(bl4[r, h:]) > 0)
+            assert sorted(bl4[r].tolist()) == list(range(nb))
     ctx.close()
 
 
@@ -358,7 +367,7 @@ def test_propose_partial_selection_equals_composed_calls():
     fg, kf = _grid(FINE)
     cg, kc = _grid(COARSE)
     M = 12
-    bi, bp, fb = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, M, 1e9, 1e9, R)
+    bi, bp, fb, bl = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, M, 1e9, 1e9, R, return_blocks=True)
     # the same steps through the public calls
     pc = torch.empty((R, c_in * L), dtype=torch.float64, device="cuda")
     ltgw.ltgw_stack_psi(ctx.h, cg, 1, pc, nan_to_zero=True)
@@ -375,6 +384,8 @@ def test_propose_partial_selection_equals_composed_calls():
     for r in range(R):
         i, p = op.best_template(o[r], tpl[r])
         assert bi[r] == i and bp[r] == p
+        # blocks of one cell are fine templates (group * 2 L + f0 index)
+        assert bl[r].tolist() == sorted(tpl[r].tolist())
     # the fallback rule: coarse maximum above the threshold, best below the detection threshold
     cmax = np.nanmax(pc.cpu().numpy(), axis=1)
     thr = float(np.max(bp)) + 1.0
