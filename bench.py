@@ -48,10 +48,11 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload, store, variant):
-    """HBM-side bytes of one step's statistic launches from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE runs, each scaled by
-    what the same counter reads for a device copy of known size), or None
-    when the summary is for another workload, store, variant or kernel source."""
+    """HBM-side bytes per statistic launch (the step's launches averaged) from
+    the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE runs,
+    each scaled by what the same counter reads for a device copy of known
+    size), or None when the summary is for another workload, store, variant or
+    kernel source."""
     path = os.path.join(ROOT, "profiles", "eval_kernel_traffic.json")
     if not os.path.exists(path):
         return None
@@ -60,7 +61,8 @@ def measured_traffic(workload, store, variant):
     if (t.get("source_sha256") != kernel_source_hash() or t.get("workload") != workload
             or t.get("store") != store or t.get("variant") != variant):
         return None
-    return (t["fetch_kib_per_step"] * t["fetch_scale"] + t["write_kib_per_step"] * t["write_scale"]) * 1024.0
+    per_step = (t["fetch_kib_per_step"] * t["fetch_scale"] + t["write_kib_per_step"] * t["write_scale"]) * 1024.0
+    return per_step / t["dispatches_per_step"]
 
 
 def cpu_baseline(wl, rho, target_s=15.0):
@@ -93,7 +95,7 @@ def cpu_baseline(wl, rho, target_s=15.0):
 
 
 def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_signal=2048, eval_noise=1024, seed=7,
-                 coarse_segments=4, select2_frac=0.10, block=16, label="near", select_frac=0.05):
+                 coarse_segments=4, select2_frac=0.10, block=16, label="near", select_frac=0.05, tier2_quantile=None):
     """The learned proposer on the small workload's shape (1024 segments x 800
     bins, 4800 fine templates): trained on `realisations` device-generated
     noise + injection realisations (amplitudes U[0.3, 3]), then recall and
@@ -124,7 +126,7 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t
     ev = pr.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
-                     coarse_quantiles=(1.0, 0.9, 0.7, 0.5, 0.3))
+                     coarse_quantiles=(1.0, 0.9, 0.7, 0.5, 0.3), tier2_quantile=tier2_quantile)
     untrained = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed + 1, select_frac=select_frac, store="f32",
                          block=block, select2_frac=select2_frac, coarse_segments=coarse_segments)
     ev0 = untrained.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
@@ -277,8 +279,12 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     value = evals * args.steps / elapsed
     kms = float(np.mean(kern_ms))
-    alg_bytes = in_band * BYTES[args.store]
-    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    launches = max(int(dg["eval_launches"]), 1)
+    # per launch of the statistic kernel (the step's launches averaged): the
+    # algorithmic bytes over the average launch duration
+    alg_bytes = in_band * BYTES[args.store] / launches
+    launch_ms = kms / launches
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     print(f"[bench] {ms_step:.3f} ms/step, eval kernel {kms:.3f} ms, in-band {in_band / evals:.4f}, "
           f"top power {tp[0]['index']} psi {tp[0]['psi']:.2f}, top count {tc[0]['index']} "
           f"psi {tc[0]['psi']:.2f}, pow undecided {dg['pow_undecided']}",
@@ -292,7 +298,8 @@ def main():
                    "templates": int(dg["templates"]), "segments": int(d["rho"].shape[0]),
                    "bins": int(d["rho"].shape[1]), "evals_per_step": int(evals),
                    "in_band_fraction": in_band / evals, "eval_kernel_ms": kms,
-                   "tile_shape": int(dg["tile_shape"])},
+                   "eval_launches_per_step": launches, "eval_launch_ms": launch_ms,
+                   "alg_bytes_per_launch": alg_bytes, "tile_shape": int(dg["tile_shape"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(wl.name, args.store, int(dg["tile_shape"]))},

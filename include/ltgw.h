@@ -208,7 +208,8 @@ typedef struct {
     double tables_ms;       /* duration of the last eval's track-table kernels
                                (Eq. 1 powers, Eq. 2 factors, in-band moments) */
     int32_t tile_shape;     /* tile shape of the last eval's statistic kernel */
-    int32_t reserved;
+    int32_t eval_launches;  /* dispatches of the statistic kernel in the last
+                               eval (segment slabs, generations of workgroups) */
 } ltgw_diag;
 
 /* ltgw_diagnostics: synchronous; reads the device counters of the last eval. */
@@ -379,7 +380,9 @@ int32_t ltgw_cells_from_templates(ltgw_ctx *ctx, const int32_t *tpl, int32_t n, 
  * convolution; parameters are one FP32 vector W1 b1 W2 b2 W3 b3 W4 b4
  * (W[o][c][t] row-major, ltgw_cnn_param_count values).  Products on BF16
  * matrix cores with FP32 accumulation.  act: device [3][B][32][L] (the three
- * hidden activations, kept for the backward pass).  All pointers device;
+ * hidden activations, kept for the backward pass), or NULL for inference
+ * only (one fused pass with the activations in on-chip memory, the same
+ * logits bit for bit; c_in, c_out <= 32 and L <= 256).  All pointers device;
  * asynchronous. */
 int64_t ltgw_cnn_param_count(int32_t c_in, int32_t c_out);
 int64_t ltgw_cnn_work_floats(int32_t B, int32_t c_in, int32_t c_out, int32_t L);
@@ -413,6 +416,9 @@ typedef struct {
     double psi_threshold;     /* detection threshold on Psi (largest noise value)  */
     double coarse_threshold;  /* fallback when the coarse map exceeds this but no
                                  selected cell passes psi_threshold               */
+    double tier2_threshold;   /* the second tier is taken only where the largest
+                                 coarse ratio exceeds this (finite; a very
+                                 negative value: wherever no cell passes)    */
     int32_t *blocks;          /* optional host output (NULL: none), [R][K1 + K2]
                                  with K1 = ceil(n_select / block), K2 =
                                  ceil(n_select2 / block): the blocks evaluated
@@ -430,8 +436,9 @@ typedef struct {
  * fine f0 of one group, scored by their largest logit -> the
  * ceil(n_select / block) best blocks -> exact fine critical ratios of their
  * templates -> the best.  Realisations with no template above psi_threshold
- * then get the next ceil(n_select2 / block) blocks; those still below it
- * whose largest coarse ratio exceeds coarse_threshold are evaluated
+ * whose largest coarse ratio exceeds tier2_threshold then get the next
+ * ceil(n_select2 / block) blocks; those still below psi_threshold whose
+ * largest coarse ratio exceeds coarse_threshold are evaluated
  * exhaustively on the fine grid (the fallback).  Cell (channel ch, position
  * l) is fine template ((ch / 2) group, f0 index 2 l + ch % 2): the fine grid
  * has twice the coarse positions in f0 and c_out / 2 (tau, n) groups.

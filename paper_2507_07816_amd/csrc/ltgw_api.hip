@@ -189,7 +189,7 @@ void ltgw_destroy(ltgw_ctx *c) {
         release(d.store_buf); release(d.t_seg); release(d.w); release(d.wq);
         release(d.scale); release(d.v); release(d.g); release(d.H); release(d.wfix); release(d.win);
     }
-    DevBuf *all[] = {&c->staging, &c->counters, &c->tau_d, &c->brake_d, &c->sky_d,
+    DevBuf *all[] = {&c->staging, &c->counters, &c->cnn_packed, &c->tau_d, &c->brake_d, &c->sky_d,
                      &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2, &c->diff,
                      &c->cand_pa, &c->cand_ia, &c->cand_pb, &c->cand_ib, &c->cand_out, &c->n_out};
     for (DevBuf *b : all) release(*b);
@@ -551,7 +551,9 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     }
     HIP_TRY(c, hipEventRecord(c->ev_h2d, c->stream), "event record");
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream), "event record");
-    HIP_TRY(c, launch_eval(P.store, moments_in_loop, variant, a, c->cu_count, c->stream), "eval launch");
+    int launches = 0;
+    HIP_TRY(c, launch_eval(P.store, moments_in_loop, variant, a, c->cu_count, c->stream, &launches), "eval launch");
+    c->last_launches = launches;
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream), "event record");
     c->have_eval = true;
     c->last_variant = variant;
@@ -740,7 +742,7 @@ int32_t ltgw_diagnostics(ltgw_ctx *c, ltgw_diag *out) {
     out->eval_kernel_ms = 0.0;
     out->tables_ms = 0.0;
     out->tile_shape = c->have_eval ? c->last_variant : -1;
-    out->reserved = 0;
+    out->eval_launches = c->have_eval ? c->last_launches : 0;
     if (c->have_eval) {
         float a = 0.f, b = 0.f;
         if (hipEventElapsedTime(&a, c->ev[1], c->ev[2]) == hipSuccess) out->eval_kernel_ms = a;

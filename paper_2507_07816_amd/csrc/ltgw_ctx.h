@@ -120,6 +120,7 @@ struct ltgw_ctx {
     std::string err;
     ltgw::Det det[LTGW_MAX_DET];
     ltgw::DevBuf staging, counters;
+    ltgw::DevBuf cnn_packed;  // BF16 weights of the fused inference pass
     ltgw::DevBuf tau_d, brake_d, sky_d;
     ltgw::DevBuf res_s, res_c, res_n, res_w1, res_w2, diff;
     ltgw::DevBuf cand_pa, cand_ia, cand_pb, cand_ib, cand_out, n_out;
@@ -136,6 +137,7 @@ struct ltgw_ctx {
     int32_t n_f0 = 0, n_tau = 0, n_brake = 0, n_sky = 0;
     float rho_th = 1.6f;
     int last_variant = 1;
+    int last_launches = 0;  // statistic-kernel dispatches of the last eval
     int forced_variant = -1;      // ltgw_set_tile_shape; -1 = autotuner
     ltgw::BatchState batch;
     ltgw::StackState stack;

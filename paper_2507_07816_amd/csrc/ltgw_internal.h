@@ -76,8 +76,9 @@ hipError_t launch_track_factor(const double *g, int32_t n_tn, const double *v, i
 constexpr int kNumShapes = 4;
 constexpr int kNumVariants = 16;
 int variant_templates_per_block(int variant);
+// *launches receives the number of statistic-kernel dispatches queued.
 hipError_t launch_eval(int store, bool moments_in_loop, int variant, const EvalArgs &a, int cu_count,
-                       hipStream_t st);
+                       hipStream_t st, int *launches);
 
 // Batched searches (device-resident descriptors).
 struct BatchSearch {

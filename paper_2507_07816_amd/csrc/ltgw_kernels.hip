@@ -241,7 +241,9 @@ int variant_templates_per_block(int variant) { return 256 * kVariantTpl[variant 
 constexpr int kSlab = 1024;
 
 template <int STORE, bool MOMENTS, int TPL, int U>
-static hipError_t launch_eval_v(const EvalArgs &a, bool generations, bool slabs, int cu_count, hipStream_t st) {
+static hipError_t launch_eval_v(const EvalArgs &a, bool generations, bool slabs, int cu_count, hipStream_t st,
+                                int *launches) {
+    *launches = 0;
     const int64_t blocks = (int64_t)((a.n_f0 + 256 * TPL - 1) / (256 * TPL)) * a.n_groups;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     int64_t step = blocks;
@@ -266,6 +268,7 @@ static hipError_t launch_eval_v(const EvalArgs &a, bool generations, bool slabs,
                                (int)first, (int)blocks, j_lo, j_hi, last);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
+            ++*launches;
         }
         if (last) break;
     }
@@ -273,27 +276,29 @@ static hipError_t launch_eval_v(const EvalArgs &a, bool generations, bool slabs,
 }
 
 template <int STORE, bool MOMENTS>
-static hipError_t launch_eval_m(int variant, const EvalArgs &a, int cu_count, hipStream_t st) {
+static hipError_t launch_eval_m(int variant, const EvalArgs &a, int cu_count, hipStream_t st, int *launches) {
     const bool gen = (variant & 4) != 0, slabs = (variant & 8) != 0;
     switch (variant & 3) {
-        case 0: return launch_eval_v<STORE, MOMENTS, 1, 8>(a, gen, slabs, cu_count, st);
-        case 1: return launch_eval_v<STORE, MOMENTS, 1, 16>(a, gen, slabs, cu_count, st);
-        case 2: return launch_eval_v<STORE, MOMENTS, 2, 8>(a, gen, slabs, cu_count, st);
-        default: return launch_eval_v<STORE, MOMENTS, 2, 16>(a, gen, slabs, cu_count, st);
+        case 0: return launch_eval_v<STORE, MOMENTS, 1, 8>(a, gen, slabs, cu_count, st, launches);
+        case 1: return launch_eval_v<STORE, MOMENTS, 1, 16>(a, gen, slabs, cu_count, st, launches);
+        case 2: return launch_eval_v<STORE, MOMENTS, 2, 8>(a, gen, slabs, cu_count, st, launches);
+        default: return launch_eval_v<STORE, MOMENTS, 2, 16>(a, gen, slabs, cu_count, st, launches);
     }
 }
 
 template <int STORE>
-static hipError_t launch_eval_s(bool moments, int variant, const EvalArgs &a, int cu_count, hipStream_t st) {
-    return moments ? launch_eval_m<STORE, true>(variant, a, cu_count, st)
-                   : launch_eval_m<STORE, false>(variant, a, cu_count, st);
+static hipError_t launch_eval_s(bool moments, int variant, const EvalArgs &a, int cu_count, hipStream_t st,
+                                int *launches) {
+    return moments ? launch_eval_m<STORE, true>(variant, a, cu_count, st, launches)
+                   : launch_eval_m<STORE, false>(variant, a, cu_count, st, launches);
 }
 
-hipError_t launch_eval(int store, bool moments, int variant, const EvalArgs &a, int cu_count, hipStream_t st) {
+hipError_t launch_eval(int store, bool moments, int variant, const EvalArgs &a, int cu_count, hipStream_t st,
+                       int *launches) {
     if (variant < 0 || variant >= kNumVariants) return hipErrorInvalidValue;
-    if (store == LTGW_STORE_F32) return launch_eval_s<LTGW_STORE_F32>(moments, variant, a, cu_count, st);
-    if (store == LTGW_STORE_BF16) return launch_eval_s<LTGW_STORE_BF16>(moments, variant, a, cu_count, st);
-    return launch_eval_s<LTGW_STORE_FP8>(moments, variant, a, cu_count, st);
+    if (store == LTGW_STORE_F32) return launch_eval_s<LTGW_STORE_F32>(moments, variant, a, cu_count, st, launches);
+    if (store == LTGW_STORE_BF16) return launch_eval_s<LTGW_STORE_BF16>(moments, variant, a, cu_count, st, launches);
+    return launch_eval_s<LTGW_STORE_FP8>(moments, variant, a, cu_count, st, launches);
 }
 
 // ---------------------------------------------------------------------------

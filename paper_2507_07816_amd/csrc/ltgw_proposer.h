@@ -53,6 +53,15 @@ hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins,
                           unsigned short *out, hipStream_t st);
 hipError_t launch_cnn_forward(const float *params, const float *x, int B, int c_in, int c_out, int L,
                               float *act /* [3][B][32][L] */, float *logits, hipStream_t st);
+// The forward pass for inference only, fused in one kernel (no activations
+// kept); the same logits bit for bit.  Supported for c_in, c_out <= 32, L <= 256.
+// scratch: cnn_infer_scratch_shorts(c_in) shorts of device memory (the packed
+// weights).  logits and score may each be NULL; score receives the scores of
+// ltgw_propose's blocks of W fine f0 (W = 16, 32 or 64) as launch_block_scores.
+bool cnn_infer_supported(int c_in, int c_out, int L);
+int64_t cnn_infer_scratch_shorts(int c_in);
+hipError_t launch_cnn_infer(const float *params, const float *x, int B, int c_in, int c_out, int L, short *scratch,
+                            float *logits, float *score, int W, hipStream_t st);
 hipError_t launch_cnn_backward(const float *params, const float *x, int B, int c_in, int c_out, int L,
                                const float *act, const float *dlogits, float *work, int64_t work_floats,
                                float *grads, hipStream_t st);

@@ -171,6 +171,11 @@ struct ConvDims {
     int B, C, L, O, k, p;
 };
 
+// Offsets of W1 b1 W2 b2 W3 b3 W4 b4 in the flat parameter vector.
+struct CnnOffsets {
+    int64_t o[8];
+};
+
 // Y = conv(X; W, b) (+ relu).  GEMM rows o, columns n = (b, l), K = (c, t).
 template <int KT>  // taps (1 or 5), zero padding KT / 2
 __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvDims d, const float *__restrict__ X,
@@ -489,6 +494,181 @@ __host__ __device__ inline CnnLayout cnn_layout(int c_in, int c_out) {
 
 int64_t cnn_n_params(int c_in, int c_out) { return cnn_layout(c_in, c_out).total; }
 
+// ---------------------------------------------------------------------------
+// Inference: the whole network for one sample per workgroup (L <= 256, at
+// most 32 input channels and 32 logits per position).  The weights are first
+// packed as BF16 matrices [32 rows][Kw] with K ordered (t, c) and zero
+// padding (cnn_pack_kernel); each wavefront keeps its A fragments of a layer
+// in registers.  The input window and the two hidden activations live in LDS
+// as BF16, so only the input and the logits cross HBM.  Each layer is the
+// product of conv_fwd_win_kernel (the same fragments, zero padding and
+// accumulation order), so the logits equal those of the layer-by-layer
+// forward pass bit for bit.  Activation rows hold position row - 2 (two zero
+// rows of halo on each side of the 256 positions; positions >= L are zero).
+constexpr int kInferPos = 256, kInferRows = kInferPos + 4, kInferSH = kWidth + 4;
+
+struct CnnPacked {
+    int Cp1, Kw1;       // input channels rounded to 4; layer 1's K rounded to 16
+    int64_t o[4];       // offsets (shorts) of the four packed [32][Kw] matrices
+    int64_t total;
+};
+
+__host__ __device__ inline CnnPacked cnn_packed(int c_in) {
+    CnnPacked P;
+    P.Cp1 = (c_in + 3) / 4 * 4;
+    P.Kw1 = (kTaps * P.Cp1 + 15) / 16 * 16;
+    const int kw[4] = {P.Kw1, kTaps * kWidth, kTaps * kWidth, kWidth};
+    int64_t o = 0;
+    for (int i = 0; i < 4; ++i) {
+        P.o[i] = o;
+        o += 32 * (int64_t)kw[i];
+    }
+    P.total = o;
+    return P;
+}
+
+// Packed[r][k] = bf16(W[r][c][t]) with k = t Cp + c, zero for r >= O,
+// c >= C or t >= KT (one thread per entry of the four matrices).
+__global__ void cnn_pack_kernel(const float *__restrict__ params, CnnOffsets off, int c_in, int c_out,
+                                CnnPacked P, short *__restrict__ packed) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= P.total) return;
+    int layer = 3;
+    while (layer > 0 && e < P.o[layer]) --layer;
+    const int Kw = layer == 0 ? P.Kw1 : layer == 3 ? kWidth : kTaps * kWidth;
+    const int Cp = layer == 0 ? P.Cp1 : kWidth, C = layer == 0 ? c_in : kWidth;
+    const int KT = layer == 3 ? 1 : kTaps, O = layer == 3 ? c_out : kWidth;
+    const int64_t q = e - P.o[layer];
+    const int r = (int)(q / Kw), k = (int)(q % Kw);
+    const int t = k / Cp, c = k % Cp;
+    float v = 0.f;
+    if (r < O && t < KT && c < C) v = params[off.o[2 * layer] + ((int64_t)r * C + c) * KT + t];
+    packed[e] = to_bf16(v);
+}
+
+// One layer: 32 output rows (o < O) over the 256 positions from input rows
+// `in` (SXin shorts per row).  Hidden layers write bf16(relu(acc + bias)) to
+// `out` (zero at positions >= L); the last writes acc + bias to gout (when
+// given) and, with score given, the proposal-block scores of ltgw_propose:
+// block k of fine group g covers positions [k pb, k pb + pb) of channels 2g
+// and 2g + 1 (fine f0 index 2 l + ch % 2, blocks of 2 pb f0), and scores the
+// largest of those logits (pb = 8, 16 or 32).
+template <int KT, int KW>
+__device__ void infer_layer(const short *__restrict__ wp, const float *__restrict__ bias, int O, int Cp,
+                            const short *in, int SXin, int L, bool relu, short *out, float *__restrict__ gout,
+                            float *__restrict__ score = nullptr, int pb = 0, int nbg = 0) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r0 = (wv & 1) * 16, c0 = (wv >> 1) * 128;
+    const int row = lane & 15, kq = (lane >> 4) * 4;
+    constexpr int NK = KW / 16;
+    bf16x4 a[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) a[s] = *(const bf16x4 *)&wp[(r0 + row) * KW + s * 16 + kq];
+    f32x4 acc[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) acc[h] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+        const int k = s * 16 + kq;
+        const int t = k / Cp, c = k % Cp;
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            bf16x4 bv = {0, 0, 0, 0};
+            if (t < KT) bv = *(const bf16x4 *)&in[(c0 + h * 16 + row + t + 2 - KT / 2) * SXin + c];
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], bv, acc[h], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+        const int l = c0 + h * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = r0 + kq + i;
+            if (o >= O) continue;
+            float y = acc[h][i] + bias[o];
+            if (relu) y = y > 0.f ? y : 0.f;
+            if (out)
+                out[(l + 2) * kInferSH + o] = l < L ? to_bf16(y) : (short)0;
+            else if (gout && l < L)
+                gout[(int64_t)o * L + l] = y;
+        }
+    }
+    if (!score) return;
+    // a lane holds channels r0 + kq .. + 3, i.e. groups (r0 + kq) / 2 and + 1,
+    // at position c0 + 16 h + (lane % 16): reduce over pb positions
+    const int span = pb < 16 ? pb : 16;
+    float m[8][2];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+        const int l = c0 + h * 16 + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int o = r0 + kq + 2 * j;
+            float v = -__builtin_inff();
+            if (l < L && o < O) {
+                const float y0 = acc[h][2 * j] + bias[o], y1 = acc[h][2 * j + 1] + bias[o + 1];
+                v = y1 > y0 ? y1 : y0;
+            }
+            for (int sh = 1; sh < span; sh <<= 1) {
+                const float w = __shfl_xor(v, sh, 64);
+                v = w > v ? w : v;
+            }
+            m[h][j] = v;
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+        const int l = c0 + h * 16 + (lane & 15);
+        if ((lane & 15) % span != 0 || (pb == 32 && (h & 1)) || l >= L) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int o = r0 + kq + 2 * j;
+            if (o >= O) continue;
+            float v = m[h][j];
+            if (pb == 32) v = m[h + 1][j] > v ? m[h + 1][j] : v;  // the block's second 16 positions
+            score[(o / 2) * nbg + l / pb] = v;
+        }
+    }
+}
+
+template <int KW1>
+__global__ __launch_bounds__(256) void cnn_infer_kernel(const float *__restrict__ params,
+                                                        const short *__restrict__ packed,
+                                                        const float *__restrict__ X, int c_in, int c_out, int L,
+                                                        CnnOffsets off, CnnPacked P, float *__restrict__ logits,
+                                                        float *__restrict__ score, int pb, int nbg) {
+    __shared__ short hA[kInferRows * kInferSH], hB[kInferRows * kInferSH];
+    short *x0 = hB;  // the input window [260][Cp1 + 4] until layer 2 writes hB
+    const int SX0 = P.Cp1 + 4;
+    const int b = blockIdx.x;
+    for (int e = threadIdx.x; e < kInferRows * P.Cp1; e += 256) {
+        const int rr = e / P.Cp1, c = e % P.Cp1, l = rr - 2;
+        float v = 0.f;
+        if (c < c_in && l >= 0 && l < L) v = X[((int64_t)b * c_in + c) * L + l];
+        x0[rr * SX0 + c] = to_bf16(v);
+    }
+    for (int e = threadIdx.x; e < 4 * kWidth; e += 256) {  // halo rows of hA
+        const int rr = e / kWidth, c = e % kWidth;
+        hA[(rr < 2 ? rr : kInferRows - 4 + rr) * kInferSH + c] = 0;
+    }
+    __syncthreads();
+    infer_layer<kTaps, KW1>(packed + P.o[0], params + off.o[1], kWidth, P.Cp1, x0, SX0, L, true, hA, nullptr);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 4 * kWidth; e += 256) {  // halo rows of hB (the input window is spent)
+        const int rr = e / kWidth, c = e % kWidth;
+        hB[(rr < 2 ? rr : kInferRows - 4 + rr) * kInferSH + c] = 0;
+    }
+    infer_layer<kTaps, kTaps * kWidth>(packed + P.o[1], params + off.o[3], kWidth, kWidth, hA, kInferSH, L, true,
+                                       hB, nullptr);
+    __syncthreads();
+    infer_layer<kTaps, kTaps * kWidth>(packed + P.o[2], params + off.o[5], kWidth, kWidth, hB, kInferSH, L, true,
+                                       hA, nullptr);
+    __syncthreads();
+    infer_layer<1, kWidth>(packed + P.o[3], params + off.o[7], c_out, kWidth, hA, kInferSH, L, false, nullptr,
+                           logits ? logits + (int64_t)b * c_out * L : nullptr,
+                           score ? score + (int64_t)b * (c_out / 2) * nbg : nullptr, pb, nbg);
+}
+
 static hipError_t conv_fwd(const ConvDims &d, const float *X, const float *W, const float *b, int relu,
                            float *Y, hipStream_t st) {
     {
@@ -539,6 +719,39 @@ hipError_t launch_cnn_forward(const float *params, const float *x, int B, int c_
     if ((e = conv_fwd(d2, h2, params + P.off[4], params + P.off[5], 1, h3, st)) != hipSuccess) return e;
     ConvDims d4{B, kWidth, L, c_out, 1, 0};
     return conv_fwd(d4, h3, params + P.off[6], params + P.off[7], 0, logits, st);
+}
+
+bool cnn_infer_supported(int c_in, int c_out, int L) {
+    return c_in >= 1 && c_in <= kWidth && c_out >= 1 && c_out <= kWidth && L >= 1 && L <= kInferPos;
+}
+
+int64_t cnn_infer_scratch_shorts(int c_in) { return cnn_packed(c_in).total; }
+
+hipError_t launch_cnn_infer(const float *params, const float *x, int B, int c_in, int c_out, int L, short *scratch,
+                            float *logits, float *score, int W, hipStream_t st) {
+    if (B < 1 || !cnn_infer_supported(c_in, c_out, L)) return hipErrorInvalidValue;
+    if (score && ((W != 16 && W != 32 && W != 64) || (c_out & 1))) return hipErrorInvalidValue;
+    const int pb = score ? W / 2 : 0, nbg = score ? (2 * L + W - 1) / W : 0;
+    const CnnLayout PL = cnn_layout(c_in, c_out);
+    CnnOffsets off;
+    for (int i = 0; i < 8; ++i) off.o[i] = PL.off[i];
+    const CnnPacked P = cnn_packed(c_in);
+    hipLaunchKernelGGL(cnn_pack_kernel, dim3((unsigned)((P.total + 255) / 256)), dim3(256), 0, st, params, off, c_in,
+                       c_out, P, scratch);
+    const dim3 grid((unsigned)B), block(256);
+    // layer 1's K: 5 taps x channels rounded to 4, rounded to 16
+    switch (P.Kw1) {
+        case 32: hipLaunchKernelGGL(cnn_infer_kernel<32>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+        case 48: hipLaunchKernelGGL(cnn_infer_kernel<48>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+        case 64: hipLaunchKernelGGL(cnn_infer_kernel<64>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+        case 80: hipLaunchKernelGGL(cnn_infer_kernel<80>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+        case 96: hipLaunchKernelGGL(cnn_infer_kernel<96>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+        case 112: hipLaunchKernelGGL(cnn_infer_kernel<112>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+        case 128: hipLaunchKernelGGL(cnn_infer_kernel<128>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+        case 144: hipLaunchKernelGGL(cnn_infer_kernel<144>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+        default: hipLaunchKernelGGL(cnn_infer_kernel<160>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+    }
+    return hipGetLastError();
 }
 
 // Work area of the backward pass: two activation-sized gradients plus the

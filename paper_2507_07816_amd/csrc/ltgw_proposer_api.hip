@@ -405,9 +405,22 @@ int32_t ltgw_cnn_forward(ltgw_ctx *c, const float *params, const float *x, int32
     Enter en(c);
     int rc = cnn_shape_ok(c, B, c_in, c_out, L);
     if (rc != LTGW_OK) return rc;
-    const void *ptrs[] = {params, x, act, logits};
+    const void *ptrs[] = {params, x, logits};
     for (const void *p : ptrs)
         if ((rc = need_device(c, p, "network arrays")) != LTGW_OK) return rc;
+    if (!act) {  // inference only: the fused pass where the shape allows it
+        if (cnn_infer_supported(c_in, c_out, L)) {
+            if ((rc = ensure(c, c->cnn_packed, (size_t)cnn_infer_scratch_shorts(c_in) * 2, "packed weights")) !=
+                LTGW_OK)
+                return rc;
+            HIP_TRY(c, launch_cnn_infer(params, x, B, c_in, c_out, L, (short *)c->cnn_packed.p, logits, nullptr, 0,
+                                        c->stream),
+                    "network forward");
+            return LTGW_OK;
+        }
+        return fail(c, LTGW_E_INVALID_ARG, "act may be NULL only for c_in, c_out <= 32 and L <= 256");
+    }
+    if ((rc = need_device(c, act, "network activations")) != LTGW_OK) return rc;
     HIP_TRY(c, launch_cnn_forward(params, x, B, c_in, c_out, L, act, logits, c->stream), "network forward");
     return LTGW_OK;
 }
@@ -547,7 +560,7 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
     if (nb > 8192 || p->n_select < 1 || p->n_select2 < 0 || K1 + K2 > nb)
         return fail(c, LTGW_E_INVALID_ARG, "need 1 <= n_select, 0 <= n_select2, blocks of both <= %lld <= 8192",
                     (long long)nb);
-    if (!fin(p->psi_threshold) || !fin(p->coarse_threshold))
+    if (!fin(p->psi_threshold) || !fin(p->coarse_threshold) || !fin(p->tier2_threshold))
         return fail(c, LTGW_E_INVALID_ARG, "thresholds must be finite");
     const int64_t nc = g_c * L, n_cells = (int64_t)p->c_out * L;
     const int M1 = K1 * W, M2 = K2 * W;
@@ -566,11 +579,22 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
     // 1. coarse map -> network -> block scores -> the K1 best blocks -> their exact fine ratios
     if ((rc = stack_psi_impl(c, coarse, 1, 1, (double *)S.psi_c.p)) != LTGW_OK) return rc;
     HIP_TRY(c, launch_f64_to_f32((const double *)S.psi_c.p, (float *)S.x.p, R * nc, c->stream), "input convert");
-    HIP_TRY(c, launch_cnn_forward(p->params, (const float *)S.x.p, R, p->c_in, p->c_out, L, (float *)S.act.p,
-                                  (float *)S.logits.p, c->stream),
-            "network forward");
-    HIP_TRY(c, launch_block_scores((const float *)S.logits.p, R, p->c_out, L, W, nbg, (float *)S.bscore.p, c->stream),
-            "block score launch");
+    // the network and the block scores: one fused pass where the shape allows it
+    if (cnn_infer_supported(p->c_in, p->c_out, L) && (W == 16 || W == 32 || W == 64)) {
+        if ((rc = ensure(c, c->cnn_packed, (size_t)cnn_infer_scratch_shorts(p->c_in) * 2, "packed weights")) !=
+            LTGW_OK)
+            return rc;
+        HIP_TRY(c, launch_cnn_infer(p->params, (const float *)S.x.p, R, p->c_in, p->c_out, L,
+                                    (short *)c->cnn_packed.p, nullptr, (float *)S.bscore.p, W, c->stream),
+                "network forward");
+    } else {
+        HIP_TRY(c, launch_cnn_forward(p->params, (const float *)S.x.p, R, p->c_in, p->c_out, L, (float *)S.act.p,
+                                      (float *)S.logits.p, c->stream),
+                "network forward");
+        HIP_TRY(c, launch_block_scores((const float *)S.logits.p, R, p->c_out, L, W, nbg, (float *)S.bscore.p,
+                                       c->stream),
+                "block score launch");
+    }
     HIP_TRY(c, launch_select_top((const float *)S.bscore.p, R, (int)nb, K1, (int32_t *)S.blk.p, c->stream),
             "selection launch");
     SearchPlan P;
@@ -627,8 +651,8 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
         for (auto &n : need3)
             if ((rc = ensure(c, *n.b, n.bytes, "proposer buffers")) != LTGW_OK) return rc;
         const int32_t *rows2 = (const int32_t *)S.rows2.p;
-        HIP_TRY(c, launch_take_rows(R, best_p, thr, nullptr, 0.0, (int32_t *)S.rows2.p, counts, (int32_t *)S.flag2.p,
-                                    c->stream),
+        HIP_TRY(c, launch_take_rows(R, best_p, thr, (const double *)S.cm.p, p->tier2_threshold, (int32_t *)S.rows2.p,
+                                    counts, (int32_t *)S.flag2.p, c->stream),
                 "second-tier rows launch");
         HIP_TRY(c, launch_mask_blocks((float *)S.bscore.p, (const int32_t *)S.blk.p, R, K1, (int)nb, c->stream),
                 "block mask launch");

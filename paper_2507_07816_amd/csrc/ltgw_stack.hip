@@ -73,44 +73,59 @@ __device__ inline double stack_ratio(double s, const StackMoments &m, int64_t tt
 }
 
 // Every template of a grid on every realisation: the power critical ratio.
-// Output row rr holds realisation rmap[rr] (rr without a map); with a device
-// row count n_rows, rows rr >= *n_rows are skipped.
+// One workgroup per (256 f0, group, output row) and pass.  The hardware deals
+// workgroups to the XCDs in turn; workgroup w goes to row x + 8 (k / per_row)
+// of XCD x = w % 8 (k = w / 8), so the workgroups of one row run on one XCD
+// and share its L2, and rows 0, 1, 2 ... go to different XCDs (the listed
+// rows of a fallback are the first ones).  A grid of P rows (P a multiple of
+// 8) visits rows rr, rr + P, rr + 2P ...  Output row rr holds realisation
+// rmap[rr] (rr without a map); rows rr >= R, or >= *n_rows when that device
+// count is given, are skipped.
 template <int STORE, int SHIFT>
-__global__ __launch_bounds__(256) void stack_eval_kernel(const EvalArgs a, int64_t stack_bytes,
+__global__ __launch_bounds__(256) void stack_eval_kernel(const EvalArgs a, int R, int64_t stack_bytes,
                                                          int64_t stack_rows, double mu, double var,
                                                          int nan_to_zero, const int32_t *__restrict__ rmap,
                                                          const int32_t *__restrict__ n_rows, const StackMoments m,
                                                          double *__restrict__ out_psi) {
-    if (n_rows && (int)blockIdx.y >= *n_rows) return;
     const int n_tiles = (a.n_f0 + 255) / 256;
-    int tile, grp;
-    xcd_tile_group(blockIdx.x, gridDim.x, n_tiles, tile, grp);
+    const int per_row = n_tiles * a.n_groups;
+    const int P = (int)gridDim.x / per_row;
+    const int x = (int)blockIdx.x % kXcds, k = (int)blockIdx.x / kXcds;
+    const int q = k % per_row;
+    const int tile = q / a.n_groups, grp = q % a.n_groups;
     // a wave whose 64 f0 all lie past the grid has nothing to do (no barrier follows)
     if (tile * 256 + (int)(threadIdx.x & ~63u) >= a.n_f0) return;
-    const int rr = blockIdx.y;
-    const int r = rmap ? rmap[rr] : rr;
-    int i[1] = {tile * 256 + (int)threadIdx.x};
-    double f0[1] = {a.f0_min + (double)i[0] * a.f0_step};
-    DetView D = a.det[0];
-    D.store = (const char *)D.store + (int64_t)r * stack_bytes;
-    D.wq += (int64_t)r * stack_rows;
-    D.w += (int64_t)r * stack_rows;
-    Acc<1> acc;
-    acc.zero();
-    accumulate_det<STORE, false, 1, 16, HTable, SHIFT>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc);
-    if (i[0] >= a.n_f0) return;
-    const int64_t tt = (int64_t)grp * a.n_f0 + i[0];
-    out_psi[(int64_t)rr * ((int64_t)a.n_groups * a.n_f0) + tt] = stack_ratio(acc.s[0], m, tt, mu, var, nan_to_zero);
+    const int rows = n_rows ? min(R, *n_rows) : R;
+    const int i = tile * 256 + (int)threadIdx.x;
+    const double f0[1] = {a.f0_min + (double)i * a.f0_step};
+    const int64_t tt = (int64_t)grp * a.n_f0 + i;
+    for (int rr = x + kXcds * (k / per_row); rr < rows; rr += P) {
+        const int r = rmap ? rmap[rr] : rr;
+        DetView D = a.det[0];
+        D.store = (const char *)D.store + (int64_t)r * stack_bytes;
+        D.wq += (int64_t)r * stack_rows;
+        D.w += (int64_t)r * stack_rows;
+        Acc<1> acc;
+        acc.zero();
+        accumulate_det<STORE, false, 1, 16, HTable, SHIFT>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc);
+        if (i < a.n_f0)
+            out_psi[(int64_t)rr * ((int64_t)a.n_groups * a.n_f0) + tt] =
+                stack_ratio(acc.s[0], m, tt, mu, var, nan_to_zero);
+    }
 }
 
 hipError_t launch_stack_eval(int store, int shift, const EvalArgs &a, int R, int64_t stack_bytes,
                              int64_t stack_rows, double mu, double var, int nan_to_zero, const int32_t *rmap,
                              const int32_t *n_rows, StackMoments m, double *out_psi, hipStream_t st) {
-    const int64_t blocks = (int64_t)((a.n_f0 + 255) / 256) * a.n_groups;
+    // rows per pass: all of them rounded up to a multiple of the XCD count (the
+    // extra workgroups return), or at most 256 when a device count may leave
+    // most rows idle
+    const int P = (n_rows && R > 256 ? 256 : R + kXcds - 1) / kXcds * kXcds;
+    const int64_t blocks = (int64_t)((a.n_f0 + 255) / 256) * a.n_groups * P;
     if (blocks > 0x7fffffff || R > 65535 || R < 1) return hipErrorInvalidValue;
-    dim3 grid((unsigned)blocks, (unsigned)R), block(256);
-#define LTGW_STACK_EVAL(S, SH)                                                                                   \
-    hipLaunchKernelGGL((stack_eval_kernel<S, SH>), grid, block, 0, st, a, stack_bytes, stack_rows, mu, var, \
+    dim3 grid((unsigned)blocks), block(256);
+#define LTGW_STACK_EVAL(S, SH)                                                                                     \
+    hipLaunchKernelGGL((stack_eval_kernel<S, SH>), grid, block, 0, st, a, R, stack_bytes, stack_rows, mu, var, \
                        nan_to_zero, rmap, n_rows, m, out_psi)
     if (store == LTGW_STORE_F32 && shift == 0)
         LTGW_STACK_EVAL(LTGW_STORE_F32, 0);

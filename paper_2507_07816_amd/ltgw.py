@@ -71,7 +71,7 @@ class ltgw_candidate(C.Structure):
 class ltgw_diag(C.Structure):
     _fields_ = [("pow_undecided", C.c_int64), ("templates", C.c_int64), ("evals", C.c_int64),
                 ("in_band", C.c_int64), ("eval_kernel_ms", C.c_double), ("tables_ms", C.c_double),
-                ("tile_shape", C.c_int32), ("reserved", C.c_int32)]
+                ("tile_shape", C.c_int32), ("eval_launches", C.c_int32)]
 
 
 class ltgw_search(C.Structure):
@@ -89,7 +89,8 @@ class ltgw_batch_stats(C.Structure):
 class ltgw_proposer(C.Structure):
     _fields_ = [("params", C.c_void_p), ("c_in", C.c_int32), ("c_out", C.c_int32), ("L", C.c_int32),
                 ("n_select", C.c_int32), ("block", C.c_int32), ("n_select2", C.c_int32),
-                ("psi_threshold", C.c_double), ("coarse_threshold", C.c_double), ("blocks", C.c_void_p)]
+                ("psi_threshold", C.c_double), ("coarse_threshold", C.c_double), ("tier2_threshold", C.c_double),
+                ("blocks", C.c_void_p)]
 
 
 class LtgwError(RuntimeError):
@@ -407,7 +408,7 @@ def ltgw_cnn_forward(ctx, params, x, c_out, act, logits):
     B, c_in, L = (int(v) for v in x.shape)
     f = torch.float32
     _check(ctx, library().ltgw_cnn_forward(ctx, _dev(params, f), _dev(x, f), B, c_in, int(c_out), L,
-                                           _dev(act, f), _dev(logits, f)))
+                                           None if act is None else _dev(act, f), _dev(logits, f)))
 
 
 def ltgw_cnn_backward(ctx, params, x, c_out, act, dlogits, work, grads):
@@ -448,14 +449,14 @@ def propose_block_counts(n_select, n_select2, block):
 
 
 def ltgw_propose(ctx, fine, coarse, params, c_in, c_out, L, n_select, psi_threshold, coarse_threshold, R,
-                 block=1, n_select2=0, return_blocks=False):
+                 block=1, n_select2=0, return_blocks=False, tier2_threshold=-1e300):
     """(best_index[R], best_psi[R], fallback[R]) numpy arrays, and with
     return_blocks the evaluated blocks [R][K1 + K2] (-1: tier not taken)."""
     import torch
     K1, K2 = propose_block_counts(n_select, n_select2, block)
     blocks = np.empty((R, K1 + K2), np.int32) if return_blocks else None
     p = ltgw_proposer(_dev(params, torch.float32), int(c_in), int(c_out), int(L), int(n_select), int(block),
-                      int(n_select2), float(psi_threshold), float(coarse_threshold),
+                      int(n_select2), float(psi_threshold), float(coarse_threshold), float(tier2_threshold),
                       blocks.ctypes.data if return_blocks else None)
     bi = np.empty(R, np.int32)
     bp = np.empty(R, np.float64)

@@ -239,11 +239,12 @@ class Proposer:
                                               label_psi=label_psi, label=label))
         return losses
 
-    def propose(self, psi_threshold, coarse_threshold, R, return_blocks=False):
+    def propose(self, psi_threshold, coarse_threshold, R, return_blocks=False, tier2_threshold=-1e300):
         """ltgw_propose on the loaded stack: (best_index, best_psi, fallback[, blocks])."""
         return ltgw.ltgw_propose(self.ctx.h, self._fg, self._cg, self.params, self.c_in, self.c_out, self.L,
                                  self.n_select, psi_threshold, coarse_threshold, R, block=self.block,
-                                 n_select2=self.n_select2, return_blocks=return_blocks)
+                                 n_select2=self.n_select2, return_blocks=return_blocks,
+                                 tier2_threshold=tier2_threshold)
 
     def close_region(self, inj, df=2, dg=1):
         return close_region(self.fine, inj, df, dg)
@@ -258,14 +259,15 @@ class Proposer:
         return b["best"].cpu().numpy().copy(), b["best_psi"].cpu().numpy().copy()
 
     def evaluate(self, R_noise=256, R_signal=256, amp_range=(1.0, 3.0), fine_store="bf16", reps=3,
-                 coarse_quantiles=(1.0,), target_recall=0.99):
+                 coarse_quantiles=(1.0,), target_recall=0.99, tier2_quantile=None):
         """Recall and speed against the exhaustive search.
 
         Thresholds: psi_threshold is the largest exhaustive fine ratio over
         R_noise noise-only realisations (the detection rule of Sec. 3); for
         each q in coarse_quantiles the fallback's coarse threshold is the q
         quantile of the largest coarse ratio of each noise realisation (1.0:
-        their maximum).  On R_signal realisations with injections, an
+        their maximum); with tier2_quantile, the second tier is taken only
+        above that quantile of the same maxima.  On R_signal realisations with injections, an
         injection is detectable when the exhaustive FP32 search passes
         psi_threshold, and recalled when the proposer (coarse BF16 map,
         network, n_select exact cells on the `fine_store` store, fallback)
@@ -321,7 +323,9 @@ class Proposer:
             hit = self.evaluated(blocks, fb, near_tpl) & (near_prop > psi_thr)
             return frac(hit, det_near, n_near), frac(pp > psi_thr, det_ex, n_det)
 
-        _, pp_nf, fb_nf, bl_nf = self.propose(psi_thr, 1e300, R_signal, return_blocks=True)   # fallback never taken
+        t2 = -1e300 if tier2_quantile is None else float(np.quantile(coarse_max, tier2_quantile))
+        _, pp_nf, fb_nf, bl_nf = self.propose(psi_thr, 1e300, R_signal, return_blocks=True,
+                                              tier2_threshold=t2)          # fallback never taken
         rec_nf, rec_best_nf = recalls(pp_nf, fb_nf, bl_nf)
         points = []
         for q in coarse_quantiles:
@@ -329,11 +333,11 @@ class Proposer:
             t_pr = []
             for _ in range(reps):
                 ev0.record()
-                self.propose(psi_thr, coarse_thr, R_signal)
+                self.propose(psi_thr, coarse_thr, R_signal, tier2_threshold=t2)
                 ev1.record()
                 ev1.synchronize()
                 t_pr.append(ev0.elapsed_time(ev1))
-            pi, pp, fb, bl = self.propose(psi_thr, coarse_thr, R_signal, return_blocks=True)
+            pi, pp, fb, bl = self.propose(psi_thr, coarse_thr, R_signal, return_blocks=True, tier2_threshold=t2)
             rec, rec_best = recalls(pp, fb, bl)
             points.append(dict(coarse_quantile=q, coarse_threshold=coarse_thr, recall=rec, recall_best=rec_best,
                                fallback_frac=float(fb.mean()), propose_ms=min(t_pr),
@@ -346,7 +350,8 @@ class Proposer:
         out.update(recall_no_fallback=rec_nf, recall_best_no_fallback=rec_best_nf, detectable=n_near,
                    detectable_best=n_det, realisations=R_signal,
                    detectable_min_amp=float(amp[det_near].min()) if n_near else float("nan"),
-                   psi_threshold=psi_thr, exhaustive_ms=min(t_ex), n_select=self.n_select,
+                   psi_threshold=psi_thr, tier2_quantile=tier2_quantile, tier2_threshold=t2,
+                   exhaustive_ms=min(t_ex), n_select=self.n_select,
                    n_select2=self.n_select2, block=self.block, coarse_segments=self.coarse_segments,
                    n_cells=self.n_cells,
                    fine_store=fine_store, target_recall=target_recall, points=points)

@@ -71,7 +71,7 @@ int main(void) {
   F(ltgw_diag, tile_shape);
   printf("ltgw_proposer %zu\n", sizeof(ltgw_proposer));
   F(ltgw_proposer, c_in); F(ltgw_proposer, n_select); F(ltgw_proposer, psi_threshold);
-  F(ltgw_proposer, coarse_threshold); F(ltgw_proposer, blocks);
+  F(ltgw_proposer, coarse_threshold); F(ltgw_proposer, tier2_threshold); F(ltgw_proposer, blocks);
   return 0;
 }
 ''')

@@ -250,6 +250,21 @@ def test_cnn_forward_backward_vs_oracle():
     grads2 = torch.empty_like(grads)
     ltgw.ltgw_cnn_backward(ctx.h, pd, xd, c_out, act, dzd, work, grads2)
     assert torch.equal(grads, grads2)
+    # inference without activations (one fused pass): the same logits bit for bit,
+    # up to the largest supported shape; beyond it the call is refused
+    for (Bi, ci, co, Li) in ((B, c_in, c_out, L), (5, 4, 24, 200), (2, 32, 32, 256), (3, 7, 9, 1)):
+        print(f"case: fused inference B={Bi} c_in={ci} c_out={co} L={Li}", flush=True)
+        pi = T(_net(9, ci, co))
+        xi = T(rng.normal(size=(Bi, ci, Li)).astype(np.float32))
+        ai = torch.empty((3, Bi, 32, Li), dtype=torch.float32, device="cuda")
+        z1 = torch.empty((Bi, co, Li), dtype=torch.float32, device="cuda")
+        z2 = torch.full((Bi, co, Li), float("nan"), dtype=torch.float32, device="cuda")
+        ltgw.ltgw_cnn_forward(ctx.h, pi, xi, co, ai, z1)
+        ltgw.ltgw_cnn_forward(ctx.h, pi, xi, co, None, z2)
+        assert torch.equal(z1, z2)
+    with pytest.raises(ltgw.LtgwError):
+        ltgw.ltgw_cnn_forward(ctx.h, T(_net(9, 4, 6)), T(np.zeros((1, 4, 257), np.float32)), 6, None,
+                              torch.empty((1, 6, 257), dtype=torch.float32, device="cuda"))
     ctx.close()
 
 
@@ -391,6 +406,50 @@ def test_propose_partial_selection_equals_composed_calls():
     thr = float(np.max(bp)) + 1.0
     bi3, bp3, fb3 = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, M, thr, float(np.median(cmax)), R)
     assert np.array_equal(fb3, (cmax > np.median(cmax)).astype(np.int32))
+    ctx.close()
+
+
+def test_propose_block_selection_equals_composed_scores():
+    """Blocks of 16, 32 and 64 f0 take the fused network + block-score pass;
+    the reported first-tier blocks must be the best blocks by the largest
+    logit of their cells (ties to the lower block), from the layer-by-layer
+    network, and the first tier's best its exact ratios' best."""
+    import torch
+    from paper_2507_07816_amd import ltgw
+
+    ctx, st, t, v, w, R, L, c_in, c_out, params = _propose_setup()
+    fg, kf = _grid(FINE)
+    cg, kc = _grid(COARSE)
+    pc = torch.empty((R, c_in * L), dtype=torch.float64, device="cuda")
+    ltgw.ltgw_stack_psi(ctx.h, cg, 1, pc, nan_to_zero=True)
+    x = pc.float().reshape(R, c_in, L).contiguous()
+    act = torch.empty((3, R, 32, L), dtype=torch.float32, device="cuda")
+    logits = torch.empty((R, c_out, L), dtype=torch.float32, device="cuda")
+    ltgw.ltgw_cnn_forward(ctx.h, params, x, c_out, act, logits)
+    z = logits.cpu().numpy()
+    G = c_out // 2
+    for W in (16, 32, 64):
+        print(f"case: fused block scores W={W}", flush=True)
+        nbg = -(-2 * L // W)
+        score = np.full((R, G * nbg), -np.inf)
+        for g in range(G):
+            for k in range(nbg):
+                for i in range(k * W, min(k * W + W, 2 * L)):
+                    score[:, g * nbg + k] = np.maximum(score[:, g * nbg + k], z[:, 2 * g + i % 2, i // 2])
+        K1 = 2
+        bi, bp, fb, bl = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, K1 * W, 1e9, 1e9, R, block=W,
+                                           return_blocks=True)
+        for r in range(R):
+            order = np.lexsort((np.arange(G * nbg), -score[r]))
+            assert bl[r].tolist() == sorted(order[:K1].tolist())
+            tpl = [g * 2 * L + i for b in bl[r] for g in [b // nbg] for i in range((b % nbg) * W,
+                                                                                   min((b % nbg) * W + W, 2 * L))]
+            one = torch.empty((R, len(tpl)), dtype=torch.int32, device="cuda")
+            one[:] = torch.tensor(tpl, dtype=torch.int32)
+            allp = torch.empty((R, len(tpl)), dtype=torch.float64, device="cuda")
+            ltgw.ltgw_stack_psi_list(ctx.h, fg, one, allp)
+            i, p = op.best_template(allp.cpu().numpy()[r], np.array(tpl))
+            assert bi[r] == i and bp[r] == p
     ctx.close()
 
 
