@@ -202,6 +202,48 @@ def test_stack_psi_list_is_bit_identical_and_nan_outside():
     ctx.close()
 
 
+def test_bf16_stack_store_against_oracle_odd_shape():
+    """A BF16 stack of 94 segments x 189 bins (neither a multiple of 4 nor of
+    16, a bright pixel in the last segment and bin): every template's ratio
+    matches the oracle on the BF16-rounded power, and the listed evaluation
+    of every template equals the full one bit for bit."""
+    import torch
+    from paper_2507_07816_amd import ltgw
+
+    ns, nb = 94, 189
+    r = np.random.default_rng(31)
+    t = np.arange(ns) * 40.0 + 2.0
+    v = r.normal(size=(ns, 3))
+    v = v / np.linalg.norm(v, axis=1, keepdims=True) * 3.0e4
+    w = r.uniform(0.5, 2.0, ns).astype(np.float32)
+    ctx = ltgw.Context(0)
+    ctx.load_spectrogram(0, torch.zeros((ns, nb), dtype=torch.float32, device="cuda"), K_LO, T_SFT, t, weights=w)
+    ctx.set_velocity_table(0, v)
+    R = 3
+    P = r.exponential(size=(R, ns, nb)).astype(np.float32)
+    P[0, 10, 50] = 40.0
+    P[2, ns - 1, nb - 1] = 30.0                      # the last segment's last bin
+    ltgw.ltgw_load_stack(ctx.h, 0, torch.from_numpy(P).cuda(), "bf16", coarse=False)
+    fg, keep = _grid(FINE)
+    g = _ogrid(FINE)
+    n = g.n_templates
+    full = torch.empty((R, n), dtype=torch.float64, device="cuda")
+    ltgw.ltgw_stack_psi(ctx.h, fg, 0, full)
+    f = full.cpu().numpy()
+    for q in range(R):
+        Pb = (oracle.bf16_rne(P[q]).astype(np.uint32) << 16).view(np.float32)
+        ref = oracle.evaluate(oracle.Detector(Pb, t, v, K_LO, T_SFT, weights=w), g)
+        psi = oracle.psi_power(ref)
+        ok = np.isfinite(psi)
+        assert ok.sum() > 50 and np.array_equal(ok, np.isfinite(f[q]))
+        assert np.all(np.abs(f[q][ok] - psi[ok]) <= psi_tolerance(ref)[ok])
+    idx = np.tile(np.arange(n, dtype=np.int32), (R, 1))
+    out = torch.empty((R, n), dtype=torch.float64, device="cuda")
+    ltgw.ltgw_stack_psi_list(ctx.h, fg, torch.from_numpy(idx).cuda(), out)
+    assert np.array_equal(out.cpu().numpy(), f, equal_nan=True)
+    ctx.close()
+
+
 def _net(seed, c_in, c_out):
     p = cnn.init_params(c_in, c_out, seed).astype(np.float64)
     p += np.random.default_rng(seed + 1).normal(scale=0.05, size=p.size)
@@ -371,6 +413,20 @@ def test_propose_all_cells_finds_the_exhaustive_best():
         for r in range(R):
             assert np.all(np.diff(bl4[r, :h]) > 0) and np.all(np.diff(bl4[r, h:]) > 0)
             assert sorted(bl4[r].tolist()) == list(range(nb))
+    # a BF16 store: blocks of 16 evaluated in place, the exhaustive fallback
+    # and the exhaustive best find the same template and ratio
+    print("case: propose on a BF16 store", flush=True)
+    import torch
+    ltgw.ltgw_load_stack(ctx.h, 0, st, "bf16", coarse=True)
+    bb = torch.empty(R, dtype=torch.int32, device="cuda")
+    bpp = torch.empty(R, dtype=torch.float64, device="cuda")
+    ltgw.ltgw_stack_best(ctx.h, fg, bb, bpp)
+    nb16 = 4 * ((2 * L + 15) // 16)
+    bi5, bp5, fb5 = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, nb16 * 16, 1e9, 1e9, R, block=16)
+    bi6, bp6, fb6 = ltgw.ltgw_propose(ctx.h, fg, cg, params, c_in, c_out, L, 16, 1e9, -1e9, R, block=16)
+    assert np.all(fb5 == 0) and np.all(fb6 == 1)
+    assert np.array_equal(bi5, bb.cpu().numpy()) and np.array_equal(bp5, bpp.cpu().numpy())
+    assert np.array_equal(bi6, bi5) and np.array_equal(bp6, bp5)
     ctx.close()
 
 
