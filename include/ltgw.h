@@ -334,7 +334,7 @@ int32_t ltgw_inject_stack(ltgw_ctx *ctx, int32_t det, float *stack, int32_t R, c
 /* ltgw_load_stack: R realisations of detector slot det's geometry (its
  * segment times, weights and velocity table are used for all): a fine store
  * of format `store` from the device FP32 stack [R][n_seg][n_bins], and with
- * coarse = S (2 or 4; 1 means 2) a coarsened BF16 store: sums over groups of
+ * coarse = S (2, 4 or 8; 1 means 2) a coarsened BF16 store: sums over groups of
  * S consecutive segments and pairs of bins (n_seg a multiple of S, n_bins
  * even); a group's weight is the mean of its S weights.  coarse = 0: none.
  * The stack data must be finite and >= 0.  Synchronous.  Errors: STATE (slot

@@ -109,7 +109,7 @@ struct StackState {
     DevBuf bscore, blk, blk2, tpl2, psi2, cm_idx, cm;
     // per-realisation step lists of a proposal: rows and flags of the second
     // tier and of the fallback, their counts, the later bests, the block output
-    DevBuf rows2, flag2, bi2, bp2, counts, blocks;
+    DevBuf rows2, flag2, bi2, bp2, counts, blocks, records;
 };
 
 }  // namespace ltgw

@@ -37,6 +37,12 @@ hipError_t launch_take_rows(int R, const double *best_psi, double thr, const dou
                             int32_t *count, int32_t *flag, hipStream_t st);
 hipError_t launch_merge_rows(int R, const int32_t *rows, const int32_t *count, const int32_t *bi, const double *bp,
                              int32_t *best_idx, double *best_psi, hipStream_t st);
+struct ProposeRecord {
+    double psi;
+    int32_t idx, fallback;
+};
+hipError_t launch_pack_results(int R, const int32_t *best_idx, const double *best_psi, const int32_t *fb,
+                               ProposeRecord *out, hipStream_t st);
 hipError_t launch_blocks_out(int R, const int32_t *blk1, int K1, const int32_t *blk2, int K2, const int32_t *flag2,
                              int32_t *out, hipStream_t st);
 hipError_t launch_row_best(const double *psi, int rows, int64_t n, const int32_t *idx, const int32_t *n_rows,

@@ -21,7 +21,8 @@ void free_stack(StackState &S) {
                      &S.v,      &S.t2,       &S.v2,       &S.params, &S.psi_c, &S.x,      &S.act,
                      &S.logits, &S.cells,    &S.tpl,      &S.psi_sel, &S.best_idx, &S.best_psi, &S.fb,
                      &S.rmap,   &S.psi_all, &S.bscore, &S.blk, &S.blk2, &S.tpl2, &S.psi2,
-                     &S.cm_idx, &S.cm,      &S.rows2,   &S.flag2, &S.bi2,  &S.bp2,   &S.counts, &S.blocks};
+                     &S.cm_idx, &S.cm,      &S.rows2,   &S.flag2, &S.bi2,  &S.bp2,   &S.counts, &S.blocks,
+                     &S.records};
     for (DevBuf *b : all) release(*b);
     for (StackLevel &L : S.lv) {
         release(L.tau);
@@ -287,8 +288,8 @@ int32_t ltgw_load_stack(ltgw_ctx *c, int32_t det, int32_t R, const float *stack,
     if (rc != LTGW_OK) return rc;
     const int64_t ns = D.n_seg, nb = D.n_bins;
     const int Sg = coarse == 1 ? 2 : coarse;  // segments per coarse row
-    if (coarse < 0 || (coarse > 0 && Sg != 2 && Sg != 4))
-        return fail(c, LTGW_E_INVALID_ARG, "coarse must be 0 (none), 1 or 2 (pairs of segments) or 4");
+    if (coarse < 0 || (coarse > 0 && Sg != 2 && Sg != 4 && Sg != 8))
+        return fail(c, LTGW_E_INVALID_ARG, "coarse must be 0 (none), 1 or 2 (pairs of segments), 4 or 8");
     if (coarse && ((ns % Sg) || (nb & 1)))
         return fail(c, LTGW_E_INVALID_ARG, "a coarse store needs n_seg a multiple of %d and even n_bins (have %lld, %lld)",
                     Sg, (long long)ns, (long long)nb);
@@ -564,11 +565,14 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
         return fail(c, LTGW_E_INVALID_ARG, "thresholds must be finite");
     const int64_t nc = g_c * L, n_cells = (int64_t)p->c_out * L;
     const int M1 = K1 * W, M2 = K2 * W;
+    // the fused network pass keeps activations and logits on chip
+    const bool fused = cnn_infer_supported(p->c_in, p->c_out, L) && (W == 16 || W == 32 || W == 64);
     struct {
         DevBuf *b;
         size_t bytes;
     } need[] = {{&S.psi_c, (size_t)(R * nc) * 8},       {&S.x, (size_t)(R * nc) * 4},
-                {&S.act, (size_t)R * 3 * 32 * L * 4},    {&S.logits, (size_t)(R * n_cells) * 4},
+                {&S.act, fused ? 0 : (size_t)R * 3 * 32 * L * 4},
+                {&S.logits, fused ? 0 : (size_t)(R * n_cells) * 4},
                 {&S.bscore, (size_t)(R * nb) * 4},       {&S.blk, (size_t)R * K1 * 4},
                 {&S.tpl, (size_t)R * M1 * 4},            {&S.psi_sel, (size_t)R * M1 * 8},
                 {&S.best_idx, (size_t)R * 4},            {&S.best_psi, (size_t)R * 8},
@@ -580,7 +584,7 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
     if ((rc = stack_psi_impl(c, coarse, 1, 1, (double *)S.psi_c.p)) != LTGW_OK) return rc;
     HIP_TRY(c, launch_f64_to_f32((const double *)S.psi_c.p, (float *)S.x.p, R * nc, c->stream), "input convert");
     // the network and the block scores: one fused pass where the shape allows it
-    if (cnn_infer_supported(p->c_in, p->c_out, L) && (W == 16 || W == 32 || W == 64)) {
+    if (fused) {
         if ((rc = ensure(c, c->cnn_packed, (size_t)cnn_infer_scratch_shorts(p->c_in) * 2, "packed weights")) !=
             LTGW_OK)
             return rc;
@@ -692,10 +696,20 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
         HIP_TRY(c, hipMemcpyAsync(p->blocks, S.blocks.p, (size_t)R * KB * 4, hipMemcpyDeviceToHost, c->stream),
                 "copy");
     }
-    HIP_TRY(c, hipMemcpyAsync(best_index, best_i, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");
-    HIP_TRY(c, hipMemcpyAsync(best_psi, best_p, (size_t)R * 8, hipMemcpyDeviceToHost, c->stream), "copy");
-    HIP_TRY(c, hipMemcpyAsync(fallback, S.fb.p, (size_t)R * 4, hipMemcpyDeviceToHost, c->stream), "copy");
+    if ((rc = ensure(c, S.records, (size_t)R * sizeof(ProposeRecord), "proposer results")) != LTGW_OK) return rc;
+    HIP_TRY(c, launch_pack_results(R, best_i, best_p, (const int32_t *)S.fb.p, (ProposeRecord *)S.records.p,
+                                   c->stream),
+            "result packing launch");
+    std::vector<ProposeRecord> rec((size_t)R);
+    HIP_TRY(c, hipMemcpyAsync(rec.data(), S.records.p, (size_t)R * sizeof(ProposeRecord), hipMemcpyDeviceToHost,
+                              c->stream),
+            "copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "propose");
+    for (int r = 0; r < R; ++r) {
+        best_index[r] = rec[(size_t)r].idx;
+        best_psi[r] = rec[(size_t)r].psi;
+        fallback[r] = rec[(size_t)r].fallback;
+    }
     return LTGW_OK;
 }
 

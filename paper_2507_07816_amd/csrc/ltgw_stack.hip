@@ -223,20 +223,24 @@ hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_b
 // sums are those of the listed evaluation, in the same order.  Writes the
 // expanded template (-1 past the grid) and its ratio (NaN there).
 template <int STORE, int W>
-__global__ __launch_bounds__(256) void block_eval_kernel(const EvalArgs a, int64_t stack_bytes, int64_t stack_rows,
-                                                         const int32_t *__restrict__ blk, int K, int nbg,
-                                                         const int32_t *__restrict__ rmap,
+__global__ __launch_bounds__(256) void block_eval_kernel(const EvalArgs a, int R, int64_t stack_bytes,
+                                                         int64_t stack_rows, const int32_t *__restrict__ blk, int K,
+                                                         int nbg, const int32_t *__restrict__ rmap,
                                                          const int32_t *__restrict__ n_rows, const StackMoments mom,
                                                          int32_t *__restrict__ out_tpl,
                                                          double *__restrict__ out_psi) {
     constexpr int NB = 256 / W;
     __shared__ double sh[NB][kChunk];
     __shared__ int sg[NB];
-    const int rr = blockIdx.y;
-    if (n_rows && rr >= *n_rows) return;  // the whole workgroup, before any barrier
+    // XCD order as in stack_eval_kernel: the workgroups of one row share an
+    // XCD (and its L2), consecutive rows go to different XCDs
+    const int per_row = (K + NB - 1) / NB;
+    const int xcd = (int)blockIdx.x % kXcds, kk = (int)blockIdx.x / kXcds;
+    const int rr = xcd + kXcds * (kk / per_row), part = kk % per_row;
+    if (rr >= R || (n_rows && rr >= *n_rows)) return;  // the whole workgroup, before any barrier
     const int r = rmap ? rmap[rr] : rr;
     const int slot = (int)threadIdx.x / W, lf = (int)threadIdx.x % W;
-    const int q = (int)blockIdx.x * NB + slot;
+    const int q = part * NB + slot;
     const int b = q < K ? blk[(int64_t)r * K + q] : -1;
     const int i = (b >= 0 ? (b % nbg) * W : 0) + lf;
     const bool valid = b >= 0 && i < a.n_f0;
@@ -302,9 +306,12 @@ hipError_t launch_block_eval(int store, int W, const EvalArgs &a, int R, int64_t
                              StackMoments mom, int32_t *out_tpl, double *out_psi, hipStream_t st) {
     if (R > 65535 || R < 1 || K < 1 || !block_eval_supported(W)) return hipErrorInvalidValue;
     const int NB = 256 / W;
-    const dim3 grid((unsigned)((K + NB - 1) / NB), (unsigned)R), block(256);
-#define LTGW_BLOCK_EVAL(S, WW)                                                                                   \
-    hipLaunchKernelGGL((block_eval_kernel<S, WW>), grid, block, 0, st, a, stack_bytes, stack_rows, blk, K, nbg, \
+    // rows rounded up to a multiple of the XCD count (the extra workgroups return)
+    const int64_t wgs = (int64_t)((K + NB - 1) / NB) * ((R + kXcds - 1) / kXcds * kXcds);
+    if (wgs > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)wgs), block(256);
+#define LTGW_BLOCK_EVAL(S, WW)                                                                                      \
+    hipLaunchKernelGGL((block_eval_kernel<S, WW>), grid, block, 0, st, a, R, stack_bytes, stack_rows, blk, K, nbg, \
                        rmap, n_rows, mom, out_tpl, out_psi)
 #define LTGW_BLOCK_EVAL_W(S)          \
     if (W == 16)                      \
@@ -523,6 +530,22 @@ hipError_t launch_merge_rows(int R, const int32_t *rows, const int32_t *count, c
                              int32_t *best_idx, double *best_psi, hipStream_t st) {
     hipLaunchKernelGGL(merge_rows_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, rows, count, bi, bp,
                        best_idx, best_psi);
+    return hipGetLastError();
+}
+
+// The three per-realisation outputs of a proposal in one array of records,
+// so that one copy brings them to the host.
+__global__ void pack_results_kernel(int R, const int32_t *best_idx, const double *best_psi, const int32_t *fb,
+                                    ProposeRecord *out) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= R) return;
+    out[r] = ProposeRecord{best_psi[r], best_idx[r], fb[r]};
+}
+
+hipError_t launch_pack_results(int R, const int32_t *best_idx, const double *best_psi, const int32_t *fb,
+                               ProposeRecord *out, hipStream_t st) {
+    hipLaunchKernelGGL(pack_results_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, R, best_idx,
+                       best_psi, fb, out);
     return hipGetLastError();
 }
 

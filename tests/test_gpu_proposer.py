@@ -130,7 +130,7 @@ def test_inject_stack_matches_oracle_bins():
     ctx.close()
 
 
-@pytest.mark.parametrize("weights,S", [(True, 2), (False, 2), (True, 4)])
+@pytest.mark.parametrize("weights,S", [(True, 2), (False, 2), (True, 4), (True, 8)])
 def test_stack_psi_fine_and_coarse_vs_oracle(weights, S):
     import torch
     from paper_2507_07816_amd import ltgw

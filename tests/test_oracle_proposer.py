@@ -5,7 +5,7 @@ operand rounding and Adam).
   tie, groups of 2 and of 4 segments);
 - the coarse critical ratio against the fine oracle: with each group of S
   segments sharing one time and velocity and power constant on S x 2 blocks,
-  the coarse ratio is sqrt(2) times the fine one, for S = 2 and 4;
+  the coarse ratio is sqrt(2) times the fine one, for S = 2, 4 and 8;
 - only the first segment of a pair places the coarse column;
 - noise-free constant power gives Psi = 0 on every in-band template;
 - cells <-> templates is a bijection; best_template's tie rule;
@@ -62,12 +62,13 @@ def test_coarse_power_block_sums_and_bf16_tie():
     assert C[0, 1] == 0.0 and C[0, 2] == 0.0 and C[1, 0] == 0.0
 
 
-@pytest.mark.parametrize("S", [2, 4])
+@pytest.mark.parametrize("S", [2, 4, 8])
 def test_coarse_psi_is_sqrt2_times_fine_on_duplicated_groups(S):
     """Each group of S segments shares one time and velocity, the weights are
     equal within a group and the power is constant on S x 2 blocks: the fine
     sum is S w q per group, the coarse one 2 S w q, so the coarse ratio is
-    sqrt(2) times the fine one for every S."""
+    sqrt(2) times the fine one for every S (with weights whose group sums are
+    exact in FP32)."""
     n_seg, n_bins, k_lo, t_sft = 64, 96, 1900, 4.0
     t, v = _geometry(n_seg)
     for k in range(1, S):
@@ -76,7 +77,9 @@ def test_coarse_psi_is_sqrt2_times_fine_on_duplicated_groups(S):
     r = np.random.default_rng(3)
     q = r.integers(0, 6, size=(n_seg // S, n_bins // 2)).astype(np.float32)
     P = np.repeat(np.repeat(q, S, axis=0), 2, axis=1)        # constant on S x 2 blocks
-    w = np.repeat(r.uniform(0.5, 2.0, n_seg // S).astype(np.float32), S)  # equal within a group
+    # equal within a group, and dyadic (k / 8) so that the FP32 sums of a group's
+    # weights are exact and the coarse weight is the fine one
+    w = np.repeat((r.integers(4, 17, n_seg // S) / 8.0).astype(np.float32), S)
     det = oracle.Detector(P, t, v, k_lo, t_sft, weights=w)
     g = _grid()
     fine = oracle.psi_power(oracle.evaluate(det, g))
