@@ -94,8 +94,8 @@ def cpu_baseline(wl, rho, target_s=15.0):
                       f"({idx.size * n_seg:.3g} evals, {dt:.1f} s, FP64, incl. its Eq. 1 table)"}
 
 
-def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_signal=2048, eval_noise=1024, seed=7,
-                 coarse_segments=4, select2_frac=0.10, block=16, label="near", select_frac=0.05, tier2_quantile=None):
+def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_signal=4096, eval_noise=1024, seed=7,
+                 coarse_segments=4, select2_frac=0.20, block=64, label="near", select_frac=0.10, tier2_quantile=None):
     """The learned proposer on the small workload's shape (1024 segments x 800
     bins, 4800 fine templates): trained on `realisations` device-generated
     noise + injection realisations (amplitudes U[0.3, 3]), then recall and

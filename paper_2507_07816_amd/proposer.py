@@ -144,14 +144,14 @@ class Proposer:
                 target=T.empty(R, **i32))}
         return self._bufs[R]
 
-    def draw_injections(self, R, p_signal, amp_range):
+    def draw_injections(self, R, p_signal, amp_range, rng=None):
         """Host draw of (f0, tau, n, amp) per realisation: f0 uniform over the fine
         band, tau log-uniform and n uniform over the fine grid's ranges."""
         f = self.fine
         f_lo = f["f0_min"]
         f_hi = f["f0_min"] + (f["n_f0"] - 1) * f["f0_step"]
         tau, brake = np.asarray(f["tau"]), np.asarray(f["brake"])
-        r = self.rng
+        r = self.rng if rng is None else rng
         sig = r.uniform(size=R) < p_signal
         out = np.zeros((R, 4))
         out[:, 0] = r.uniform(f_lo, f_hi, R)
@@ -292,7 +292,10 @@ class Proposer:
         _, noise_best = self.exhaustive(R_noise)
         psi_thr = float(np.max(noise_best))
         coarse_max = b["x"].cpu().numpy().reshape(R_noise, -1).max(axis=1)
-        inj, sig = self.draw_injections(R_signal, 1.0, amp_range)
+        # the held-out injections come from their own generator, so the
+        # evaluation set does not depend on how long the network was trained
+        inj, sig = self.draw_injections(R_signal, 1.0, amp_range,
+                                        rng=np.random.Generator(np.random.PCG64(self.seed + 7919)))
         b = self.make_batch(R_signal, 3, 0, inj, with_labels=False)
         ev0, ev1 = T.cuda.Event(enable_timing=True), T.cuda.Event(enable_timing=True)
         t_ex = []
