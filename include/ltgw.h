@@ -312,8 +312,9 @@ int32_t ltgw_tune_load(ltgw_ctx *ctx, const char *path);
  * A system pattern on top of the method (not part of the paper): a small
  * network reads a coarse statistic map and picks the fine-grid cells that
  * are then evaluated exactly; the exhaustive grid stays the fallback and the
- * judge of its recall (detection as in Sec. 3: Psi above the largest noise-only
- * value).  Training data are realisations generated on the device. */
+ * reference its recall is measured against (detection as in Sec. 3: Psi above
+ * the largest noise-only value).  Training data are realisations generated on
+ * the device. */
 
 /* ltgw_generate_noise: Exp(1) noise for realisations r0 .. r0+R-1, n values
  * each, into the device array out[R][n].  Element e of realisation r is word

@@ -18,10 +18,10 @@
  *     bins that the track selects                                   (Sec. 2)
  *   - critical ratio Psi = (s - <s>)/sigma_s                        (Sec. 2, Eq. 4)
  *
- * Readings where the paper is silent (one bin per segment at the segment
- * reference time; nearest bin with ties up; out-of-band and t < T0 segments
- * contribute nothing; per-segment weights; an unweighted integer count) are
- * the ones listed in the design notes of this repository.
+ * Readings where the paper is silent: one bin per segment at the segment
+ * reference time; the nearest bin, ties up; out-of-band and t < T0 segments
+ * contribute nothing; per-segment weights on the power; an unweighted
+ * integer count.
  */
 #include <math.h>
 #include <quadmath.h>

@@ -8,7 +8,8 @@ compute), on the tiny workload (1024 segments, 4800 templates, one injection):
 - bin indices: the storage cannot change them, so N and the count c (decided
   on the FP32 input) stay bit-exact;
 - top-k agreement with the FP32 search, for both statistics.
-The report is written to gpurun_out/precision_report.json when that folder exists.
+The report is printed, and written to $LTGW_REPORT_DIR/precision_report.json when
+that variable names a folder.
 """
 import json
 import os
@@ -22,7 +23,6 @@ from test_gpu_parity import tiny_oracle
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 BOUND = {"bf16": 2.0 ** -8, "fp8": 2.0 ** -3}
 
 
@@ -57,7 +57,7 @@ def test_quantised_store_precision_report():
             assert r["s_rel_err_max"] < BOUND[store]
             assert r["top10_power_overlap"] >= 8
     print(json.dumps(report, indent=1), flush=True)
-    out = os.path.join(ROOT, "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("LTGW_REPORT_DIR", "")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "precision_report.json"), "w") as fh:
             json.dump(report, fh, indent=1)
