@@ -163,6 +163,34 @@ typedef struct {
 int32_t ltgw_eval_templates(ltgw_ctx *ctx, const ltgw_grid *g, uint32_t stats, float *out_s,
                             int32_t *out_c, int32_t *out_n);
 
+/* ---- eval_list ---------------------------------------------------------------
+ * Uniform random template bank (Sec. 2): templates with their own parameters,
+ * e.g. drawn uniformly over the parameter space. */
+typedef struct {
+    double f0;     /* > 0, Hz                                            */
+    double tau;    /* > 0, s                                             */
+    double brake;  /* > 1, braking index n                               */
+    double sky[3]; /* unit vector (|1 - |n|| <= 1e-12)                    */
+} ltgw_template;
+
+/* ltgw_eval_list: statistic of each template of tpl[0..n) (host array), summed
+ * over the detectors det_mask selects (as in ltgw_grid; 0 = every loaded slot
+ * below 32), with T0 = t0.  Every template is evaluated exactly as a lattice
+ * template with those parameters: Eq. 1's power correctly rounded per segment,
+ * Eq. 2, the bin rule and FP32 sums over chunks of 32 segments carried in FP64,
+ * so s, c and N of a lattice template are the lattice's bit for bit (W1, W2
+ * are summed in that order too; the lattice forms them exactly, so they agree
+ * to FP32 rounding of 32-term sums).  The evaluation runs in ascending f0
+ * (results stay in list order) and is bound by FP64 arithmetic: no table is
+ * shared between templates.  Outputs as ltgw_eval_templates, in list order;
+ * the results are kept for ltgw_psi and ltgw_topk_candidates (whose records
+ * then carry the listed parameters, index = list position and sky = -1).
+ * Asynchronous (the list is copied before the call returns).  Errors:
+ * INVALID_ARG (values, a device pointer for tpl, f0 * t_sft too large),
+ * STATE (no detector selected, or one without velocities), NOMEM, DEVICE. */
+int32_t ltgw_eval_list(ltgw_ctx *ctx, const ltgw_template *tpl, int64_t n, double t0, uint32_t det_mask,
+                       float *out_s, int32_t *out_c, int32_t *out_n);
+
 /* ---- critical ratios ---------------------------------------------------------
  * Eq. 4 with Exp(1) noise moments: power Psi = (s - W1)/sqrt(W2); count
  * Psi = (c - N q)/sqrt(N q (1 - q)) with q = exp(-(double)rho_th) taken from

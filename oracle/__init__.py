@@ -48,6 +48,8 @@ def lib():
         L.oracle_eval.argtypes = [P, i32, P, i64, i64, P, P, P, P, P]
         L.oracle_eval_list.restype = None
         L.oracle_eval_list.argtypes = [P, i32, P, P, i64, P, P, P, P, P]
+        L.oracle_eval_params.restype = None
+        L.oracle_eval_params.argtypes = [P, i32, P, i64, d, P, P, P, P, P]
         L.oracle_philox4x32_10.restype = None
         L.oracle_philox4x32_10.argtypes = [P, P, P]
         L.oracle_exp_noise.restype = None
@@ -223,6 +225,22 @@ def evaluate_list(dets, grid: Grid, index):
     gs = grid._struct()
     lib().oracle_eval_list(C.cast(arr, C.c_void_p), len(dets), C.byref(gs), _p(index), n,
                            _p(out["s"]), _p(out["c"]), _p(out["N"]), _p(out["W1"]), _p(out["W2"]))
+    return out
+
+
+def evaluate_params(dets, params, t0=0.0):
+    """Statistic of explicit templates, params [n][6] = (f0, tau, n, sky x, y, z)
+    (the uniform random bank of Sec. 2): dict of s, c, N, W1, W2 arrays."""
+    if isinstance(dets, Detector):
+        dets = [dets]
+    params = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, 6)
+    n = params.shape[0]
+    out = {"s": np.empty(n, np.float64), "c": np.empty(n, np.int32),
+           "N": np.empty(n, np.int32), "W1": np.empty(n, np.float64),
+           "W2": np.empty(n, np.float64)}
+    arr = (_Det * len(dets))(*[d._struct() for d in dets])
+    lib().oracle_eval_params(C.cast(arr, C.c_void_p), len(dets), _p(params), n, float(t0),
+                             _p(out["s"]), _p(out["c"]), _p(out["N"]), _p(out["W1"]), _p(out["W2"]))
     return out
 
 

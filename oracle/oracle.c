@@ -233,6 +233,42 @@ void oracle_eval_list(const oracle_det *dets, int32_t n_det, const oracle_grid *
     eval_templates(dets, n_det, g, list, 0, n, s, c, N, W1, W2);
 }
 
+/* The statistic of explicit templates (the uniform random template bank of
+ * Sec. 2): params[q] = (f0, tau, n, sky x, y, z).  Each template is evaluated
+ * exactly as a lattice template with those parameters would be. */
+void oracle_eval_params(const oracle_det *dets, int32_t n_det, const double *params, int64_t n, double t0,
+                        double *s, int32_t *c, int32_t *N, double *W1, double *W2)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t o = 0; o < n; ++o) {
+        const double *p = params + 6 * o;
+        double acc = 0.0, w1 = 0.0, w2 = 0.0;
+        int32_t cnt = 0, nin = 0;
+        for (int32_t d = 0; d < n_det; ++d) {
+            const oracle_det *D = dets + d;
+            for (int32_t j = 0; j < D->n_seg; ++j) {
+                if (D->t_seg[j] < t0) continue;
+                double gj = oracle_spin_factor(D->t_seg[j], t0, p[1], p[2]);
+                double Dj = oracle_doppler(D->v + 3 * j, p + 3);
+                int64_t b = oracle_bin(p[0], gj, Dj, D->t_sft, D->k_lo);
+                if (b < 0 || b >= D->n_bins) continue;
+                double wj = D->w ? (double)D->w[j] : 1.0;
+                int64_t off = (int64_t)j * D->n_bins + b;
+                acc = acc + wj * D->P[off];
+                if (D->rho[off] > D->rho_th) cnt += 1;
+                nin += 1;
+                w1 = w1 + wj;
+                w2 = w2 + wj * wj;
+            }
+        }
+        s[o] = acc;
+        c[o] = cnt;
+        N[o] = nin;
+        W1[o] = w1;
+        W2[o] = w2;
+    }
+}
+
 /* Bins of one template on one detector: b_out[j] = column, or INT64_MIN for a
  * masked segment (t_j < T0).  Out-of-band columns are returned as computed. */
 void oracle_track_bins(const oracle_det *D, double f0, double tau, double brake,

@@ -2,6 +2,7 @@
 // The declarations and their contracts are in include/ltgw.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -10,6 +11,7 @@
 #include <vector>
 
 #include "ltgw_ctx.h"
+#include "ltgw_list.h"
 
 using namespace ltgw;
 
@@ -189,8 +191,8 @@ void ltgw_destroy(ltgw_ctx *c) {
         release(d.store_buf); release(d.t_seg); release(d.w); release(d.wq);
         release(d.scale); release(d.v); release(d.g); release(d.H); release(d.wfix); release(d.win);
     }
-    DevBuf *all[] = {&c->staging, &c->counters, &c->cnn_packed, &c->tau_d, &c->brake_d, &c->sky_d,
-                     &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2, &c->diff,
+    DevBuf *all[] = {&c->staging, &c->counters, &c->cnn_packed, &c->list_d, &c->perm_d,
+                     &c->tau_d,   &c->brake_d,  &c->sky_d,      &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2, &c->diff,
                      &c->cand_pa, &c->cand_ia, &c->cand_pb, &c->cand_ib, &c->cand_out, &c->n_out};
     for (DevBuf *b : all) release(*b);
     delete c;
@@ -556,6 +558,7 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     c->last_launches = launches;
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream), "event record");
     c->have_eval = true;
+    c->list_mode = false;
     c->last_variant = variant;
     c->n_templates = n_tpl;
     c->n_evals = P.n_evals;
@@ -578,6 +581,111 @@ int32_t ltgw_eval_templates(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, flo
     if (!c) return LTGW_E_INVALID_ARG;
     Enter en(c);
     return eval_single(c, g, stats, out_s, out_c, out_n, -1);
+}
+
+int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double t0, uint32_t det_mask,
+                       float *out_s, int32_t *out_c, int32_t *out_n) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    c->have_eval = false;
+    if (!tpl) return fail(c, LTGW_E_INVALID_ARG, "template list is NULL");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(c, LTGW_E_INVALID_ARG, "n must be in 1 .. 2^31 - 1");
+    if (is_device_ptr(tpl)) return fail(c, LTGW_E_INVALID_ARG, "the template list must be host memory");
+    if (!fin(t0)) return fail(c, LTGW_E_INVALID_ARG, "t0 must be finite");
+    double f0_max = 0.0;
+    for (int64_t q = 0; q < n; ++q) {
+        const ltgw_template &T = tpl[q];
+        if (!fin(T.f0) || !(T.f0 > 0.0)) return fail(c, LTGW_E_INVALID_ARG, "template %lld: f0 must be > 0", (long long)q);
+        if (!fin(T.tau) || !(T.tau > 0.0))
+            return fail(c, LTGW_E_INVALID_ARG, "template %lld: tau must be > 0", (long long)q);
+        if (!fin(T.brake) || !(T.brake > 1.0))
+            return fail(c, LTGW_E_INVALID_ARG, "template %lld: the braking index must be > 1", (long long)q);
+        const double *k = T.sky;
+        if (!fin(k[0]) || !fin(k[1]) || !fin(k[2]) ||
+            std::fabs(std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]) - 1.0) > 1e-12)
+            return fail(c, LTGW_E_INVALID_ARG, "template %lld: sky is not a unit vector", (long long)q);
+        f0_max = T.f0 > f0_max ? T.f0 : f0_max;
+    }
+    int slots[LTGW_MAX_SEARCH_DET], n_slots = 0;
+    for (int d = 0; d < 32; ++d) {
+        const bool want = det_mask ? ((det_mask >> d) & 1u) : c->det[d].loaded;
+        if (!want) continue;
+        if (n_slots == LTGW_MAX_SEARCH_DET)
+            return fail(c, LTGW_E_UNSUPPORTED, "a search sums at most %d detectors", LTGW_MAX_SEARCH_DET);
+        slots[n_slots++] = d;
+    }
+    if (n_slots < 1) return fail(c, LTGW_E_STATE, "no detector selected");
+    ListArgs a;
+    std::memset(&a, 0, sizeof a);
+    int64_t n_seg_total = 0;
+    for (int q = 0; q < n_slots; ++q) {
+        const Det &D = c->det[slots[q]];
+        if (!D.loaded) return fail(c, LTGW_E_STATE, "detector %d selected but not loaded", slots[q]);
+        if (!D.has_v) return fail(c, LTGW_E_STATE, "detector %d has no velocity table", slots[q]);
+        if (q > 0 && (D.rho_th != c->det[slots[0]].rho_th || D.store != c->det[slots[0]].store))
+            return fail(c, LTGW_E_UNSUPPORTED, "selected detectors differ in rho_th or store");
+        if (!(f0_max * D.t_sft * (1.0 + D.v_max) < (double)(1 << 30) - 4.0))
+            return fail(c, LTGW_E_INVALID_ARG, "f0_max * t_sft too large for detector %d", slots[q]);
+        ListDet &V = a.det[q];
+        V.store = D.store_buf.p;
+        V.pitch_bytes = (int32_t)(D.pitch * (D.store == LTGW_STORE_F32 ? 4 : D.store == LTGW_STORE_BF16 ? 2 : 1));
+        V.n_seg = D.n_seg;
+        V.n_bins = D.n_bins;
+        V.t = (const double *)D.t_seg.p;
+        V.v = (const double *)D.v.p;
+        V.wq = (const float *)D.wq.p;
+        V.w = (const float *)D.w.p;
+        V.t_sft = D.t_sft;
+        V.cshift = 1.5 - (double)D.k_lo;
+        n_seg_total += D.n_seg;
+    }
+    // evaluation order: ascending f0, so that neighbouring lanes gather neighbouring columns
+    std::vector<int32_t> perm((size_t)n);
+    for (int64_t q = 0; q < n; ++q) perm[(size_t)q] = (int32_t)q;
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return tpl[x].f0 < tpl[y].f0; });
+    HIP_TRY(c, hipEventSynchronize(c->ev_h2d), "previous upload");
+    c->h_list.assign(tpl, tpl + n);
+    c->h_perm.swap(perm);
+    int rc;
+    if ((rc = ensure(c, c->list_d, (size_t)n * sizeof(ltgw_template), "template list")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->perm_d, (size_t)n * 4, "template order")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, c->list_d.p, c->h_list.data(), (size_t)n * sizeof(ltgw_template), "template upload")) != LTGW_OK)
+        return rc;
+    if ((rc = h2d(c, c->perm_d.p, c->h_perm.data(), (size_t)n * 4, "template order upload")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->res_s, n * 8, "results s")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->res_c, n * 4, "results c")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->res_n, n * 4, "results N")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->res_w1, n * 8, "results W1")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->res_w2, n * 8, "results W2")) != LTGW_OK) return rc;
+    if ((rc = zero_counter(c, kCntInBand, 1)) != LTGW_OK) return rc;
+    a.n_det = n_slots;
+    a.t0 = t0;
+    a.tpl = (const ltgw_template *)c->list_d.p;
+    a.perm = (const int32_t *)c->perm_d.p;
+    a.n = n;
+    a.s = (double *)c->res_s.p;
+    a.c = (int32_t *)c->res_c.p;
+    a.n_in = (int32_t *)c->res_n.p;
+    a.w1 = (double *)c->res_w1.p;
+    a.w2 = (double *)c->res_w2.p;
+    a.out_s = out_s;
+    a.out_c = out_c;
+    a.out_n = out_n;
+    a.in_band_total = (unsigned long long *)c->counters.p + kCntInBand;
+    a.undecided = (unsigned long long *)c->counters.p + kCntUndecided;
+    HIP_TRY(c, hipEventRecord(c->ev_h2d, c->stream), "event record");
+    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream), "event record");
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream), "event record");
+    HIP_TRY(c, launch_template_list(c->det[slots[0]].store, a, c->stream), "template list launch");
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream), "event record");
+    c->have_eval = true;
+    c->list_mode = true;
+    c->last_variant = -1;
+    c->last_launches = 1;
+    c->n_templates = n;
+    c->n_evals = n * n_seg_total;
+    c->rho_th = c->det[slots[0]].rho_th;
+    return LTGW_OK;
 }
 
 int32_t ltgw_autotune(ltgw_ctx *c, const ltgw_grid *g, int32_t *best_variant) {
@@ -712,6 +820,7 @@ int32_t ltgw_topk_candidates(ltgw_ctx *c, uint32_t stat, int32_t k, ltgw_candida
     dec.n_brake = c->n_brake;
     dec.tau = (const double *)c->tau_d.p;
     dec.brake = (const double *)c->brake_d.p;
+    dec.list = c->list_mode ? (const ltgw_template *)c->list_d.p : nullptr;
     const double q = std::exp(-(double)c->rho_th);
     HIP_TRY(c, launch_topk(stat, c->n_templates, (const double *)c->res_s.p, (const int32_t *)c->res_c.p,
                            (const int32_t *)c->res_n.p, (const double *)c->res_w1.p,

@@ -138,6 +138,10 @@ struct ltgw_ctx {
     float rho_th = 1.6f;
     int last_variant = 1;
     int last_launches = 0;  // statistic-kernel dispatches of the last eval
+    bool list_mode = false;      // the last eval was an explicit template list
+    std::vector<ltgw_template> h_list;  // its templates (top-k records) ...
+    std::vector<int32_t> h_perm;        // ... and their evaluation order
+    ltgw::DevBuf list_d, perm_d;
     int forced_variant = -1;      // ltgw_set_tile_shape; -1 = autotuner
     ltgw::BatchState batch;
     ltgw::StackState stack;

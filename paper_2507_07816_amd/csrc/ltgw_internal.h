@@ -131,11 +131,14 @@ hipError_t launch_psi(uint32_t stat, int64_t n, const double *s, const int32_t *
                       const int32_t *N, const double *w1, const double *w2, double q,
                       double *out, hipStream_t st);
 
+// How a top-k record gets its parameters: from the lattice's index split, or,
+// for an explicit template list, from the device copy of that list (sky = -1).
 struct TopkDecode {
     double f0_min, f0_step;
     int32_t n_f0, n_tau, n_brake;
     const double *tau;
     const double *brake;
+    const ltgw_template *list = nullptr;
 };
 // Scratch for top-k: two candidate buffers of (psi, index) pairs.
 hipError_t launch_topk(uint32_t stat, int64_t n, const double *s, const int32_t *c,

@@ -836,15 +836,23 @@ __global__ void topk_records_kernel(int32_t k, uint32_t stat, const double *s, c
         rec.sky = -1;
         rec.n_valid = 0;
     } else {
-        const int64_t i_f0 = t % dec.n_f0;
-        const int64_t grp = t / dec.n_f0;
-        const int64_t i_tau = grp % dec.n_tau;
-        const int64_t rr = grp / dec.n_tau;
+        if (dec.list) {
+            const ltgw_template &T = dec.list[t];
+            rec.f0 = T.f0;
+            rec.tau = T.tau;
+            rec.brake = T.brake;
+            rec.sky = -1;
+        } else {
+            const int64_t i_f0 = t % dec.n_f0;
+            const int64_t grp = t / dec.n_f0;
+            const int64_t i_tau = grp % dec.n_tau;
+            const int64_t rr = grp / dec.n_tau;
+            rec.f0 = dec.f0_min + (double)i_f0 * dec.f0_step;
+            rec.tau = dec.tau[i_tau];
+            rec.brake = dec.brake[rr % dec.n_brake];
+            rec.sky = (int32_t)(rr / dec.n_brake);
+        }
         rec.index = t;
-        rec.f0 = dec.f0_min + (double)i_f0 * dec.f0_step;
-        rec.tau = dec.tau[i_tau];
-        rec.brake = dec.brake[rr % dec.n_brake];
-        rec.sky = (int32_t)(rr / dec.n_brake);
         rec.n_valid = N[t];
         rec.stat = stat == LTGW_STAT_POWER ? s[t] : (double)c[t];
         rec.psi = psi[r];

@@ -1,0 +1,104 @@
+// The statistic of an explicit template list: the uniform random template
+// bank of Sec. 2, where every template has its own (f0, tau, n, sky) and no
+// per-group table can be shared.
+#include "ltgw_gather.h"
+#include "ltgw_list.h"
+#include "ddpow.h"
+
+#pragma clang fp contract(off)
+
+namespace ltgw {
+
+// Lane q evaluates template perm[q] over every selected detector and segment
+// with the lattice's arithmetic, in its order:
+//   t < T0: masked (g = 0, so the column falls out of band)
+//   u = 1 + (t - T0)/tau, e = 1/(1 - n), g = RN(u^e)            (Eq. 1)
+//   D = 1 + ((vx nx + vy ny) + vz nz)/c, H = RN(RN(g D) T_sft)   (Eq. 2)
+//   x = f0 H, column = trunc(x + 1.5 - k_lo), gather, FP32 sums over chunks
+//   of 32 segments carried in FP64                               (Sec. 2)
+// so a template of a lattice gets that lattice's s, c and N bit for bit.
+// The power is correctly rounded per segment (double-double, the undecided
+// cases counted), which makes this mode bound by FP64 arithmetic: sorting
+// the list by f0 (the caller's perm) keeps neighbouring lanes on
+// neighbouring columns for the gathers.
+template <int STORE>
+__global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = q < a.n;
+    const int32_t o = live ? a.perm[q] : a.perm[0];
+    const ltgw_template T = a.tpl[o];
+    const double e = 1.0 / (1.0 - T.brake);
+    double s = 0.0, w1 = 0.0, w2 = 0.0;
+    int cnt = 0, nin = 0;
+    for (int d = 0; d < a.n_det; ++d) {
+        const ListDet D = a.det[d];
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)D.store, Store<STORE>::kBytes, D.n_bins + 2, kBufDword3);
+        const unsigned nb = (unsigned)D.n_bins;
+        for (int j0 = 0; j0 < D.n_seg; j0 += kChunk) {
+            const int je = min(j0 + kChunk, D.n_seg);
+            float sc = 0.0f, w1c = 0.0f, w2c = 0.0f;
+            for (int j = j0; j < je; ++j) {
+                const double t = D.t[j];
+                double g = 0.0;
+                if (!(t < a.t0)) {
+                    const double dt = t - a.t0;
+                    const double qq = dt / T.tau;
+                    const double u = 1.0 + qq;
+                    int und = 0;
+                    g = pow_cr(u, e, &und);
+                    if (und) atomicAdd(a.undecided, 1ull);
+                }
+                const double va = D.v[3 * j + 0] * T.sky[0];
+                const double vb = D.v[3 * j + 1] * T.sky[1];
+                const double vz = D.v[3 * j + 2] * T.sky[2];
+                const double vn = (va + vb) + vz;
+                const double r = vn / kC;
+                const double Df = 1.0 + r;
+                const double h = g * Df;
+                const double H = h * D.t_sft;
+                const double x = T.f0 * H;
+                const double vv = x + D.cshift;
+                const unsigned idx = (unsigned)__double2int_rz(vv);
+                const float p = Store<STORE>::get(rs, (int)idx, j * D.pitch_bytes, cnt);
+                sc = __builtin_fmaf(D.wq[j], p, sc);
+                const bool inb = (idx - 1u) < nb;
+                nin += inb ? 1 : 0;
+                const float wv = D.w[j];
+                const float wj = inb ? wv : 0.0f;
+                w1c += wj;
+                w2c = __builtin_fmaf(wj, wj, w2c);
+            }
+            s += (double)sc;
+            w1 += (double)w1c;
+            w2 += (double)w2c;
+        }
+    }
+    // the in-band total of the list (diagnostics): one atomic per wavefront
+    unsigned long long mine = live ? (unsigned long long)nin : 0ull;
+    for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
+    if ((threadIdx.x & 63) == 0 && mine) atomicAdd(a.in_band_total, mine);
+    if (!live) return;
+    a.s[o] = s;
+    a.c[o] = cnt;
+    a.n_in[o] = nin;
+    a.w1[o] = w1;
+    a.w2[o] = w2;
+    if (a.out_s) a.out_s[o] = (float)s;
+    if (a.out_c) a.out_c[o] = cnt;
+    if (a.out_n) a.out_n[o] = nin;
+}
+
+hipError_t launch_template_list(int store, const ListArgs &a, hipStream_t st) {
+    if (a.n < 1 || a.n > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    if (store == LTGW_STORE_F32)
+        hipLaunchKernelGGL(template_list_kernel<LTGW_STORE_F32>, grid, block, 0, st, a);
+    else if (store == LTGW_STORE_BF16)
+        hipLaunchKernelGGL(template_list_kernel<LTGW_STORE_BF16>, grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL(template_list_kernel<LTGW_STORE_FP8>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace ltgw

@@ -46,13 +46,18 @@ EXPORTS = ("ltgw_create", "ltgw_destroy", "ltgw_last_error", "ltgw_load_spectrog
            "ltgw_generate_noise", "ltgw_inject_stack", "ltgw_load_stack", "ltgw_stack_psi",
            "ltgw_stack_psi_list", "ltgw_cnn_param_count", "ltgw_cnn_work_floats", "ltgw_cnn_forward",
            "ltgw_cnn_backward", "ltgw_softmax_xent", "ltgw_adam_step", "ltgw_select_top",
-           "ltgw_propose", "ltgw_stack_features", "ltgw_stack_best", "ltgw_cells_from_templates")
+           "ltgw_propose", "ltgw_stack_features", "ltgw_stack_best", "ltgw_cells_from_templates",
+           "ltgw_eval_list")
 
 
 class ltgw_spec_desc(C.Structure):
     _fields_ = [("n_seg", C.c_int32), ("n_bins", C.c_int32), ("k_lo", C.c_int64),
                 ("t_sft", C.c_double), ("t_seg", C.c_void_p), ("weights", C.c_void_p),
                 ("rho_th", C.c_float), ("store", C.c_int32)]
+
+
+class ltgw_template(C.Structure):
+    _fields_ = [("f0", C.c_double), ("tau", C.c_double), ("brake", C.c_double), ("sky", C.c_double * 3)]
 
 
 class ltgw_grid(C.Structure):
@@ -118,6 +123,7 @@ def library():
             "ltgw_load_spectrogram": (i32, [P, i32, C.POINTER(ltgw_spec_desc), P]),
             "ltgw_set_velocity_table": (i32, [P, i32, P, i32]),
             "ltgw_eval_templates": (i32, [P, C.POINTER(ltgw_grid), u32, P, P, P]),
+            "ltgw_eval_list": (i32, [P, P, C.c_int64, d, u32, P, P, P]),
             "ltgw_psi": (i32, [P, u32, P]),
             "ltgw_topk_candidates": (i32, [P, u32, i32, C.POINTER(ltgw_candidate), C.POINTER(i32)]),
             "ltgw_diagnostics": (i32, [P, C.POINTER(ltgw_diag)]),
@@ -232,6 +238,16 @@ def ltgw_eval_templates(ctx, grid, stats=LTGW_STAT_POWER | LTGW_STAT_COUNT, out_
     cp, _b = _addr(out_c)
     np_, _c = _addr(out_n)
     _check(ctx, library().ltgw_eval_templates(ctx, C.byref(grid), int(stats), sp, cp, np_))
+
+
+def ltgw_eval_list(ctx, params, t0=0.0, det_mask=0, out_s=None, out_c=None, out_n=None):
+    """params: [n][6] host array of (f0, tau, n, sky x, y, z) (ltgw_template records)."""
+    p = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, 6)
+    assert C.sizeof(ltgw_template) == 48
+    sp, _a = _addr(out_s)
+    cp, _b = _addr(out_c)
+    np_, _c = _addr(out_n)
+    _check(ctx, library().ltgw_eval_list(ctx, p.ctypes.data, p.shape[0], float(t0), int(det_mask), sp, cp, np_))
 
 
 def ltgw_psi(ctx, stat, out_psi):
@@ -514,6 +530,20 @@ class Context:
             ltgw_eval_templates(self.h, g, stats, s, c, N)
             return s, c, N
         ltgw_eval_templates(self.h, g, stats)
+        return None
+
+    def eval_list(self, params, t0=0.0, det_mask=0, outputs=True):
+        """Explicit templates (f0, tau, n, sky x, y, z) per row; with outputs=True
+        returns device tensors (s, c, N) in list order."""
+        n = int(np.asarray(params).reshape(-1, 6).shape[0])
+        if outputs:
+            T = self.torch
+            s = T.empty(n, dtype=T.float32, device=self.device)
+            c = T.empty(n, dtype=T.int32, device=self.device)
+            N = T.empty(n, dtype=T.int32, device=self.device)
+            ltgw_eval_list(self.h, params, t0, det_mask, s, c, N)
+            return s, c, N
+        ltgw_eval_list(self.h, params, t0, det_mask)
         return None
 
     def psi(self, stat, n):

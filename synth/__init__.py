@@ -182,3 +182,19 @@ def batch_searches(seed=5, n_searches=64, t_sft=8.0):
         out.append(dict(dets=dets, grid=grid, n_templates=n_bins * 12 * n_sky,
                         n_evals=n_bins * 12 * n_sky * 2 * n_seg))
     return out
+
+
+def random_bank(n, f0_range, tau_range, brake_range, sky, seed=11):
+    """The uniform random template bank of Sec. 2: n templates drawn uniformly
+    (linearly) in f0, tau and the braking index over the given closed ranges,
+    all at one sky direction (the search's sky point is fixed).  Returns the
+    [n][6] rows (f0, tau, n, sky x, y, z) that the explicit-template
+    evaluation takes."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty((int(n), 6), np.float64)
+    out[:, 0] = r.uniform(f0_range[0], f0_range[1], n)
+    out[:, 1] = r.uniform(tau_range[0], tau_range[1], n)
+    out[:, 2] = r.uniform(brake_range[0], brake_range[1], n)
+    k = np.asarray(sky, np.float64).reshape(3)
+    out[:, 3:] = k / np.linalg.norm(k)
+    return out

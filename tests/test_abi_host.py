@@ -72,6 +72,8 @@ int main(void) {
   printf("ltgw_proposer %zu\n", sizeof(ltgw_proposer));
   F(ltgw_proposer, c_in); F(ltgw_proposer, n_select); F(ltgw_proposer, psi_threshold);
   F(ltgw_proposer, coarse_threshold); F(ltgw_proposer, tier2_threshold); F(ltgw_proposer, blocks);
+  printf("ltgw_template %zu\n", sizeof(ltgw_template));
+  F(ltgw_template, tau); F(ltgw_template, brake); F(ltgw_template, sky);
   return 0;
 }
 ''')
@@ -81,7 +83,7 @@ int main(void) {
     got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
                                                          check=True).stdout.splitlines())
     for name in ("ltgw_spec_desc", "ltgw_grid", "ltgw_candidate", "ltgw_diag", "ltgw_search",
-                 "ltgw_batch_stats", "ltgw_proposer"):
+                 "ltgw_batch_stats", "ltgw_proposer", "ltgw_template"):
         cls = getattr(ltgw, name)
         assert int(got[name]) == C.sizeof(cls), name
         for key, val in got.items():

@@ -1,0 +1,307 @@
+"""GPU parity of the explicit-template evaluation: the uniform random bank of
+Sec. 2, each template with its own (f0, tau, n, sky).
+
+Bar, as for the lattice: number count c and in-band count N bit-exact; the
+power sum s within 1e-5 relative of the FP64 oracle (exact on the bin
+checksum, which pins every bin of every template and segment); Psi within the
+change that tolerance allows; top-k identical for the count, identical up to
+float near-ties for the power.  On lattice points the list's s, c and N equal
+the lattice evaluation's bit for bit, at full size in the benchmark's launch
+configuration.
+"""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_sums_close, assert_topk_count, assert_topk_power, psi_tolerance, run_gpu
+from test_gpu_parity import _realistic_det, _small, tiny_oracle
+
+pytestmark = pytest.mark.gpu
+
+SKY = [0.6, 0.0, 0.8]
+
+
+def _load(ctx, dets, store="f32"):
+    import torch
+
+    for d, det in enumerate(dets):
+        ctx.load_spectrogram(d, torch.from_numpy(det.rho).cuda(), det.k_lo, det.t_sft, det.t_seg,
+                             weights=det.w, rho_th=float(det.rho_th), store=store)
+        ctx.set_velocity_table(d, det.v)
+
+
+def _run_list(ctx, params, t0=0.0, det_mask=0, k=10):
+    s, c, N = ctx.eval_list(params, t0, det_mask)
+    n = len(params)
+    return {"s": s.cpu().numpy().astype(np.float64), "c": c.cpu().numpy(), "N": N.cpu().numpy(),
+            "psi_power": ctx.psi("power", n).cpu().numpy(),
+            "psi_count": ctx.psi("count", n).cpu().numpy(),
+            "top_power": ctx.topk("power", k), "top_count": ctx.topk("count", k),
+            "diag": ctx.diagnostics()}
+
+
+def _list(dets, params, t0=0.0, det_mask=0, store="f32", k=10):
+    from paper_2507_07816_amd import ltgw
+
+    ctx = ltgw.Context(0)
+    try:
+        _load(ctx, dets, store)
+        return _run_list(ctx, params, t0, det_mask, k)
+    finally:
+        ctx.close()
+
+
+def _bank(n, det, seed, pad=2.0, tau=(300.0, 40000.0), brake=(1.5, 7.0), sky=SKY):
+    """Random templates over the detector's band widened by `pad` Hz on both
+    sides (tracks that start or end out of band), short and long tau."""
+    f_lo = det.k_lo / det.t_sft
+    f_hi = (det.k_lo + det.n_bins) / det.t_sft
+    return synth.random_bank(n, (f_lo - pad, f_hi + pad), tau, brake, sky, seed)
+
+
+def _lattice_params(grid, idx=None):
+    idx = np.arange(grid.n_templates) if idx is None else np.asarray(idx)
+    f0, tau, brake, isky = grid.params(idx)
+    return np.column_stack([f0, tau, brake, grid.sky[isky]])
+
+
+def _check(gpu, ref, params, k):
+    assert np.array_equal(gpu["N"], ref["N"])
+    assert np.array_equal(gpu["c"], ref["c"])
+    assert_sums_close(gpu["s"], ref["s"])
+    pp = oracle.psi_power(ref)
+    ok = ~np.isnan(pp)
+    assert np.array_equal(np.isnan(gpu["psi_power"]), ~ok)
+    assert np.all(np.abs(gpu["psi_power"][ok] - pp[ok]) <= psi_tolerance(ref)[ok] + 1e-9)
+    pc = oracle.psi_count(ref)
+    okc = ~np.isnan(pc)
+    assert np.array_equal(np.isnan(gpu["psi_count"]), ~okc)
+    assert np.allclose(gpu["psi_count"][okc], pc[okc], rtol=1e-13, atol=1e-13)
+    if (ref["N"] > 0).sum() >= k:
+        assert_topk_count(gpu["top_count"], ref, k)
+        assert_topk_power(gpu["top_power"], ref, k)
+    # candidate records carry the listed parameters (sky = -1: not a lattice point)
+    for t in gpu["top_power"] + gpu["top_count"]:
+        row = params[t["index"]]
+        assert (t["f0"], t["tau"], t["brake"], t["sky"]) == (row[0], row[1], row[2], -1)
+        assert t["n_valid"] == ref["N"][t["index"]]
+    assert gpu["diag"]["pow_undecided"] == 0
+    assert gpu["diag"]["templates"] == len(params)
+    assert gpu["diag"]["in_band"] == int(ref["N"].sum())
+
+
+def test_list_tiny_random_bank():
+    """5000 random templates over the small workload (with its injection)."""
+    print("case: list tiny workload, 5000 random templates", flush=True)
+    det, _, _ = tiny_oracle()
+    params = _bank(5000, det, seed=21)
+    ref = oracle.evaluate_params(det, params)
+    gpu = _list([det], params)
+    _check(gpu, ref, params, 10)
+    assert gpu["diag"]["evals"] == 5000 * det.n_seg
+    assert gpu["diag"]["eval_launches"] == 1
+
+
+@pytest.mark.parametrize("t0", [0.0, 1500.0])
+def test_list_bin_checksum_exact(t0):
+    """rho[j, b] = b: s is an exact integer sum of the selected bins (at most
+    1024 x 799 < 2^24 per template), so equality pins every bin; t0 inside
+    the data masks the segments before it."""
+    print(f"case: list bin checksum t0={t0}", flush=True)
+    rho = np.tile(np.arange(800, dtype=np.float32), (1024, 1))
+    det, _, _ = tiny_oracle(with_injection=False, rho=rho)
+    params = _bank(3000, det, seed=22)
+    ref = oracle.evaluate_params(det, params, t0)
+    gpu = _list([det], params, t0)
+    assert np.array_equal(gpu["s"], ref["s"])
+    assert np.array_equal(gpu["N"], ref["N"])
+    assert np.array_equal(gpu["c"], ref["c"])
+    if t0 > 0.0:
+        assert ref["N"].max() <= int(np.sum(det.t_seg >= t0))
+
+
+@pytest.mark.parametrize("n_seg,n_bins,n,t0,weights", [
+    (1, 1, 1, 0.0, True),           # degenerate: one segment, one bin, one template
+    (77, 33, 63, 0.0, True),        # ragged: segments not a multiple of 32, a part wave
+    (5, 800, 64, 0.0, True),
+    (40, 256, 65, 700.0, True),     # T0 inside the data
+    (129, 97, 1000, 0.0, "wide"),   # weights over 12 binades
+    (77, 120, 257, 0.0, False),     # unit weights
+])
+def test_list_ragged_shapes(n_seg, n_bins, n, t0, weights):
+    print(f"case: list ragged n_seg={n_seg} n_bins={n_bins} n={n} t0={t0} w={weights}", flush=True)
+    det = _small(n_seg + n_bins, n_seg, n_bins, k_lo=1990 - n_bins // 4, spacing=37.0,
+                 weights=weights)
+    params = _bank(n, det, seed=n_seg, pad=1.0, tau=(512.0, 35000.0), brake=(2.5, 5.0))
+    ref = oracle.evaluate_params(det, params, t0)
+    gpu = _list([det], params, t0, k=min(7, n))
+    _check(gpu, ref, params, min(7, n))
+
+
+def test_list_two_detectors_and_mask():
+    d1 = _small(1, 60, 256, k_lo=1900)
+    d2 = _small(2, 45, 200, k_lo=1930, t_sft=4.0)
+    params = _bank(2000, d1, seed=23, tau=(5000.0, 20000.0), brake=(3.0, 7.0))
+    ref = oracle.evaluate_params([d1, d2], params)
+    gpu = _list([d1, d2], params)
+    _check(gpu, ref, params, 10)
+    ref1 = oracle.evaluate_params([d2], params)
+    gpu1 = _list([d1, d2], params, det_mask=2)
+    _check(gpu1, ref1, params, 10)
+
+
+def test_list_mixed_sky_directions():
+    """Each template has its own sky direction (unit vectors over the sphere)."""
+    det = _small(4, 200, 300, k_lo=1900, vmag=3.0e4)
+    params = _bank(1500, det, seed=24, tau=(2000.0, 30000.0), brake=(2.0, 7.0))
+    r = np.random.default_rng(25)
+    k = r.normal(size=(len(params), 3))
+    params[:, 3:] = k / np.linalg.norm(k, axis=1, keepdims=True)
+    ref = oracle.evaluate_params(det, params)
+    gpu = _list([det], params)
+    _check(gpu, ref, params, 10)
+
+
+@pytest.mark.parametrize("store", ["bf16", "fp8"])
+def test_list_quantised_stores(store):
+    """Sums within 1e-5 of the FP64 oracle over the same dequantised values;
+    the count exact (decided on the FP32 input)."""
+    det, _, _ = tiny_oracle()
+    rho = det.rho.copy()
+    rho[7, :] = 0.0
+    rho[11, 5] = 5000.0
+    vals, _ = oracle.dequantised(rho, store)
+    qdet = oracle.Detector(rho, det.t_seg, det.v, det.k_lo, det.t_sft, values=vals)
+    params = _bank(3000, qdet, seed=26)
+    ref = oracle.evaluate_params(qdet, params)
+    gpu = _list([qdet], params, store=store)
+    _check(gpu, ref, params, 10)
+
+
+def test_list_equals_lattice_on_lattice_points():
+    """The lattice's templates, listed in shuffled order, give the lattice's
+    s, c and N bit for bit (weights over 12 binades, ragged segments, T0 inside
+    the data, two sky points)."""
+    from paper_2507_07816_amd import ltgw
+
+    det = _small(7, 129, 300, k_lo=1900, spacing=37.0, weights="wide")
+    grid = oracle.Grid(478.0, 0.25, 300, [512.0, 5000.0, 35000.0], [2.5, 5.0],
+                       [[0.6, 0.0, 0.8], [0.0, -1.0, 0.0]], 700.0)
+    params = _lattice_params(grid)
+    order = np.random.default_rng(27).permutation(len(params))
+    ctx = ltgw.Context(0)
+    try:
+        _load(ctx, [det])
+        lat = run_gpu([det], grid, ctx=ctx)
+        lst = _run_list(ctx, params[order], t0=grid.t0)
+    finally:
+        ctx.close()
+    for key in ("s", "c", "N"):
+        assert np.array_equal(lst[key], lat[key][order]), key
+    ok = ~np.isnan(lat["psi_power"])
+    assert np.array_equal(np.isnan(lst["psi_power"]), ~ok[order])
+    assert np.allclose(lst["psi_power"][ok[order]], lat["psi_power"][order][ok[order]],
+                       rtol=1e-6, atol=1e-9)
+
+
+def test_list_then_lattice_records():
+    """A lattice eval after a list eval reports lattice records again."""
+    from paper_2507_07816_amd import ltgw
+
+    det = _small(8, 64, 256, k_lo=1900)
+    params = _bank(100, det, seed=28, tau=(5000.0, 20000.0), brake=(3.0, 7.0))
+    ctx = ltgw.Context(0)
+    try:
+        _load(ctx, [det])
+        ctx.eval_list(params)
+        assert all(t["sky"] == -1 for t in ctx.topk("count", 5))
+        ctx.eval_templates(478.0, 0.5, 100, [5000.0], [5.0], [SKY])
+        top = ctx.topk("count", 5)
+        assert all(t["sky"] == 0 and t["tau"] == 5000.0 for t in top)
+    finally:
+        ctx.close()
+
+
+def test_list_error_paths():
+    import torch
+    from paper_2507_07816_amd import ltgw
+
+    det = _small(9, 32, 128, k_lo=1900)
+    good = _bank(10, det, seed=29, tau=(5000.0, 20000.0), brake=(3.0, 7.0))
+    ctx = ltgw.Context(0)
+    E = ltgw.LtgwError
+    try:
+        with pytest.raises(E) as ei:          # nothing loaded
+            ctx.eval_list(good)
+        assert ei.value.code == ltgw.LTGW_E_STATE
+        _load(ctx, [det])
+        for col, val in [(0, float("nan")), (0, -1.0), (1, 0.0), (2, 1.0), (2, 0.5),
+                         (3, 1.0), (5, float("inf")), (0, 3.0e8)]:
+            bad = good.copy()
+            bad[4, col] = val
+            with pytest.raises(E) as ei:
+                ctx.eval_list(bad)
+            assert ei.value.code == ltgw.LTGW_E_INVALID_ARG, (col, val)
+            assert ltgw.ltgw_last_error(ctx.h)
+        with pytest.raises(E) as ei:          # empty list
+            ctx.eval_list(good[:0])
+        assert ei.value.code == ltgw.LTGW_E_INVALID_ARG
+        with pytest.raises(E) as ei:          # an unloaded detector selected
+            ctx.eval_list(good, det_mask=2)
+        assert ei.value.code == ltgw.LTGW_E_STATE
+        with pytest.raises(E) as ei:          # a device pointer for the list
+            dev = torch.from_numpy(good).cuda()
+            rc = ltgw.library().ltgw_eval_list(ctx.h, C.c_void_p(dev.data_ptr()), len(good),
+                                               C.c_double(0.0), C.c_uint32(0), None, None, None)
+            ltgw._check(ctx.h, rc)
+        assert ei.value.code == ltgw.LTGW_E_INVALID_ARG
+        with pytest.raises(E):                # the failed evals left no results
+            ctx.topk("power", 5)
+        s, c, N = ctx.eval_list(good)
+        ref = oracle.evaluate_params(det, good)
+        assert np.array_equal(N.cpu().numpy(), ref["N"])
+        assert len(ctx.topk("power", 3)) == 3
+    finally:
+        ctx.close()
+
+
+@pytest.mark.slow
+def test_list_realistic_full_size_random_bank():
+    """50,000 random templates over the realistic search at full size
+    (10800 segments x 8000 bins, per-segment weights, 20 injections), every
+    one against the oracle."""
+    print("case: list realistic full size, 50000 random templates", flush=True)
+    det, grid, _ = _realistic_det()
+    params = _bank(50000, det, seed=30, pad=0.5, tau=(3500.0, 35000.0), brake=(3.0, 7.0),
+                   sky=grid.sky[0])
+    ref = oracle.evaluate_params(det, params)
+    gpu = _list([det], params)
+    _check(gpu, ref, params, 10)
+
+
+@pytest.mark.slow
+def test_list_realistic_full_size_equals_lattice():
+    """Sampled lattice templates of the full-size realistic search, evaluated
+    as a list, equal the lattice evaluation (the benchmark's launch
+    configuration) bit for bit."""
+    from paper_2507_07816_amd import ltgw
+
+    print("case: list realistic full size against the lattice", flush=True)
+    det, grid, _ = _realistic_det()
+    idx = np.random.default_rng(31).choice(grid.n_templates, 20000, replace=False)
+    params = _lattice_params(grid, idx)
+    ctx = ltgw.Context(0)
+    try:
+        _load(ctx, [det])
+        lat = run_gpu([det], grid, ctx=ctx)
+        lst = _run_list(ctx, params, t0=grid.t0)
+    finally:
+        ctx.close()
+    for key in ("s", "c", "N"):
+        assert np.array_equal(lst[key], lat[key][idx]), key
+    assert lst["diag"]["pow_undecided"] == 0
+    assert math.isfinite(lst["diag"]["eval_kernel_ms"])

@@ -343,3 +343,54 @@ def test_dequantised_fp8_scale():
     vals, sc = oracle.dequantised(rho, "fp8")
     assert sc[0] == 1.0 and sc[1] == np.float32(448.0 * 3) / np.float32(448.0)
     assert vals[1, 1] == 448.0 * 3 and vals[0, 0] == 0.0
+
+
+# ------------------------------------------------ explicit templates (Sec. 2) ---
+def _random_params(rng, n, sky=None):
+    """(f0, tau, n, sky) drawn uniformly over ranges around the small grid's."""
+    out = np.empty((n, 6))
+    out[:, 0] = rng.uniform(478.0, 540.0, n)
+    out[:, 1] = np.exp(rng.uniform(math.log(3500.0), math.log(35000.0), n))
+    out[:, 2] = rng.uniform(3.0, 7.0, n)
+    s = rng.normal(size=(n, 3)) if sky is None else np.tile(sky, (n, 1))
+    out[:, 3:] = s / np.linalg.norm(s, axis=1, keepdims=True)
+    return out
+
+
+def test_explicit_templates_bin_checksum_against_exact_tracks():
+    """Random (f0, tau, n, sky) off any lattice, on rho[j, b] = b: the power sum
+    is the sum of the exact-real in-band columns of each template's track."""
+    det0 = small_det(seed=17)
+    rng = np.random.default_rng(18)
+    params = _random_params(rng, 40)
+    rho = np.tile(np.arange(det0.n_bins, dtype=np.float32), (det0.n_seg, 1))
+    det = oracle.Detector(rho, det0.t_seg, det0.v, det0.k_lo, det0.t_sft)
+    res = oracle.evaluate_params(det, params, t0=0.0)
+    n_in = 0
+    for q in range(len(params)):
+        cols = []
+        for j in range(det.n_seg):
+            b, _ = truth.true_bin(float(params[q, 0]), det.t_seg[j], 0.0, params[q, 1], params[q, 2], det.v[j],
+                                  params[q, 3:], det.t_sft, det.k_lo)
+            if 0 <= b < det.n_bins:
+                cols.append(b)
+        n_in += len(cols)
+        assert res["s"][q] == float(sum(cols))
+        assert res["N"][q] == len(cols)
+    assert n_in > 100
+
+
+def test_explicit_templates_equal_the_lattice_on_lattice_points():
+    """A template given by its parameters evaluates exactly as the same lattice
+    template (noise, weights, two masked segments)."""
+    det = small_det(seed=19, rho=np.random.default_rng(20).exponential(size=(8, 256)).astype(np.float32),
+                    weights=np.linspace(0.5, 2.0, 8).astype(np.float32),
+                    t_seg=np.arange(8) * 300.0 - 298.0)
+    grid = small_grid(t0=100.0)
+    res = oracle.evaluate(det, grid)
+    f0, tau, brake, isky = grid.params(np.arange(grid.n_templates))
+    params = np.column_stack([f0, tau, brake, grid.sky[isky]])
+    lst = oracle.evaluate_params(det, params, t0=grid.t0)
+    for k in ("s", "c", "N", "W1", "W2"):
+        assert np.array_equal(lst[k], res[k]), k
+    assert (res["N"] > 0).sum() > 10
