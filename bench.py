@@ -37,11 +37,16 @@ KERNEL_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_kernels.hip", "paper_2507_0781
                   "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_internal.h")
 
 
-def kernel_source_hash():
+# the explicit-template kernel's code (its committed FP64 instruction count)
+LIST_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_list.hip", "paper_2507_07816_amd/csrc/ltgw_list.h",
+                "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_gather.h")
+
+
+def kernel_source_hash(sources=KERNEL_SOURCES):
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -63,6 +68,21 @@ def measured_traffic(workload, store, variant):
         return None
     per_step = (t["fetch_kib_per_step"] * t["fetch_scale"] + t["write_kib_per_step"] * t["write_scale"]) * 1024.0
     return per_step / t["dispatches_per_step"]
+
+
+def measured_list_fp64():
+    """Executed FP64 VALU lane-instructions per evaluation of the
+    explicit-template kernel, from the committed rocprofv3 counter summary
+    (SQ_INSTS_VALU_*_F64 over the launch, times 64 lanes, over its
+    evaluations), or None when it is for another kernel source."""
+    path = os.path.join(ROOT, "profiles", "list_kernel_fp64.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != kernel_source_hash(LIST_SOURCES):
+        return None
+    return t["fp64_lane_instructions_per_eval"]
 
 
 def cpu_baseline(wl, rho, target_s=15.0):
@@ -141,6 +161,49 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
     return out
 
 
+# FP64 vector instruction issue of the chip: 256 CUs x 64 lanes x 2.4 GHz
+# (the 78.6 TFLOP/s FP64 peak counts each FMA as 2 flops)
+FP64_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def list_leg(torch, ltgw, ctx, wl, n=100000, reps=3, seed=11, fp64_per_eval=None):
+    """The uniform random bank over the loaded search: n templates drawn
+    uniformly in f0 (the band), tau and n, at the search's sky point.  Every
+    (template, segment) takes its own correctly rounded Eq. 1 power, so the
+    kernel is bound by FP64 issue; the rate is compared with the chip's FP64
+    lane-instruction rate given the instructions per evaluation of the
+    kernel's inner loop (counted in its gfx950 code)."""
+    import synth
+
+    d = wl.dets[0]
+    g = wl.grid
+    f_hi = g["f0_min"] + (d["rho"].shape[1] - 1) * g["f0_step"]
+    params = synth.random_bank(n, (g["f0_min"], f_hi), (float(g["tau"][0]), float(g["tau"][-1])),
+                               (float(g["brake"][0]), float(g["brake"][-1])), g["sky"][0], seed)
+    ctx.eval_list(params, g["t0"], outputs=False)            # warm-up
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        ctx.eval_list(params, g["t0"], outputs=False)
+        dg = ctx.diagnostics()                                 # synchronises
+        runs.append((time.perf_counter() - t, dg["eval_kernel_ms"]))
+    wall = min(r[0] for r in runs)
+    kms = float(np.mean([r[1] for r in runs]))
+    evals = int(dg["evals"])
+    out = {"workload": f"uniform random bank, {n} templates over {wl.name}, seed {seed}",
+           "templates": n, "evals": evals, "in_band_fraction": dg["in_band"] / evals,
+           "value": evals / wall, "unit": "template·segment evals/s", "wall_ms": wall * 1e3,
+           "kernel_ms": kms, "kernel_evals_per_s": evals / (kms * 1e-3),
+           "pow_undecided": int(dg["pow_undecided"])}
+    if fp64_per_eval:
+        rate = fp64_per_eval * evals / (kms * 1e-3)
+        out["roofline"] = {"bound": "alu", "achieved": rate / 1e12, "peak": FP64_LANE_OPS / 1e12,
+                           "unit": "T FP64 lane-instructions/s", "frac": rate / FP64_LANE_OPS,
+                           "fp64_instructions_per_eval": fp64_per_eval}
+    return out
+
+
 def batch_leg(torch, ltgw, reps=2, seed=5):
     """The batch of 64 uneven searches (two detectors each, sky patches of 16 to
     1024 points, 1.76e13 template x segment evaluations) in one persistent,
@@ -200,6 +263,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-proposer", action="store_true", help="skip the learned-proposer leg")
     ap.add_argument("--batch", action="store_true", help="add the 64-search batch leg")
+    ap.add_argument("--list-templates", type=int, default=100000,
+                    help="templates of the uniform random bank leg (0 skips it)")
     ap.add_argument("--tile-shape", type=int, default=-1,
                     help="force the statistic kernel's variant (0..15) instead of autotuning (profiling runs)")
     ap.add_argument("--proposer-realisations", type=int, default=50000)
@@ -304,6 +369,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(wl.name, args.store, int(dg["tile_shape"]))},
     }
+    if args.list_templates > 0:
+        print("[bench] uniform random bank", file=sys.stderr, flush=True)
+        out["random_bank"] = list_leg(torch, ltgw, ctx, wl, n=args.list_templates,
+                                      fp64_per_eval=measured_list_fp64())
+        print(f"[bench] random bank: {json.dumps(out['random_bank'])}", file=sys.stderr, flush=True)
     if args.batch:
         print("[bench] batch of 64 searches", file=sys.stderr, flush=True)
         out["batch"] = batch_leg(torch, ltgw)

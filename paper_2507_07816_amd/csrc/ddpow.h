@@ -43,6 +43,13 @@ constexpr double kLn2_1 = 0x1.62e42fefa3800p-1;
 constexpr double kLn2_2 = 0x1.ef35793c76730p-45;
 constexpr double kLn2_3 = 0x1.f97b57a079a19p-103;
 constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+// 1/3 and 1/5 as double-doubles: hi = RN(1/m), lo = RN(1/m - hi) (relative
+// error 3.1e-33, checked by a host test with exact rationals)
+constexpr double kInv3_hi = 0x1.5555555555555p-2, kInv3_lo = 0x1.5555555555555p-56;
+constexpr double kInv5_hi = 0x1.999999999999ap-3, kInv5_lo = -0x1.999999999999ap-57;
+// RN(1/m) for the FP64 Taylor factors (indices 6..10 used)
+constexpr double kRecip[11] = {0.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5,
+                               1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9, 1.0 / 10};
 
 LTGW_HD dd two_sum(double a, double b) {
     double s = a + b;
@@ -84,16 +91,6 @@ LTGW_HD dd dd_mul_d(dd a, double b) {
     p.lo += a.lo * b;
     return fast_two_sum(p.hi, p.lo);
 }
-LTGW_HD dd dd_div_d(dd a, double b) {
-    double q1 = a.hi / b;
-    dd p = two_prod(q1, b);
-    dd s = two_sum(a.hi, -p.hi);
-    s.lo -= p.lo;
-    s.lo += a.lo;
-    double q2 = (s.hi + s.lo) / b;
-    return fast_two_sum(q1, q2);
-}
-
 // e^Y for |Y.hi| < 700.
 LTGW_HD dd dd_exp(dd Y) {
     double kf = std::rint(Y.hi * kInvLn2);
@@ -106,9 +103,19 @@ LTGW_HD dd dd_exp(dd Y) {
     // r in [-0.35, 0.35]; scale into |r| < 1.36e-3
     r.hi *= 0x1p-8;
     r.lo *= 0x1p-8;
-    // expm1(r) = r (1 + r/2 (1 + r/3 (... (1 + r/10))))
-    dd p = dd_div_d(r, 10.0);
-    for (int m = 9; m >= 2; --m) p = dd_div_d(dd_mul(dd_add_d(p, 1.0), r), (double)m);
+    // expm1(r) = r (1 + r/2 (1 + r/3 (... (1 + r/10)))).  The inner factors
+    // r/10 ... r/6 (...) are formed in FP64 from r.hi: their rounding reaches
+    // expm1(r) scaled by r^5/5! < 2^-54, i.e. below 2^-110 relative.  The
+    // outer four stay in double-double, dividing by 5 and 3 as products with
+    // double-double reciprocals (by 4 and 2 exactly).
+    double q = r.hi * kRecip[10];
+    for (int m = 9; m >= 6; --m) q = ((q + 1.0) * r.hi) * kRecip[m];
+    dd p = dd_mul(dd_mul(two_sum(1.0, q), r), dd{kInv5_hi, kInv5_lo});
+    p = dd_mul(dd_add_d(p, 1.0), r);
+    p = {p.hi * 0.25, p.lo * 0.25};
+    p = dd_mul(dd_mul(dd_add_d(p, 1.0), r), dd{kInv3_hi, kInv3_lo});
+    p = dd_mul(dd_add_d(p, 1.0), r);
+    p = {p.hi * 0.5, p.lo * 0.5};
     p = dd_mul(dd_add_d(p, 1.0), r);
     for (int i = 0; i < 8; ++i) p = dd_mul(p, dd_add_d(p, 2.0));
     dd e = dd_add_d(p, 1.0);

@@ -107,6 +107,17 @@ def test_ln2_split_constants():
     assert abs(float(resid)) < 2.0 ** -150
 
 
+def test_reciprocal_constants():
+    """1/3 and 1/5 as double-doubles: hi = RN(1/m), lo = RN(1/m - hi)."""
+    src = open(DDPOW).read()
+    for m in (3, 5):
+        got = re.search(rf"kInv{m}_hi = (0x[0-9a-fp.+-]+), kInv{m}_lo = (-?0x[0-9a-fp.+-]+);", src)
+        hi, lo = float.fromhex(got.group(1)), float.fromhex(got.group(2))
+        assert hi == float(Fraction(1, m))
+        assert lo == float(Fraction(1, m) - Fraction(hi))
+        assert abs(Fraction(1, m) - Fraction(hi) - Fraction(lo)) < Fraction(1, m) * Fraction(2) ** -106
+
+
 def test_create_without_gpu_reports_error():
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():
