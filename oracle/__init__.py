@@ -80,6 +80,8 @@ def lib():
         L.oracle_bf16_rne_array.argtypes = [P, i64, P]
         L.oracle_e4m3_rne_sat_array.restype = None
         L.oracle_e4m3_rne_sat_array.argtypes = [P, i64, P]
+        L.oracle_antenna.restype = d
+        L.oracle_antenna.argtypes = [P, d, P]
         L.oracle_spin_factor_array.restype = None
         L.oracle_spin_factor_array.argtypes = [P, i64, d, d, d, P]
         _lib = L
@@ -94,7 +96,7 @@ class _Det(C.Structure):
     _fields_ = [("n_seg", C.c_int32), ("n_bins", C.c_int32), ("k_lo", C.c_int64),
                 ("t_sft", C.c_double), ("t_seg", C.c_void_p), ("w", C.c_void_p),
                 ("v", C.c_void_p), ("P", C.c_void_p), ("rho", C.c_void_p),
-                ("rho_th", C.c_float)]
+                ("rho_th", C.c_float), ("arms", C.c_void_p), ("era", C.c_void_p)]
 
 
 class _Grid(C.Structure):
@@ -112,7 +114,8 @@ class Detector:
     by default the FP32 powers themselves, or the dequantised values of a
     BF16/FP8 store (see ``dequantised``)."""
 
-    def __init__(self, rho, t_seg, v, k_lo, t_sft, weights=None, rho_th=1.6, values=None):
+    def __init__(self, rho, t_seg, v, k_lo, t_sft, weights=None, rho_th=1.6, values=None,
+                 arms=None, era=None):
         self.rho = np.ascontiguousarray(rho, dtype=np.float32)
         self.n_seg, self.n_bins = self.rho.shape
         self.t_seg = np.ascontiguousarray(t_seg, dtype=np.float64)
@@ -124,10 +127,17 @@ class Detector:
         self.values = (self.rho.astype(np.float64) if values is None
                        else np.ascontiguousarray(values, dtype=np.float64))
         assert self.values.shape == self.rho.shape
+        # antenna response (Sec. 2 weighting): arms [2][3] Earth-fixed unit
+        # vectors and the Earth rotation angle at each segment; the weight of
+        # segment j for sky n is then w_j * (F+^2 + Fx^2)(n, j)
+        self.arms = None if arms is None else np.ascontiguousarray(arms, dtype=np.float64).reshape(2, 3)
+        self.era = None if era is None else np.ascontiguousarray(era, dtype=np.float64).reshape(self.n_seg)
+        assert (self.arms is None) == (self.era is None)
 
     def _struct(self):
         return _Det(self.n_seg, self.n_bins, self.k_lo, self.t_sft, _p(self.t_seg), _p(self.w),
-                    _p(self.v), _p(self.values), _p(self.rho), float(self.rho_th))
+                    _p(self.v), _p(self.values), _p(self.rho), float(self.rho_th), _p(self.arms),
+                    _p(self.era))
 
 
 class Grid:
@@ -170,6 +180,14 @@ def spin_factor_array(t, t0, tau, brake):
     out = np.empty_like(t)
     lib().oracle_spin_factor_array(_p(t), t.size, float(t0), float(tau), float(brake), _p(out))
     return out
+
+
+def antenna(arms, era, n):
+    """F+^2 + Fx^2 of a detector with Earth-fixed arms [2][3] at Earth rotation
+    angle era, for a wave from unit direction n (Sec. 2 weighting)."""
+    a = np.ascontiguousarray(arms, dtype=np.float64).reshape(6)
+    k = np.ascontiguousarray(n, dtype=np.float64).reshape(3)
+    return lib().oracle_antenna(_p(a), float(era), _p(k))
 
 
 def doppler(v, n):

@@ -97,7 +97,62 @@ typedef struct {
     const double *P;     /* [n_seg][n_bins] power values that are summed         */
     const float *rho;    /* [n_seg][n_bins] FP32 normalised power (count source) */
     float rho_th;        /* number-count threshold, compared in FP32             */
+    const double *arms;  /* [2][3] unit arm vectors in the Earth-fixed frame, or
+                            NULL: no antenna factor on the weights             */
+    const double *era;   /* [n_seg] Earth rotation angle (rad) at each segment  */
 } oracle_det;
+
+/* ------------------------------------------------------------------------ */
+/* Antenna response of an interferometer (the weighting of Sec. 2): the sum
+ * F+^2 + Fx^2 of the two polarisation responses to a wave from direction n.
+ * The arms a, b (unit vectors, Earth-fixed frame, z on the rotation axis) are
+ * carried into the equatorial frame of n by a rotation of era about z.  With
+ * the detector tensor Dt = (a a^T - b b^T)/2 and a polarisation basis (p, q)
+ * orthogonal to n, F+ = p^T Dt p - q^T Dt q and Fx = p^T Dt q + q^T Dt p;
+ * their squares summed do not depend on the polarisation angle, so any such
+ * basis serves: p along z x n (x when n is on the z axis), q = n x p. */
+static void cross3(const double *u, const double *v, double *o)
+{
+    o[0] = u[1] * v[2] - u[2] * v[1];
+    o[1] = u[2] * v[0] - u[0] * v[2];
+    o[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+static double quad_form(const double Dt[3][3], const double *u, const double *v)
+{
+    double acc = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) acc = acc + u[i] * Dt[i][k] * v[k];
+    return acc;
+}
+
+double oracle_antenna(const double *arms, double era, const double *n)
+{
+    double c = cos(era), sn = sin(era);
+    double a[3], b[3];
+    a[0] = c * arms[0] - sn * arms[1];
+    a[1] = sn * arms[0] + c * arms[1];
+    a[2] = arms[2];
+    b[0] = c * arms[3] - sn * arms[4];
+    b[1] = sn * arms[3] + c * arms[4];
+    b[2] = arms[5];
+    double Dt[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) Dt[i][k] = 0.5 * (a[i] * a[k] - b[i] * b[k]);
+    const double zax[3] = {0.0, 0.0, 1.0};
+    double p[3], q[3];
+    cross3(zax, n, p);
+    double pn = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    if (pn < 1e-12) {
+        p[0] = 1.0; p[1] = 0.0; p[2] = 0.0;
+    } else {
+        p[0] = p[0] / pn; p[1] = p[1] / pn; p[2] = p[2] / pn;
+    }
+    cross3(n, p, q);
+    double fp = quad_form(Dt, p, p) - quad_form(Dt, q, q);
+    double fx = quad_form(Dt, p, q) + quad_form(Dt, q, p);
+    return fp * fp + fx * fx;
+}
 
 typedef struct {
     double f0_min, f0_step;
@@ -159,6 +214,22 @@ static double **build_D(const oracle_det *dets, int32_t n_det, const oracle_grid
     return tab;
 }
 
+/* A[d][sky][j]: antenna response of detector d at segment j to sky point
+ * sky, or NULL for a detector without one. */
+static double **build_A(const oracle_det *dets, int32_t n_det, const oracle_grid *g)
+{
+    double **tab = (double **)calloc((size_t)n_det, sizeof(double *));
+    for (int32_t d = 0; d < n_det; ++d) {
+        if (!dets[d].arms) continue;
+        int64_t ns = dets[d].n_seg;
+        tab[d] = (double *)malloc((size_t)(g->n_sky * ns) * sizeof(double));
+        for (int64_t s = 0; s < g->n_sky; ++s)
+            for (int64_t j = 0; j < ns; ++j)
+                tab[d][s * ns + j] = oracle_antenna(dets[d].arms, dets[d].era[j], g->sky + 3 * s);
+    }
+    return tab;
+}
+
 static void free_tabs(double **t, int32_t n)
 {
     for (int32_t i = 0; i < n; ++i) free(t[i]);
@@ -167,6 +238,8 @@ static void free_tabs(double **t, int32_t n)
 
 /* Statistic over templates [t_begin, t_end) (Sec. 2):
  *   s  = sum over in-band (d, j) of w_j * P_d[j][b]        (FP64, segment order)
+ *   with w_j the segment weight, times the antenna response A_d(sky, j) for a
+ *   detector that has one (the product formed in FP64)
  *   c  = number of in-band (d, j) with rho_d[j][b] > rho_th (FP32 compare)
  *   N  = number of in-band (d, j); W1 = sum w_j ; W2 = sum w_j^2
  * Outputs are indexed by t - t_begin.  Masked (t_j < T0) and out-of-band
@@ -182,6 +255,7 @@ static void eval_templates(const oracle_det *dets, int32_t n_det, const oracle_g
     }
     double **gt = build_g(dets, n_det, g, need);
     double **Dt = build_D(dets, n_det, g);
+    double **At = build_A(dets, n_det, g);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t o = 0; o < n; ++o) {
         int64_t t = list ? list[o] : t_begin + o;
@@ -194,11 +268,13 @@ static void eval_templates(const oracle_det *dets, int32_t n_det, const oracle_g
             const oracle_det *D = dets + d;
             const double *grow = gt[d] + (i_n * g->n_tau + i_tau) * (int64_t)D->n_seg;
             const double *drow = Dt[d] + i_sky * (int64_t)D->n_seg;
+            const double *arow = At[d] ? At[d] + i_sky * (int64_t)D->n_seg : NULL;
             for (int32_t j = 0; j < D->n_seg; ++j) {
                 if (D->t_seg[j] < g->t0) continue;
                 int64_t b = oracle_bin(f0, grow[j], drow[j], D->t_sft, D->k_lo);
                 if (b < 0 || b >= D->n_bins) continue;
                 double wj = D->w ? (double)D->w[j] : 1.0;
+                if (arow) wj = wj * arow[j];
                 int64_t off = (int64_t)j * D->n_bins + b;
                 acc = acc + wj * D->P[off];
                 if (D->rho[off] > D->rho_th) cnt += 1;
@@ -215,6 +291,7 @@ static void eval_templates(const oracle_det *dets, int32_t n_det, const oracle_g
     }
     free_tabs(gt, n_det);
     free_tabs(Dt, n_det);
+    free_tabs(At, n_det);
     free(need);
 }
 
@@ -253,6 +330,7 @@ void oracle_eval_params(const oracle_det *dets, int32_t n_det, const double *par
                 int64_t b = oracle_bin(p[0], gj, Dj, D->t_sft, D->k_lo);
                 if (b < 0 || b >= D->n_bins) continue;
                 double wj = D->w ? (double)D->w[j] : 1.0;
+                if (D->arms) wj = wj * oracle_antenna(D->arms, D->era[j], p + 3);
                 int64_t off = (int64_t)j * D->n_bins + b;
                 acc = acc + wj * D->P[off];
                 if (D->rho[off] > D->rho_th) cnt += 1;

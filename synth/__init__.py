@@ -29,6 +29,35 @@ SITE_H = (46.455, -119.408)
 SITE_L = (30.563, -90.774)
 
 
+# azimuth of the first arm in degrees east of north (the second is 90 degrees
+# further east), approximately those of the two LIGO sites
+ARM_AZ_H = 324.0
+ARM_AZ_L = 252.3
+
+
+def earth_rotation_angle(t):
+    """Rotation angle of the Earth-fixed frame about z at times t (rad): the
+    same rotation that carries the site in `velocity` (longitude 0 on the
+    equatorial x axis at t = 0)."""
+    return 2.0 * np.pi * np.asarray(t, dtype=np.float64) / P_SIDEREAL
+
+
+def site_arms(lat_deg, lon_deg, azimuth_deg, opening_deg=90.0):
+    """Unit vectors [2][3] of the two arms of a detector at a site, in the
+    Earth-fixed frame (z on the rotation axis, x at longitude 0): the first
+    arm at `azimuth_deg` east of north in the local horizontal plane, the
+    second `opening_deg` further east."""
+    la, lo = math.radians(lat_deg), math.radians(lon_deg)
+    north = np.array([-math.sin(la) * math.cos(lo), -math.sin(la) * math.sin(lo), math.cos(la)])
+    east = np.array([-math.sin(lo), math.cos(lo), 0.0])
+    out = []
+    for az in (azimuth_deg, azimuth_deg + opening_deg):
+        a = math.radians(az)
+        v = math.cos(a) * north + math.sin(a) * east
+        out.append(v / np.linalg.norm(v))
+    return np.ascontiguousarray(out)
+
+
 def exp_noise(n_seg, n_bins, seed):
     """FP32 Exp(1) spectrogram by inverse CDF in FP64 (numpy PCG64)."""
     rng = np.random.Generator(np.random.PCG64(seed))
