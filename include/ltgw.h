@@ -130,6 +130,26 @@ int32_t ltgw_load_spectrogram(ltgw_ctx *ctx, int32_t det, const ltgw_spec_desc *
  * Errors: STATE (no spectrogram for det), INVALID_ARG, NOMEM, DEVICE. */
 int32_t ltgw_set_velocity_table(ltgw_ctx *ctx, int32_t det, const double *v_xyz, int32_t n_seg);
 
+/* ltgw_set_antenna: antenna-pattern weights for detector slot det.  Sec. 2
+ * weights the statistics by the antenna patterns as well as the noise floor;
+ * after this call the weight of segment j for a template with sky direction n
+ * is w_j * A_j(n) in place of w_j, where w_j is the loaded weight and
+ * A_j(n) = F+^2 + Fx^2 is the summed response of the detector to the two
+ * polarisations of a wave from n (independent of the polarisation angle).
+ *   arms: host [2][3] unit vectors (|1 - |a|| <= 1e-12) of the two arms in the
+ *         Earth-fixed frame (z on the rotation axis), or NULL to clear.
+ *   era:  [n_seg] host or device, the Earth rotation angle (rad) at each
+ *         segment: the rotation about z that carries the Earth-fixed frame
+ *         into the frame of the velocities and sky directions.
+ * The power sum and W1, W2 use the product rounded once to FP32 (the count
+ * and N do not use weights).  Honoured by ltgw_eval_templates (one weight row
+ * per sky point of the grid; W1, W2 are then summed by the statistic kernel)
+ * and ltgw_eval_list; ltgw_eval_batch rejects such a detector (UNSUPPORTED).
+ * A new ltgw_load_spectrogram on the slot clears it.  Synchronous.
+ * Errors: STATE (nothing loaded), INVALID_ARG (values, n_seg not the
+ * spectrogram's, arms in device memory), NOMEM, DEVICE. */
+int32_t ltgw_set_antenna(ltgw_ctx *ctx, int32_t det, const double *arms, const double *era, int32_t n_seg);
+
 /* ---- eval_templates --------------------------------------------------------
  * Cubic-lattice bank (Sec. 2).  Template index order (f0 fastest):
  *     index = ((sky * n_brake + i_n) * n_tau + i_tau) * n_f0 + i_f0 */

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ltgw_ctx.h"
+#include "ltgw_antenna.h"
 #include "ltgw_list.h"
 
 using namespace ltgw;
@@ -190,6 +191,7 @@ void ltgw_destroy(ltgw_ctx *c) {
     for (auto &d : c->det) {
         release(d.store_buf); release(d.t_seg); release(d.w); release(d.wq);
         release(d.scale); release(d.v); release(d.g); release(d.H); release(d.wfix); release(d.win);
+        release(d.era); release(d.w_sky); release(d.wq_sky);
     }
     DevBuf *all[] = {&c->staging, &c->counters, &c->cnn_packed, &c->list_d, &c->perm_d,
                      &c->tau_d,   &c->brake_d,  &c->sky_d,      &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2, &c->diff,
@@ -219,6 +221,7 @@ int32_t ltgw_load_spectrogram(ltgw_ctx *c, int32_t det, const ltgw_spec_desc *d,
     Det &D = c->det[det];
     D.loaded = false;
     D.has_v = false;
+    D.has_antenna = false;
     const int64_t ns = d->n_seg, nb = d->n_bins;
     std::vector<double> ht(ns);
     std::vector<float> hw(ns, 1.0f);
@@ -308,6 +311,40 @@ int32_t ltgw_set_velocity_table(ltgw_ctx *c, int32_t det, const double *v, int32
     return LTGW_OK;
 }
 
+int32_t ltgw_set_antenna(ltgw_ctx *c, int32_t det, const double *arms, const double *era, int32_t n_seg) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (det < 0 || det >= LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "detector %d out of range", det);
+    Det &D = c->det[det];
+    if (!D.loaded) return fail(c, LTGW_E_STATE, "no spectrogram loaded for detector %d", det);
+    c->have_eval = false;
+    if (!arms) {
+        D.has_antenna = false;
+        return LTGW_OK;
+    }
+    if (is_device_ptr(arms)) return fail(c, LTGW_E_INVALID_ARG, "arms must be host memory");
+    if (!era) return fail(c, LTGW_E_INVALID_ARG, "era is NULL");
+    if (n_seg != D.n_seg)
+        return fail(c, LTGW_E_INVALID_ARG, "era has %d entries, spectrogram %d segments", n_seg, D.n_seg);
+    for (int k = 0; k < 2; ++k) {
+        const double *a = arms + 3 * k;
+        if (!fin(a[0]) || !fin(a[1]) || !fin(a[2]) ||
+            std::fabs(std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) - 1.0) > 1e-12)
+            return fail(c, LTGW_E_INVALID_ARG, "arm %d is not a unit vector", k);
+    }
+    std::vector<double> he((size_t)n_seg);
+    int rc;
+    if ((rc = to_host(c, he.data(), era, he.size() * sizeof(double), "era")) != LTGW_OK) return rc;
+    for (int32_t j = 0; j < n_seg; ++j)
+        if (!fin(he[j])) return fail(c, LTGW_E_INVALID_ARG, "era[%d] is not finite", j);
+    if ((rc = ensure(c, D.era, he.size() * sizeof(double), "rotation angles")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, D.era.p, he.data(), he.size() * sizeof(double), "rotation angle upload")) != LTGW_OK) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "rotation angle upload");
+    std::memcpy(D.arms, arms, sizeof D.arms);
+    D.has_antenna = true;
+    return LTGW_OK;
+}
+
 }  // extern "C"
 
 namespace ltgw {
@@ -382,6 +419,11 @@ int plan_search(ltgw_ctx *c, const ltgw_grid *g, const int *slots, int n_slots, 
 Moments plan_moments(ltgw_ctx *c, const int *slots, int n_slots) {
     Moments M;
     M.w_uniform = c->det[slots[0]].w_uniform;
+    for (int q = 0; q < n_slots; ++q)
+        if (c->det[slots[q]].has_antenna) {  // weights per (sky, segment): summed by the statistic kernel
+            M.mode = 2;
+            return M;
+        }
     bool uniform = true;
     for (int q = 0; q < n_slots; ++q) {
         const Det &D = c->det[slots[q]];
@@ -502,6 +544,22 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
         V.wfix = nullptr;
         V.n_seg = D.n_seg;
         V.n_bins = D.n_bins;
+        V.w_sky_stride = 0;
+        if (D.has_antenna) {  // one row of weights per sky point of the grid
+            const size_t nw = (size_t)g->n_sky * (size_t)D.n_seg;
+            if ((rc = ensure(c, D.w_sky, nw * 4, "antenna weights")) != LTGW_OK) return rc;
+            if ((rc = ensure(c, D.wq_sky, nw * 4, "antenna weights")) != LTGW_OK) return rc;
+            Arms A;
+            std::memcpy(A.a, D.arms, sizeof A.a);
+            std::memcpy(A.b, D.arms + 3, sizeof A.b);
+            HIP_TRY(c, launch_antenna_weights(A, (const double *)D.era.p, D.n_seg, (const double *)c->sky_d.p,
+                                              g->n_sky, (const float *)D.w.p, (const float *)D.scale.p,
+                                              (float *)D.w_sky.p, (float *)D.wq_sky.p, c->stream),
+                    "antenna weight launch");
+            V.w = (const float *)D.w_sky.p;
+            V.wq = (const float *)D.wq_sky.p;
+            V.w_sky_stride = D.n_seg;
+        }
         if (M.mode == 1) {
             if ((rc = ensure(c, D.wfix, D.h_wfix.size() * 8, "fixed-point weights")) != LTGW_OK) return rc;
             if ((rc = h2d(c, D.wfix.p, D.h_wfix.data(), D.h_wfix.size() * 8, "weights upload")) != LTGW_OK)
@@ -637,6 +695,10 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
         V.w = (const float *)D.w.p;
         V.t_sft = D.t_sft;
         V.cshift = 1.5 - (double)D.k_lo;
+        V.scale = (const float *)D.scale.p;
+        V.era = D.has_antenna ? (const double *)D.era.p : nullptr;
+        std::memcpy(V.arms.a, D.arms, sizeof V.arms.a);
+        std::memcpy(V.arms.b, D.arms + 3, sizeof V.arms.b);
         n_seg_total += D.n_seg;
     }
     // evaluation order: ascending f0, so that neighbouring lanes gather neighbouring columns

@@ -84,6 +84,7 @@ std::vector<unsigned char> signature(ltgw_ctx *c, const ltgw_search *S, int n, i
             put(v, D.pitch);
             put(v, D.loaded);
             put(v, D.has_v);
+            put(v, D.has_antenna);
             put_array(v, D.h_w.data(), D.h_w.size());
         }
     }
@@ -201,6 +202,10 @@ int build(ltgw_ctx *c, const ltgw_search *S, int n, int k) {
         }
         if (B.plans[i].store != B.plans[0].store)
             return fail(c, LTGW_E_UNSUPPORTED, "searches of one batch must use one store format");
+        for (int q = 0; q < S[i].n_dets; ++q)
+            if (c->det[S[i].dets[q]].has_antenna)
+                return fail(c, LTGW_E_UNSUPPORTED, "search %d: detector %d has antenna-pattern weights, which "
+                            "a batch does not take", i, S[i].dets[q]);
         for (int q = 0; q < S[i].n_dets; ++q)
             if (std::find(all_slots.begin(), all_slots.end(), S[i].dets[q]) == all_slots.end())
                 all_slots.push_back(S[i].dets[q]);

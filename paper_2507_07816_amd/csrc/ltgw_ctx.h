@@ -29,7 +29,9 @@ struct Det {
     std::vector<double> h_t;      // segment times as loaded
     std::vector<double> h_v;      // velocity table as set
     std::vector<int64_t> h_wfix;  // [n_seg][3] fixed-point w, w^2 high, w^2 low
-    DevBuf store_buf, t_seg, w, wq, scale, v, g, H, wfix, win;
+    bool has_antenna = false;     // weights times the antenna response (ltgw_set_antenna)
+    double arms[6] = {0, 0, 0, 0, 0, 0};
+    DevBuf store_buf, t_seg, w, wq, scale, v, g, H, wfix, win, era, w_sky, wq_sky;
 };
 
 // How the in-band moments W1, W2 are formed for a set of detectors.

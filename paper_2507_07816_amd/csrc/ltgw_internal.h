@@ -29,6 +29,8 @@ struct DetView {
                             // f0 has a lane in band ({n_seg, -1}: none), or NULL: every segment
     int32_t win_blocks;     // runs per group
     int32_t win_run;        // f0 per run (64: batch tiles; 256: single-search tiles)
+    int32_t w_sky_stride;   // 0: wq, w shared by every group; else they are [n_sky][n_seg]
+                            // (antenna-pattern weights) with rows this far apart
 };
 
 struct EvalArgs {

@@ -218,7 +218,12 @@ __global__ __launch_bounds__(256) void eval_kernel(const EvalArgs a, int first, 
             }
         }
     for (int d = 0; d < a.n_det; ++d) {
-        const DetView D = a.det[d];
+        DetView D = a.det[d];
+        if (D.w_sky_stride) {  // antenna-pattern weights: the row of this group's sky point
+            const int64_t off = (int64_t)(grp / a.n_tn) * D.w_sky_stride;
+            D.wq += off;
+            D.w += off;
+        }
         int jb, je;
         const int runs = D.win ? 256 * TPL / D.win_run : 1;
         seg_window(D, grp, tile * runs, (tile + 1) * runs, jb, je);

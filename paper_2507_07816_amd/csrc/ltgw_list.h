@@ -1,6 +1,7 @@
 // Internal interface of the explicit-template evaluation (ltgw_list.hip) for
 // the C-ABI layer.  Not part of the public boundary.
 #pragma once
+#include "ltgw_antenna.h"
 #include "ltgw_internal.h"
 
 namespace ltgw {
@@ -17,6 +18,9 @@ struct ListDet {
     const float *wq;  // [n_seg] weights x per-segment scale (the power sum)
     const float *w;   // [n_seg] weights (W1, W2)
     double t_sft, cshift;
+    const double *era;     // [n_seg] Earth rotation angles, or NULL: no antenna factor
+    const float *scale;    // [n_seg] store row scales (antenna weights are formed per template)
+    Arms arms;
 };
 
 struct ListArgs {

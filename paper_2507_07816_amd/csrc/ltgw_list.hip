@@ -61,10 +61,12 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
                 const double vv = x + D.cshift;
                 const unsigned idx = (unsigned)__double2int_rz(vv);
                 const float p = Store<STORE>::get(rs, (int)idx, j * D.pitch_bytes, cnt);
-                sc = __builtin_fmaf(D.wq[j], p, sc);
+                float wq = D.wq[j], wv = D.w[j];
+                if (D.era)  // antenna-pattern weights for this template's sky direction
+                    antenna_weights(D.arms, D.era[j], T.sky[0], T.sky[1], T.sky[2], wv, D.scale[j], wv, wq);
+                sc = __builtin_fmaf(wq, p, sc);
                 const bool inb = (idx - 1u) < nb;
                 nin += inb ? 1 : 0;
-                const float wv = D.w[j];
                 const float wj = inb ? wv : 0.0f;
                 w1c += wj;
                 w2c = __builtin_fmaf(wj, wj, w2c);

@@ -39,7 +39,7 @@ TILE_SHAPES = {0: (1, 8), 1: (1, 16), 2: (2, 8), 3: (2, 16)}  # (templates per l
 
 # every symbol include/ltgw.h declares
 EXPORTS = ("ltgw_create", "ltgw_destroy", "ltgw_last_error", "ltgw_load_spectrogram",
-           "ltgw_set_velocity_table", "ltgw_eval_templates", "ltgw_psi",
+           "ltgw_set_velocity_table", "ltgw_set_antenna", "ltgw_eval_templates", "ltgw_psi",
            "ltgw_topk_candidates", "ltgw_diagnostics", "ltgw_inject_track", "ltgw_read_store",
            "ltgw_eval_batch", "ltgw_batch_results", "ltgw_batch_latency", "ltgw_autotune",
            "ltgw_set_tile_shape", "ltgw_tune_save", "ltgw_tune_load",
@@ -122,6 +122,7 @@ def library():
             "ltgw_last_error": (C.c_char_p, [P]),
             "ltgw_load_spectrogram": (i32, [P, i32, C.POINTER(ltgw_spec_desc), P]),
             "ltgw_set_velocity_table": (i32, [P, i32, P, i32]),
+            "ltgw_set_antenna": (i32, [P, i32, P, P, i32]),
             "ltgw_eval_templates": (i32, [P, C.POINTER(ltgw_grid), u32, P, P, P]),
             "ltgw_eval_list": (i32, [P, P, C.c_int64, d, u32, P, P, P]),
             "ltgw_psi": (i32, [P, u32, P]),
@@ -219,6 +220,19 @@ def ltgw_set_velocity_table(ctx, det, v):
         v = np.ascontiguousarray(v, dtype=np.float64)
     vp, kv = _addr(v)
     _check(ctx, library().ltgw_set_velocity_table(ctx, int(det), vp, int(v.shape[0])))
+
+
+def ltgw_set_antenna(ctx, det, arms, era):
+    """arms: [2][3] Earth-fixed unit arm vectors (host), or None to clear;
+    era: [n_seg] Earth rotation angles (host array or device tensor)."""
+    if arms is None:
+        _check(ctx, library().ltgw_set_antenna(ctx, int(det), None, None, 0))
+        return
+    a = np.ascontiguousarray(arms, dtype=np.float64).reshape(6)
+    if not hasattr(era, "data_ptr"):
+        era = np.ascontiguousarray(era, dtype=np.float64)
+    ep, ke = _addr(era)
+    _check(ctx, library().ltgw_set_antenna(ctx, int(det), a.ctypes.data, ep, int(era.shape[0])))
 
 
 def make_grid(f0_min, f0_step, n_f0, tau, brake, sky, t0=0.0, det_mask=0):
@@ -515,6 +529,9 @@ class Context:
 
     def set_velocity_table(self, det, v):
         ltgw_set_velocity_table(self.h, det, v)
+
+    def set_antenna(self, det, arms, era=None):
+        ltgw_set_antenna(self.h, det, arms, era)
 
     def eval_templates(self, f0_min, f0_step, n_f0, tau, brake, sky, t0=0.0, det_mask=0,
                        stats=LTGW_STAT_POWER | LTGW_STAT_COUNT, outputs=True):
