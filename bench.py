@@ -39,7 +39,8 @@ KERNEL_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_kernels.hip", "paper_2507_0781
 
 # the explicit-template kernel's code (its committed FP64 instruction count)
 LIST_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_list.hip", "paper_2507_07816_amd/csrc/ltgw_list.h",
-                "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_gather.h")
+                "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_gather.h",
+                "paper_2507_07816_amd/csrc/ltgw_antenna.h")
 
 
 def kernel_source_hash(sources=KERNEL_SOURCES):
@@ -166,7 +167,7 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
 FP64_LANE_OPS = 256 * 64 * 2.4e9
 
 
-def list_leg(torch, ltgw, ctx, wl, n=100000, reps=3, seed=11, fp64_per_eval=None):
+def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, fp64_per_eval=None):
     """The uniform random bank over the loaded search: n templates drawn
     uniformly in f0 (the band), tau and n, at the search's sky point.  Every
     (template, segment) takes its own correctly rounded Eq. 1 power, so the
@@ -201,6 +202,45 @@ def list_leg(torch, ltgw, ctx, wl, n=100000, reps=3, seed=11, fp64_per_eval=None
         out["roofline"] = {"bound": "alu", "achieved": rate / 1e12, "peak": FP64_LANE_OPS / 1e12,
                            "unit": "T FP64 lane-instructions/s", "frac": rate / FP64_LANE_OPS,
                            "fp64_instructions_per_eval": fp64_per_eval}
+    return out
+
+
+def campaign_leg(torch, ltgw, R_noise=128, amps=(1.0, 1.5, 2.0, 2.5, 3.0, 4.0), per_level=32, seed=2024):
+    """The synthetic sensitivity campaign (Sec. 3) on the small workload's
+    geometry (1024 segments x 800 bins, U[0.5, 2] weights): thresholds from
+    R_noise noise-only full searches, per_level injections (f0 uniform in the
+    band, tau = 10000 s, n = 5) at each amplitude, detection near the
+    injection, logistic fit and A90, for the power and the count statistic,
+    over the cubic lattice (4800 templates) and a uniform random bank of as
+    many templates."""
+    import synth
+    from paper_2507_07816_amd.campaign import Campaign
+
+    wl = synth.tiny()
+    d = wl.dets[0]
+    w = np.random.Generator(np.random.PCG64(55)).uniform(0.5, 2.0, d["rho"].shape[0]).astype(np.float32)
+    geo = dict(t_seg=d["t_seg"], v=d["v"], weights=w, k_lo=d["k_lo"], t_sft=d["t_sft"], n_bins=d["rho"].shape[1])
+    g = dict(wl.grid)
+    out = {"workload": f"{wl.name}: {R_noise} noise-only realisations, {len(amps)} amplitudes x {per_level} "
+                       "injections (tau 10000 s, n 5)", "amplitudes": list(amps)}
+    ctx = ltgw.Context(0)
+    try:
+        for bank_name in ("cubic", "random"):
+            bank = None if bank_name == "cubic" else synth.random_bank(
+                wl.n_templates, (500.0, 600.0), (3500.0, 35000.0), (3.0, 7.0), g["sky"][0], seed=56)
+            camp = Campaign(ctx, geo, g, bank=bank, seed=seed)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = camp.run(list(amps), per_level, R_noise, f0_range=(505.0, 595.0), tau=10000.0, brake=5.0)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+            n_real = R_noise + len(amps) * per_level
+            out[bank_name] = {"templates": int(wl.n_templates), "wall_s": wall, "realisations_per_s": n_real / wall,
+                              **{name: {"threshold": res["threshold"][name],
+                                        "efficiency": [float(x) for x in res[name]["efficiency"]],
+                                        "a90": res[name]["fit"]["a90"]} for name in ("power", "count")}}
+    finally:
+        ctx.close()
     return out
 
 
@@ -263,7 +303,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-proposer", action="store_true", help="skip the learned-proposer leg")
     ap.add_argument("--batch", action="store_true", help="add the 64-search batch leg")
-    ap.add_argument("--list-templates", type=int, default=100000,
+    ap.add_argument("--no-campaign", action="store_true", help="skip the sensitivity campaign leg")
+    ap.add_argument("--list-templates", type=int, default=1000000,
                     help="templates of the uniform random bank leg (0 skips it)")
     ap.add_argument("--tile-shape", type=int, default=-1,
                     help="force the statistic kernel's variant (0..15) instead of autotuning (profiling runs)")
@@ -374,6 +415,10 @@ def main():
         out["random_bank"] = list_leg(torch, ltgw, ctx, wl, n=args.list_templates,
                                       fp64_per_eval=measured_list_fp64())
         print(f"[bench] random bank: {json.dumps(out['random_bank'])}", file=sys.stderr, flush=True)
+    if not args.no_campaign:
+        print("[bench] sensitivity campaign", file=sys.stderr, flush=True)
+        out["campaign"] = campaign_leg(torch, ltgw)
+        print(f"[bench] campaign: {json.dumps(out['campaign'])}", file=sys.stderr, flush=True)
     if args.batch:
         print("[bench] batch of 64 searches", file=sys.stderr, flush=True)
         out["batch"] = batch_leg(torch, ltgw)

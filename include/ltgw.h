@@ -200,8 +200,8 @@ typedef struct {
  * Eq. 2, the bin rule and FP32 sums over chunks of 32 segments carried in FP64,
  * so s, c and N of a lattice template are the lattice's bit for bit (W1, W2
  * are summed in that order too; the lattice forms them exactly, so they agree
- * to FP32 rounding of 32-term sums).  The evaluation runs in ascending f0
- * (results stay in list order) and is bound by FP64 arithmetic: no table is
+ * to FP32 rounding of 32-term sums).  The evaluation runs in f0 order
+ * (2^16 buckets over the list's range; results stay in list order) and is bound by FP64 arithmetic: no table is
  * shared between templates.  Outputs as ltgw_eval_templates, in list order;
  * the results are kept for ltgw_psi and ltgw_topk_candidates (whose records
  * then carry the listed parameters, index = list position and sky = -1).

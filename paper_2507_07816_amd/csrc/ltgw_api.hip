@@ -701,10 +701,22 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
         std::memcpy(V.arms.b, D.arms + 3, sizeof V.arms.b);
         n_seg_total += D.n_seg;
     }
-    // evaluation order: ascending f0, so that neighbouring lanes gather neighbouring columns
-    std::vector<int32_t> perm((size_t)n);
-    for (int64_t q = 0; q < n; ++q) perm[(size_t)q] = (int32_t)q;
-    std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return tpl[x].f0 < tpl[y].f0; });
+    // evaluation order: f0 in 2^16 buckets over the list's range (a stable
+    // counting sort), so that neighbouring lanes gather neighbouring columns;
+    // every result goes to its list position, so the order changes none
+    double f0_lo = tpl[0].f0;
+    for (int64_t q = 1; q < n; ++q) f0_lo = tpl[q].f0 < f0_lo ? tpl[q].f0 : f0_lo;
+    constexpr int kBuckets = 1 << 16;
+    const double bscale = f0_max > f0_lo ? (kBuckets - 1) / (f0_max - f0_lo) : 0.0;
+    std::vector<int32_t> bucket_start(kBuckets + 1, 0), perm((size_t)n);
+    std::vector<uint16_t> key((size_t)n);
+    for (int64_t q = 0; q < n; ++q) {
+        const int b = (int)((tpl[q].f0 - f0_lo) * bscale);
+        key[(size_t)q] = (uint16_t)(b < 0 ? 0 : b > kBuckets - 1 ? kBuckets - 1 : b);
+        ++bucket_start[key[(size_t)q] + 1];
+    }
+    for (int b = 0; b < kBuckets; ++b) bucket_start[b + 1] += bucket_start[b];
+    for (int64_t q = 0; q < n; ++q) perm[(size_t)bucket_start[key[(size_t)q]]++] = (int32_t)q;
     HIP_TRY(c, hipEventSynchronize(c->ev_h2d), "previous upload");
     c->h_list.assign(tpl, tpl + n);
     c->h_perm.swap(perm);
