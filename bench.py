@@ -244,6 +244,37 @@ def campaign_leg(torch, ltgw, R_noise=128, amps=(1.0, 1.5, 2.0, 2.5, 3.0, 4.0), 
     return out
 
 
+def sft_leg(torch, ltgw, n_seg=10800, n_fft=32768, k_lo=4000, n_bins=8000, window=101, reps=3, seed=17):
+    """Data preparation: 24 h of 4096-Hz strain (Gaussian, seeded, generated
+    on the device) in 10,800 segments of 8 s -> Hann-windowed FP32 transforms
+    -> normalised power over 500-1500 Hz (8000 bins), running median of 101
+    bins; the realistic search's input.  Rates are for the whole call."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    strain = torch.randn(n_seg * n_fft, generator=g, device="cuda", dtype=torch.float32)
+    out = torch.empty((n_seg, n_bins), dtype=torch.float32, device="cuda")
+    ctx = ltgw.Context(0)
+    try:
+        ltgw.ltgw_sft_normalise(ctx.h, strain, n_seg, n_fft, k_lo, n_bins, window, out)  # plans, warm-up
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            ltgw.ltgw_sft_normalise(ctx.h, strain, n_seg, n_fft, k_lo, n_bins, window, out)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+    finally:
+        ctx.close()
+    wall = min(ts)
+    rho = out[:, ::97].double()
+    strain_bytes = n_seg * n_fft * 4
+    return {"workload": f"{n_seg} segments x {n_fft} samples (8 s at 4096 Hz), band {k_lo}..{k_lo + n_bins - 1} "
+                        f"(500-1500 Hz), running median of {window} bins, seed {seed}",
+            "ms": wall * 1e3, "segments_per_s": n_seg / wall, "strain_gb_per_s": strain_bytes / wall / 1e9,
+            "strain_frac_of_hbm_peak": strain_bytes / wall / 1e9 / HBM_PEAK_GBS,
+            "rho_mean": float(rho.mean()), "rho_tail_1.6": float((rho > 1.6).double().mean())}
+
+
 def batch_leg(torch, ltgw, reps=2, seed=5):
     """The batch of 64 uneven searches (two detectors each, sky patches of 16 to
     1024 points, 1.76e13 template x segment evaluations) in one persistent,
@@ -304,6 +335,7 @@ def main():
     ap.add_argument("--no-proposer", action="store_true", help="skip the learned-proposer leg")
     ap.add_argument("--batch", action="store_true", help="add the 64-search batch leg")
     ap.add_argument("--no-campaign", action="store_true", help="skip the sensitivity campaign leg")
+    ap.add_argument("--no-sft", action="store_true", help="skip the data-preparation leg")
     ap.add_argument("--list-templates", type=int, default=1000000,
                     help="templates of the uniform random bank leg (0 skips it)")
     ap.add_argument("--tile-shape", type=int, default=-1,
@@ -415,6 +447,10 @@ def main():
         out["random_bank"] = list_leg(torch, ltgw, ctx, wl, n=args.list_templates,
                                       fp64_per_eval=measured_list_fp64())
         print(f"[bench] random bank: {json.dumps(out['random_bank'])}", file=sys.stderr, flush=True)
+    if not args.no_sft:
+        print("[bench] data preparation (strain -> normalised power)", file=sys.stderr, flush=True)
+        out["sft"] = sft_leg(torch, ltgw)
+        print(f"[bench] sft: {json.dumps(out['sft'])}", file=sys.stderr, flush=True)
     if not args.no_campaign:
         print("[bench] sensitivity campaign", file=sys.stderr, flush=True)
         out["campaign"] = campaign_leg(torch, ltgw)

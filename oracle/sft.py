@@ -39,7 +39,9 @@ def normalise(P, k_lo, n_bins, window):
     h = window // 2
     band = P[:, k_lo - h:k_lo + n_bins + h]
     med = np.median(sliding_window_view(band, window, axis=1), axis=2)
-    return P[:, k_lo:k_lo + n_bins] * math.log(2.0) / med
+    # a window whose median is 0 (zero strain) carries no noise-floor estimate: rho = 0
+    safe = np.where(med > 0.0, med, 1.0)
+    return np.where(med > 0.0, P[:, k_lo:k_lo + n_bins] * math.log(2.0) / safe, 0.0)
 
 
 def normalised_power(strain, n_fft, k_lo, n_bins, window):

@@ -15,7 +15,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["hipcc", *FLAGS, "-o", LIB + ".tmp", *SRC]
+    cmd = ["hipcc", *FLAGS, "-o", LIB + ".tmp", *SRC, "-lhipfft"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

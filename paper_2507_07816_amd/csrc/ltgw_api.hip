@@ -188,6 +188,7 @@ void ltgw_destroy(ltgw_ctx *c) {
     if (c->ev_h2d) (void)hipEventDestroy(c->ev_h2d);
     free_batch(c->batch);
     free_stack(c->stack);
+    sft_release(c);
     for (auto &d : c->det) {
         release(d.store_buf); release(d.t_seg); release(d.w); release(d.wq);
         release(d.scale); release(d.v); release(d.g); release(d.H); release(d.wfix); release(d.win);

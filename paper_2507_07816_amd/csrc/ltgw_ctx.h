@@ -144,6 +144,14 @@ struct ltgw_ctx {
     std::vector<ltgw_template> h_list;  // its templates (top-k records) ...
     std::vector<int32_t> h_perm;        // ... and their evaluation order
     ltgw::DevBuf list_d, perm_d;
+    // data preparation (ltgw_sft_normalise): window table, chunk buffers, FFT plans
+    struct SftPlan {
+        int n_fft, batch;
+        void *plan;  // hipfftHandle
+    };
+    int sft_n_fft = 0;
+    ltgw::DevBuf sft_hann, sft_in, sft_spec;
+    std::vector<SftPlan> sft_plans;
     int forced_variant = -1;      // ltgw_set_tile_shape; -1 = autotuner
     ltgw::BatchState batch;
     ltgw::StackState stack;
@@ -156,6 +164,7 @@ int hip_fail(ltgw_ctx *c, hipError_t e, const char *what);
 int ensure(ltgw_ctx *c, DevBuf &b, size_t bytes, const char *what);
 void release(DevBuf &b);
 bool is_device_ptr(const void *p);
+void sft_release(ltgw_ctx *c);  // FFT plans and buffers of the data preparation
 int to_host(ltgw_ctx *c, void *dst, const void *src, size_t n, const char *what);
 int h2d(ltgw_ctx *c, void *dst, const void *src, size_t n, const char *what);
 bool fin(double x);

@@ -1,0 +1,197 @@
+// Data preparation (Sec. 2): strain -> Hann-windowed short Fourier transforms
+// -> normalised power rho = P ln 2 / (running median of P over frequency).
+//
+// Segment j is samples [j N, (j + 1) N) of the strain.  Per chunk of segments:
+//   hann_kernel: x_n w_n with w_n = RN32(1/2 - 1/2 cos(2 pi n / N)) from a table;
+//   one batched real-to-complex FFT (hipFFT, FP32);
+//   normalise_kernel: P_k = re^2 + im^2 for the band and its median halo, a
+//   bitonic sort of (P, position) in LDS, then each bin's median is the
+//   (h + 1)-th smallest value whose position lies in its window, found by one
+//   scan of the sorted tile (every lane reads the same sorted entry at each
+//   step: an LDS broadcast).  Under Gaussian noise P_k is exponential with
+//   mean S_k and median S_k ln 2, hence rho_k = P_k ln 2 / median.
+#include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
+
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "ltgw_ctx.h"
+
+#pragma clang fp contract(off)
+
+namespace ltgw {
+
+constexpr int kSftTile = 256;      // output bins per workgroup
+constexpr int kSftSort = 512;      // sorted entries: tile + halo, padded to a power of two
+constexpr int kSftMaxWindow = kSftSort - kSftTile + 1;  // 257
+
+__global__ __launch_bounds__(256) void hann_table_kernel(int n_fft, float *w) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= n_fft) return;
+    const double c = cos(2.0 * M_PI * (double)n / (double)n_fft);
+    w[n] = (float)(0.5 - 0.5 * c);
+}
+
+__global__ __launch_bounds__(256) void hann_kernel(const float *__restrict__ x, int64_t n_total, int n_fft,
+                                                   const float *__restrict__ w, float *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_total; i += (int64_t)gridDim.x * 256)
+        out[i] = x[i] * w[i % n_fft];
+}
+
+// One workgroup: segment blockIdx.y, output bins [t0, t0 + 256) of the band.
+__global__ __launch_bounds__(256) void normalise_kernel(const float2 *__restrict__ spec, int64_t spec_pitch,
+                                                        int64_t k_lo, int n_bins, int h, float *__restrict__ out) {
+    __shared__ float val[kSftSort];
+    __shared__ short pos[kSftSort];
+    __shared__ float pw[kSftSort];
+    const int t = threadIdx.x;
+    const int t0 = blockIdx.x * kSftTile;
+    const int seg = blockIdx.y;
+    const float2 *row = spec + (int64_t)seg * spec_pitch;
+    // tile positions p = 0 .. 255 + 2h hold bin k_lo + t0 - h + p; positions
+    // past the last needed bin (band end + h) are padding that sorts last
+    const int n_pos = kSftTile + 2 * h;
+    const int last_needed = n_bins - 1 - t0 + 2 * h;  // last position any active lane reads
+    for (int p = t; p < kSftSort; p += 256) {
+        float v = __builtin_inff();
+        if (p < n_pos && p <= last_needed) {
+            const float2 z = row[k_lo + t0 - h + p];
+            const float a = z.x * z.x;
+            const float b = z.y * z.y;
+            v = a + b;
+        }
+        val[p] = v;
+        pw[p] = v;
+        pos[p] = (short)p;
+    }
+    __syncthreads();
+    // bitonic sort of (val, pos) ascending in val
+    for (int size = 2; size <= kSftSort; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int a = 2 * t - (t & (stride - 1));
+            const int b = a + stride;
+            const bool up = (a & size) == 0;
+            const float va = val[a], vb = val[b];
+            if ((va > vb) == up) {
+                val[a] = vb;
+                val[b] = va;
+                const short pa = pos[a];
+                pos[a] = pos[b];
+                pos[b] = pa;
+            }
+            __syncthreads();
+        }
+    }
+    // lane t: output bin t0 + t, window positions [t, t + 2h], median = the
+    // (h + 1)-th smallest value among them
+    const bool active = t0 + t < n_bins;
+    float med = 0.0f;
+    int cnt = 0;
+    const int lo = t, hi = t + 2 * h;
+    for (int s = 0; s < kSftSort && cnt <= h; ++s) {
+        const int p = pos[s];
+        if (p >= lo && p <= hi) {
+            ++cnt;
+            if (cnt == h + 1) med = val[s];
+        }
+    }
+    if (!active) return;
+    const float P = pw[t + h];
+    // rho = P ln2 / median; a window whose median is 0 carries no noise-floor estimate: 0
+    const double r = med > 0.0f ? (double)P * 0.69314718055994530942 / (double)med : 0.0;
+    out[(int64_t)seg * n_bins + t0 + t] = (float)r;
+}
+
+void sft_release(ltgw_ctx *c) {
+    for (auto &pl : c->sft_plans) (void)hipfftDestroy((hipfftHandle)pl.plan);
+    c->sft_plans.clear();
+    release(c->sft_hann);
+    release(c->sft_in);
+    release(c->sft_spec);
+    c->sft_n_fft = 0;
+}
+
+}  // namespace ltgw
+
+namespace {
+
+const char *fft_error(hipfftResult r) {
+    switch (r) {
+        case HIPFFT_ALLOC_FAILED: return "allocation failed";
+        case HIPFFT_INVALID_VALUE: return "invalid value";
+        case HIPFFT_INVALID_SIZE: return "invalid size";
+        case HIPFFT_EXEC_FAILED: return "execution failed";
+        case HIPFFT_SETUP_FAILED: return "setup failed";
+        default: return "error";
+    }
+}
+
+}  // namespace
+
+using namespace ltgw;
+
+extern "C" {
+
+int32_t ltgw_sft_normalise(ltgw_ctx *c, const float *strain, int32_t n_seg, int32_t n_fft, int64_t k_lo,
+                           int32_t n_bins, int32_t window, float *out) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (!strain || !out) return fail(c, LTGW_E_INVALID_ARG, "strain or out is NULL");
+    if (!is_device_ptr(strain) || !is_device_ptr(out))
+        return fail(c, LTGW_E_INVALID_ARG, "strain and out must be device memory");
+    if (n_seg < 1 || n_seg > 65535) return fail(c, LTGW_E_INVALID_ARG, "n_seg must be in 1 .. 65535");
+    if (n_fft < 2 || (n_fft & 1) || n_fft > (1 << 24))
+        return fail(c, LTGW_E_INVALID_ARG, "n_fft must be even and in 2 .. 2^24");
+    if (window < 1 || !(window & 1) || window > kSftMaxWindow)
+        return fail(c, LTGW_E_INVALID_ARG, "window must be odd and in 1 .. %d", kSftMaxWindow);
+    const int h = window / 2;
+    if (n_bins < 1 || k_lo < h || k_lo + n_bins - 1 + h > n_fft / 2)
+        return fail(c, LTGW_E_INVALID_ARG, "band [k_lo - window/2, k_lo + n_bins - 1 + window/2] must lie in 0 .. n_fft/2");
+    int rc;
+    // the window table, for this n_fft
+    if (c->sft_n_fft != n_fft) {
+        if ((rc = ensure(c, c->sft_hann, (size_t)n_fft * 4, "Hann window")) != LTGW_OK) return rc;
+        hipLaunchKernelGGL(hann_table_kernel, dim3((n_fft + 255) / 256), dim3(256), 0, c->stream, n_fft,
+                           (float *)c->sft_hann.p);
+        HIP_TRY(c, hipGetLastError(), "Hann table launch");
+        c->sft_n_fft = n_fft;
+    }
+    // chunks of segments: windowed input and spectrum within about 512 MB
+    const int64_t per_seg = (int64_t)n_fft * 4 + (int64_t)(n_fft / 2 + 1) * 8;
+    int batch = (int)std::max<int64_t>(1, std::min<int64_t>(n_seg, ((int64_t)512 << 20) / per_seg));
+    if ((rc = ensure(c, c->sft_in, (size_t)batch * n_fft * 4, "windowed segments")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->sft_spec, (size_t)batch * (n_fft / 2 + 1) * 8, "spectra")) != LTGW_OK) return rc;
+    for (int j0 = 0; j0 < n_seg; j0 += batch) {
+        const int nb = std::min(batch, n_seg - j0);
+        // a plan per (n_fft, batch size), kept for later calls
+        hipfftHandle plan = nullptr;
+        for (auto &pl : c->sft_plans)
+            if (pl.n_fft == n_fft && pl.batch == nb) plan = (hipfftHandle)pl.plan;
+        if (!plan) {
+            int n = n_fft;
+            const hipfftResult r = hipfftPlanMany(&plan, 1, &n, nullptr, 1, n_fft, nullptr, 1, n_fft / 2 + 1,
+                                                  HIPFFT_R2C, nb);
+            if (r != HIPFFT_SUCCESS) return fail(c, LTGW_E_DEVICE, "FFT plan: %s", fft_error(r));
+            c->sft_plans.push_back({n_fft, nb, (void *)plan});
+        }
+        const int64_t n_total = (int64_t)nb * n_fft;
+        const int64_t blocks = std::min<int64_t>((n_total + 255) / 256, 65536);
+        hipLaunchKernelGGL(hann_kernel, dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                           strain + (int64_t)j0 * n_fft, n_total, n_fft, (const float *)c->sft_hann.p,
+                           (float *)c->sft_in.p);
+        HIP_TRY(c, hipGetLastError(), "window launch");
+        hipfftResult r = hipfftSetStream(plan, c->stream);
+        if (r == HIPFFT_SUCCESS)
+            r = hipfftExecR2C(plan, (hipfftReal *)c->sft_in.p, (hipfftComplex *)c->sft_spec.p);
+        if (r != HIPFFT_SUCCESS) return fail(c, LTGW_E_DEVICE, "FFT: %s", fft_error(r));
+        hipLaunchKernelGGL(normalise_kernel, dim3((unsigned)((n_bins + kSftTile - 1) / kSftTile), (unsigned)nb),
+                           dim3(256), 0, c->stream, (const float2 *)c->sft_spec.p, (int64_t)(n_fft / 2 + 1), k_lo,
+                           n_bins, h, out + (int64_t)j0 * n_bins);
+        HIP_TRY(c, hipGetLastError(), "normalise launch");
+    }
+    return LTGW_OK;
+}
+
+}  // extern "C"

@@ -39,7 +39,7 @@ TILE_SHAPES = {0: (1, 8), 1: (1, 16), 2: (2, 8), 3: (2, 16)}  # (templates per l
 
 # every symbol include/ltgw.h declares
 EXPORTS = ("ltgw_create", "ltgw_destroy", "ltgw_last_error", "ltgw_load_spectrogram",
-           "ltgw_set_velocity_table", "ltgw_set_antenna", "ltgw_eval_templates", "ltgw_psi",
+           "ltgw_set_velocity_table", "ltgw_set_antenna", "ltgw_sft_normalise", "ltgw_eval_templates", "ltgw_psi",
            "ltgw_topk_candidates", "ltgw_diagnostics", "ltgw_inject_track", "ltgw_read_store",
            "ltgw_eval_batch", "ltgw_batch_results", "ltgw_batch_latency", "ltgw_autotune",
            "ltgw_set_tile_shape", "ltgw_tune_save", "ltgw_tune_load",
@@ -123,6 +123,7 @@ def library():
             "ltgw_load_spectrogram": (i32, [P, i32, C.POINTER(ltgw_spec_desc), P]),
             "ltgw_set_velocity_table": (i32, [P, i32, P, i32]),
             "ltgw_set_antenna": (i32, [P, i32, P, P, i32]),
+            "ltgw_sft_normalise": (i32, [P, P, i32, i32, C.c_int64, i32, i32, P]),
             "ltgw_eval_templates": (i32, [P, C.POINTER(ltgw_grid), u32, P, P, P]),
             "ltgw_eval_list": (i32, [P, P, C.c_int64, d, u32, P, P, P]),
             "ltgw_psi": (i32, [P, u32, P]),
@@ -233,6 +234,13 @@ def ltgw_set_antenna(ctx, det, arms, era):
         era = np.ascontiguousarray(era, dtype=np.float64)
     ep, ke = _addr(era)
     _check(ctx, library().ltgw_set_antenna(ctx, int(det), a.ctypes.data, ep, int(era.shape[0])))
+
+
+def ltgw_sft_normalise(ctx, strain, n_seg, n_fft, k_lo, n_bins, window, out):
+    """strain: device FP32 [n_seg * n_fft]; out: device FP32 [n_seg][n_bins]."""
+    sp, _a = _addr(strain)
+    op, _b = _addr(out)
+    _check(ctx, library().ltgw_sft_normalise(ctx, sp, int(n_seg), int(n_fft), int(k_lo), int(n_bins), int(window), op))
 
 
 def make_grid(f0_min, f0_step, n_f0, tau, brake, sky, t0=0.0, det_mask=0):
@@ -532,6 +540,13 @@ class Context:
 
     def set_antenna(self, det, arms, era=None):
         ltgw_set_antenna(self.h, det, arms, era)
+
+    def sft_normalise(self, strain, n_fft, k_lo, n_bins, window=101):
+        """Normalised power [n_seg][n_bins] (device FP32) of a device strain series."""
+        n_seg = int(strain.numel()) // int(n_fft)
+        out = self.torch.empty((n_seg, int(n_bins)), dtype=self.torch.float32, device=self.device)
+        ltgw_sft_normalise(self.h, strain, n_seg, n_fft, k_lo, n_bins, window, out)
+        return out
 
     def eval_templates(self, f0_min, f0_step, n_f0, tau, brake, sky, t0=0.0, det_mask=0,
                        stats=LTGW_STAT_POWER | LTGW_STAT_COUNT, outputs=True):
