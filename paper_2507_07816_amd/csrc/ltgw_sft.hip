@@ -4,8 +4,8 @@
 // Segment j is samples [j N, (j + 1) N) of the strain.  Per chunk of segments:
 //   hann_kernel: x_n w_n with w_n = RN32(1/2 - 1/2 cos(2 pi n / N)) from a table;
 //   one batched real-to-complex FFT (hipFFT, FP32);
-//   normalise_kernel: P_k = re^2 + im^2 for the band and its median halo, a
-//   bitonic sort of (P, position) in LDS, then each bin's median is the
+//   normalise_kernel: P_k = re^2 + im^2 for a 256-bin tile of the band and its
+//   median halo, a bitonic sort of (P, position) in LDS, then each bin's median is the
 //   (h + 1)-th smallest value whose position lies in its window, found by one
 //   scan of the sorted tile (every lane reads the same sorted entry at each
 //   step: an LDS broadcast).  Under Gaussian noise P_k is exponential with
@@ -40,20 +40,23 @@ __global__ __launch_bounds__(256) void hann_kernel(const float *__restrict__ x, 
         out[i] = x[i] * w[i % n_fft];
 }
 
-// One workgroup: segment blockIdx.y, output bins [t0, t0 + 256) of the band.
+// One workgroup: segment blockIdx.y, output bins [t0, t0 + 256) of the band;
+// lane t takes bin t0 + t.  (Wider tiles that fill all 512 sorted entries
+// were measured slower: the per-bin scans, not the sort, dominate.)
 __global__ __launch_bounds__(256) void normalise_kernel(const float2 *__restrict__ spec, int64_t spec_pitch,
                                                         int64_t k_lo, int n_bins, int h, float *__restrict__ out) {
     __shared__ float val[kSftSort];
-    __shared__ short pos[kSftSort];
+    __shared__ __attribute__((aligned(16))) short pos[kSftSort];
     __shared__ float pw[kSftSort];
     const int t = threadIdx.x;
-    const int t0 = blockIdx.x * kSftTile;
+    const int T = kSftTile;
+    const int t0 = blockIdx.x * T;
     const int seg = blockIdx.y;
     const float2 *row = spec + (int64_t)seg * spec_pitch;
     // tile positions p = 0 .. 255 + 2h hold bin k_lo + t0 - h + p; positions
     // past the last needed bin (band end + h) are padding that sorts last
-    const int n_pos = kSftTile + 2 * h;
-    const int last_needed = n_bins - 1 - t0 + 2 * h;  // last position any active lane reads
+    const int n_pos = T + 2 * h;
+    const int last_needed = n_bins - 1 - t0 + 2 * h;  // last position any output reads
     for (int p = t; p < kSftSort; p += 256) {
         float v = __builtin_inff();
         if (p < n_pos && p <= last_needed) {
@@ -84,24 +87,34 @@ __global__ __launch_bounds__(256) void normalise_kernel(const float2 *__restrict
             __syncthreads();
         }
     }
-    // lane t: output bin t0 + t, window positions [t, t + 2h], median = the
-    // (h + 1)-th smallest value among them
-    const bool active = t0 + t < n_bins;
-    float med = 0.0f;
-    int cnt = 0;
-    const int lo = t, hi = t + 2 * h;
-    for (int s = 0; s < kSftSort && cnt <= h; ++s) {
-        const int p = pos[s];
-        if (p >= lo && p <= hi) {
-            ++cnt;
-            if (cnt == h + 1) med = val[s];
+    // output o: window positions [o, o + 2h]; its median is the (h + 1)-th
+    // smallest value among them.  Four sorted positions per LDS read; the
+    // group that holds the (h + 1)-th in-window entry is resolved entry by entry.
+    const short4 *pos4 = reinterpret_cast<const short4 *>(pos);
+    for (int o = t; o < T && t0 + o < n_bins; o += 256) {
+        float med = 0.0f;
+        int cnt = 0;
+        const int lo = o, hi = o + 2 * h;
+        for (int g = 0; g < kSftSort / 4 && cnt <= h; ++g) {
+            const short4 q = pos4[g];
+            const int i0 = (q.x >= lo && q.x <= hi), i1 = (q.y >= lo && q.y <= hi);
+            const int i2 = (q.z >= lo && q.z <= hi), i3 = (q.w >= lo && q.w <= hi);
+            const int c = cnt + ((i0 + i1) + (i2 + i3));
+            if (c > h) {
+                int k = h + 1 - cnt, e = 0;
+                if (i0 && --k == 0) e = 0;
+                else if (i1 && --k == 0) e = 1;
+                else if (i2 && --k == 0) e = 2;
+                else e = 3;
+                med = val[4 * g + e];
+            }
+            cnt = c;
         }
+        const float P = pw[o + h];
+        // rho = P ln2 / median; a window whose median is 0 carries no noise-floor estimate: 0
+        const double r = med > 0.0f ? (double)P * 0.69314718055994530942 / (double)med : 0.0;
+        out[(int64_t)seg * n_bins + t0 + o] = (float)r;
     }
-    if (!active) return;
-    const float P = pw[t + h];
-    // rho = P ln2 / median; a window whose median is 0 carries no noise-floor estimate: 0
-    const double r = med > 0.0f ? (double)P * 0.69314718055994530942 / (double)med : 0.0;
-    out[(int64_t)seg * n_bins + t0 + t] = (float)r;
 }
 
 void sft_release(ltgw_ctx *c) {
