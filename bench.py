@@ -205,6 +205,46 @@ def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, fp64_per_eval=Non
     return out
 
 
+def antenna_leg(torch, ltgw, ctx, wl, power, t_seg, v, w, store, steps=5):
+    """The realistic search with antenna-pattern weights on (the H-site arms,
+    Earth rotation angles of the segment times): one weight row per sky point,
+    W1 and W2 summed by the statistic kernel.  Same step as the headline."""
+    import synth
+
+    d = wl.dets[0]
+    g = wl.grid
+    arms = synth.site_arms(*synth.SITE_H, synth.ARM_AZ_H)
+    era = synth.earth_rotation_angle(d["t_seg"])
+
+    def step():
+        ctx.load_spectrogram(0, power, d["k_lo"], d["t_sft"], t_seg, weights=w, store=store)
+        ctx.set_velocity_table(0, v)
+        ctx.set_antenna(0, arms, era)
+        ctx.eval_templates(g["f0_min"], g["f0_step"], g["n_f0"], g["tau"], g["brake"], g["sky"], g["t0"],
+                           outputs=False)
+        ctx.topk("power", 10)
+        ctx.topk("count", 10)
+        return ctx.diagnostics()
+
+    step()
+    # the tile shape for this search with in-kernel moments (the autotuner's cache key includes the mode)
+    ctx.autotune(g["f0_min"], g["f0_step"], g["n_f0"], g["tau"], g["brake"], g["sky"], g["t0"])
+    step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    kms = []
+    for _ in range(steps):
+        dg = step()
+        kms.append(dg["eval_kernel_ms"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    ctx.set_antenna(0, None)
+    return {"workload": f"{wl.name} with H-site antenna-pattern weights", "steps": steps,
+            "value": dg["evals"] * steps / el, "unit": "template·segment evals/s", "ms_per_step": el * 1e3 / steps,
+            "eval_kernel_ms": float(np.mean(kms)), "eval_launches_per_step": int(dg["eval_launches"]),
+            "tile_shape": int(dg["tile_shape"])}
+
+
 def campaign_leg(torch, ltgw, R_noise=128, amps=(1.0, 1.5, 2.0, 2.5, 3.0, 4.0), per_level=32, seed=2024):
     """The synthetic sensitivity campaign (Sec. 3) on the small workload's
     geometry (1024 segments x 800 bins, U[0.5, 2] weights): thresholds from
@@ -336,6 +376,7 @@ def main():
     ap.add_argument("--batch", action="store_true", help="add the 64-search batch leg")
     ap.add_argument("--no-campaign", action="store_true", help="skip the sensitivity campaign leg")
     ap.add_argument("--no-sft", action="store_true", help="skip the data-preparation leg")
+    ap.add_argument("--no-antenna", action="store_true", help="skip the antenna-weights leg")
     ap.add_argument("--list-templates", type=int, default=1000000,
                     help="templates of the uniform random bank leg (0 skips it)")
     ap.add_argument("--tile-shape", type=int, default=-1,
@@ -442,6 +483,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(wl.name, args.store, int(dg["tile_shape"]))},
     }
+    if not args.no_antenna:
+        print("[bench] antenna-pattern weights", file=sys.stderr, flush=True)
+        out["antenna"] = antenna_leg(torch, ltgw, ctx, wl, power, t_seg, v, w, args.store)
+        print(f"[bench] antenna: {json.dumps(out['antenna'])}", file=sys.stderr, flush=True)
     if args.list_templates > 0:
         print("[bench] uniform random bank", file=sys.stderr, flush=True)
         out["random_bank"] = list_leg(torch, ltgw, ctx, wl, n=args.list_templates,
