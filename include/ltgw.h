@@ -277,7 +277,9 @@ typedef struct {
     double eval_kernel_ms;  /* duration of the last eval's statistic kernel,
                                from HIP events on the context's stream       */
     double tables_ms;       /* duration of the last eval's track-table kernels
-                               (Eq. 1 powers, Eq. 2 factors, in-band moments) */
+                               (Eq. 1 powers, Eq. 2 factors, in-band windows);
+                               the in-band moments run beside the statistic
+                               kernel on a second stream of the context    */
     int32_t tile_shape;     /* tile shape of the last eval's statistic kernel */
     int32_t eval_launches;  /* dispatches of the statistic kernel in the last
                                eval (segment slabs, generations of workgroups) */

@@ -160,7 +160,10 @@ int32_t ltgw_create(int32_t device, void *hip_stream, ltgw_ctx **out) {
     }
     if (rc == LTGW_OK) {
         hipError_t ee = hipEventCreateWithFlags(&c->ev_h2d, hipEventDisableTiming);
-        if (ee != hipSuccess) rc = hip_fail(c, ee, "event create");
+        if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+        if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (ee == hipSuccess) ee = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        if (ee != hipSuccess) rc = hip_fail(c, ee, "event/stream create");
     }
     if (rc == LTGW_OK) {
         int v = 0;
@@ -172,7 +175,7 @@ int32_t ltgw_create(int32_t device, void *hip_stream, ltgw_ctx **out) {
     }
     if (rc != LTGW_OK) {
         g_create_error = c->err;
-        delete c;
+        ltgw_destroy(c);
         return rc;
     }
     *out = c;
@@ -183,9 +186,13 @@ void ltgw_destroy(ltgw_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->side) (void)hipStreamSynchronize(c->side);
     for (hipEvent_t e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->ev_h2d) (void)hipEventDestroy(c->ev_h2d);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side) (void)hipStreamDestroy(c->side);
     free_batch(c->batch);
     free_stack(c->stack);
     sft_release(c);
@@ -600,10 +607,27 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     a.out_c = out_c;
     a.out_n = out_n;
     a.in_band_total = (unsigned long long *)c->counters.p + kCntInBand;
+    // The in-band moments (N, W1, W2, out_n, the in-band total) read only the
+    // tables and the weights, and the statistic kernel without moments reads
+    // none of them: they run beside it on the second stream.  `join` makes the
+    // context's stream wait for them on every way out of this call.
+    struct Join {
+        ltgw_ctx *c;
+        bool on = false;
+        ~Join() {
+            if (on) (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
+        }
+    } join{c};
     if (!moments_in_loop) {
         const size_t n_diff = (size_t)(M.mode ? 4 : 1) * (size_t)P.n_groups * (size_t)(g->n_f0 + 1);
         if ((rc = ensure(c, c->diff, n_diff * 8, "moment difference arrays")) != LTGW_OK) return rc;
-        HIP_TRY(c, launch_moments(a, M.mode, M.e0, (int64_t *)c->diff.p, c->stream), "moments launch");
+        HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream), "event record");
+        HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "stream wait");
+        const hipError_t me = launch_moments(a, M.mode, M.e0, (int64_t *)c->diff.p, c->side);
+        const hipError_t je = hipEventRecord(c->ev_join, c->side);
+        join.on = je == hipSuccess;
+        HIP_TRY(c, me, "moments launch");
+        HIP_TRY(c, je, "event record");
     }
     if (variant < 0) variant = c->forced_variant;
     if (variant < 0) {

@@ -129,6 +129,11 @@ struct ltgw_ctx {
     std::vector<double> h_tau, h_brake, h_sky;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // tables start, eval start, eval end
     hipEvent_t ev_h2d = nullptr;  // after the grid uploads from h_tau/h_brake/h_sky
+    // second stream (default priority): the in-band moments run there beside the
+    // statistic kernel; ev_fork orders them after the tables, ev_join before
+    // anything on `stream` that reads them
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int cu_count = 256;
     int wall_khz = 100000;        // device wall-clock rate
     std::map<std::string, int> tune;  // autotuner cache: key -> tile shape
