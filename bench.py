@@ -415,9 +415,11 @@ def main():
           f"store {args.store}", file=sys.stderr, flush=True)
     ctx = ltgw.Context(0)
     power = torch.from_numpy(d["rho"]).to(dev)
-    t_seg = torch.from_numpy(d["t_seg"]).to(dev)
-    v = torch.from_numpy(d["v"]).to(dev)
-    w = None if d["weights"] is None else torch.from_numpy(d["weights"]).to(dev)
+    # the spectrogram is resident in HBM; the per-segment geometry (times,
+    # velocities, weights: 0.3 MB) is host metadata, as in a search
+    t_seg = np.ascontiguousarray(d["t_seg"])
+    v = np.ascontiguousarray(d["v"])
+    w = None if d["weights"] is None else np.ascontiguousarray(d["weights"])
     # injected tracks, added on the device by the library's own injection call
     ctx.load_spectrogram(0, power, d["k_lo"], d["t_sft"], t_seg, weights=w, store="f32")
     ctx.set_velocity_table(0, v)
