@@ -55,7 +55,7 @@ extern "C" {
                                    unknown detector */
 #define LTGW_E_NOMEM (-3)       /* device allocation failed */
 #define LTGW_E_DEVICE (-4)      /* HIP runtime error; text in ltgw_last_error */
-#define LTGW_E_UNSUPPORTED (-5) /* valid request outside what this build supports */
+#define LTGW_E_UNSUPPORTED (-5) /* valid request outside what the library supports */
 
 /* ---- storage of the spectrogram on the device -------------------------- */
 #define LTGW_STORE_F32 0  /* IEEE binary32                                     */
