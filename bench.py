@@ -34,13 +34,14 @@ BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
 
 # the statistic kernel's code: a change to any of these voids the committed counters
 KERNEL_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_kernels.hip", "paper_2507_07816_amd/csrc/ltgw_gather.h",
-                  "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_internal.h")
+                  "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_internal.h",
+                  "paper_2507_07816_amd/csrc/exp2_table.h")
 
 
 # the explicit-template kernel's code (its committed FP64 instruction count)
 LIST_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_list.hip", "paper_2507_07816_amd/csrc/ltgw_list.h",
                 "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_gather.h",
-                "paper_2507_07816_amd/csrc/ltgw_antenna.h")
+                "paper_2507_07816_amd/csrc/ltgw_antenna.h", "paper_2507_07816_amd/csrc/exp2_table.h")
 
 
 def kernel_source_hash(sources=KERNEL_SOURCES):

@@ -5,25 +5,28 @@
 // Dekker (Fast2Sum; exact product via a fused multiply-add), combined into
 // double-double add/multiply/divide in the way of Hida, Li and Bailey's
 // double-double arithmetic.  On top of them:
-//   exp:  Y = k ln2 + r with a three-part ln2 (so k*ln2_1 is exact for
-//         |k| < 2^11), r scaled by 2^-8, Taylor series of expm1(r) to r^10,
-//         then eight doublings expm1(2x) = expm1(x) (expm1(x) + 2).
+//   exp:  Y = N ln2/256 + r with a three-part ln2/256 (so N times its head
+//         is exact for |N| < 2^18), |r| <= ln2/512, Taylor series of
+//         expm1(r) to r^10, times 2^(j/256) (N = 256 k + j) from a
+//         double-double table, times 2^k.
 //   log:  one Newton step on exp: y0 = log(u) from the device math library,
 //         d = u e^-y0 - 1, log u = y0 + d - d^2/2 (+O(d^3), |d| < 2^-50).
 //   pow:  exp(e * log u); result error below 2^-98 relative.  The nearest
 //         double is returned; when the double-double value lies too close to
 //         a rounding boundary to decide, the caller is told (undecided = 1).
 //
-// ln 2 = 0.693147180559945309417232121458176568075500134360255254120680...
-// split as ln2_1 (42 significant bits) + ln2_2 + ln2_3 (each the nearest
-// double of the remainder); the split is checked by a host test against a
-// 60-digit decimal ln 2.
+// ln 2 / 256 is split as a 35-bit head plus two tails (each the nearest
+// double of the remainder), and 2^(j/256) is tabulated as double-doubles;
+// both come from exp2_table.h, whose values a host test checks against
+// 60-digit decimal arithmetic.
 //
 // Everything here must be compiled without floating-point contraction.
 #pragma once
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+
+#include "exp2_table.h"
 
 #ifdef __HIPCC__
 #define LTGW_HD __host__ __device__ inline
@@ -39,9 +42,6 @@ struct dd {
     double hi, lo;
 };
 
-constexpr double kLn2_1 = 0x1.62e42fefa3800p-1;
-constexpr double kLn2_2 = 0x1.ef35793c76730p-45;
-constexpr double kLn2_3 = 0x1.f97b57a079a19p-103;
 constexpr double kInvLn2 = 0x1.71547652b82fep+0;
 // 1/3 and 1/5 as double-doubles: hi = RN(1/m), lo = RN(1/m - hi) (relative
 // error 3.1e-33, checked by a host test with exact rationals)
@@ -91,23 +91,24 @@ LTGW_HD dd dd_mul_d(dd a, double b) {
     p.lo += a.lo * b;
     return fast_two_sum(p.hi, p.lo);
 }
-// e^Y for |Y.hi| < 700.
+// e^Y for |Y.hi| < 700.  Y = N ln2/256 + r with N = rint(Y 256/ln2), so
+// |r| <= ln2/512; e^Y = 2^k 2^(j/256) e^r with N = 256 k + j, 0 <= j < 256,
+// 2^(j/256) from a double-double table.
 LTGW_HD dd dd_exp(dd Y) {
-    double kf = std::rint(Y.hi * kInvLn2);
-    // Y - k ln2: k*ln2_1 is exact and Y.hi - k*ln2_1 is exact (Sterbenz)
-    double a = Y.hi - kf * kLn2_1;
+    const double nf = std::rint(Y.hi * (kInvLn2 * 256.0));
+    // N * head is exact (35-bit head, |N| < 2^18); Y.hi - N * head is exact
+    // too: both are multiples of the finer of their last bits and the
+    // difference is below 2^-9.5
+    const double a = Y.hi - nf * kLn2d256_1;
     dd r = two_sum(a, Y.lo);
-    dd kl2 = two_prod(kf, kLn2_2);
-    kl2.lo += kf * kLn2_3;
-    r = dd_add(r, dd{-kl2.hi, -kl2.lo});
-    // r in [-0.35, 0.35]; scale into |r| < 1.36e-3
-    r.hi *= 0x1p-8;
-    r.lo *= 0x1p-8;
-    // expm1(r) = r (1 + r/2 (1 + r/3 (... (1 + r/10)))).  The inner factors
-    // r/10 ... r/6 (...) are formed in FP64 from r.hi: their rounding reaches
-    // expm1(r) scaled by r^5/5! < 2^-54, i.e. below 2^-110 relative.  The
-    // outer four stay in double-double, dividing by 5 and 3 as products with
-    // double-double reciprocals (by 4 and 2 exactly).
+    dd nl = two_prod(nf, kLn2d256_2);
+    nl.lo += nf * kLn2d256_3;
+    r = dd_add(r, dd{-nl.hi, -nl.lo});
+    // expm1(r) = r (1 + r/2 (1 + r/3 (... (1 + r/10)))), |r| < 1.36e-3.  The
+    // inner factors r/10 ... r/6 (...) are formed in FP64 from r.hi: their
+    // rounding reaches expm1(r) scaled by r^5/5! < 2^-54, i.e. below 2^-110
+    // relative.  The outer four stay in double-double, dividing by 5 and 3 as
+    // products with double-double reciprocals (by 4 and 2 exactly).
     double q = r.hi * kRecip[10];
     for (int m = 9; m >= 6; --m) q = ((q + 1.0) * r.hi) * kRecip[m];
     dd p = dd_mul(dd_mul(two_sum(1.0, q), r), dd{kInv5_hi, kInv5_lo});
@@ -117,9 +118,10 @@ LTGW_HD dd dd_exp(dd Y) {
     p = dd_mul(dd_add_d(p, 1.0), r);
     p = {p.hi * 0.5, p.lo * 0.5};
     p = dd_mul(dd_add_d(p, 1.0), r);
-    for (int i = 0; i < 8; ++i) p = dd_mul(p, dd_add_d(p, 2.0));
-    dd e = dd_add_d(p, 1.0);
-    int k = (int)kf;
+    const int n = (int)nf;
+    const int jj = n & 255;       // the residue in [0, 256), also for n < 0
+    const int k = (n - jj) / 256;  // exact
+    const dd e = dd_mul(dd_add_d(p, 1.0), dd{kExp2Tab[jj][0], kExp2Tab[jj][1]});
     return {std::ldexp(e.hi, k), std::ldexp(e.lo, k)};
 }
 

@@ -8,6 +8,7 @@
 - without a GPU, ltgw_create fails with a message instead of crashing.
 """
 import ctypes as C
+import math
 import os
 import re
 import subprocess
@@ -91,20 +92,32 @@ int main(void) {
                 assert int(val) == getattr(cls, key.split(".")[1]).offset, key
 
 
-def test_ln2_split_constants():
+EXP2 = os.path.join(ROOT, "paper_2507_07816_amd", "csrc", "exp2_table.h")
+
+
+def test_exp2_table_and_ln2_split():
+    """ln 2 / 256 = head (35 significant bits: N * head is exact for |N| < 2^18)
+    + two tails, each the nearest double of the remainder; 2^(j/256) as
+    double-doubles hi = RN(x), lo = RN(x - hi); against 60-digit decimals."""
     getcontext().prec = 60
-    src = open(DDPOW).read()
+    src = open(EXP2).read()
     vals = {m.group(1): float.fromhex(m.group(2))
-            for m in re.finditer(r"constexpr double (kLn2_\d) = (0x[0-9a-fp.+-]+);", src)}
-    assert set(vals) == {"kLn2_1", "kLn2_2", "kLn2_3"}
-    ln2 = Fraction(Decimal(2).ln())
-    a1 = Fraction(vals["kLn2_1"])
-    # 42 significant bits: k * ln2_1 is exact for |k| < 2^11
-    assert (a1 * 2 ** 42).denominator == 1
-    assert vals["kLn2_2"] == float(ln2 - a1)
-    assert vals["kLn2_3"] == float(ln2 - a1 - Fraction(vals["kLn2_2"]))
-    resid = ln2 - a1 - Fraction(vals["kLn2_2"]) - Fraction(vals["kLn2_3"])
-    assert abs(float(resid)) < 2.0 ** -150
+            for m in re.finditer(r"constexpr double (kLn2d256_\d) = (-?0x[0-9a-fp.+-]+);", src)}
+    assert set(vals) == {"kLn2d256_1", "kLn2d256_2", "kLn2d256_3"}
+    c = Fraction(Decimal(2).ln()) / 256
+    h1 = Fraction(vals["kLn2d256_1"])
+    m, e = math.frexp(vals["kLn2d256_1"])
+    assert (Fraction(m) * 2 ** 35).denominator == 1
+    assert vals["kLn2d256_2"] == float(c - h1)
+    assert vals["kLn2d256_3"] == float(c - h1 - Fraction(vals["kLn2d256_2"]))
+    assert abs(float(c - h1 - Fraction(vals["kLn2d256_2"]) - Fraction(vals["kLn2d256_3"]))) < 2.0 ** -150
+    rows = re.findall(r"\{(-?0x[0-9a-fp.+-]+), (-?0x[0-9a-fp.+-]+)\},", src)
+    assert len(rows) == 256
+    for j in (0, 1, 2, 17, 64, 128, 200, 255):
+        x = Fraction(Decimal(2) ** (Decimal(j) / Decimal(256)))
+        hi, lo = float.fromhex(rows[j][0]), float.fromhex(rows[j][1])
+        assert hi == float(x) and lo == float(x - Fraction(hi))
+    assert all(float.fromhex(h) * 2 > 1.99 for h, _ in rows[128:])
 
 
 def test_reciprocal_constants():
