@@ -87,6 +87,21 @@ def measured_list_fp64():
     return t["fp64_lane_instructions_per_eval"]
 
 
+def measured_valu(workload, store, variant):
+    """VALU lane-instructions per template x segment evaluation of the
+    statistic kernel from the committed counter summary (same kernel source,
+    workload, store and tile shape), or None."""
+    path = os.path.join(ROOT, "profiles", "eval_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if (t.get("source_sha256") != kernel_source_hash() or t.get("workload") != workload
+            or t.get("store") != store or t.get("variant") != variant):
+        return None
+    return t.get("valu_lane_instructions_per_eval")
+
+
 def cpu_baseline(wl, rho, target_s=15.0):
     """Oracle throughput on this host over a bounded sample of the workload:
     whole (tau, n) groups of all f0, all segments.  Returns the JSON object."""
@@ -163,8 +178,8 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
     return out
 
 
-# FP64 vector instruction issue of the chip: 256 CUs x 64 lanes x 2.4 GHz
-# (the 78.6 TFLOP/s FP64 peak counts each FMA as 2 flops)
+# vector instruction issue of the chip: 256 CUs x 64 lanes x 2.4 GHz (FP64
+# included: the 78.6 TFLOP/s FP64 peak counts each FMA as 2 flops)
 FP64_LANE_OPS = 256 * 64 * 2.4e9
 
 
@@ -486,6 +501,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(wl.name, args.store, int(dg["tile_shape"]))},
     }
+    valu = measured_valu(wl.name, args.store, int(dg["tile_shape"]))
+    if valu:
+        # the second bound: VALU issue at the kernel's counted instructions per evaluation
+        kernel_rate = evals / (kms * 1e-3)
+        ceiling = FP64_LANE_OPS / valu
+        out["second_bound"] = {"bound": "valu", "instructions_per_eval": valu, "achieved_evals_per_s": kernel_rate,
+                               "peak_evals_per_s": ceiling, "frac": kernel_rate / ceiling}
     if not args.no_antenna:
         print("[bench] antenna-pattern weights", file=sys.stderr, flush=True)
         out["antenna"] = antenna_leg(torch, ltgw, ctx, wl, power, t_seg, v, w, args.store)
