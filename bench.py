@@ -255,10 +255,16 @@ def antenna_leg(torch, ltgw, ctx, wl, power, t_seg, v, w, store, steps=5):
     torch.cuda.synchronize()
     el = time.perf_counter() - t
     ctx.set_antenna(0, None)
+    kms_mean = float(np.mean(kms))
+    launches = max(int(dg["eval_launches"]), 1)
+    alg_bytes = dg["in_band"] * BYTES[store] / launches
+    achieved = alg_bytes / (kms_mean / launches * 1e-3) / 1e9
     return {"workload": f"{wl.name} with H-site antenna-pattern weights", "steps": steps,
             "value": dg["evals"] * steps / el, "unit": "template·segment evals/s", "ms_per_step": el * 1e3 / steps,
-            "eval_kernel_ms": float(np.mean(kms)), "eval_launches_per_step": int(dg["eval_launches"]),
-            "tile_shape": int(dg["tile_shape"])}
+            "eval_kernel_ms": kms_mean, "eval_launches_per_step": launches,
+            "tile_shape": int(dg["tile_shape"]),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes}}
 
 
 def campaign_leg(torch, ltgw, R_noise=128, amps=(1.0, 1.5, 2.0, 2.5, 3.0, 4.0), per_level=32, seed=2024):
@@ -292,6 +298,8 @@ def campaign_leg(torch, ltgw, R_noise=128, amps=(1.0, 1.5, 2.0, 2.5, 3.0, 4.0), 
             wall = time.perf_counter() - t
             n_real = R_noise + len(amps) * per_level
             out[bank_name] = {"templates": int(wl.n_templates), "wall_s": wall, "realisations_per_s": n_real / wall,
+                              "bound": "host: one search per realisation through the C ABI, each a few ms of "
+                                       "calls around microseconds of kernels",
                               **{name: {"threshold": res["threshold"][name],
                                         "efficiency": [float(x) for x in res[name]["efficiency"]],
                                         "a90": res[name]["fit"]["a90"]} for name in ("power", "count")}}
