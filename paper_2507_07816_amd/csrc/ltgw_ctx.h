@@ -146,8 +146,8 @@ struct ltgw_ctx {
     int last_variant = 1;
     int last_launches = 0;  // statistic-kernel dispatches of the last eval
     bool list_mode = false;      // the last eval was an explicit template list
-    std::vector<ltgw_template> h_list;  // its templates (top-k records) ...
-    std::vector<int32_t> h_perm;        // ... and their evaluation order
+    std::vector<ltgw_template> h_list;  // host staging of its templates for the upload ...
+    std::vector<int32_t> h_perm;        // ... and of their evaluation order
     ltgw::DevBuf list_d, perm_d;
     // data preparation (ltgw_sft_normalise): window table, chunk buffers, FFT plans
     struct SftPlan {
