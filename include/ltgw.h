@@ -251,16 +251,17 @@ int32_t ltgw_topk_candidates(ltgw_ctx *ctx, uint32_t stat, int32_t k, ltgw_candi
  * S ln 2, so the median / ln 2 estimates the noise floor S).
  *   strain: device FP32 [n_seg * n_fft]; segment j is samples
  *           [j n_fft, (j + 1) n_fft) (no overlap); n_fft = T_sft * sample rate.
- *   Window w_n = 1/2 - 1/2 cos(2 pi n / n_fft) (periodic Hann), rounded to
- *   FP32; the transform is FP32 (hipFFT, real to complex), X_k =
- *   sum_n x_n w_n e^{-2 pi i k n / n_fft}.
+ *   Window w_n = 1/2 - 1/2 cos(2 pi n / n_fft) (periodic Hann), applied in
+ *   frequency: with Y the FP32 transform of the raw segment (hipFFT, real to
+ *   complex, out of place: the strain is not written), X_k = Y_k/2 -
+ *   (Y_{k-1} + Y_{k+1})/4, which equals sum_n x_n w_n e^{-2 pi i k n / n_fft}.
  *   out: device FP32 [n_seg][n_bins], column b = bin k_lo + b (frequency
  *        k / T_sft), ready for ltgw_load_spectrogram.  A window whose median
  *        is 0 (e.g. zero strain) gives rho = 0.
  *   n_fft even, 2 .. 2^24; n_seg 1 .. 65535; window odd, 1 .. 257; the bins
  *   k_lo - window/2 .. k_lo + n_bins - 1 + window/2 must lie in 0 .. n_fft/2.
  * Non-finite strain propagates to rho (ltgw_load_spectrogram rejects it).
- * Works in chunks of segments with about 512 MB of scratch; FFT plans are
+ * Works in chunks of segments with about 512 MB of spectra; FFT plans are
  * kept per (n_fft, chunk).  Asynchronous.  Errors: INVALID_ARG (sizes,
  * host pointers), NOMEM, DEVICE. */
 int32_t ltgw_sft_normalise(ltgw_ctx *ctx, const float *strain, int32_t n_seg, int32_t n_fft, int64_t k_lo,

@@ -149,13 +149,12 @@ struct ltgw_ctx {
     std::vector<ltgw_template> h_list;  // host staging of its templates for the upload ...
     std::vector<int32_t> h_perm;        // ... and of their evaluation order
     ltgw::DevBuf list_d, perm_d;
-    // data preparation (ltgw_sft_normalise): window table, chunk buffers, FFT plans
+    // data preparation (ltgw_sft_normalise): spectra of a chunk, FFT plans
     struct SftPlan {
         int n_fft, batch;
         void *plan;  // hipfftHandle
     };
-    int sft_n_fft = 0;
-    ltgw::DevBuf sft_hann, sft_in, sft_spec;
+    ltgw::DevBuf sft_spec;
     std::vector<SftPlan> sft_plans;
     int forced_variant = -1;      // ltgw_set_tile_shape; -1 = autotuner
     ltgw::BatchState batch;

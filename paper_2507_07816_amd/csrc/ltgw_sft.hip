@@ -2,10 +2,12 @@
 // -> normalised power rho = P ln 2 / (running median of P over frequency).
 //
 // Segment j is samples [j N, (j + 1) N) of the strain.  Per chunk of segments:
-//   hann_kernel: x_n w_n with w_n = RN32(1/2 - 1/2 cos(2 pi n / N)) from a table;
-//   one batched real-to-complex FFT (hipFFT, FP32);
-//   normalise_kernel: P_k = re^2 + im^2 for a 256-bin tile of the band and its
-//   median halo, a bitonic sort of (P, position) in LDS, then each bin's median is the
+//   one batched real-to-complex FFT (hipFFT, FP32) of the raw segments;
+//   normalise_kernel: the Hann window applied in frequency: with the periodic
+//   window w_n = 1/2 - 1/2 cos(2 pi n / N) = 1/2 - e^{2 pi i n/N}/4 - e^{-2 pi i n/N}/4
+//   the windowed transform is X_k/2 - (X_{k-1} + X_{k+1})/4 (X_{-1} = conj X_1 and
+//   X_{N/2+1} = conj X_{N/2-1} for real input); P_k = |.|^2 for a 256-bin tile of the band
+//   and its median halo, a bitonic sort of (P, position) in LDS, then each bin's median is the
 //   (h + 1)-th smallest value whose position lies in its window, found by one
 //   scan of the sorted tile (every lane reads the same sorted entry at each
 //   step: an LDS broadcast).  Under Gaussian noise P_k is exponential with
@@ -27,22 +29,22 @@ constexpr int kSftTile = 256;      // output bins per workgroup
 constexpr int kSftSort = 512;      // sorted entries: tile + halo, padded to a power of two
 constexpr int kSftMaxWindow = kSftSort - kSftTile + 1;  // 257
 
-__global__ __launch_bounds__(256) void hann_table_kernel(int n_fft, float *w) {
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= n_fft) return;
-    const double c = cos(2.0 * M_PI * (double)n / (double)n_fft);
-    w[n] = (float)(0.5 - 0.5 * c);
-}
-
-__global__ __launch_bounds__(256) void hann_kernel(const float *__restrict__ x, int64_t n_total, int n_fft,
-                                                   const float *__restrict__ w, float *__restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_total; i += (int64_t)gridDim.x * 256)
-        out[i] = x[i] * w[i % n_fft];
-}
-
 // One workgroup: segment blockIdx.y, output bins [t0, t0 + 256) of the band;
 // lane t takes bin t0 + t.  (Wider tiles that fill all 512 sorted entries
 // were measured slower: the per-bin scans, not the sort, dominate.)
+__device__ __forceinline__ float2 spec_at(const float2 *row, int64_t k, int64_t half) {
+    // X_{-1} = conj X_1, X_{half+1} = conj X_{half-1} (real input)
+    if (k < 0) {
+        const float2 z = row[-k];
+        return make_float2(z.x, -z.y);
+    }
+    if (k > half) {
+        const float2 z = row[2 * half - k];
+        return make_float2(z.x, -z.y);
+    }
+    return row[k];
+}
+
 __global__ __launch_bounds__(256) void normalise_kernel(const float2 *__restrict__ spec, int64_t spec_pitch,
                                                         int64_t k_lo, int n_bins, int h, float *__restrict__ out) {
     __shared__ float val[kSftSort];
@@ -60,9 +62,13 @@ __global__ __launch_bounds__(256) void normalise_kernel(const float2 *__restrict
     for (int p = t; p < kSftSort; p += 256) {
         float v = __builtin_inff();
         if (p < n_pos && p <= last_needed) {
-            const float2 z = row[k_lo + t0 - h + p];
-            const float a = z.x * z.x;
-            const float b = z.y * z.y;
+            const int64_t k = k_lo + t0 - h + p;
+            const int64_t half = spec_pitch - 1;
+            const float2 z = row[k], zm = spec_at(row, k - 1, half), zp = spec_at(row, k + 1, half);
+            const float re = 0.5f * z.x - 0.25f * (zm.x + zp.x);
+            const float im = 0.5f * z.y - 0.25f * (zm.y + zp.y);
+            const float a = re * re;
+            const float b = im * im;
             v = a + b;
         }
         val[p] = v;
@@ -120,10 +126,7 @@ __global__ __launch_bounds__(256) void normalise_kernel(const float2 *__restrict
 void sft_release(ltgw_ctx *c) {
     for (auto &pl : c->sft_plans) (void)hipfftDestroy((hipfftHandle)pl.plan);
     c->sft_plans.clear();
-    release(c->sft_hann);
-    release(c->sft_in);
     release(c->sft_spec);
-    c->sft_n_fft = 0;
 }
 
 }  // namespace ltgw
@@ -163,18 +166,9 @@ int32_t ltgw_sft_normalise(ltgw_ctx *c, const float *strain, int32_t n_seg, int3
     if (n_bins < 1 || k_lo < h || k_lo + n_bins - 1 + h > n_fft / 2)
         return fail(c, LTGW_E_INVALID_ARG, "band [k_lo - window/2, k_lo + n_bins - 1 + window/2] must lie in 0 .. n_fft/2");
     int rc;
-    // the window table, for this n_fft
-    if (c->sft_n_fft != n_fft) {
-        if ((rc = ensure(c, c->sft_hann, (size_t)n_fft * 4, "Hann window")) != LTGW_OK) return rc;
-        hipLaunchKernelGGL(hann_table_kernel, dim3((n_fft + 255) / 256), dim3(256), 0, c->stream, n_fft,
-                           (float *)c->sft_hann.p);
-        HIP_TRY(c, hipGetLastError(), "Hann table launch");
-        c->sft_n_fft = n_fft;
-    }
-    // chunks of segments: windowed input and spectrum within about 512 MB
-    const int64_t per_seg = (int64_t)n_fft * 4 + (int64_t)(n_fft / 2 + 1) * 8;
+    // chunks of segments: spectra within about 512 MB
+    const int64_t per_seg = (int64_t)(n_fft / 2 + 1) * 8;
     int batch = (int)std::max<int64_t>(1, std::min<int64_t>(n_seg, ((int64_t)512 << 20) / per_seg));
-    if ((rc = ensure(c, c->sft_in, (size_t)batch * n_fft * 4, "windowed segments")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->sft_spec, (size_t)batch * (n_fft / 2 + 1) * 8, "spectra")) != LTGW_OK) return rc;
     for (int j0 = 0; j0 < n_seg; j0 += batch) {
         const int nb = std::min(batch, n_seg - j0);
@@ -189,15 +183,11 @@ int32_t ltgw_sft_normalise(ltgw_ctx *c, const float *strain, int32_t n_seg, int3
             if (r != HIPFFT_SUCCESS) return fail(c, LTGW_E_DEVICE, "FFT plan: %s", fft_error(r));
             c->sft_plans.push_back({n_fft, nb, (void *)plan});
         }
-        const int64_t n_total = (int64_t)nb * n_fft;
-        const int64_t blocks = std::min<int64_t>((n_total + 255) / 256, 65536);
-        hipLaunchKernelGGL(hann_kernel, dim3((unsigned)blocks), dim3(256), 0, c->stream,
-                           strain + (int64_t)j0 * n_fft, n_total, n_fft, (const float *)c->sft_hann.p,
-                           (float *)c->sft_in.p);
-        HIP_TRY(c, hipGetLastError(), "window launch");
+        // out-of-place real-to-complex: the caller's strain is read, not written
         hipfftResult r = hipfftSetStream(plan, c->stream);
         if (r == HIPFFT_SUCCESS)
-            r = hipfftExecR2C(plan, (hipfftReal *)c->sft_in.p, (hipfftComplex *)c->sft_spec.p);
+            r = hipfftExecR2C(plan, const_cast<hipfftReal *>(strain + (int64_t)j0 * n_fft),
+                              (hipfftComplex *)c->sft_spec.p);
         if (r != HIPFFT_SUCCESS) return fail(c, LTGW_E_DEVICE, "FFT: %s", fft_error(r));
         hipLaunchKernelGGL(normalise_kernel, dim3((unsigned)((n_bins + kSftTile - 1) / kSftTile), (unsigned)nb),
                            dim3(256), 0, c->stream, (const float2 *)c->sft_spec.p, (int64_t)(n_fft / 2 + 1), k_lo,
