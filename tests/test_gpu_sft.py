@@ -103,3 +103,22 @@ def test_zero_strain_and_errors():
         assert float(out.abs().max()) == 0.0
     finally:
         ctx.close()
+
+
+def test_strain_is_not_written():
+    """The transform reads the caller's strain out of place: a second call on
+    the same strain gives the same rho, and the strain is unchanged."""
+    import torch
+    from paper_2507_07816_amd import ltgw
+
+    r = np.random.default_rng(65)
+    x = r.normal(size=8192 * 6).astype(np.float32)
+    ctx = ltgw.Context(0)
+    try:
+        dev = torch.from_numpy(x).cuda()
+        a = ctx.sft_normalise(dev, 8192, 1000, 2000, 101).cpu().numpy()
+        b = ctx.sft_normalise(dev, 8192, 1000, 2000, 101).cpu().numpy()
+        assert np.array_equal(dev.cpu().numpy(), x)
+        assert np.array_equal(a, b)
+    finally:
+        ctx.close()
