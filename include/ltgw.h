@@ -530,6 +530,20 @@ int32_t ltgw_propose(ltgw_ctx *ctx, const ltgw_grid *fine, const ltgw_grid *coar
  * Synchronous.  Errors: STATE (not loaded), INVALID_ARG, DEVICE. */
 int32_t ltgw_read_store(ltgw_ctx *ctx, int32_t det, void *out_host, float *scale_host);
 
+/* ltgw_read_tables: copy the per-segment track tables that the last
+ * ltgw_eval_templates built for detector det to host memory, for inspection:
+ *   g_host: FP64 [n_brake * n_tau][n_seg], row i_n * n_tau + i_tau, the spin-down
+ *           factor g = RN(u^e) of Eq. 1 (u = 1 + (t_j - T0)/tau, e = 1/(1 - n);
+ *           0 where t_j < T0), or NULL;
+ *   h_host: FP64 [n_sky * n_brake * n_tau][n_seg], row (sky * n_brake + i_n) *
+ *           n_tau + i_tau, the bin-scaled track factor RN(RN(g D) t_sft) with
+ *           D = 1 + v.n/c of Eq. 2, or NULL;
+ *   n_rows: host int32[2] receiving the two row counts, or NULL.
+ * Buffers are caller-owned and must hold the row counts of the last eval's
+ * grid.  Synchronous.  Errors: STATE (no eval used det since it was loaded),
+ * INVALID_ARG, DEVICE. */
+int32_t ltgw_read_tables(ltgw_ctx *ctx, int32_t det, double *g_host, double *h_host, int32_t *n_rows);
+
 #ifdef __cplusplus
 }
 #endif

@@ -230,6 +230,7 @@ int32_t ltgw_load_spectrogram(ltgw_ctx *c, int32_t det, const ltgw_spec_desc *d,
     D.loaded = false;
     D.has_v = false;
     D.has_antenna = false;
+    D.tab_n_tn = D.tab_n_groups = 0;
     const int64_t ns = d->n_seg, nb = d->n_bins;
     std::vector<double> ht(ns);
     std::vector<float> hw(ns, 1.0f);
@@ -493,10 +494,53 @@ std::string tune_key_batch(int store, bool moments_in_loop, int n_searches, int6
 
 namespace {
 
-// The single-search evaluation; variant < 0 takes the tuned (or default) shape.
+// Device memory of one single-search evaluation: the context's own buffers,
+// grown on demand, or consecutive 256-byte aligned slices of the device's
+// static scratch array (the no-allocation entry point).  In scratch mode the
+// caller has checked the total (eval_bytes) before anything is enqueued.
+struct EvalMem {
+    ltgw_ctx *c;
+    char *base = nullptr;  // scratch base (device address), or NULL: context buffers
+    size_t used = 0;
+    int get(DevBuf &b, size_t bytes, const char *what, void **p) {
+        if (!base) {
+            const int rc = ensure(c, b, bytes, what);
+            *p = b.p;
+            return rc;
+        }
+        used = (used + 255) & ~(size_t)255;
+        *p = base + used;
+        used += bytes ? bytes : 16;
+        return LTGW_OK;
+    }
+};
+
+// Bytes of scratch the evaluation of plan P takes (every table, window,
+// moment array and per-template result), each slice rounded up to 256.
+size_t eval_bytes(const ltgw_ctx *c, const SearchPlan &P, const Moments &M, const ltgw_grid *g) {
+    auto r = [](size_t b) { return ((b ? b : 16) + 255) & ~(size_t)255; };
+    size_t t = r((size_t)g->n_tau * 8) + r((size_t)g->n_brake * 8) + r((size_t)g->n_sky * 24);
+    const size_t win_blocks = (size_t)(g->n_f0 + 255) / 256;
+    for (int q = 0; q < P.n_sel; ++q) {
+        const Det &D = c->det[P.sel[q]];
+        t += r((size_t)P.n_tn * D.n_seg * 8) + r((size_t)P.n_groups * D.n_seg * 8);
+        if (D.has_antenna) t += 2 * r((size_t)g->n_sky * D.n_seg * 4);
+        if (M.mode == 1) t += r((size_t)D.n_seg * 3 * 8);
+        t += r((size_t)P.n_groups * win_blocks * sizeof(int2));
+    }
+    const size_t n = (size_t)P.n_tpl;
+    t += r(n * 8) + r(n * 4) + r(n * 4) + r(n * 8) + r(n * 8);
+    if (M.mode != 2) t += r((size_t)(M.mode ? 4 : 1) * (size_t)P.n_groups * (size_t)(g->n_f0 + 1) * 8);
+    return t;
+}
+
+// The single-search evaluation; variant < 0 takes the tuned (or default)
+// shape.  scratch != NULL: every buffer is a slice of it (no allocation) and
+// the results are not kept for ltgw_psi / ltgw_topk_candidates.
 int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, int32_t *out_c,
-                int32_t *out_n, int variant) {
+                int32_t *out_n, int variant, void *scratch = nullptr, size_t scratch_cap = 0) {
     c->have_eval = false;
+    c->results_kept = false;
     if (!g) return fail(c, LTGW_E_INVALID_ARG, "grid is NULL");
     if (stats == 0 || (stats & ~(LTGW_STAT_POWER | LTGW_STAT_COUNT)))
         return fail(c, LTGW_E_INVALID_ARG, "stats must be a non-empty mask of POWER and COUNT");
@@ -515,35 +559,51 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     HIP_TRY(c, hipEventSynchronize(c->ev_h2d), "previous grid upload");
     const Moments M = plan_moments(c, P.sel, P.n_sel);
     const bool moments_in_loop = M.mode == 2;
+    EvalMem mem{c};
+    if (scratch) {
+        const size_t need = eval_bytes(c, P, M, g);
+        if (need > scratch_cap)
+            return fail(c, LTGW_E_UNSUPPORTED,
+                        "this search needs %zu bytes of device scratch; the no-allocation entry point "
+                        "has %zu (use ltgw_eval_templates)",
+                        need, scratch_cap);
+        mem.base = (char *)scratch;
+    }
     c->h_tau.assign(g->tau, g->tau + g->n_tau);
     c->h_brake.assign(g->brake, g->brake + g->n_brake);
     c->h_sky.assign(g->sky, g->sky + 3 * (size_t)g->n_sky);
-    if ((rc = ensure(c, c->tau_d, c->h_tau.size() * 8, "tau")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, c->brake_d, c->h_brake.size() * 8, "brake")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, c->sky_d, c->h_sky.size() * 8, "sky")) != LTGW_OK) return rc;
-    if ((rc = h2d(c, c->tau_d.p, c->h_tau.data(), c->h_tau.size() * 8, "tau upload")) != LTGW_OK) return rc;
-    if ((rc = h2d(c, c->brake_d.p, c->h_brake.data(), c->h_brake.size() * 8, "brake upload")) != LTGW_OK) return rc;
-    if ((rc = h2d(c, c->sky_d.p, c->h_sky.data(), c->h_sky.size() * 8, "sky upload")) != LTGW_OK) return rc;
+    void *tau_p, *brake_p, *sky_p;
+    if ((rc = mem.get(c->tau_d, c->h_tau.size() * 8, "tau", &tau_p)) != LTGW_OK) return rc;
+    if ((rc = mem.get(c->brake_d, c->h_brake.size() * 8, "brake", &brake_p)) != LTGW_OK) return rc;
+    if ((rc = mem.get(c->sky_d, c->h_sky.size() * 8, "sky", &sky_p)) != LTGW_OK) return rc;
+    if ((rc = h2d(c, tau_p, c->h_tau.data(), c->h_tau.size() * 8, "tau upload")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, brake_p, c->h_brake.data(), c->h_brake.size() * 8, "brake upload")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, sky_p, c->h_sky.data(), c->h_sky.size() * 8, "sky upload")) != LTGW_OK) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream), "event record");
     EvalArgs a;
     std::memset(&a, 0, sizeof a);
     for (int q = 0; q < P.n_sel; ++q) {
         Det &D = c->det[P.sel[q]];
-        if ((rc = ensure(c, D.g, (size_t)P.n_tn * D.n_seg * 8, "spin-factor table")) != LTGW_OK) return rc;
-        if ((rc = ensure(c, D.H, (size_t)P.n_groups * D.n_seg * 8, "track-factor table")) != LTGW_OK) return rc;
-        HIP_TRY(c, launch_spin_factor((const double *)D.t_seg.p, D.n_seg, g->t0, (const double *)c->tau_d.p,
-                                      g->n_tau, (const double *)c->brake_d.p, g->n_brake, (double *)D.g.p,
+        D.tab_n_tn = D.tab_n_groups = 0;  // the tables below are the last eval's once filled
+        void *g_p, *H_p;
+        if ((rc = mem.get(D.g, (size_t)P.n_tn * D.n_seg * 8, "spin-factor table", &g_p)) != LTGW_OK) return rc;
+        if ((rc = mem.get(D.H, (size_t)P.n_groups * D.n_seg * 8, "track-factor table", &H_p)) != LTGW_OK) return rc;
+        HIP_TRY(c, launch_spin_factor((const double *)D.t_seg.p, D.n_seg, g->t0, (const double *)tau_p,
+                                      g->n_tau, (const double *)brake_p, g->n_brake, (double *)g_p,
                                       (unsigned long long *)c->counters.p + kCntUndecided, c->stream),
                 "spin-factor launch");
-        HIP_TRY(c, launch_track_factor((const double *)D.g.p, P.n_tn, (const double *)D.v.p, D.n_seg,
-                                       (const double *)c->sky_d.p, g->n_sky, D.t_sft, (double *)D.H.p,
-                                       c->stream),
+        HIP_TRY(c, launch_track_factor((const double *)g_p, P.n_tn, (const double *)D.v.p, D.n_seg,
+                                       (const double *)sky_p, g->n_sky, D.t_sft, (double *)H_p, c->stream),
                 "track-factor launch");
+        if (!scratch) {
+            D.tab_n_tn = P.n_tn;
+            D.tab_n_groups = (int32_t)P.n_groups;
+        }
         DetView &V = a.det[q];
         V.store = D.store_buf.p;
         V.pitch_bytes = (int32_t)(D.pitch * (D.store == LTGW_STORE_F32 ? 4 : D.store == LTGW_STORE_BF16 ? 2 : 1));
-        V.H = (const double *)D.H.p;
-        V.g = (const double *)D.g.p;
+        V.H = (const double *)H_p;
+        V.g = (const double *)g_p;
         V.D = nullptr;
         V.t_sft = D.t_sft;
         V.wq = (const float *)D.wq.p;
@@ -555,41 +615,46 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
         V.w_sky_stride = 0;
         if (D.has_antenna) {  // one row of weights per sky point of the grid
             const size_t nw = (size_t)g->n_sky * (size_t)D.n_seg;
-            if ((rc = ensure(c, D.w_sky, nw * 4, "antenna weights")) != LTGW_OK) return rc;
-            if ((rc = ensure(c, D.wq_sky, nw * 4, "antenna weights")) != LTGW_OK) return rc;
+            void *ws_p, *wqs_p;
+            if ((rc = mem.get(D.w_sky, nw * 4, "antenna weights", &ws_p)) != LTGW_OK) return rc;
+            if ((rc = mem.get(D.wq_sky, nw * 4, "antenna weights", &wqs_p)) != LTGW_OK) return rc;
             Arms A;
             std::memcpy(A.a, D.arms, sizeof A.a);
             std::memcpy(A.b, D.arms + 3, sizeof A.b);
-            HIP_TRY(c, launch_antenna_weights(A, (const double *)D.era.p, D.n_seg, (const double *)c->sky_d.p,
+            HIP_TRY(c, launch_antenna_weights(A, (const double *)D.era.p, D.n_seg, (const double *)sky_p,
                                               g->n_sky, (const float *)D.w.p, (const float *)D.scale.p,
-                                              (float *)D.w_sky.p, (float *)D.wq_sky.p, c->stream),
+                                              (float *)ws_p, (float *)wqs_p, c->stream),
                     "antenna weight launch");
-            V.w = (const float *)D.w_sky.p;
-            V.wq = (const float *)D.wq_sky.p;
+            V.w = (const float *)ws_p;
+            V.wq = (const float *)wqs_p;
             V.w_sky_stride = D.n_seg;
         }
         if (M.mode == 1) {
-            if ((rc = ensure(c, D.wfix, D.h_wfix.size() * 8, "fixed-point weights")) != LTGW_OK) return rc;
-            if ((rc = h2d(c, D.wfix.p, D.h_wfix.data(), D.h_wfix.size() * 8, "weights upload")) != LTGW_OK)
+            void *wf_p;
+            if ((rc = mem.get(D.wfix, D.h_wfix.size() * 8, "fixed-point weights", &wf_p)) != LTGW_OK) return rc;
+            if ((rc = h2d(c, wf_p, D.h_wfix.data(), D.h_wfix.size() * 8, "weights upload")) != LTGW_OK)
                 return rc;
-            V.wfix = (const int64_t *)D.wfix.p;
+            V.wfix = (const int64_t *)wf_p;
         }
-        // in-band segment windows of every (group, run of 64 f0)
+        // in-band segment windows of every (group, run of 256 f0)
         V.win_run = 256;  // the statistic kernel's tiles are whole multiples of 256 f0
         V.win_blocks = (g->n_f0 + 255) / 256;
-        if ((rc = ensure(c, D.win, (size_t)P.n_groups * V.win_blocks * sizeof(int2), "segment windows")) != LTGW_OK)
+        void *win_p;
+        if ((rc = mem.get(D.win, (size_t)P.n_groups * V.win_blocks * sizeof(int2), "segment windows", &win_p)) !=
+            LTGW_OK)
             return rc;
-        V.win = (const int2 *)D.win.p;
-        HIP_TRY(c, launch_windows(V, (int)P.n_groups, P.n_tn, g->f0_min, g->f0_step, g->n_f0, (int2 *)D.win.p,
+        V.win = (const int2 *)win_p;
+        HIP_TRY(c, launch_windows(V, (int)P.n_groups, P.n_tn, g->f0_min, g->f0_step, g->n_f0, (int2 *)win_p,
                                   c->stream),
                 "window launch");
     }
     const int64_t n_tpl = P.n_tpl;
-    if ((rc = ensure(c, c->res_s, n_tpl * 8, "results s")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, c->res_c, n_tpl * 4, "results c")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, c->res_n, n_tpl * 4, "results N")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, c->res_w1, n_tpl * 8, "results W1")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, c->res_w2, n_tpl * 8, "results W2")) != LTGW_OK) return rc;
+    void *s_p, *c_p, *n_p, *w1_p, *w2_p;
+    if ((rc = mem.get(c->res_s, n_tpl * 8, "results s", &s_p)) != LTGW_OK) return rc;
+    if ((rc = mem.get(c->res_c, n_tpl * 4, "results c", &c_p)) != LTGW_OK) return rc;
+    if ((rc = mem.get(c->res_n, n_tpl * 4, "results N", &n_p)) != LTGW_OK) return rc;
+    if ((rc = mem.get(c->res_w1, n_tpl * 8, "results W1", &w1_p)) != LTGW_OK) return rc;
+    if ((rc = mem.get(c->res_w2, n_tpl * 8, "results W2", &w2_p)) != LTGW_OK) return rc;
     if ((rc = zero_counter(c, kCntInBand, 1)) != LTGW_OK) return rc;
     a.n_det = P.n_sel;
     a.n_f0 = g->n_f0;
@@ -598,11 +663,11 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     a.f0_min = g->f0_min;
     a.f0_step = g->f0_step;
     a.w_uniform = M.w_uniform;
-    a.s = (double *)c->res_s.p;
-    a.c = (int32_t *)c->res_c.p;
-    a.n = (int32_t *)c->res_n.p;
-    a.w1 = (double *)c->res_w1.p;
-    a.w2 = (double *)c->res_w2.p;
+    a.s = (double *)s_p;
+    a.c = (int32_t *)c_p;
+    a.n = (int32_t *)n_p;
+    a.w1 = (double *)w1_p;
+    a.w2 = (double *)w2_p;
     a.out_s = out_s;
     a.out_c = out_c;
     a.out_n = out_n;
@@ -620,10 +685,11 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     } join{c};
     if (!moments_in_loop) {
         const size_t n_diff = (size_t)(M.mode ? 4 : 1) * (size_t)P.n_groups * (size_t)(g->n_f0 + 1);
-        if ((rc = ensure(c, c->diff, n_diff * 8, "moment difference arrays")) != LTGW_OK) return rc;
+        void *diff_p;
+        if ((rc = mem.get(c->diff, n_diff * 8, "moment difference arrays", &diff_p)) != LTGW_OK) return rc;
         HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream), "event record");
         HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "stream wait");
-        const hipError_t me = launch_moments(a, M.mode, M.e0, (int64_t *)c->diff.p, c->side);
+        const hipError_t me = launch_moments(a, M.mode, M.e0, (int64_t *)diff_p, c->side);
         const hipError_t je = hipEventRecord(c->ev_join, c->side);
         join.on = je == hipSuccess;
         HIP_TRY(c, me, "moments launch");
@@ -641,6 +707,7 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     c->last_launches = launches;
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream), "event record");
     c->have_eval = true;
+    c->results_kept = scratch == nullptr;
     c->list_mode = false;
     c->last_variant = variant;
     c->n_templates = n_tpl;
@@ -778,6 +845,7 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
     HIP_TRY(c, launch_template_list(c->det[slots[0]].store, a, c->stream), "template list launch");
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream), "event record");
     c->have_eval = true;
+    c->results_kept = true;
     c->list_mode = true;
     c->last_variant = -1;
     c->last_launches = 1;
@@ -884,7 +952,7 @@ int32_t ltgw_tune_load(ltgw_ctx *c, const char *path) {
 int32_t ltgw_psi(ltgw_ctx *c, uint32_t stat, double *out) {
     if (!c) return LTGW_E_INVALID_ARG;
     Enter en(c);
-    if (!c->have_eval) return fail(c, LTGW_E_STATE, "no evaluation to rank");
+    if (!c->have_eval || !c->results_kept) return fail(c, LTGW_E_STATE, "no evaluation to rank");
     if (stat != LTGW_STAT_POWER && stat != LTGW_STAT_COUNT) return fail(c, LTGW_E_INVALID_ARG, "stat must be POWER or COUNT");
     if (!out) return fail(c, LTGW_E_INVALID_ARG, "out_psi is NULL");
     const double q = std::exp(-(double)c->rho_th);
@@ -899,7 +967,7 @@ int32_t ltgw_topk_candidates(ltgw_ctx *c, uint32_t stat, int32_t k, ltgw_candida
                              int32_t *n_out) {
     if (!c) return LTGW_E_INVALID_ARG;
     Enter en(c);
-    if (!c->have_eval) return fail(c, LTGW_E_STATE, "no evaluation to rank");
+    if (!c->have_eval || !c->results_kept) return fail(c, LTGW_E_STATE, "no evaluation to rank");
     if (stat != LTGW_STAT_POWER && stat != LTGW_STAT_COUNT) return fail(c, LTGW_E_INVALID_ARG, "stat must be POWER or COUNT");
     if (k < 1 || k > LTGW_MAX_TOPK) return fail(c, LTGW_E_INVALID_ARG, "k must be in 1..%d", LTGW_MAX_TOPK);
     if (!out_host || !n_out) return fail(c, LTGW_E_INVALID_ARG, "output pointers are NULL");
@@ -980,6 +1048,27 @@ int32_t ltgw_inject_track(ltgw_ctx *c, int32_t det, float *power, double f0, dou
                              sky3[1], sky3[2], t0, amp,
                              (unsigned long long *)c->counters.p + kCntUndecided, c->stream),
             "inject launch");
+    return LTGW_OK;
+}
+
+int32_t ltgw_read_tables(ltgw_ctx *c, int32_t det, double *g_host, double *h_host, int32_t *n_rows) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    if (det < 0 || det >= LTGW_MAX_DET) return fail(c, LTGW_E_INVALID_ARG, "detector %d out of range", det);
+    const Det &D = c->det[det];
+    if (!D.loaded || D.tab_n_tn == 0) return fail(c, LTGW_E_STATE, "detector %d has no tables of an evaluation", det);
+    if (n_rows) {
+        n_rows[0] = D.tab_n_tn;
+        n_rows[1] = D.tab_n_groups;
+    }
+    if (g_host)
+        HIP_TRY(c, hipMemcpyAsync(g_host, D.g.p, (size_t)D.tab_n_tn * D.n_seg * 8, hipMemcpyDeviceToHost, c->stream),
+                "spin-factor table download");
+    if (h_host)
+        HIP_TRY(c, hipMemcpyAsync(h_host, D.H.p, (size_t)D.tab_n_groups * D.n_seg * 8, hipMemcpyDeviceToHost,
+                                  c->stream),
+                "track-factor table download");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "table download");
     return LTGW_OK;
 }
 

@@ -32,6 +32,9 @@ struct Det {
     bool has_antenna = false;     // weights times the antenna response (ltgw_set_antenna)
     double arms[6] = {0, 0, 0, 0, 0, 0};
     DevBuf store_buf, t_seg, w, wq, scale, v, g, H, wfix, win, era, w_sky, wq_sky;
+    // shape of the Eq. 1 and Eq. 2 tables in g and H as the last single-search
+    // eval left them ([tab_n_tn][n_seg] and [tab_n_groups][n_seg]; 0: none)
+    int32_t tab_n_tn = 0, tab_n_groups = 0;
 };
 
 // How the in-band moments W1, W2 are formed for a set of detectors.
@@ -137,8 +140,9 @@ struct ltgw_ctx {
     int cu_count = 256;
     int wall_khz = 100000;        // device wall-clock rate
     std::map<std::string, int> tune;  // autotuner cache: key -> tile shape
-    // last single-search eval
-    bool have_eval = false;
+    // last single-search eval; results_kept: its per-template results are in
+    // res_* for ltgw_psi and ltgw_topk_candidates
+    bool have_eval = false, results_kept = false;
     int64_t n_templates = 0, n_evals = 0;
     double f0_min = 0.0, f0_step = 0.0;
     int32_t n_f0 = 0, n_tau = 0, n_brake = 0, n_sky = 0;

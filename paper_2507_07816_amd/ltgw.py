@@ -40,7 +40,7 @@ TILE_SHAPES = {0: (1, 8), 1: (1, 16), 2: (2, 8), 3: (2, 16)}  # (templates per l
 # every symbol include/ltgw.h declares
 EXPORTS = ("ltgw_create", "ltgw_destroy", "ltgw_last_error", "ltgw_load_spectrogram",
            "ltgw_set_velocity_table", "ltgw_set_antenna", "ltgw_sft_normalise", "ltgw_eval_templates", "ltgw_psi",
-           "ltgw_topk_candidates", "ltgw_diagnostics", "ltgw_inject_track", "ltgw_read_store",
+           "ltgw_topk_candidates", "ltgw_diagnostics", "ltgw_inject_track", "ltgw_read_store", "ltgw_read_tables",
            "ltgw_eval_batch", "ltgw_batch_results", "ltgw_batch_latency", "ltgw_autotune",
            "ltgw_set_tile_shape", "ltgw_tune_save", "ltgw_tune_load",
            "ltgw_generate_noise", "ltgw_inject_stack", "ltgw_load_stack", "ltgw_stack_psi",
@@ -131,6 +131,7 @@ def library():
             "ltgw_diagnostics": (i32, [P, C.POINTER(ltgw_diag)]),
             "ltgw_inject_track": (i32, [P, i32, P, d, d, d, P, d, f]),
             "ltgw_read_store": (i32, [P, i32, P, P]),
+            "ltgw_read_tables": (i32, [P, i32, P, P, P]),
             "ltgw_eval_batch": (i32, [P, P, i32, i32, P, P, P, P, C.POINTER(ltgw_batch_stats)]),
             "ltgw_batch_results": (i32, [P, i32, P, P, P, P, P]),
             "ltgw_batch_latency": (i32, [P, P]),
@@ -305,6 +306,17 @@ def ltgw_read_store(ctx, det, n_seg, n_bins, store):
     sc = np.empty(n_seg, np.float32)
     _check(ctx, library().ltgw_read_store(ctx, int(det), out.ctypes.data, sc.ctypes.data))
     return out, sc
+
+
+def ltgw_read_tables(ctx, det, n_seg):
+    """(g, H) tables of the last eval on detector slot `det` as FP64 numpy
+    arrays [rows][n_seg]."""
+    rows = (C.c_int32 * 2)()
+    _check(ctx, library().ltgw_read_tables(ctx, int(det), None, None, rows))
+    g = np.empty((rows[0], int(n_seg)), np.float64)
+    h = np.empty((rows[1], int(n_seg)), np.float64)
+    _check(ctx, library().ltgw_read_tables(ctx, int(det), g.ctypes.data, h.ctypes.data, None))
+    return g, h
 
 
 def ltgw_eval_batch(ctx, searches, k):
@@ -595,6 +607,9 @@ class Context:
     def read_store(self, det):
         n_seg, n_bins, store = self.shapes[det]
         return ltgw_read_store(self.h, det, n_seg, n_bins, store)
+
+    def read_tables(self, det):
+        return ltgw_read_tables(self.h, det, self.shapes[det][0])
 
     def eval_batch(self, searches, k=10):
         """searches: list of dicts with f0_min, f0_step, n_f0, tau, brake, sky, t0, dets."""

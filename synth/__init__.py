@@ -213,6 +213,32 @@ def batch_searches(seed=5, n_searches=64, t_sft=8.0):
     return out
 
 
+POOL_SIZE = 1 << 24
+
+
+def exp_pool(seed=5, size=POOL_SIZE):
+    """A pool of `size` FP32 Exp(1) values (exp_noise) from which the rows of
+    the many-search workload are cut."""
+    return exp_noise(1, size, seed)[0]
+
+
+def pool_offsets(search, det, n_seg, n_bins, seed=5, size=POOL_SIZE):
+    """Start of each row's window in the pool for detector `det` of search
+    `search`: independent uniform integers in [0, size - n_bins]."""
+    r = np.random.Generator(np.random.PCG64([seed, 1000 + search, det]))
+    return r.integers(0, size - n_bins + 1, n_seg)
+
+
+def pool_rows(pool, offsets, n_bins):
+    """The spectrogram whose row j is pool[offsets[j] : offsets[j] + n_bins]:
+    every pixel is one of the pool's Exp(1) values, and rows are windows at
+    independent random positions.  Works on numpy arrays and on torch tensors
+    (a device pool gives a device spectrogram with the same values)."""
+    if hasattr(pool, "unfold"):
+        return pool.unfold(0, int(n_bins), 1)[offsets].contiguous()
+    return np.lib.stride_tricks.sliding_window_view(pool, int(n_bins))[np.asarray(offsets)]
+
+
 def random_bank(n, f0_range, tau_range, brake_range, sky, seed=11):
     """The uniform random template bank of Sec. 2: n templates drawn uniformly
     (linearly) in f0, tau and the braking index over the given closed ranges,
