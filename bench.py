@@ -9,11 +9,18 @@ Workload (default): the realistic single search -- 10800 segments of 8 s
 U[0.5, 2] per-segment weights and 20 injected tracks; 8000 f0 x 32 tau x 9 n
 x 1 sky = 2,304,000 templates, i.e. 2.49e10 template x segment evaluations.
 
-Prints one JSON line.  The roofline object is for the statistic kernel:
-algorithmic bytes = in-band evaluations x stored bytes per element, over the
-kernel's average duration from HIP events recorded around its launch on the
-stream it runs on.  The CPU baseline is the FP64 oracle timed on this host's
-cores over a bounded sample of the same workload.
+Prints one JSON line.  The roofline object is for the statistic kernel, per
+launch: the HBM-side bytes its committed rocprofv3 counter runs measured
+(copy-calibrated FETCH_SIZE + WRITE_SIZE) over its average launch duration
+from HIP events recorded around its launches on the stream they run on,
+against the HBM peak; beside it the algorithmic bytes (in-band evaluations x
+stored bytes per element, mostly served by the caches) and the gather-path
+unit that binds.  Further legs: the same search with BF16 and FP8 stores,
+antenna-pattern weights, the uniform random bank, data preparation, the
+sensitivity campaign, the 64-search batch and the learned proposer.  The CPU
+baseline is the FP64 oracle timed on this host's cores over a bounded sample
+of the same workload (every template when that fits); the stores' errors
+against FP64 are taken on that sample.
 """
 import argparse
 import json
@@ -54,24 +61,6 @@ def kernel_source_hash(sources=KERNEL_SOURCES):
     return h.hexdigest()
 
 
-def measured_traffic(workload, store, variant):
-    """HBM-side bytes per statistic launch (the step's launches averaged) from
-    the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE runs,
-    each scaled by what the same counter reads for a device copy of known
-    size), or None when the summary is for another workload, store, variant or
-    kernel source."""
-    path = os.path.join(ROOT, "profiles", "eval_kernel_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        t = json.load(fh)
-    if (t.get("source_sha256") != kernel_source_hash() or t.get("workload") != workload
-            or t.get("store") != store or t.get("variant") != variant):
-        return None
-    per_step = (t["fetch_kib_per_step"] * t["fetch_scale"] + t["write_kib_per_step"] * t["write_scale"]) * 1024.0
-    return per_step / t["dispatches_per_step"]
-
-
 def measured_list_fp64():
     """Executed FP64 VALU lane-instructions per evaluation of the
     explicit-template kernel, from the committed rocprofv3 counter summary
@@ -102,9 +91,13 @@ def measured_valu(workload, store, variant):
     return t.get("valu_lane_instructions_per_eval")
 
 
-def cpu_baseline(wl, rho, target_s=15.0):
+def cpu_baseline(wl, rho, target_s=20.0, full_factor=1.5):
     """Oracle throughput on this host over a bounded sample of the workload:
-    whole (tau, n) groups of all f0, all segments.  Returns the JSON object."""
+    whole (tau, n) groups of all f0, all segments; every template when the
+    whole workload fits in full_factor x target_s.  Returns the JSON object
+    and the oracle's statistic of the sampled templates (index, s, c, N and
+    the critical ratios; with every template also its two top-10 lists), which
+    the precision report compares the device's stores against."""
     import oracle
 
     d = wl.dets[0]
@@ -118,17 +111,74 @@ def cpu_baseline(wl, rho, target_s=15.0):
     oracle.evaluate_list(det, grid, probe)
     dt = time.perf_counter() - t
     rate = probe.size * n_seg / dt
-    n_tpl = int(min(grid.n_templates, max(grid.n_f0, rate * target_s / n_seg)))
-    n_groups = max(1, n_tpl // grid.n_f0)
-    groups = np.linspace(0, grid.n_templates // grid.n_f0 - 1, n_groups).astype(np.int64)
-    idx = (groups[:, None] * grid.n_f0 + np.arange(grid.n_f0)[None, :]).ravel()
-    t = time.perf_counter()
-    oracle.evaluate_list(det, grid, idx)
-    dt = time.perf_counter() - t
-    return {"value": idx.size * n_seg / dt, "unit": "template·segment evals/s",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{n_groups} (tau, n) groups x {grid.n_f0} f0 x {n_seg} segments "
-                      f"({idx.size * n_seg:.3g} evals, {dt:.1f} s, FP64, incl. its Eq. 1 table)"}
+    n_all = grid.n_templates
+    full = n_all * n_seg / rate <= full_factor * target_s
+    n_groups_all = n_all // grid.n_f0
+    if full:
+        t = time.perf_counter()
+        res = oracle.evaluate(det, grid)
+        dt = time.perf_counter() - t
+        idx = np.arange(n_all, dtype=np.int64)
+        sample = f"every template: {n_groups_all} (tau, n) groups x {grid.n_f0} f0 x {n_seg} segments"
+    else:
+        n_tpl = int(min(n_all, max(grid.n_f0, rate * target_s / n_seg)))
+        n_groups = max(1, n_tpl // grid.n_f0)
+        groups = np.linspace(0, n_groups_all - 1, n_groups).astype(np.int64)
+        idx = (groups[:, None] * grid.n_f0 + np.arange(grid.n_f0)[None, :]).ravel()
+        t = time.perf_counter()
+        res = oracle.evaluate_list(det, grid, idx)
+        dt = time.perf_counter() - t
+        sample = f"{n_groups} (tau, n) groups x {grid.n_f0} f0 x {n_seg} segments"
+    ref = dict(idx=idx, s=res["s"], c=res["c"], N=res["N"], psi_power=oracle.psi_power(res),
+               psi_count=oracle.psi_count(res), full=full)
+    if full:
+        ref["top_power"] = [int(i) for i in oracle.topk(ref["psi_power"], 10)]
+        ref["top_count"] = [int(i) for i in oracle.topk(ref["psi_count"], 10)]
+        # largest change of a power ratio the float-sum tolerance allows (near-ties may swap)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ref["psi_tol"] = 1e-5 * np.abs(res["s"]) / np.sqrt(res["W2"])
+    out = {"value": idx.size * n_seg / dt, "unit": "template·segment evals/s",
+           "cores": oracle.threads(), "kind": "oracle", "cpu": cpu_model(),
+           "sample": f"{sample} ({idx.size * n_seg:.3g} evals, {dt:.1f} s, FP64, incl. its Eq. 1 table)"}
+    return out, ref
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def precision_report(ref, runs):
+    """Per-result error of each store's statistic against the FP64 oracle of
+    the CPU baseline (the same templates), and top-10 agreement.  runs: store
+    -> dict of the device's s (FP32 output), c, N over every template and its
+    top-10 lists."""
+    idx = ref["idx"]
+    out = {"reference": "FP64 oracle over " + ("every template" if ref["full"] else f"{idx.size} templates")}
+    for store, r in runs.items():
+        s = r["s"][idx].astype(np.float64)
+        nz = ref["s"] != 0
+        rel = np.abs(s[nz] - ref["s"][nz]) / np.abs(ref["s"][nz])
+        e = {"max_rel_s": float(rel.max()), "mean_rel_s": float(rel.mean()),
+             "n_mismatches": int(np.count_nonzero(r["N"][idx] != ref["N"])),
+             "count_mismatches": int(np.count_nonzero(r["c"][idx] != ref["c"]))}
+        if ref["full"]:
+            e["top10_count_identical"] = r["top_count"] == ref["top_count"]
+            e["top10_power_identical"] = r["top_power"] == ref["top_power"]
+            e["top10_power_same_set"] = sorted(r["top_power"]) == sorted(ref["top_power"])
+            # rank by rank within the ratio tolerance of the float sum
+            pp, tol = ref["psi_power"], ref["psi_tol"]
+            e["top10_power_within_tolerance"] = bool(all(
+                abs(pp[a] - pp[b]) <= 2 * max(tol[a], tol[b]) + 1e-12
+                for a, b in zip(r["top_power"], ref["top_power"])))
+        out[store] = e
+    return out
 
 
 def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_signal=4096, eval_noise=1024, seed=7,
@@ -263,8 +313,8 @@ def antenna_leg(torch, ltgw, ctx, wl, power, t_seg, v, w, store, steps=5):
             "value": dg["evals"] * steps / el, "unit": "template·segment evals/s", "ms_per_step": el * 1e3 / steps,
             "eval_kernel_ms": kms_mean, "eval_launches_per_step": launches,
             "tile_shape": int(dg["tile_shape"]),
-            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes}}
+            "algorithmic": {"gbs": achieved, "x_hbm_peak": achieved / HBM_PEAK_GBS, "bytes_per_launch": alg_bytes,
+                            "unit": "one stored element per in-band template x segment evaluation"}}
 
 
 def campaign_leg(torch, ltgw, R_noise=128, amps=(1.0, 1.5, 2.0, 2.5, 3.0, 4.0), per_level=32, seed=2024):
@@ -342,27 +392,30 @@ def sft_leg(torch, ltgw, n_seg=10800, n_fft=32768, k_lo=4000, n_bins=8000, windo
 def batch_leg(torch, ltgw, reps=2, seed=5):
     """The batch of 64 uneven searches (two detectors each, sky patches of 16 to
     1024 points, 1.76e13 template x segment evaluations) in one persistent,
-    graph-captured launch: aggregate evals/s, in-band fraction, % of the HBM
-    roofline of the persistent statistic launch, and per-search latency.
-    The power (Exp(1)) is generated on the device by the library."""
+    graph-captured launch: aggregate evals/s, in-band fraction, the persistent
+    statistic launch's time and per-search latency.  Every detector's power is
+    cut on the device from one seeded pool of Exp(1) values (synth.pool_rows,
+    the input the batch parity tests check against the oracle)."""
     import synth
 
     searches = synth.batch_searches(seed)
     ctx = ltgw.Context(0)
     dev = torch.device("cuda", 0)
+    pool = torch.from_numpy(synth.exp_pool(seed)).to(dev)
     specs = []
     slot = 0
     for i, srch in enumerate(searches):
         dets = []
-        for d in srch["dets"]:
-            p = torch.empty((d["n_seg"], d["n_bins"]), dtype=torch.float32, device=dev)
-            ltgw.ltgw_generate_noise(ctx.h, 1000003 + seed, 7, slot, p.view(1, -1))
+        for q, d in enumerate(srch["dets"]):
+            off = torch.from_numpy(synth.pool_offsets(i, q, d["n_seg"], d["n_bins"], seed)).to(dev)
+            p = synth.pool_rows(pool, off, d["n_bins"])
             ctx.load_spectrogram(slot, p, d["k_lo"], d["t_sft"], d["t_seg"], store="f32")
             ctx.set_velocity_table(slot, d["v"])
             del p
             dets.append(slot)
             slot += 1
         specs.append(dict(srch["grid"], dets=dets))
+    del pool
     torch.cuda.synchronize()
     t = time.perf_counter()
     top_p, top_c, st0 = ctx.eval_batch(specs, k=10)       # tunes the tile shape, captures the graph
@@ -376,15 +429,108 @@ def batch_leg(torch, ltgw, reps=2, seed=5):
     lat = ctx.batch_latency(len(specs))
     ctx.close()
     evals = st["evals"]
-    achieved = st["in_band"] * 4 / (st["kernel_ms"] * 1e-3) / 1e9
-    return {"workload": f"{len(specs)} searches, 2 detectors each, sky 16-1024 points, seed {seed}",
+    alg = st["in_band"] * 4 / (st["kernel_ms"] * 1e-3) / 1e9
+    return {"workload": f"{len(specs)} searches, T_obs 2-48 h, bands 100-1000 Hz in 500-3000 Hz, 2 detectors each, "
+                        f"sky 16-1024 points, seed {seed}",
             "searches": len(specs), "templates": int(st["templates"]), "evals": int(evals),
             "in_band_fraction": st["in_band"] / evals, "value": evals / wall, "unit": "template·segment evals/s",
-            "wall_s": wall, "kernel_ms": st["kernel_ms"], "graph_ms": st["total_ms"], "graph_replayed": st["graph_replayed"],
-            "first_call_s": build_s, "tile_shape": int(st["variant"]), "workgroups": int(st["workgroups"]),
-            "tiles": int(st["tiles"]), "roofline_frac": achieved / HBM_PEAK_GBS, "achieved_gbs": achieved,
+            "wall_s": wall, "kernel_ms": st["kernel_ms"], "kernel_evals_per_s": evals / (st["kernel_ms"] * 1e-3),
+            "graph_ms": st["total_ms"], "graph_replayed": st["graph_replayed"],
+            "first_call_s": build_s, "tile_shape": int(st["variant"]),
+            "templates_per_lane": int(st["templates_per_lane"]), "segments_per_batch": int(st["segments_per_batch"]),
+            "workgroups": int(st["workgroups"]), "tiles": int(st["tiles"]),
+            "algorithmic_gbs": alg, "algorithmic_x_hbm_peak": alg / HBM_PEAK_GBS,
             "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
             "latency_ms_max": float(lat.max())}
+
+
+def timed_search(torch, ctx, wl, power, t_seg, v, w, store, steps, warmup, tile_shape=-1):
+    """Time `steps` steps of the search (after autotuning and `warmup` steps);
+    then one more evaluation with outputs for the error report.  Returns a
+    dict of figures, the device results (s, c, N) and the top-10 lists."""
+    d = wl.dets[0]
+    g = wl.grid
+
+    def step():
+        ctx.load_spectrogram(0, power, d["k_lo"], d["t_sft"], t_seg, weights=w, store=store)
+        ctx.set_velocity_table(0, v)
+        ctx.eval_templates(g["f0_min"], g["f0_step"], g["n_f0"], g["tau"], g["brake"], g["sky"],
+                           g["t0"], outputs=False)
+        tp = ctx.topk("power", 10)
+        tc = ctx.topk("count", 10)
+        return tp, tc, ctx.diagnostics()
+
+    # the context's autotuner picks the statistic kernel's tile shape for this
+    # search on the device (cached for every later step)
+    ctx.load_spectrogram(0, power, d["k_lo"], d["t_sft"], t_seg, weights=w, store=store)
+    ctx.set_velocity_table(0, v)
+    if tile_shape >= 0:
+        ctx.set_tile_shape(tile_shape)
+    else:
+        ctx.set_tile_shape(-1)
+        ctx.autotune(g["f0_min"], g["f0_step"], g["n_f0"], g["tau"], g["brake"], g["sky"], g["t0"])
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern_ms = []
+    for _ in range(steps):
+        tp, tc, dg = step()
+        kern_ms.append(dg["eval_kernel_ms"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s, c, N = ctx.eval_templates(g["f0_min"], g["f0_step"], g["n_f0"], g["tau"], g["brake"], g["sky"], g["t0"])
+    res = {"s": s.cpu().numpy(), "c": c.cpu().numpy(), "N": N.cpu().numpy(),
+           "top_power": [t["index"] for t in tp], "top_count": [t["index"] for t in tc]}
+    launches = max(int(dg["eval_launches"]), 1)
+    kms = float(np.mean(kern_ms))
+    fig = {"evals": int(dg["evals"]), "in_band": int(dg["in_band"]), "templates": int(dg["templates"]),
+           "ms_per_step": elapsed * 1e3 / steps, "value": dg["evals"] * steps / elapsed,
+           "eval_kernel_ms": kms, "eval_launches": launches, "eval_launch_ms": kms / launches,
+           "tile_shape": int(dg["tile_shape"]), "pow_undecided": int(dg["pow_undecided"]),
+           "top_power": tp[0], "top_count": tc[0]}
+    return fig, res
+
+
+def roofline(workload, store, fig):
+    """The statistic kernel's roofline, per launch (the step's launches
+    averaged): HBM-side bytes measured by the committed counter runs (FETCH_SIZE
+    and WRITE_SIZE, copy-calibrated) over the average launch duration from HIP
+    events, against the 8 TB/s HBM peak; beside it the algorithmic bytes (one
+    stored element per in-band evaluation, served mostly by L1/L2, so above the
+    HBM peak) and the unit that binds (the vector-memory gather path, TA/TD
+    busy fractions from the counters)."""
+    launch_s = fig["eval_launch_ms"] * 1e-3
+    alg = fig["in_band"] * BYTES[store] / fig["eval_launches"]
+    t = traffic_record(workload, store, fig["tile_shape"])
+    traffic = None if t is None else t["bytes_per_launch"]
+    achieved = None if traffic is None else traffic / launch_s / 1e9
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": None if achieved is None else achieved / HBM_PEAK_GBS, "traffic": traffic,
+           "launch_us": launch_s * 1e6,
+           "algorithmic": {"bytes_per_launch": alg, "gbs": alg / launch_s / 1e9,
+                           "x_hbm_peak": alg / launch_s / 1e9 / HBM_PEAK_GBS,
+                           "unit": "one stored element per in-band template x segment evaluation"}}
+    if t is not None and t.get("binding"):
+        out["binding"] = t["binding"]
+    return out
+
+
+def traffic_record(workload, store, variant):
+    """The committed counter summary of the statistic kernel (HBM-side bytes per
+    launch, gather-path busy fractions) when it was taken for this workload,
+    store, tile shape and kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "eval_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if (t.get("source_sha256") != kernel_source_hash() or t.get("workload") != workload
+            or t.get("store") != store or t.get("variant") != variant):
+        return None
+    per_step = (t["fetch_kib_per_step"] * t["fetch_scale"] + t["write_kib_per_step"] * t["write_scale"]) * 1024.0
+    t["bytes_per_launch"] = per_step / t["dispatches_per_step"]
+    return t
 
 
 def main():
@@ -395,9 +541,10 @@ def main():
     ap.add_argument("--store", choices=sorted(BYTES), default="f32")
     ap.add_argument("--workload", choices=["realistic", "tiny"], default="realistic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-precision", action="store_true", help="skip the BF16 and FP8 stores of the same search")
     ap.add_argument("--no-proposer", action="store_true", help="skip the learned-proposer leg")
-    ap.add_argument("--batch", action="store_true", help="add the 64-search batch leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-search batch leg")
     ap.add_argument("--no-campaign", action="store_true", help="skip the sensitivity campaign leg")
     ap.add_argument("--no-sft", action="store_true", help="skip the data-preparation leg")
     ap.add_argument("--no-antenna", action="store_true", help="skip the antenna-weights leg")
@@ -452,70 +599,52 @@ def main():
                          inj["amp"])
     torch.cuda.synchronize()
 
-    def step():
-        ctx.load_spectrogram(0, power, d["k_lo"], d["t_sft"], t_seg, weights=w, store=args.store)
-        ctx.set_velocity_table(0, v)
-        ctx.eval_templates(g["f0_min"], g["f0_step"], g["n_f0"], g["tau"], g["brake"], g["sky"],
-                           g["t0"], outputs=False)
-        tp = ctx.topk("power", 10)
-        tc = ctx.topk("count", 10)
-        return tp, tc, ctx.diagnostics()
-
-    # the context's autotuner picks the statistic kernel's tile shape for this
-    # search on the device (cached for every later step)
-    ctx.load_spectrogram(0, power, d["k_lo"], d["t_sft"], t_seg, weights=w, store=args.store)
-    ctx.set_velocity_table(0, v)
-    if args.tile_shape >= 0:
-        ctx.set_tile_shape(args.tile_shape)
-    else:
-        ctx.autotune(g["f0_min"], g["f0_step"], g["n_f0"], g["tau"], g["brake"], g["sky"], g["t0"])
-    for i in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kern_ms = []
-    for i in range(args.steps):
-        tp, tc, dg = step()
-        kern_ms.append(dg["eval_kernel_ms"])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    evals = dg["evals"]
-    in_band = dg["in_band"]
-    ms_step = elapsed * 1e3 / args.steps
-    value = evals * args.steps / elapsed
-    kms = float(np.mean(kern_ms))
-    launches = max(int(dg["eval_launches"]), 1)
-    # per launch of the statistic kernel (the step's launches averaged): the
-    # algorithmic bytes over the average launch duration
-    alg_bytes = in_band * BYTES[args.store] / launches
-    launch_ms = kms / launches
-    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
-    print(f"[bench] {ms_step:.3f} ms/step, eval kernel {kms:.3f} ms, in-band {in_band / evals:.4f}, "
-          f"top power {tp[0]['index']} psi {tp[0]['psi']:.2f}, top count {tc[0]['index']} "
-          f"psi {tc[0]['psi']:.2f}, pow undecided {dg['pow_undecided']}",
-          file=sys.stderr, flush=True)
+    fig, res = timed_search(torch, ctx, wl, power, t_seg, v, w, args.store, args.steps, args.warmup,
+                            args.tile_shape)
+    results = {args.store: res}
+    evals, in_band = fig["evals"], fig["in_band"]
+    print(f"[bench] {fig['ms_per_step']:.3f} ms/step, eval kernel {fig['eval_kernel_ms']:.3f} ms, "
+          f"in-band {in_band / evals:.4f}, top power {fig['top_power']['index']} psi {fig['top_power']['psi']:.2f}, "
+          f"top count {fig['top_count']['index']} psi {fig['top_count']['psi']:.2f}, "
+          f"pow undecided {fig['pow_undecided']}", file=sys.stderr, flush=True)
+    rl = roofline(wl.name, args.store, fig)
     out = {
-        "metric": METRIC, "value": value, "unit": "template·segment evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "metric": METRIC, "value": fig["value"], "unit": "template·segment evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": fig["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.store, "data": "synthetic",
         "config": {"workload": wl.name, "store": args.store, "bin_arithmetic": "f64",
-                   "templates": int(dg["templates"]), "segments": int(d["rho"].shape[0]),
-                   "bins": int(d["rho"].shape[1]), "evals_per_step": int(evals),
-                   "in_band_fraction": in_band / evals, "eval_kernel_ms": kms,
-                   "eval_launches_per_step": launches, "eval_launch_ms": launch_ms,
-                   "alg_bytes_per_launch": alg_bytes, "tile_shape": int(dg["tile_shape"])},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(wl.name, args.store, int(dg["tile_shape"]))},
+                   "templates": fig["templates"], "segments": int(d["rho"].shape[0]),
+                   "bins": int(d["rho"].shape[1]), "evals_per_step": evals,
+                   "in_band_fraction": in_band / evals, "eval_kernel_ms": fig["eval_kernel_ms"],
+                   "eval_launches_per_step": fig["eval_launches"], "eval_launch_ms": fig["eval_launch_ms"],
+                   "tile_shape": fig["tile_shape"]},
+        "roofline": rl,
     }
-    valu = measured_valu(wl.name, args.store, int(dg["tile_shape"]))
+    valu = measured_valu(wl.name, args.store, fig["tile_shape"])
     if valu:
-        # the second bound: VALU issue at the kernel's counted instructions per evaluation
-        kernel_rate = evals / (kms * 1e-3)
+        # the VALU bound at the kernel's counted instructions per evaluation
+        kernel_rate = evals / (fig["eval_kernel_ms"] * 1e-3)
         ceiling = FP64_LANE_OPS / valu
         out["second_bound"] = {"bound": "valu", "instructions_per_eval": valu, "achieved_evals_per_s": kernel_rate,
                                "peak_evals_per_s": ceiling, "frac": kernel_rate / ceiling}
+    if not args.no_precision and args.workload == "realistic":
+        # the same search with the power stored in BF16 and in FP8 (per-segment
+        # scale): FP32 accumulation, FP64 track and bins
+        prec = {}
+        for st in ("bf16", "fp8"):
+            if st == args.store:
+                continue
+            print(f"[bench] store {st}", file=sys.stderr, flush=True)
+            f2, r2 = timed_search(torch, ctx, wl, power, t_seg, v, w, st, max(args.steps // 2, 1), 1)
+            results[st] = r2
+            alg = f2["in_band"] * BYTES[st] / f2["eval_launches"]
+            prec[st] = {"value": f2["value"], "unit": "template·segment evals/s", "ms_per_step": f2["ms_per_step"],
+                        "eval_kernel_ms": f2["eval_kernel_ms"], "eval_launch_ms": f2["eval_launch_ms"],
+                        "tile_shape": f2["tile_shape"],
+                        "algorithmic_gbs": alg / (f2["eval_launch_ms"] * 1e-3) / 1e9,
+                        "bytes_per_in_band_eval": BYTES[st]}
+        out["precision"] = prec
     if not args.no_antenna:
         print("[bench] antenna-pattern weights", file=sys.stderr, flush=True)
         out["antenna"] = antenna_leg(torch, ltgw, ctx, wl, power, t_seg, v, w, args.store)
@@ -525,6 +654,7 @@ def main():
         out["random_bank"] = list_leg(torch, ltgw, ctx, wl, n=args.list_templates,
                                       fp64_per_eval=measured_list_fp64())
         print(f"[bench] random bank: {json.dumps(out['random_bank'])}", file=sys.stderr, flush=True)
+    ctx.close()
     if not args.no_sft:
         print("[bench] data preparation (strain -> normalised power)", file=sys.stderr, flush=True)
         out["sft"] = sft_leg(torch, ltgw)
@@ -533,7 +663,7 @@ def main():
         print("[bench] sensitivity campaign", file=sys.stderr, flush=True)
         out["campaign"] = campaign_leg(torch, ltgw)
         print(f"[bench] campaign: {json.dumps(out['campaign'])}", file=sys.stderr, flush=True)
-    if args.batch:
+    if not args.no_batch:
         print("[bench] batch of 64 searches", file=sys.stderr, flush=True)
         out["batch"] = batch_leg(torch, ltgw)
         print(f"[bench] batch: {json.dumps(out['batch'])}", file=sys.stderr, flush=True)
@@ -543,9 +673,10 @@ def main():
                                        epochs=args.proposer_epochs)
         print(f"[bench] proposer: {json.dumps(out['proposer'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "realistic":
-        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, power.cpu().numpy(), args.cpu_seconds)
-    ctx.close()
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"], ref = cpu_baseline(wl, power.cpu().numpy(), args.cpu_seconds)
+        if len(results) > 1 or "precision" in out:
+            out.setdefault("precision", {})["error_vs_fp64"] = precision_report(ref, results)
     print(json.dumps(out), flush=True)
 
 

@@ -1,6 +1,6 @@
 """Host-side checks of the C ABI (no GPU needed).
 
-- the library loads and exports every function include/ltgw.h declares;
+- the library loads and exports every function the headers in include/ declare;
 - the ctypes structures match the C layout (sizes and offsets from a C
   program compiled against the header);
 - the double-double ln 2 split used by the correctly rounded power matches a
@@ -19,13 +19,17 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ltgw.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 DDPOW = os.path.join(ROOT, "paper_2507_07816_amd", "csrc", "ddpow.h")
 
 
 def _declared():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(ltgw_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(ltgw_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():

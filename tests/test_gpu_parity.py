@@ -375,8 +375,9 @@ def _sample_indices(n, seed=0):
 @pytest.mark.slow
 def test_realistic_full_size_sampled():
     """The realistic search at full size (10800 segments x 8000 bins, 2,304,000
-    templates, per-segment weights, 20 injections) in the benchmark's launch
-    configuration; sampled templates against the oracle one by one."""
+    templates, per-segment weights, 20 injections) in the untuned default tile
+    shape; sampled templates against the oracle one by one.  (Every template
+    in the tuned shape and in all others: test_gpu_headline.)"""
     print("case: realistic full size, weighted FP32", flush=True)
     det, grid, wl = _realistic_det()
     gpu = run_gpu([det], grid)
