@@ -11,6 +11,13 @@ infrastructure only: the product never imports this module).
   j' is its fine column (Eqs. 1-2 and the bin rule of Sec. 2) at the group's
   first segment, halved (floor); the group's weight is the FP32 sum of its S
   weights (in order) times 1/S.
+- coarse_count / coarse_psi_count: the number count on the same blocks.
+  Pixel (j', m) counts the 2 S fine pixels of the block whose normalised
+  power exceeds rho_th (compared in FP32, strictly, as the fine count of
+  Sec. 2); under noise alone it is Binomial(2 S, q) with q = exp(-rho_th).
+  The count ratio of a template (Eq. 4 for the count) sums the counts of its
+  coarse pixels (same columns as coarse_psi) against N 2 S q, N the in-band
+  coarse segments, with variance N 2 S q (1 - q); the count is unweighted.
 - cells and templates: network output cell (channel ch, position l) is fine
   template (group ch // 2, f0 index 2 l + ch % 2).
 - best_template: the largest Psi of a list (ties: lowest template index),
@@ -62,6 +69,39 @@ def coarse_psi(det: "oracle.Detector", grid: "oracle.Grid", P, nan_to_zero=False
         W1 = np.sum(w2[j])
         W2 = np.sum(w2[j] ** 2)
         out[t] = (s - mu * W1) / np.sqrt(mu * W2)
+    return out
+
+
+def coarse_count(P, S=2, rho_th=1.6):
+    """P: FP32 [n_seg][n_bins] -> int [n_seg / S][n_bins / 2]: pixels above
+    rho_th (FP32, strict) in each S x 2 block."""
+    above = (np.asarray(P, dtype=np.float32) > np.float32(rho_th)).astype(np.int64)
+    c = above[0::S, 0::2] + above[0::S, 1::2]
+    for k in range(1, S):
+        c = c + above[k::S, 0::2] + above[k::S, 1::2]
+    return c
+
+
+def coarse_psi_count(det: "oracle.Detector", grid: "oracle.Grid", P, nan_to_zero=False, S=2):
+    """Coarse count critical ratio of every template (columns as coarse_psi);
+    FP64 [n_templates]."""
+    C = coarse_count(P, S, float(det.rho_th))
+    nb2 = det.n_bins // 2
+    q = oracle.count_q(float(det.rho_th))
+    m = 2.0 * S
+    out = np.empty(grid.n_templates)
+    for t in range(grid.n_templates):
+        f0, tau, brake, i_sky = grid.params(t)
+        b = oracle.track_bins(det, float(f0), float(tau), float(brake), grid.sky[int(i_sky)], grid.t0)
+        b = b[0::S]
+        col = np.where(b == np.iinfo(np.int64).min, -1, b // 2)
+        j = np.nonzero((col >= 0) & (col < nb2))[0]
+        if j.size == 0:
+            out[t] = 0.0 if nan_to_zero else np.nan
+            continue
+        c = float(np.sum(C[j, col[j]]))
+        n = float(j.size)
+        out[t] = (c - n * m * q) / np.sqrt(n * m * q * (1.0 - q))
     return out
 
 

@@ -8,6 +8,10 @@ operand rounding and Adam).
   the coarse ratio is sqrt(2) times the fine one, for S = 2, 4 and 8;
 - only the first segment of a pair places the coarse column;
 - noise-free constant power gives Psi = 0 on every in-band template;
+- the coarse count: hand values at the strict FP32 threshold; with count
+  bits constant on S x 2 blocks of duplicated groups the coarse count ratio is
+  sqrt(2) times the fine one (Eq. 4 for the count); every pixel above the
+  threshold gives the closed form sqrt(N 2 S (1 - q) / q);
 - cells <-> templates is a bijection; best_template's tie rule;
 - BF16 operand rounding; Adam's first step on a constant gradient moves every
   parameter by lr against the gradient's sign.
@@ -114,6 +118,59 @@ def test_coarse_psi_constant_power_is_zero():
     det = oracle.Detector(P, t, v, 1900, 4.0)
     psi = op.coarse_psi(det, _grid(), P, nan_to_zero=True)
     assert np.all(psi == 0.0)
+
+
+def test_coarse_count_hand_values_and_strict_threshold():
+    P = np.zeros((4, 4), np.float32)
+    P[0, 0], P[1, 1], P[0, 1] = 1.7, 2.0, np.float32(1.6)   # 1.6f itself is not above 1.6f
+    P[2, 2], P[3, 3], P[3, 2] = 5.0, 1.6000001, 0.5
+    C = op.coarse_count(P, S=2)
+    assert C.tolist() == [[2, 0], [0, 2]]
+    assert op.coarse_count(P, S=4).tolist() == [[2, 2]]
+
+
+@pytest.mark.parametrize("S", [2, 4])
+def test_coarse_count_psi_is_sqrt2_times_fine_on_duplicated_groups(S):
+    """Duplicated groups of S segments and count bits constant on S x 2
+    blocks: a template collects S bits per group on the fine map and 2 S on
+    the coarse one, over S times fewer segments, so the coarse count ratio is
+    sqrt(2) times the fine one."""
+    n_seg, n_bins, k_lo, t_sft = 64, 96, 1900, 4.0
+    t, v = _geometry(n_seg, seed=11)
+    for k in range(1, S):
+        t[k::S] = t[0::S]
+        v[k::S] = v[0::S]
+    r = np.random.default_rng(12)
+    bits = r.integers(0, 2, size=(n_seg // S, n_bins // 2))
+    P = np.repeat(np.repeat(np.where(bits == 1, 2.5, 0.5).astype(np.float32), S, axis=0), 2, axis=1)
+    det = oracle.Detector(P, t, v, k_lo, t_sft)
+    g = _grid()
+    fine = oracle.psi_count(oracle.evaluate(det, g))
+    coarse = op.coarse_psi_count(det, g, P, S=S)
+    ok = np.isfinite(fine)
+    assert ok.sum() > 50
+    assert np.array_equal(ok, np.isfinite(coarse))
+    assert np.allclose(coarse[ok], math.sqrt(2.0) * fine[ok], rtol=1e-12, atol=1e-12)
+
+
+def test_coarse_count_psi_all_above_threshold():
+    """Every pixel above the threshold: each in-band coarse segment adds 2 S
+    counts, so Psi = (2 S N - 2 S N q) / sqrt(2 S N q (1 - q))."""
+    n_seg, n_bins, S = 32, 64, 4
+    t, v = _geometry(n_seg)
+    P = np.full((n_seg, n_bins), 3.0, np.float32)
+    det = oracle.Detector(P, t, v, 1900, 4.0)
+    g = _grid()
+    psi = op.coarse_psi_count(det, g, P, S=S)
+    q = oracle.count_q(1.6)
+    n = np.zeros(g.n_templates)
+    for k in range(g.n_templates):
+        f0, tau, brake, _ = g.params(k)
+        b = oracle.track_bins(det, float(f0), float(tau), float(brake), g.sky[0], g.t0)[0::S]
+        n[k] = np.count_nonzero((b >= 0) & (b // 2 < n_bins // 2))
+    ok = n > 0
+    assert ok.sum() > 10 and np.all(np.isnan(psi[~ok]))
+    assert np.allclose(psi[ok], np.sqrt(n[ok] * 2 * S * (1 - q) / q), rtol=1e-12)
 
 
 def test_cells_templates_bijection_and_best():
