@@ -56,6 +56,8 @@ extern "C" {
 #define LTGW_E_NOMEM (-3)       /* device allocation failed */
 #define LTGW_E_DEVICE (-4)      /* HIP runtime error; text in ltgw_last_error */
 #define LTGW_E_UNSUPPORTED (-5) /* valid request outside what the library supports */
+#define LTGW_E_IO (-6)          /* a file could not be opened, read or written, or is
+                                   not a valid file of the kind asked for        */
 
 /* ---- storage of the spectrogram on the device -------------------------- */
 #define LTGW_STORE_F32 0  /* IEEE binary32                                     */
@@ -86,8 +88,9 @@ int32_t ltgw_create(int32_t device, void *hip_stream, ltgw_ctx **out);
 void ltgw_destroy(ltgw_ctx *ctx);
 
 /* ltgw_last_error: text of the last failure on ctx (empty string if none).
- * Valid until the next call on ctx.  With ctx == NULL: the last failure of
- * ltgw_create on this thread. */
+ * Valid until the next call on ctx.  With ctx == NULL: the last failure on
+ * this thread of a call made without a context (ltgw_create, and
+ * ltgw_proposer_save / ltgw_proposer_load with ctx NULL). */
 const char *ltgw_last_error(const ltgw_ctx *ctx);
 
 /* ---- load_spectrogram ------------------------------------------------------
@@ -521,6 +524,28 @@ typedef struct {
  * fallback flag.  Synchronous. */
 int32_t ltgw_propose(ltgw_ctx *ctx, const ltgw_grid *fine, const ltgw_grid *coarse,
                      const ltgw_proposer *p, int32_t *best_index, double *best_psi, int32_t *fallback);
+
+/* ltgw_proposer_save: write a ranking network to the file `path` (replaced
+ * whole: written beside it, then renamed over it).  params: the
+ * ltgw_cnn_param_count(c_in, c_out) FP32 parameters, device or host memory;
+ * with ctx NULL they must be host memory and no device call is made.  The
+ * file is a 64-byte header (magic "LTGWCNN", format version 1, c_in, c_out,
+ * width 32, taps 5, parameter count, FNV-1a 64-bit hash of the parameter
+ * bytes) and the parameters, little-endian.  Synchronous.  Errors:
+ * INVALID_ARG (NULL path or params, shape out of range), IO, DEVICE. */
+int32_t ltgw_proposer_save(ltgw_ctx *ctx, const char *path, const float *params, int32_t c_in, int32_t c_out);
+
+/* ltgw_proposer_load: read a network written by ltgw_proposer_save.
+ *   c_in, c_out: receive the network's shape (each may be NULL);
+ *   params: NULL to read the shape only, else n_params floats (device or
+ *           host memory; host only when ctx is NULL), n_params equal to the
+ *           file's parameter count, receiving the parameters bit for bit.
+ * The header, the shape, the length and the hash are checked before params
+ * is written.  Synchronous.  Errors: INVALID_ARG (NULL path, n_params
+ * mismatch), IO (missing, short, corrupt or foreign file), UNSUPPORTED (other
+ * format version), DEVICE. */
+int32_t ltgw_proposer_load(ltgw_ctx *ctx, const char *path, int32_t *c_in, int32_t *c_out, float *params,
+                           int64_t n_params);
 
 /* ltgw_read_store: copy detector det's device store to host for inspection.
  *   out_host: n_seg rows of n_bins elements (guards dropped), each element 4

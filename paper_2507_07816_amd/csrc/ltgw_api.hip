@@ -28,7 +28,10 @@ int fail(ltgw_ctx *c, int code, const char *fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (c) c->err = buf;
+    if (c)
+        c->err = buf;
+    else
+        g_create_error = buf;  // a call made without a context: ltgw_last_error(NULL)
     return code;
 }
 

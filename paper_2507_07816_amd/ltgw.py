@@ -22,6 +22,7 @@ LTGW_E_STATE = -2
 LTGW_E_NOMEM = -3
 LTGW_E_DEVICE = -4
 LTGW_E_UNSUPPORTED = -5
+LTGW_E_IO = -6
 
 LTGW_STORE_F32 = 0
 LTGW_STORE_BF16 = 1
@@ -47,7 +48,7 @@ EXPORTS = ("ltgw_create", "ltgw_destroy", "ltgw_last_error", "ltgw_load_spectrog
            "ltgw_stack_psi_list", "ltgw_cnn_param_count", "ltgw_cnn_work_floats", "ltgw_cnn_forward",
            "ltgw_cnn_backward", "ltgw_softmax_xent", "ltgw_adam_step", "ltgw_select_top",
            "ltgw_propose", "ltgw_stack_features", "ltgw_stack_best", "ltgw_cells_from_templates",
-           "ltgw_eval_list")
+           "ltgw_eval_list", "ltgw_proposer_save", "ltgw_proposer_load")
 
 
 class ltgw_spec_desc(C.Structure):
@@ -125,6 +126,8 @@ def library():
             "ltgw_set_antenna": (i32, [P, i32, P, P, i32]),
             "ltgw_sft_normalise": (i32, [P, P, i32, i32, C.c_int64, i32, i32, P]),
             "ltgw_eval_templates": (i32, [P, C.POINTER(ltgw_grid), u32, P, P, P]),
+            "ltgw_proposer_save": (i32, [P, C.c_char_p, P, i32, i32]),
+            "ltgw_proposer_load": (i32, [P, C.c_char_p, C.POINTER(i32), C.POINTER(i32), P, C.c_int64]),
             "ltgw_eval_list": (i32, [P, P, C.c_int64, d, u32, P, P, P]),
             "ltgw_psi": (i32, [P, u32, P]),
             "ltgw_topk_candidates": (i32, [P, u32, i32, C.POINTER(ltgw_candidate), C.POINTER(i32)]),
@@ -261,6 +264,35 @@ def ltgw_eval_templates(ctx, grid, stats=LTGW_STAT_POWER | LTGW_STAT_COUNT, out_
     cp, _b = _addr(out_c)
     np_, _c = _addr(out_n)
     _check(ctx, library().ltgw_eval_templates(ctx, C.byref(grid), int(stats), sp, cp, np_))
+
+
+def ltgw_proposer_save(ctx, path, params, c_in, c_out):
+    """Write the network parameters (device tensor, or host float32 array with
+    ctx None) to `path`."""
+    if not hasattr(params, "data_ptr"):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+    pp, params = _addr(params)
+    _check(ctx, library().ltgw_proposer_save(ctx, os.fsencode(path), pp, int(c_in), int(c_out)))
+
+
+def ltgw_proposer_load(ctx, path, params=None):
+    """(c_in, c_out) of the network in `path`; with params (device tensor, or
+    host float32 array with ctx None) the parameters are read into it."""
+    ci, co = C.c_int32(0), C.c_int32(0)
+    lib = library()
+    if params is None:
+        _check(ctx, lib.ltgw_proposer_load(ctx, os.fsencode(path), C.byref(ci), C.byref(co), None, 0))
+        return ci.value, co.value
+    if hasattr(params, "data_ptr"):
+        if not params.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        pp, n = params.data_ptr(), params.numel()
+    else:
+        if not (isinstance(params, np.ndarray) and params.dtype == np.float32 and params.flags.c_contiguous):
+            raise ValueError("params must be a contiguous float32 array or tensor")
+        pp, n = params.ctypes.data, params.size
+    _check(ctx, lib.ltgw_proposer_load(ctx, os.fsencode(path), C.byref(ci), C.byref(co), pp, int(n)))
+    return ci.value, co.value
 
 
 def ltgw_eval_list(ctx, params, t0=0.0, det_mask=0, out_s=None, out_c=None, out_n=None):

@@ -246,6 +246,19 @@ class Proposer:
                                  n_select2=self.n_select2, return_blocks=return_blocks,
                                  tier2_threshold=tier2_threshold)
 
+    def save(self, path):
+        """Write the network (ltgw_proposer_save)."""
+        ltgw.ltgw_proposer_save(self.ctx.h, path, self.params, self.c_in, self.c_out)
+
+    def load(self, path):
+        """Replace the network by the one in `path` (ltgw_proposer_load); its
+        shape must be this proposer's."""
+        c_in, c_out = ltgw.ltgw_proposer_load(self.ctx.h, path)
+        if (c_in, c_out) != (self.c_in, self.c_out):
+            raise ValueError(f"{path} holds a network of {c_in} -> {c_out} channels, this proposer needs "
+                             f"{self.c_in} -> {self.c_out}")
+        ltgw.ltgw_proposer_load(self.ctx.h, path, self.params)
+
     def close_region(self, inj, df=2, dg=1):
         return close_region(self.fine, inj, df, dg)
 

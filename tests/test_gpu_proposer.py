@@ -579,10 +579,12 @@ def test_stack_best_features_and_cells():
     ctx.close()
 
 
-def test_training_learns_and_proposer_recalls():
+def test_training_learns_and_proposer_recalls(tmp_path):
     """A short training run on device-generated data lowers the loss well below
     the uniform-guess value log(n_cells); the trained proposer recalls the
-    injections the exhaustive search detects (fallback included)."""
+    injections the exhaustive search detects (fallback included).  Saved to a
+    file and loaded into another proposer in a fresh context, the network
+    gives the same proposals bit for bit."""
     from paper_2507_07816_amd import ltgw
     from paper_2507_07816_amd.proposer import Proposer, coarse_grid_for
 
@@ -605,4 +607,28 @@ def test_training_learns_and_proposer_recalls():
     ev0 = raw.evaluate(R_noise=128, R_signal=256, amp_range=(3.0, 6.0), reps=1)
     print("case: untrained", ev0, flush=True)
     assert ev["recall_no_fallback"] > ev0["recall_no_fallback"]
+    # file round trip: train -> save -> load in a fresh context -> same proposals
+    import torch
+
+    path = str(tmp_path / "ranker.ltgwcnn")
+    pr.save(path)
+    assert ltgw.ltgw_proposer_load(ctx.h, path) == (pr.c_in, pr.c_out)
+    R = 64
+    inj, _ = pr.draw_injections(R, 1.0, (3.0, 6.0), rng=np.random.Generator(np.random.PCG64(99)))
+    pr.make_batch(R, 5, 0, inj, with_labels=False)
+    want = pr.propose(5.0, 6.0, R)
+    ctx2, _, _, _ = _ctx()
+    # the same seed draws the same noise; its network is the untrained one
+    other = Proposer(ctx2, 0, (N_SEG, N_BINS), fine, coarse, seed=3, select_frac=0.1)
+    assert not torch.equal(other.params, pr.params)
+    other.load(path)
+    assert torch.equal(other.params.view(torch.int32), pr.params.view(torch.int32))
+    other.make_batch(R, 5, 0, inj, with_labels=False)
+    got = other.propose(5.0, 6.0, R)
+    for a, b in zip(got, want):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+    bad = Proposer(ctx2, 0, (N_SEG, N_BINS), fine, coarse_grid_for(fine, [5000.0, 9000.0], [4.0]), seed=6)
+    with pytest.raises(ValueError):
+        bad.load(path)
+    ctx2.close()
     ctx.close()
