@@ -186,6 +186,35 @@ typedef struct {
 int32_t ltgw_eval_templates(ltgw_ctx *ctx, const ltgw_grid *g, uint32_t stats, float *out_s,
                             int32_t *out_c, int32_t *out_n);
 
+/* ---- evaluation without device allocation ----------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * ltgw_eval_templates_noalloc: ltgw_eval_templates (same arguments, same
+ * kernels, the same results bit for bit) with every table, window, moment
+ * array and per-template sum placed in the library's static device scratch
+ * array of LTGW_NOALLOC_SCRATCH_BYTES instead of buffers of the context.  It
+ * calls no hipMalloc or hipFree and no allocating library routine; the
+ * caller passes the outputs (device buffers, as for ltgw_eval_templates) and
+ * must have loaded the detectors (ltgw_load_spectrogram and
+ * ltgw_set_velocity_table allocate).
+ *   - Each device holds one scratch array for the life of the process,
+ *     shared by every context and call on it, and keeping the last call's
+ *     contents (the call clears what it accumulates).  Calls that overlap
+ *     on one device (contexts on different streams, threads) race.
+ *   - The results are not kept in the context: ltgw_psi and
+ *     ltgw_topk_candidates answer STATE after this call, and ltgw_read_tables
+ *     holds no tables of it.
+ *   - Limits: the search's buffers must fit the array (the realistic day of
+ *     10800 segments x 8000 bins with 2,304,000 templates takes about 198 MB);
+ *     at most LTGW_NOALLOC_MAX_AXIS tau, brake and sky values each.
+ * Asynchronous.  Errors: as ltgw_eval_templates, and UNSUPPORTED when the
+ * search exceeds a limit (the message gives the bytes it needs). */
+#define LTGW_NOALLOC_SCRATCH_BYTES (256ull << 20) /* 256 MiB per device */
+#define LTGW_NOALLOC_MAX_AXIS 4096
+int32_t ltgw_eval_templates_noalloc(ltgw_ctx *ctx, const ltgw_grid *g, uint32_t stats, float *out_s,
+                                    int32_t *out_c, int32_t *out_n);
+
 /* ---- eval_list ---------------------------------------------------------------
  * Uniform random template bank (Sec. 2): templates with their own parameters,
  * e.g. drawn uniformly over the parameter space. */

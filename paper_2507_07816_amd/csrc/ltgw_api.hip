@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,35 @@ using namespace ltgw;
 
 namespace {
 thread_local std::string g_create_error;
+}  // namespace
+
+// Device memory of ltgw_eval_templates_noalloc: one static array, of which
+// every device the library runs on holds its own copy until the process
+// ends.  In host code `scratch` is only a stand-in for the symbol, not a
+// device address: ltgw_create resolves the address on each device once
+// (hipGetSymbolAddress with that device current) and the contexts on that
+// device use only the resolved address.
+__device__ __align__(256) unsigned char scratch[LTGW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;     // devices whose scratch address is kept
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kScratchDevices];  // resolved address per device, NULL until then
+
+// The address of `scratch` on the current device `device` (resolved once).
+hipError_t scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kScratchDevices) return hipSuccess;  // no scratch there
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
 }  // namespace
 
 namespace ltgw {
@@ -169,6 +199,17 @@ int32_t ltgw_create(int32_t device, void *hip_stream, ltgw_ctx **out) {
         if (ee != hipSuccess) rc = hip_fail(c, ee, "event/stream create");
     }
     if (rc == LTGW_OK) {
+        const hipError_t ee = scratch_address(device, &c->scratch);
+        if (ee != hipSuccess) rc = hip_fail(c, ee, "address of the static scratch array");
+    }
+    if (rc == LTGW_OK) {
+        // host staging of the grid lists, sized once so that the
+        // no-allocation entry point never grows them
+        c->h_tau.reserve(LTGW_NOALLOC_MAX_AXIS);
+        c->h_brake.reserve(LTGW_NOALLOC_MAX_AXIS);
+        c->h_sky.reserve(3 * (size_t)LTGW_NOALLOC_MAX_AXIS);
+    }
+    if (rc == LTGW_OK) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0)
             c->cu_count = v;
@@ -287,6 +328,7 @@ int32_t ltgw_load_spectrogram(ltgw_ctx *c, int32_t det, const ltgw_spec_desc *d,
     D.w_uniform = hw[0];
     D.h_w = hw;
     D.h_t = ht;
+    D.h_wfix.reserve(3 * (size_t)D.n_seg);  // the fixed-point weights' staging never grows at eval
     D.loaded = true;
     c->have_eval = false;
     return LTGW_OK;
@@ -479,10 +521,14 @@ static int ilog2(int64_t v) {
     return r;
 }
 
-std::string tune_key_eval(const SearchPlan &P, bool moments_in_loop) {
-    char buf[160];
+void tune_key_eval(const SearchPlan &P, bool moments_in_loop, char (&buf)[160]) {
     snprintf(buf, sizeof buf, "eval/store%d/mom%d/seg%d/bins%d/tpl%d", P.store, moments_in_loop ? 1 : 0,
              ilog2(P.n_seg_total), ilog2(P.max_bins), ilog2(P.n_tpl));
+}
+
+std::string tune_key_eval(const SearchPlan &P, bool moments_in_loop) {
+    char buf[160];
+    tune_key_eval(P, moments_in_loop, buf);
     return buf;
 }
 
@@ -504,6 +550,7 @@ namespace {
 struct EvalMem {
     ltgw_ctx *c;
     char *base = nullptr;  // scratch base (device address), or NULL: context buffers
+    size_t cap = 0;        // scratch bytes
     size_t used = 0;
     int get(DevBuf &b, size_t bytes, const char *what, void **p) {
         if (!base) {
@@ -512,8 +559,11 @@ struct EvalMem {
             return rc;
         }
         used = (used + 255) & ~(size_t)255;
+        const size_t n = bytes ? bytes : 16;
+        if (used > cap || n > cap - used)  // eval_bytes was checked first: never taken
+            return fail(c, LTGW_E_UNSUPPORTED, "device scratch exhausted at %s", what);
         *p = base + used;
-        used += bytes ? bytes : 16;
+        used += n;
         return LTGW_OK;
     }
 };
@@ -564,6 +614,12 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     const bool moments_in_loop = M.mode == 2;
     EvalMem mem{c};
     if (scratch) {
+        if (g->n_tau > LTGW_NOALLOC_MAX_AXIS || g->n_brake > LTGW_NOALLOC_MAX_AXIS ||
+            g->n_sky > LTGW_NOALLOC_MAX_AXIS)
+            return fail(c, LTGW_E_UNSUPPORTED,
+                        "the no-allocation entry point takes at most %d tau, brake and sky values each "
+                        "(use ltgw_eval_templates)",
+                        LTGW_NOALLOC_MAX_AXIS);
         const size_t need = eval_bytes(c, P, M, g);
         if (need > scratch_cap)
             return fail(c, LTGW_E_UNSUPPORTED,
@@ -571,6 +627,7 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
                         "has %zu (use ltgw_eval_templates)",
                         need, scratch_cap);
         mem.base = (char *)scratch;
+        mem.cap = scratch_cap;
     }
     c->h_tau.assign(g->tau, g->tau + g->n_tau);
     c->h_brake.assign(g->brake, g->brake + g->n_brake);
@@ -700,7 +757,9 @@ int eval_single(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s, i
     }
     if (variant < 0) variant = c->forced_variant;
     if (variant < 0) {
-        const auto it = c->tune.find(tune_key_eval(P, moments_in_loop));
+        char key[160];
+        tune_key_eval(P, moments_in_loop, key);
+        const auto it = c->tune.find(key);
         variant = it == c->tune.end() ? 1 : it->second;
     }
     HIP_TRY(c, hipEventRecord(c->ev_h2d, c->stream), "event record");
@@ -734,6 +793,17 @@ int32_t ltgw_eval_templates(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, flo
     if (!c) return LTGW_E_INVALID_ARG;
     Enter en(c);
     return eval_single(c, g, stats, out_s, out_c, out_n, -1);
+}
+
+int32_t ltgw_eval_templates_noalloc(ltgw_ctx *c, const ltgw_grid *g, uint32_t stats, float *out_s,
+                                    int32_t *out_c, int32_t *out_n) {
+    if (!c) return LTGW_E_INVALID_ARG;
+    Enter en(c);
+    c->have_eval = false;
+    if (!c->scratch)
+        return fail(c, LTGW_E_UNSUPPORTED, "device %d has no static scratch array (devices 0 .. %d do)", c->device,
+                    kScratchDevices - 1);
+    return eval_single(c, g, stats, out_s, out_c, out_n, -1, c->scratch, LTGW_NOALLOC_SCRATCH_BYTES);
 }
 
 int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double t0, uint32_t det_mask,

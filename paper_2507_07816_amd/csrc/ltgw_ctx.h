@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -139,7 +140,9 @@ struct ltgw_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int cu_count = 256;
     int wall_khz = 100000;        // device wall-clock rate
-    std::map<std::string, int> tune;  // autotuner cache: key -> tile shape
+    // autotuner cache: key -> tile shape (transparent comparison: looked up
+    // by a character buffer without building a string)
+    std::map<std::string, int, std::less<>> tune;
     // last single-search eval; results_kept: its per-template results are in
     // res_* for ltgw_psi and ltgw_topk_candidates
     bool have_eval = false, results_kept = false;
@@ -161,6 +164,9 @@ struct ltgw_ctx {
     ltgw::DevBuf sft_spec;
     std::vector<SftPlan> sft_plans;
     int forced_variant = -1;      // ltgw_set_tile_shape; -1 = autotuner
+    // device address of this device's static scratch array (the no-allocation
+    // entry point), resolved by ltgw_create; NULL when the device has none
+    void *scratch = nullptr;
     ltgw::BatchState batch;
     ltgw::StackState stack;
 };
@@ -198,6 +204,7 @@ int plan_search(ltgw_ctx *c, const ltgw_grid *g, const int *slots, int n_slots, 
 Moments plan_moments(ltgw_ctx *c, const int *slots, int n_slots);
 // Autotuner keys.
 std::string tune_key_eval(const SearchPlan &P, bool moments_in_loop);
+void tune_key_eval(const SearchPlan &P, bool moments_in_loop, char (&buf)[160]);
 std::string tune_key_batch(int store, bool moments_in_loop, int n_searches, int64_t evals);
 void free_batch(BatchState &B);
 void free_stack(StackState &S);

@@ -36,6 +36,8 @@ STATS = {"power": LTGW_STAT_POWER, "count": LTGW_STAT_COUNT}
 LTGW_MAX_DET = 256
 LTGW_MAX_SEARCH_DET = 4
 LTGW_MAX_TOPK = 256
+LTGW_NOALLOC_SCRATCH_BYTES = 256 << 20
+LTGW_NOALLOC_MAX_AXIS = 4096
 TILE_SHAPES = {0: (1, 8), 1: (1, 16), 2: (2, 8), 3: (2, 16)}  # (templates per lane, segments per batch)
 
 # every symbol include/ltgw.h declares
@@ -48,7 +50,7 @@ EXPORTS = ("ltgw_create", "ltgw_destroy", "ltgw_last_error", "ltgw_load_spectrog
            "ltgw_stack_psi_list", "ltgw_cnn_param_count", "ltgw_cnn_work_floats", "ltgw_cnn_forward",
            "ltgw_cnn_backward", "ltgw_softmax_xent", "ltgw_adam_step", "ltgw_select_top",
            "ltgw_propose", "ltgw_stack_features", "ltgw_stack_best", "ltgw_cells_from_templates",
-           "ltgw_eval_list", "ltgw_proposer_save", "ltgw_proposer_load")
+           "ltgw_eval_list", "ltgw_eval_templates_noalloc", "ltgw_proposer_save", "ltgw_proposer_load")
 
 
 class ltgw_spec_desc(C.Structure):
@@ -126,6 +128,7 @@ def library():
             "ltgw_set_antenna": (i32, [P, i32, P, P, i32]),
             "ltgw_sft_normalise": (i32, [P, P, i32, i32, C.c_int64, i32, i32, P]),
             "ltgw_eval_templates": (i32, [P, C.POINTER(ltgw_grid), u32, P, P, P]),
+            "ltgw_eval_templates_noalloc": (i32, [P, C.POINTER(ltgw_grid), u32, P, P, P]),
             "ltgw_proposer_save": (i32, [P, C.c_char_p, P, i32, i32]),
             "ltgw_proposer_load": (i32, [P, C.c_char_p, C.POINTER(i32), C.POINTER(i32), P, C.c_int64]),
             "ltgw_eval_list": (i32, [P, P, C.c_int64, d, u32, P, P, P]),
@@ -264,6 +267,14 @@ def ltgw_eval_templates(ctx, grid, stats=LTGW_STAT_POWER | LTGW_STAT_COUNT, out_
     cp, _b = _addr(out_c)
     np_, _c = _addr(out_n)
     _check(ctx, library().ltgw_eval_templates(ctx, C.byref(grid), int(stats), sp, cp, np_))
+
+
+def ltgw_eval_templates_noalloc(ctx, grid, stats=LTGW_STAT_POWER | LTGW_STAT_COUNT, out_s=None,
+                                out_c=None, out_n=None):
+    sp, _a = _addr(out_s)
+    cp, _b = _addr(out_c)
+    np_, _c = _addr(out_n)
+    _check(ctx, library().ltgw_eval_templates_noalloc(ctx, C.byref(grid), int(stats), sp, cp, np_))
 
 
 def ltgw_proposer_save(ctx, path, params, c_in, c_out):
