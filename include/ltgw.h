@@ -285,7 +285,8 @@ int32_t ltgw_topk_candidates(ltgw_ctx *ctx, uint32_t stat, int32_t k, ltgw_candi
  *           [j n_fft, (j + 1) n_fft) (no overlap); n_fft = T_sft * sample rate.
  *   Window w_n = 1/2 - 1/2 cos(2 pi n / n_fft) (periodic Hann), applied in
  *   frequency: with Y the FP32 transform of the raw segment (hipFFT, real to
- *   complex, out of place: the strain is not written), X_k = Y_k/2 -
+ *   complex, on a copy of the segment in the context's buffer: the strain
+ *   is only read, never written), X_k = Y_k/2 -
  *   (Y_{k-1} + Y_{k+1})/4, which equals sum_n x_n w_n e^{-2 pi i k n / n_fft}.
  *   out: device FP32 [n_seg][n_bins], column b = bin k_lo + b (frequency
  *        k / T_sft), ready for ltgw_load_spectrogram.  A window whose median
@@ -316,6 +317,10 @@ typedef struct {
     int32_t tile_shape;     /* tile shape of the last eval's statistic kernel */
     int32_t eval_launches;  /* dispatches of the statistic kernel in the last
                                eval (segment slabs, generations of workgroups) */
+    double ingest_ms;       /* duration of the store kernels of the last
+                               ltgw_load_spectrogram or ltgw_load_stack (HIP
+                               events on the context's stream; a stack's
+                               coarse store is written in the same pass)     */
 } ltgw_diag;
 
 /* ltgw_diagnostics: synchronous; reads the device counters of the last eval. */
@@ -458,22 +463,31 @@ int32_t ltgw_load_stack(ltgw_ctx *ctx, int32_t det, int32_t R, const float *stac
 int32_t ltgw_stack_psi(ltgw_ctx *ctx, const ltgw_grid *g, int32_t level, int32_t nan_to_zero,
                        double *out_psi);
 
-/* ltgw_stack_psi_list: the same on the fine store for listed templates:
- * idx[R][m] (device int32 template indices of g) -> out_psi[R][m] (device).
+/* ltgw_stack_psi_list: critical ratios on the fine store for listed
+ * templates: idx[R][m] (device int32 template indices of g; an index outside
+ * the grid gives NaN) -> out_psi[R][m] (device), for stat LTGW_STAT_POWER or
+ * LTGW_STAT_COUNT (Eq. 4 for the number count: (c - N q) / sqrt(N q (1 - q)),
+ * q = exp(-rho_th), the value ltgw_psi gives the same template bit for bit).
  * Asynchronous. */
-int32_t ltgw_stack_psi_list(ltgw_ctx *ctx, const ltgw_grid *g, const int32_t *idx, int32_t m,
+int32_t ltgw_stack_psi_list(ltgw_ctx *ctx, const ltgw_grid *g, uint32_t stat, const int32_t *idx, int32_t m,
                             double *out_psi);
 
-/* ltgw_stack_features: the network's input from the coarse store: coarse
- * critical ratios of grid g (NaN -> 0) in FP32, x[R][groups][n_f0] (device).
- * Asynchronous.  Errors: STATE (no coarse store). */
-int32_t ltgw_stack_features(ltgw_ctx *ctx, const ltgw_grid *g, float *x);
+/* ltgw_stack_features: the network's input from the coarse store, FP32
+ * x[R][channels][n_f0] (device), 0 where a template has no in-band segment:
+ * channel gr < G (G the groups of grid g) the coarse power critical ratio of
+ * group gr, and with counts = 1 channel G + gr its coarse number-count
+ * critical ratio (c - N m q) / sqrt(N m q (1 - q)): c the count of pixels
+ * above rho_th in the track's coarse blocks, N the in-band coarse segments,
+ * m = 2 S pixels per block, q = exp(-rho_th) (Eq. 4 for the count of Sec. 2
+ * on the coarse blocks).  Asynchronous.  Errors: STATE (no coarse store). */
+int32_t ltgw_stack_features(ltgw_ctx *ctx, const ltgw_grid *g, int32_t counts, float *x);
 
 /* ltgw_stack_best: exhaustive search of grid g on every realisation of the
- * fine store: best template (largest Psi, ties to the lowest index; -1 and
- * -inf when no template has N > 0) into device best_index[R], best_psi[R].
+ * fine store for statistic stat (LTGW_STAT_POWER or LTGW_STAT_COUNT): best
+ * template (largest Psi, ties to the lowest index; -1 and -inf when no
+ * template has N > 0) into device best_index[R], best_psi[R].
  * Asynchronous. */
-int32_t ltgw_stack_best(ltgw_ctx *ctx, const ltgw_grid *g, int32_t *best_index, double *best_psi);
+int32_t ltgw_stack_best(ltgw_ctx *ctx, const ltgw_grid *g, uint32_t stat, int32_t *best_index, double *best_psi);
 
 /* ltgw_cells_from_templates: fine template t (group g, f0 index i, with fine
  * n_f0 = 2 L) -> network cell (2 g + i % 2) L + i / 2; -1 where t < 0,
@@ -513,8 +527,11 @@ int32_t ltgw_select_top(ltgw_ctx *ctx, const float *score, int32_t R, int32_t n,
                         int32_t *out_idx);
 
 typedef struct {
-    const float *params;      /* network parameters (device)                      */
-    int32_t c_in, c_out, L;   /* network shape                                    */
+    const float *params;      /* network parameters (device), or NULL: rank by the
+                                 coarse power ratios alone (coarse_map)          */
+    int32_t c_in, c_out, L;   /* network shape: c_in = G (the coarse power ratios
+                                 of the G coarse groups) or 2 G (then the count
+                                 ratios), c_out = 2 x fine groups               */
     int32_t n_select;         /* fine cells evaluated exactly per realisation     */
     int32_t block;            /* cells are taken in blocks of this many
                                  consecutive f0 of one fine group (1 .. 64)       */
@@ -535,6 +552,10 @@ typedef struct {
                                  (b % nbg) block .. + block - 1 (below 2 L),
                                  nbg = ceil(2 L / block).  A fallback
                                  realisation evaluated every template.        */
+    const int32_t *coarse_map; /* with params NULL: host [fine groups][2], the
+                                 coarse groups (-1: none) whose power ratios
+                                 score fine group g's cells, e.g. the nearest
+                                 in tau and n; ignored with a network          */
 } ltgw_proposer;
 
 /* ltgw_propose: on the loaded stack, for every realisation: coarse critical

@@ -12,14 +12,18 @@ the role of d90.
 
 Every statistic comes from the library's kernels through its C ABI:
 - noise realisations: `ltgw_generate_noise` (Philox4x32-10 Exp(1)); each is
-  searched in full (`ltgw_eval_templates` over the lattice, or
-  `ltgw_eval_list` over a random bank) and its best ratio per statistic kept
-  (`ltgw_topk_candidates`, k = 1); the threshold is their maximum;
+  searched in full and its best ratio per statistic kept; the threshold is
+  their maximum;
 - injected realisations: `ltgw_inject_stack` adds the track; only the
-  templates close to the injection decide, so only they are evaluated
-  (`ltgw_eval_list`), and the largest ratio among them is compared with the
-  threshold.
-The fit is a binomial maximum-likelihood logistic curve in log A (host).
+  templates close to the injection decide, so only they are evaluated, and
+  the largest ratio among them is compared with the threshold.
+Over the lattice, realisations go through in stacks (`ltgw_load_stack`, then
+`ltgw_stack_best` for the full searches and `ltgw_stack_psi_list` for the
+templates near each injection, power and count); over a random bank, whose
+templates share no track tables, one realisation at a time
+(`ltgw_eval_list`, `ltgw_topk_candidates` with k = 1, `ltgw_psi`).
+The fit is a binomial maximum-likelihood logistic curve in log A (host); its
+90% point is reported only where it falls within the sampled amplitudes.
 """
 import math
 
@@ -127,7 +131,7 @@ class Campaign:
     bank: the lattice `grid` (dict of f0_min, f0_step, n_f0, tau, brake, sky,
     t0), or, with `bank` ([n][6] rows), a random bank at the grid's scales."""
 
-    def __init__(self, ctx, geometry, grid, bank=None, seed=2024, store="f32", slot=0, chunk=64):
+    def __init__(self, ctx, geometry, grid, bank=None, seed=2024, store="f32", slot=0, chunk=64, stack_chunk=512):
         import torch
 
         self.torch = torch
@@ -139,6 +143,7 @@ class Campaign:
         self.store = store
         self.slot = int(slot)
         self.chunk = int(chunk)
+        self.stack_chunk = int(stack_chunk)
         self.n_seg = len(geometry["t_seg"])
         self.n_bins = int(geometry["n_bins"])
         self.sky = np.asarray(grid["sky"], np.float64).reshape(-1, 3)[0]
@@ -191,9 +196,50 @@ class Campaign:
         best = lambda a: float(np.nanmax(a)) if np.any(~np.isnan(a)) else -math.inf
         return best(pp), best(pc)
 
+    def _stack_best(self, st):
+        """(power[n], count[n]) best ratios of a device stack over the lattice."""
+        T = self.torch
+        n = st.shape[0]
+        self._load(st[0])  # the slot's geometry for the stack
+        ltgw.ltgw_load_stack(self.ctx.h, self.slot, st, self.store, coarse=0)
+        g, keep = ltgw.make_grid(self.grid["f0_min"], self.grid["f0_step"], self.grid["n_f0"], self.grid["tau"],
+                                 self.grid["brake"], self.grid["sky"], self.grid.get("t0", 0.0))
+        bi = T.empty(n, dtype=T.int32, device=self.dev)
+        out = []
+        for stat in ("power", "count"):
+            bp = T.empty(n, dtype=T.float64, device=self.dev)
+            ltgw.ltgw_stack_best(self.ctx.h, g, bi, bp, stat=stat)
+            out.append(bp.cpu().numpy())
+        return out[0], out[1]
+
+    def _stack_region(self, st, inj):
+        """(power[n], count[n]) largest ratios of each realisation of a device
+        stack over the lattice templates close to its injection inj[r]."""
+        T = self.torch
+        n = st.shape[0]
+        self._load(st[0])
+        ltgw.ltgw_load_stack(self.ctx.h, self.slot, st, self.store, coarse=0)
+        g, keep = ltgw.make_grid(self.grid["f0_min"], self.grid["f0_step"], self.grid["n_f0"], self.grid["tau"],
+                                 self.grid["brake"], self.grid["sky"], self.grid.get("t0", 0.0))
+        idx = close_region(self.grid, np.asarray(inj, np.float64)[:, :3]).astype(np.int32)  # -1: outside
+        idx_d = T.from_numpy(idx).to(self.dev)
+        out = []
+        for stat in ("power", "count"):
+            psi = T.empty(idx.shape, dtype=T.float64, device=self.dev)
+            ltgw.ltgw_stack_psi_list(self.ctx.h, g, idx_d, psi, stat=stat)
+            p = psi.cpu().numpy()
+            ok = ~np.isnan(p)
+            out.append(np.where(ok.any(axis=1), np.nanmax(np.where(ok, p, -np.inf), axis=1), -math.inf))
+        return out[0], out[1]
+
     def noise_maxima(self, R, stream=1):
         """Best ratio of each noise-only realisation: arrays (power[R], count[R])."""
         bp, bc = np.empty(R), np.empty(R)
+        if self.bank is None:
+            for r0 in range(0, R, self.stack_chunk):
+                n = min(self.stack_chunk, R - r0)
+                bp[r0:r0 + n], bc[r0:r0 + n] = self._stack_best(self._stack(stream, r0, np.zeros((n, 4))))
+            return bp, bc
         for r0 in range(0, R, self.chunk):
             n = min(self.chunk, R - r0)
             st = self._stack(stream, r0, np.zeros((n, 4)))
@@ -208,6 +254,12 @@ class Campaign:
         inj = np.asarray(inj, np.float64)
         R = len(inj)
         bp, bc = np.empty(R), np.empty(R)
+        if self.bank is None:
+            for r0 in range(0, R, self.stack_chunk):
+                n = min(self.stack_chunk, R - r0)
+                bp[r0:r0 + n], bc[r0:r0 + n] = self._stack_region(self._stack(stream, r0, inj[r0:r0 + n]),
+                                                                  inj[r0:r0 + n])
+            return bp, bc
         for r0 in range(0, R, self.chunk):
             n = min(self.chunk, R - r0)
             st = self._stack(stream, r0, inj[r0:r0 + n])
@@ -234,6 +286,9 @@ class Campaign:
         for name, m in (("power", mp), ("count", mc)):
             det = m > th[name]
             k = det.reshape(len(amps), per_level).sum(axis=1)
-            out[name] = {"detected": k, "efficiency": k / per_level,
-                         "fit": fit_logistic(amps, k, np.full(len(amps), per_level))}
+            fit = fit_logistic(amps, k, np.full(len(amps), per_level))
+            # the 90% point is a result only inside the sampled amplitudes
+            inside = fit["rising"] and min(amps) <= fit["a90"] <= max(amps)
+            out[name] = {"detected": k, "efficiency": k / per_level, "fit": fit,
+                         "a90": fit["a90"] if inside else None, "a90_in_sampled_range": bool(inside)}
         return out

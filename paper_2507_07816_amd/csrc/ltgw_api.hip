@@ -195,6 +195,8 @@ int32_t ltgw_create(int32_t device, void *hip_stream, ltgw_ctx **out) {
         hipError_t ee = hipEventCreateWithFlags(&c->ev_h2d, hipEventDisableTiming);
         if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
         if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (ee == hipSuccess) ee = hipEventCreate(&c->ev_ing[0]);
+        if (ee == hipSuccess) ee = hipEventCreate(&c->ev_ing[1]);
         if (ee == hipSuccess) ee = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
         if (ee != hipSuccess) rc = hip_fail(c, ee, "event/stream create");
     }
@@ -236,6 +238,8 @@ void ltgw_destroy(ltgw_ctx *c) {
     if (c->ev_h2d) (void)hipEventDestroy(c->ev_h2d);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    for (hipEvent_t e : c->ev_ing)
+        if (e) (void)hipEventDestroy(e);
     if (c->side) (void)hipStreamDestroy(c->side);
     free_batch(c->batch);
     free_stack(c->stack);
@@ -310,10 +314,14 @@ int32_t ltgw_load_spectrogram(ltgw_ctx *c, int32_t det, const ltgw_spec_desc *d,
         src = (const float *)c->staging.p;
     }
     if ((rc = zero_counter(c, kCntBad, 1)) != LTGW_OK) return rc;
+    c->have_ingest = false;
+    HIP_TRY(c, hipEventRecord(c->ev_ing[0], c->stream), "event record");
     HIP_TRY(c, launch_ingest(d->store, src, d->n_seg, d->n_bins, pitch, D.store_buf.p,
                              (float *)D.scale.p, (const float *)D.w.p, (float *)D.wq.p, d->rho_th,
                              (unsigned long long *)c->counters.p + kCntBad, c->stream),
             "ingest launch");
+    HIP_TRY(c, hipEventRecord(c->ev_ing[1], c->stream), "event record");
+    c->have_ingest = true;
     unsigned long long bad = 0;
     if ((rc = read_counter(c, kCntBad, &bad)) != LTGW_OK) return rc;
     if (bad) return fail(c, LTGW_E_INVALID_ARG, "%llu power values are negative or not finite", bad);
@@ -1092,6 +1100,12 @@ int32_t ltgw_diagnostics(ltgw_ctx *c, ltgw_diag *out) {
     out->tables_ms = 0.0;
     out->tile_shape = c->have_eval ? c->last_variant : -1;
     out->eval_launches = c->have_eval ? c->last_launches : 0;
+    out->ingest_ms = 0.0;
+    if (c->have_ingest) {
+        float a = 0.f;
+        if (hipEventElapsedTime(&a, c->ev_ing[0], c->ev_ing[1]) == hipSuccess) out->ingest_ms = a;
+        (void)hipGetLastError();
+    }
     if (c->have_eval) {
         float a = 0.f, b = 0.f;
         if (hipEventElapsedTime(&a, c->ev[1], c->ev[2]) == hipSuccess) out->eval_kernel_ms = a;

@@ -112,7 +112,7 @@ struct StackState {
     StackLevel lv[2];
     hipEvent_t ev_h2d = nullptr;  // after the last grid upload
     DevBuf psi_c, x, act, logits, cells, tpl, psi_sel, best_idx, best_psi, fb, rmap, psi_all;
-    DevBuf bscore, blk, blk2, tpl2, psi2, cm_idx, cm;
+    DevBuf bscore, blk, blk2, tpl2, psi2, cm_idx, cm, cmap;
     // per-realisation step lists of a proposal: rows and flags of the second
     // tier and of the fallback, their counts, the later bests, the block output
     DevBuf rows2, flag2, bi2, bp2, counts, blocks, records;
@@ -133,6 +133,8 @@ struct ltgw_ctx {
     std::vector<double> h_tau, h_brake, h_sky;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // tables start, eval start, eval end
     hipEvent_t ev_h2d = nullptr;  // after the grid uploads from h_tau/h_brake/h_sky
+    hipEvent_t ev_ing[2] = {nullptr, nullptr};  // around the last load's store kernels
+    bool have_ingest = false;
     // second stream (default priority): the in-band moments run there beside the
     // statistic kernel; ev_fork orders them after the tables, ev_join before
     // anything on `stream` that reads them

@@ -53,6 +53,17 @@ struct Store<LTGW_STORE_FP8> {
     }
 };
 
+template <>
+struct Store<kStoreCoarse> {
+    static constexpr int kBytes = 4;
+    // the upper half is the bfloat16 power sum, the low byte the count
+    __device__ static float get(__amdgpu_buffer_rsrc_t r, int i, int soff, int &cnt) {
+        const unsigned u = __float_as_uint(ltgw_sbuf_f32(r, i, 0, soff, 0));
+        cnt += (int)(u & 0xffu);
+        return __uint_as_float(u & 0xffff0000u);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Statistic (Sec. 2).  A lane carries TPL templates (f0 256 apart, so each
 // of them is a coalesced wavefront access); segments go in batches of U so

@@ -10,6 +10,11 @@ namespace ltgw {
 
 constexpr double kC = 299792458.0;  // m/s, exact by SI definition
 
+// Internal store format (beside LTGW_STORE_F32/BF16/FP8): the proposer's
+// coarse store, 32-bit words holding a bfloat16 power sum in the upper half
+// and the count of the block's pixels above rho_th in the low byte.
+constexpr int kStoreCoarse = 3;
+
 // One detector as the evaluation kernel sees it.
 struct DetView {
     const void *store;      // [n_seg][pitch] elements, element 0 of a row = 0 guard
@@ -58,6 +63,13 @@ struct EvalArgs {
 hipError_t launch_ingest(int store, const float *power, int32_t n_seg, int32_t n_bins,
                          int64_t pitch, void *out, float *scale, const float *w, float *wq,
                          float rho_th, unsigned long long *bad, hipStream_t st);
+// The learned proposer's stacks: realisations [R][n_seg][n_bins] into the fine
+// store (as launch_ingest per row) and, in the same pass, the coarse store of
+// S x 2 blocks: [R][n_seg / S][pitch2] words (bfloat16 sum << 16 | count);
+// crs NULL: the fine store alone, S rows per workgroup (n_bins even).
+hipError_t launch_stack_ingest(int store, const float *power, int R, int32_t n_seg, int32_t n_bins, int S,
+                               int64_t pitch, void *out, float *scale, const float *w, float *wq, float rho_th,
+                               int64_t pitch2, unsigned *crs, unsigned long long *bad, hipStream_t st);
 hipError_t launch_check_velocity(const double *v, int32_t n_seg, unsigned long long *bad,
                                  hipStream_t st);
 hipError_t launch_spin_factor(const double *t_seg, int32_t n_seg, double t0, const double *tau,

@@ -120,6 +120,115 @@ hipError_t launch_ingest(int store, const float *power, int32_t n_seg, int32_t n
     return hipGetLastError();
 }
 
+// Stack ingest with the proposer's coarse store in the same pass: workgroup
+// (j2, r) reads the S fine rows S j2 .. S j2 + S - 1 of realisation r once and
+//  - writes them to the fine store: the codes, count bits and FP8 scales of
+//    ingest_kernel, bit for bit;
+//  - writes coarse pixel m of coarse row j2 (column m + 1; columns 0 and
+//    nb2 + 1 .. pitch2 - 1 are 0 guards): the FP32 sum, segment by segment in
+//    order, of the pair sums P[2m] + P[2m+1], rounded to bfloat16, in the
+//    upper half of a 32-bit word whose low byte counts the 2 S pixels of the
+//    block above rho_th (the fine count bits; at most 16).
+// With crs NULL only the fine store is written (S rows per workgroup).
+template <int STORE>
+__global__ __launch_bounds__(256) void stack_ingest_kernel(const float *__restrict__ in, int n_seg, int n_bins,
+                                                           int S, int64_t pitch, void *__restrict__ out,
+                                                           float *__restrict__ scale, const float *__restrict__ w,
+                                                           float *__restrict__ wq, float th, int64_t pitch2,
+                                                           unsigned *__restrict__ crs, unsigned long long *bad) {
+    __shared__ float sh[4];
+    __shared__ float ssc[8];
+    const int j2 = blockIdx.x, r = blockIdx.y;
+    const int ns2 = n_seg / S, nb2 = n_bins / 2;
+    const int64_t row0 = (int64_t)r * n_seg + (int64_t)S * j2;  // first fine row of the block
+    for (int k = 0; k < S; ++k) {
+        float sc = 1.0f;
+        if (STORE == LTGW_STORE_FP8) {
+            const float *row = in + (row0 + k) * n_bins;
+            float m = 0.0f;
+            for (int b = threadIdx.x; b < n_bins; b += 256) {
+                const float x = row[b];
+                if (x >= 0.0f && x <= 3.402823466e38f) m = fmaxf(m, x);
+            }
+            m = block_max_256(m, sh);
+            sc = (m == 0.0f) ? 1.0f : m / 448.0f;
+        }
+        if (threadIdx.x == 0) {
+            ssc[k] = sc;
+            scale[row0 + k] = sc;
+            wq[row0 + k] = w[row0 + k] * sc;
+        }
+    }
+    __syncthreads();
+    unsigned nbad = 0;
+    unsigned *co = crs ? crs + ((int64_t)r * ns2 + j2) * pitch2 : nullptr;
+    for (int m = threadIdx.x; m < nb2; m += 256) {
+        float acc = 0.0f;
+        unsigned cnt = 0;
+        for (int k = 0; k < S; ++k) {
+            const float *src = in + (row0 + k) * n_bins + 2 * m;
+            float x[2] = {src[0], src[1]};
+            unsigned code[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                if (!(x[e] >= 0.0f && x[e] <= 3.402823466e38f)) {
+                    ++nbad;
+                    x[e] = 0.0f;
+                }
+                x[e] = __builtin_fabsf(x[e]);  // -0 -> +0
+                const unsigned bit = x[e] > th ? 1u : 0u;
+                cnt += bit;
+                if (STORE == LTGW_STORE_F32) code[e] = __float_as_uint(x[e]) | (bit << 31);
+                if (STORE == LTGW_STORE_BF16) code[e] = bf16_rne_bits(x[e]) | (bit << 15);
+                if (STORE == LTGW_STORE_FP8) code[e] = e4m3_rne_sat_bits(x[e] / ssc[k]) | (bit << 7);
+            }
+            const float pair = x[0] + x[1];
+            acc = k == 0 ? pair : acc + pair;
+            const int64_t o = (row0 + k) * pitch + 2 * m + 1;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                if (STORE == LTGW_STORE_F32) ((unsigned *)out)[o + e] = code[e];
+                if (STORE == LTGW_STORE_BF16) ((unsigned short *)out)[o + e] = (unsigned short)code[e];
+                if (STORE == LTGW_STORE_FP8) ((unsigned char *)out)[o + e] = (unsigned char)code[e];
+            }
+        }
+        if (co) co[m + 1] = (bf16_rne_bits(acc) << 16) | cnt;
+    }
+    // the guards: fine columns 0 and n_bins + 1 .. pitch - 1 of the S rows,
+    // coarse columns 0 and nb2 + 1 .. pitch2 - 1
+    const int64_t gf = pitch - n_bins;  // guard columns per fine row
+    for (int64_t e = threadIdx.x; e < (int64_t)S * gf; e += 256) {
+        const int64_t k = e / gf, q = e % gf;
+        const int64_t o = (row0 + k) * pitch + (q == 0 ? 0 : n_bins + q);
+        if (STORE == LTGW_STORE_F32) ((unsigned *)out)[o] = 0u;
+        if (STORE == LTGW_STORE_BF16) ((unsigned short *)out)[o] = 0;
+        if (STORE == LTGW_STORE_FP8) ((unsigned char *)out)[o] = 0;
+    }
+    if (co)
+        for (int64_t q = threadIdx.x; q < pitch2 - nb2; q += 256) co[q == 0 ? 0 : nb2 + q] = 0u;
+    if (nbad) atomicAdd(bad, (unsigned long long)nbad);
+}
+
+hipError_t launch_stack_ingest(int store, const float *power, int R, int32_t n_seg, int32_t n_bins, int S,
+                               int64_t pitch, void *out, float *scale, const float *w, float *wq, float rho_th,
+                               int64_t pitch2, unsigned *crs, unsigned long long *bad, hipStream_t st) {
+    if (R < 1 || R > 65535 || S < 1 || S > 8 || n_seg % S || (n_bins & 1) || pitch < n_bins + 2 ||
+        (crs && pitch2 < n_bins / 2 + 2))
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(n_seg / S), (unsigned)R), block(256);
+#define LTGW_STACK_INGEST(ST)                                                                                   \
+    hipLaunchKernelGGL(stack_ingest_kernel<ST>, grid, block, 0, st, power, n_seg, n_bins, S, pitch, out, scale, \
+                       w, wq, rho_th, pitch2, crs, bad)
+    if (store == LTGW_STORE_F32)
+        LTGW_STACK_INGEST(LTGW_STORE_F32);
+    else if (store == LTGW_STORE_BF16)
+        LTGW_STACK_INGEST(LTGW_STORE_BF16);
+    else
+        LTGW_STACK_INGEST(LTGW_STORE_FP8);
+#undef LTGW_STACK_INGEST
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Eq. 1: g[(i_n*n_tau + i_tau)][j] = RN(u^e), 0 where t_j < T0.
 __global__ __launch_bounds__(256) void spin_factor_kernel(const double *__restrict__ t_seg,

@@ -9,9 +9,13 @@ namespace ltgw {
 // Per-template moments of a stack level (the weights are the same for every
 // realisation): W1 = sum of in-band weights, W2 = sum of their squares, N =
 // in-band segments, each in the statistic's own summation order.
+// The ratio the stack kernels write: the power ratio, or with count set the
+// number-count ratio (c - N q) / sqrt(N q (1 - q)) with q = exp(-rho_th).
 struct StackMoments {
     const double *w1, *w2;
     const int32_t *n;
+    int count = 0;
+    double q = 0.0;
 };
 
 hipError_t launch_stack_moments(int shift, const EvalArgs &a, double *w1, double *w2, int32_t *n, hipStream_t st);
@@ -19,6 +23,15 @@ hipError_t launch_stack_moments(int shift, const EvalArgs &a, double *w1, double
 hipError_t launch_stack_eval(int store, int shift, const EvalArgs &a, int R, int64_t stack_bytes,
                              int64_t stack_rows, double mu, double var, int nan_to_zero, const int32_t *rmap,
                              const int32_t *n_rows, StackMoments m, double *out_psi, hipStream_t st);
+// The network's input from the coarse store (power ratios, and count ratios
+// with counts != 0) in FP32 x[R][channels][n_f0]; psi (optional) the FP64
+// power ratios [R][n_templates], NaN -> 0.
+hipError_t launch_stack_features(const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows, double mu,
+                                 double q, int counts, StackMoments m, float *x, double *psi, hipStream_t st);
+// Block scores from the coarse power ratios alone (no network): the largest
+// ratio of the coarse channels map[G][0..1] over the block's f0.
+hipError_t launch_coarse_block_scores(const float *x, int R, int nb, int c_in, int L, int W, int nbg,
+                                      const int32_t *map, float *score, hipStream_t st);
 hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,
                             const int32_t *idx, int m, const int32_t *rmap, const int32_t *n_rows, StackMoments mom,
                             double *out_psi, hipStream_t st);
@@ -55,8 +68,6 @@ hipError_t launch_inject_stack(float *power, int R, int32_t n_seg, int32_t n_bin
                                double t_sft, const double *t_seg, const double *v, const float *w,
                                const double *params, double sx, double sy, double sz, double t0,
                                unsigned long long *undecided, hipStream_t st);
-hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins, int S, int64_t pitch2,
-                          unsigned short *out, hipStream_t st);
 hipError_t launch_cnn_forward(const float *params, const float *x, int B, int c_in, int c_out, int L,
                               float *act /* [3][B][32][L] */, float *logits, hipStream_t st);
 // The forward pass for inference only, fused in one kernel (no activations

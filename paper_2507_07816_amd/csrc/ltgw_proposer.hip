@@ -1,7 +1,8 @@
 // Kernels of the learned proposer: synthetic training data (counter-based
-// Exp(1) noise, injected tracks), the 2x2-coarsened BF16 store of the coarse
-// pass, the ranking network (BF16 MFMA, FP32 accumulation) with its backward
-// pass, loss and Adam, and the per-row top-M selection of fine cells.
+// Exp(1) noise, injected tracks), the ranking network (BF16 MFMA, FP32
+// accumulation) with its backward pass, loss and Adam, and the per-row top-M
+// selection of fine cells.  (The stores, fine and coarse, are written by
+// launch_stack_ingest beside the single-detector ingest.)
 #include "ltgw_proposer.h"
 #include "ddpow.h"
 
@@ -108,41 +109,6 @@ hipError_t launch_inject_stack(float *power, int R, int32_t n_seg, int32_t n_bin
     if (R < 1 || R > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(inject_stack_kernel, dim3((n_seg + 255) / 256, R), dim3(256), 0, st, power,
                        n_seg, n_bins, k_lo, t_sft, t_seg, v, w, params, sx, sy, sz, t0, undecided);
-    return hipGetLastError();
-}
-
-// Coarsening into BF16 over S consecutive segments and 2 bins:
-// coarse[r][j'][m + 1] = RN_bf16(sum over s < S, in order, of
-// (P[S j' + s][2m] + P[S j' + s][2m+1])) (FP32 sums), zero guards at 0 and
-// n_bins/2 + 1.
-__device__ inline unsigned short bf16_rne(float x) {  // finite x >= 0
-    const unsigned u = __float_as_uint(x);
-    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-
-__global__ __launch_bounds__(256) void coarsen_kernel(const float *__restrict__ in, int n_seg,
-                                                      int n_bins, int S, int64_t pitch2,
-                                                      unsigned short *__restrict__ out) {
-    const int j2 = blockIdx.x, r = blockIdx.y;
-    const int ns2 = n_seg / S, nb2 = n_bins / 2;
-    const float *row = in + ((int64_t)r * n_seg + (int64_t)S * j2) * n_bins;
-    unsigned short *o = out + ((int64_t)r * ns2 + j2) * pitch2;
-    for (int64_t b = threadIdx.x; b < pitch2; b += 256) {
-        unsigned short code = 0;
-        if (b >= 1 && b <= nb2) {
-            const int64_t m = b - 1;
-            float acc = row[2 * m] + row[2 * m + 1];
-            for (int k = 1; k < S; ++k) acc = acc + (row[(int64_t)k * n_bins + 2 * m] + row[(int64_t)k * n_bins + 2 * m + 1]);
-            code = bf16_rne(acc);
-        }
-        o[b] = code;
-    }
-}
-
-hipError_t launch_coarsen(const float *in, int R, int32_t n_seg, int32_t n_bins, int S, int64_t pitch2,
-                          unsigned short *out, hipStream_t st) {
-    if (R < 1 || R > 65535 || S < 1 || n_seg < S) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(coarsen_kernel, dim3(n_seg / S, R), dim3(256), 0, st, in, n_seg, n_bins, S, pitch2, out);
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ void free_stack(StackState &S) {
                      &S.logits, &S.cells,    &S.tpl,      &S.psi_sel, &S.best_idx, &S.best_psi, &S.fb,
                      &S.rmap,   &S.psi_all, &S.bscore, &S.blk, &S.blk2, &S.tpl2, &S.psi2,
                      &S.cm_idx, &S.cm,      &S.rows2,   &S.flag2, &S.bi2,  &S.bp2,   &S.counts, &S.blocks,
-                     &S.records};
+                     &S.records, &S.cmap};
     for (DevBuf *b : all) release(*b);
     for (StackLevel &L : S.lv) {
         release(L.tau);
@@ -156,15 +156,16 @@ EvalArgs stack_args(const StackState &S, int level, const ltgw_grid *g, const Se
         stack_bytes = (int64_t)S.n_seg * S.pitch * esize(S.store);
         stack_rows = S.n_seg;
     } else {
-        // coarse column of fine column b is b >> 1: index trunc(x + 2.5 - k_lo) >> 1
+        // coarse column of fine column b is b >> 1: index trunc(x + 2.5 - k_lo) >> 1;
+        // 32-bit words (bfloat16 power sum, count)
         V.store = S.crs.p;
-        V.pitch_bytes = (int32_t)(S.pitch2 * 2);
+        V.pitch_bytes = (int32_t)(S.pitch2 * 4);
         V.wq = (const float *)S.w2.p;
         V.w = (const float *)S.w2.p;
         V.cshift = 2.5 - (double)S.k_lo;
         V.n_seg = S.n_seg / S.S;
         V.n_bins = S.n_bins / 2;
-        stack_bytes = (int64_t)(S.n_seg / S.S) * S.pitch2 * 2;
+        stack_bytes = (int64_t)(S.n_seg / S.S) * S.pitch2 * 4;
         stack_rows = S.n_seg / S.S;
     }
     V.H = (const double *)L.H.p;
@@ -182,7 +183,19 @@ EvalArgs stack_args(const StackState &S, int level, const ltgw_grid *g, const Se
     return a;
 }
 
-int stack_psi_impl(ltgw_ctx *c, const ltgw_grid *g, int level, int nan_to_zero, double *out_psi) {
+// The moments of a level with the statistic to write: POWER, or COUNT (the
+// fine level) with q = exp(-rho_th) of the stack's detector.
+StackMoments stat_moments(ltgw_ctx *c, int level, uint32_t stat) {
+    StackMoments m = level_moments(c->stack, level);
+    if (stat == LTGW_STAT_COUNT) {
+        m.count = 1;
+        m.q = std::exp(-(double)c->det[c->stack.det].rho_th);
+    }
+    return m;
+}
+
+int stack_psi_impl(ltgw_ctx *c, const ltgw_grid *g, int level, int nan_to_zero, double *out_psi,
+                   uint32_t stat = LTGW_STAT_POWER) {
     int rc = need_stack(c, level);
     if (rc != LTGW_OK) return rc;
     if (level != 0 && level != 1) return fail(c, LTGW_E_INVALID_ARG, "level must be 0 or 1");
@@ -192,22 +205,39 @@ int stack_psi_impl(ltgw_ctx *c, const ltgw_grid *g, int level, int nan_to_zero, 
     int64_t sb = 0, sr = 0;
     const EvalArgs a = stack_args(c->stack, level, g, P, sb, sr);
     const int shift = level;
-    const int store = level ? LTGW_STORE_BF16 : c->stack.store;
+    const int store = level ? kStoreCoarse : c->stack.store;
     const double mu = level ? 2.0 * c->stack.S : 1.0;  // a coarse pixel sums 2 S Exp(1) values
     HIP_TRY(c, launch_stack_eval(store, shift, a, c->stack.R, sb, sr, mu, mu, nan_to_zero, nullptr, nullptr,
-                                 level_moments(c->stack, level), out_psi, c->stream),
+                                 stat_moments(c, level, stat), out_psi, c->stream),
             "stack evaluation launch");
     return LTGW_OK;
 }
 
+// The network's input on the coarse store: FP32 power ratios per coarse
+// group, then (counts) the count ratios; psi (optional) the FP64 power ratios.
+int features_impl(ltgw_ctx *c, const ltgw_grid *coarse, int counts, float *x, double *psi) {
+    int rc = need_stack(c, 1);
+    if (rc != LTGW_OK) return rc;
+    SearchPlan P;
+    if ((rc = stack_tables(c, coarse, 1, P)) != LTGW_OK) return rc;
+    StackState &S = c->stack;
+    int64_t sb = 0, sr = 0;
+    const EvalArgs a = stack_args(S, 1, coarse, P, sb, sr);
+    const double q = std::exp(-(double)c->det[S.det].rho_th);  // count probability of a noise pixel
+    HIP_TRY(c, launch_stack_features(a, S.R, sb, sr, 2.0 * S.S, q, counts, level_moments(S, 1), x, psi, c->stream),
+            "features launch");
+    return LTGW_OK;
+}
+
 int list_psi_impl(ltgw_ctx *c, const ltgw_grid *g, const int32_t *idx, int rows, int32_t m,
-                  const int32_t *rmap, const int32_t *n_rows, double *out_psi, SearchPlan *plan_out) {
+                  const int32_t *rmap, const int32_t *n_rows, double *out_psi, SearchPlan *plan_out,
+                  uint32_t stat = LTGW_STAT_POWER) {
     SearchPlan P;
     int rc = stack_tables(c, g, 0, P);
     if (rc != LTGW_OK) return rc;
     int64_t sb = 0, sr = 0;
     const EvalArgs a = stack_args(c->stack, 0, g, P, sb, sr);
-    HIP_TRY(c, launch_list_eval(c->stack.store, a, rows, sb, sr, idx, m, rmap, n_rows, level_moments(c->stack, 0),
+    HIP_TRY(c, launch_list_eval(c->stack.store, a, rows, sb, sr, idx, m, rmap, n_rows, stat_moments(c, 0, stat),
                                 out_psi, c->stream),
             "listed evaluation launch");
     if (plan_out) *plan_out = P;
@@ -311,18 +341,15 @@ int32_t ltgw_load_stack(ltgw_ctx *c, int32_t det, int32_t R, const float *stack,
     if ((rc = h2d(c, S.w.p, hw.data(), hw.size() * 4, "stack weights upload")) != LTGW_OK) return rc;
     if ((rc = h2d(c, S.t.p, D.h_t.data(), (size_t)ns * 8, "segment times upload")) != LTGW_OK) return rc;
     if ((rc = h2d(c, S.v.p, D.h_v.data(), (size_t)ns * 24, "velocity upload")) != LTGW_OK) return rc;
-    if ((rc = zero_counter(c, kCntBad, 1)) != LTGW_OK) return rc;
-    HIP_TRY(c, launch_ingest(store, stack, (int32_t)rows, (int32_t)nb, pitch, S.fine.p, (float *)S.scale.p,
-                             (const float *)S.w.p, (float *)S.wq.p, D.rho_th,
-                             (unsigned long long *)c->counters.p + kCntBad, c->stream),
-            "stack ingest launch");
     std::vector<float> hw2;
     std::vector<double> ht2, hv2;
     int64_t pitch2 = 0;
     if (coarse) {
         const int64_t ns2 = ns / Sg, nb2 = nb / 2;
         pitch2 = ((nb2 + 2 + 63) / 64) * 64;
-        if ((rc = ensure(c, S.crs, (size_t)(R * ns2 * pitch2 * 2), "coarse store")) != LTGW_OK) return rc;
+        if (ns2 * pitch2 * 4 >= ((int64_t)1 << 31))
+            return fail(c, LTGW_E_UNSUPPORTED, "one realisation's coarse store exceeds 2^31 bytes");
+        if ((rc = ensure(c, S.crs, (size_t)(R * ns2 * pitch2 * 4), "coarse store")) != LTGW_OK) return rc;
         if ((rc = ensure(c, S.w2, (size_t)(R * ns2) * 4, "coarse weights")) != LTGW_OK) return rc;
         if ((rc = ensure(c, S.t2, (size_t)ns2 * 8, "coarse segment times")) != LTGW_OK) return rc;
         if ((rc = ensure(c, S.v2, (size_t)ns2 * 24, "coarse velocities")) != LTGW_OK) return rc;
@@ -343,9 +370,30 @@ int32_t ltgw_load_stack(ltgw_ctx *c, int32_t det, int32_t R, const float *stack,
         if ((rc = h2d(c, S.w2.p, hw2.data(), hw2.size() * 4, "coarse weights upload")) != LTGW_OK) return rc;
         if ((rc = h2d(c, S.t2.p, ht2.data(), ht2.size() * 8, "coarse times upload")) != LTGW_OK) return rc;
         if ((rc = h2d(c, S.v2.p, hv2.data(), hv2.size() * 8, "coarse velocity upload")) != LTGW_OK) return rc;
-        HIP_TRY(c, launch_coarsen(stack, R, (int32_t)ns, (int32_t)nb, Sg, pitch2, (unsigned short *)S.crs.p, c->stream),
-                "coarsen launch");
     }
+    if ((rc = zero_counter(c, kCntBad, 1)) != LTGW_OK) return rc;
+    // the stores: fine alone, or fine and coarse from one read of the stack
+    c->have_ingest = false;
+    HIP_TRY(c, hipEventRecord(c->ev_ing[0], c->stream), "event record");
+    if (coarse)
+        HIP_TRY(c, launch_stack_ingest(store, stack, R, (int32_t)ns, (int32_t)nb, Sg, pitch, S.fine.p,
+                                       (float *)S.scale.p, (const float *)S.w.p, (float *)S.wq.p, D.rho_th, pitch2,
+                                       (unsigned *)S.crs.p, (unsigned long long *)c->counters.p + kCntBad,
+                                       c->stream),
+                "stack ingest launch");
+    else if ((nb & 1) == 0)  // the same kernel without the coarse store: 4, 2 or 1 rows per workgroup
+        HIP_TRY(c, launch_stack_ingest(store, stack, R, (int32_t)ns, (int32_t)nb, ns % 4 == 0 ? 4 : ns % 2 == 0 ? 2 : 1,
+                                       pitch, S.fine.p, (float *)S.scale.p, (const float *)S.w.p, (float *)S.wq.p,
+                                       D.rho_th, 0, nullptr, (unsigned long long *)c->counters.p + kCntBad,
+                                       c->stream),
+                "stack ingest launch");
+    else
+        HIP_TRY(c, launch_ingest(store, stack, (int32_t)rows, (int32_t)nb, pitch, S.fine.p, (float *)S.scale.p,
+                                 (const float *)S.w.p, (float *)S.wq.p, D.rho_th,
+                                 (unsigned long long *)c->counters.p + kCntBad, c->stream),
+                "stack ingest launch");
+    HIP_TRY(c, hipEventRecord(c->ev_ing[1], c->stream), "event record");
+    c->have_ingest = true;
     unsigned long long bad = 0;
     if ((rc = read_counter(c, kCntBad, &bad)) != LTGW_OK) return rc;  // synchronises: host vectors may go
     if (bad) return fail(c, LTGW_E_INVALID_ARG, "%llu stack values are negative or not finite", bad);
@@ -371,15 +419,18 @@ int32_t ltgw_stack_psi(ltgw_ctx *c, const ltgw_grid *g, int32_t level, int32_t n
     return stack_psi_impl(c, g, level, nan_to_zero, out_psi);
 }
 
-int32_t ltgw_stack_psi_list(ltgw_ctx *c, const ltgw_grid *g, const int32_t *idx, int32_t m, double *out_psi) {
+int32_t ltgw_stack_psi_list(ltgw_ctx *c, const ltgw_grid *g, uint32_t stat, const int32_t *idx, int32_t m,
+                            double *out_psi) {
     if (!c) return LTGW_E_INVALID_ARG;
     Enter en(c);
     int rc = need_stack(c, 0);
     if (rc != LTGW_OK) return rc;
+    if (stat != LTGW_STAT_POWER && stat != LTGW_STAT_COUNT)
+        return fail(c, LTGW_E_INVALID_ARG, "stat must be POWER or COUNT");
     if (m < 1) return fail(c, LTGW_E_INVALID_ARG, "m must be >= 1");
     if ((rc = need_device(c, idx, "idx")) != LTGW_OK) return rc;
     if ((rc = need_device(c, out_psi, "out_psi")) != LTGW_OK) return rc;
-    return list_psi_impl(c, g, idx, c->stack.R, m, nullptr, nullptr, out_psi, nullptr);
+    return list_psi_impl(c, g, idx, c->stack.R, m, nullptr, nullptr, out_psi, nullptr, stat);
 }
 
 int64_t ltgw_cnn_param_count(int32_t c_in, int32_t c_out) {
@@ -484,27 +535,24 @@ int32_t ltgw_select_top(ltgw_ctx *c, const float *score, int32_t R, int32_t n, i
     return LTGW_OK;
 }
 
-int32_t ltgw_stack_features(ltgw_ctx *c, const ltgw_grid *coarse, float *x) {
+int32_t ltgw_stack_features(ltgw_ctx *c, const ltgw_grid *coarse, int32_t counts, float *x) {
     if (!c) return LTGW_E_INVALID_ARG;
     Enter en(c);
     int rc = need_stack(c, 1);
     if (rc != LTGW_OK) return rc;
     if ((rc = need_device(c, x, "x")) != LTGW_OK) return rc;
     if (!coarse) return fail(c, LTGW_E_INVALID_ARG, "grid is NULL");
-    StackState &S = c->stack;
-    const int64_t n = (int64_t)coarse->n_f0 * coarse->n_tau * coarse->n_brake * coarse->n_sky;
-    if (n < 1) return fail(c, LTGW_E_INVALID_ARG, "empty grid");
-    if ((rc = ensure(c, S.psi_c, (size_t)(S.R * n) * 8, "coarse ratios")) != LTGW_OK) return rc;
-    if ((rc = stack_psi_impl(c, coarse, 1, 1, (double *)S.psi_c.p)) != LTGW_OK) return rc;
-    HIP_TRY(c, launch_f64_to_f32((const double *)S.psi_c.p, x, S.R * n, c->stream), "input convert");
-    return LTGW_OK;
+    if (counts != 0 && counts != 1) return fail(c, LTGW_E_INVALID_ARG, "counts must be 0 or 1");
+    return features_impl(c, coarse, counts, x, nullptr);
 }
 
-int32_t ltgw_stack_best(ltgw_ctx *c, const ltgw_grid *g, int32_t *best_index, double *best_psi) {
+int32_t ltgw_stack_best(ltgw_ctx *c, const ltgw_grid *g, uint32_t stat, int32_t *best_index, double *best_psi) {
     if (!c) return LTGW_E_INVALID_ARG;
     Enter en(c);
     int rc = need_stack(c, 0);
     if (rc != LTGW_OK) return rc;
+    if (stat != LTGW_STAT_POWER && stat != LTGW_STAT_COUNT)
+        return fail(c, LTGW_E_INVALID_ARG, "stat must be POWER or COUNT");
     if ((rc = need_device(c, best_index, "best_index")) != LTGW_OK) return rc;
     if ((rc = need_device(c, best_psi, "best_psi")) != LTGW_OK) return rc;
     if (!g) return fail(c, LTGW_E_INVALID_ARG, "grid is NULL");
@@ -512,7 +560,7 @@ int32_t ltgw_stack_best(ltgw_ctx *c, const ltgw_grid *g, int32_t *best_index, do
     const int64_t n = (int64_t)g->n_f0 * g->n_tau * g->n_brake * g->n_sky;
     if (n < 1) return fail(c, LTGW_E_INVALID_ARG, "empty grid");
     if ((rc = ensure(c, S.psi_all, (size_t)(S.R * n) * 8, "fine ratios")) != LTGW_OK) return rc;
-    if ((rc = stack_psi_impl(c, g, 0, 0, (double *)S.psi_all.p)) != LTGW_OK) return rc;
+    if ((rc = stack_psi_impl(c, g, 0, 0, (double *)S.psi_all.p, stat)) != LTGW_OK) return rc;
     HIP_TRY(c, launch_row_best((const double *)S.psi_all.p, S.R, n, nullptr, nullptr, best_index, best_psi,
                                c->stream),
             "reduction launch");
@@ -544,14 +592,26 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
     StackState &S = c->stack;
     const int R = S.R;
     const int L = p->L;
-    if ((rc = need_device(c, p->params, "proposer parameters")) != LTGW_OK) return rc;
+    const bool net = p->params != nullptr;  // else: the coarse power ratios alone rank the blocks
+    if (net && (rc = need_device(c, p->params, "proposer parameters")) != LTGW_OK) return rc;
+    if (!net && !p->coarse_map) return fail(c, LTGW_E_INVALID_ARG, "without a network the coarse_map is required");
     if (L < 1 || coarse->n_f0 != L || fine->n_f0 != 2 * L)
         return fail(c, LTGW_E_INVALID_ARG, "coarse grid needs L f0 points and the fine grid 2 L");
     const int64_t g_c = (int64_t)coarse->n_tau * coarse->n_brake * coarse->n_sky;
     const int64_t g_f = (int64_t)fine->n_tau * fine->n_brake * fine->n_sky;
-    if (p->c_in != g_c || p->c_out != 2 * g_f)
-        return fail(c, LTGW_E_INVALID_ARG, "network channels must be (coarse groups, 2 x fine groups) = (%lld, %lld)",
+    if ((p->c_in != g_c && p->c_in != 2 * g_c) || p->c_out != 2 * g_f)
+        return fail(c, LTGW_E_INVALID_ARG,
+                    "network channels must be (coarse groups %lld, or twice that with the count ratios; "
+                    "2 x fine groups = %lld)",
                     (long long)g_c, (long long)(2 * g_f));
+    const int with_counts = p->c_in == 2 * g_c ? 1 : 0;
+    if (!net)
+        for (int64_t q = 0; q < 2 * g_f; ++q)
+            if (p->coarse_map[q] < -1 || p->coarse_map[q] >= g_c || (q % 2 == 0 && p->coarse_map[q] < 0))
+                return fail(c, LTGW_E_INVALID_ARG,
+                            "coarse_map[%lld] = %d: each fine group needs a first coarse group in 0 .. %lld "
+                            "and a second one or -1",
+                            (long long)(q / 2), (int)p->coarse_map[q], (long long)(g_c - 1));
     if ((rc = cnn_shape_ok(c, R, p->c_in, p->c_out, L)) != LTGW_OK) return rc;
     const int W = p->block;
     if (W < 1 || W > 64) return fail(c, LTGW_E_INVALID_ARG, "block must be in 1 .. 64");
@@ -563,14 +623,15 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
                     (long long)nb);
     if (!fin(p->psi_threshold) || !fin(p->coarse_threshold) || !fin(p->tier2_threshold))
         return fail(c, LTGW_E_INVALID_ARG, "thresholds must be finite");
-    const int64_t nc = g_c * L, n_cells = (int64_t)p->c_out * L;
+    const int64_t nc = g_c * L, n_cells = (int64_t)p->c_out * L, nx = (int64_t)p->c_in * L;
     const int M1 = K1 * W, M2 = K2 * W;
     // the fused network pass keeps activations and logits on chip
-    const bool fused = cnn_infer_supported(p->c_in, p->c_out, L) && (W == 16 || W == 32 || W == 64);
+    const bool fused = !net || (cnn_infer_supported(p->c_in, p->c_out, L) && (W == 16 || W == 32 || W == 64));
     struct {
         DevBuf *b;
         size_t bytes;
-    } need[] = {{&S.psi_c, (size_t)(R * nc) * 8},       {&S.x, (size_t)(R * nc) * 4},
+    } need[] = {{&S.psi_c, (size_t)(R * nc) * 8},       {&S.x, (size_t)(R * nx) * 4},
+                {&S.cmap, net ? 0 : (size_t)g_f * 2 * 4},
                 {&S.act, fused ? 0 : (size_t)R * 3 * 32 * L * 4},
                 {&S.logits, fused ? 0 : (size_t)(R * n_cells) * 4},
                 {&S.bscore, (size_t)(R * nb) * 4},       {&S.blk, (size_t)R * K1 * 4},
@@ -581,10 +642,15 @@ int32_t ltgw_propose(ltgw_ctx *c, const ltgw_grid *fine, const ltgw_grid *coarse
         if ((rc = ensure(c, *n.b, n.bytes, "proposer buffers")) != LTGW_OK) return rc;
     // Every step is queued on the stream; the host waits once, for the outputs.
     // 1. coarse map -> network -> block scores -> the K1 best blocks -> their exact fine ratios
-    if ((rc = stack_psi_impl(c, coarse, 1, 1, (double *)S.psi_c.p)) != LTGW_OK) return rc;
-    HIP_TRY(c, launch_f64_to_f32((const double *)S.psi_c.p, (float *)S.x.p, R * nc, c->stream), "input convert");
+    if ((rc = features_impl(c, coarse, with_counts, (float *)S.x.p, (double *)S.psi_c.p)) != LTGW_OK) return rc;
     // the network and the block scores: one fused pass where the shape allows it
-    if (fused) {
+    if (!net) {
+        // the method alone: each block scored by its nearest coarse groups' power ratios
+        if ((rc = h2d(c, S.cmap.p, p->coarse_map, (size_t)g_f * 2 * 4, "coarse map upload")) != LTGW_OK) return rc;
+        HIP_TRY(c, launch_coarse_block_scores((const float *)S.x.p, R, (int)nb, p->c_in, L, W, nbg,
+                                              (const int32_t *)S.cmap.p, (float *)S.bscore.p, c->stream),
+                "coarse block score launch");
+    } else if (fused) {
         if ((rc = ensure(c, c->cnn_packed, (size_t)cnn_infer_scratch_shorts(p->c_in) * 2, "packed weights")) !=
             LTGW_OK)
             return rc;

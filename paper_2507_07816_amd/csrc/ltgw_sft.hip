@@ -177,17 +177,24 @@ int32_t ltgw_sft_normalise(ltgw_ctx *c, const float *strain, int32_t n_seg, int3
         for (auto &pl : c->sft_plans)
             if (pl.n_fft == n_fft && pl.batch == nb) plan = (hipfftHandle)pl.plan;
         if (!plan) {
-            int n = n_fft;
-            const hipfftResult r = hipfftPlanMany(&plan, 1, &n, nullptr, 1, n_fft, nullptr, 1, n_fft / 2 + 1,
+            // in place: rows of n_fft + 2 reals in, n_fft / 2 + 1 complex out
+            int n = n_fft, in_len = n_fft + 2, out_len = n_fft / 2 + 1;
+            const hipfftResult r = hipfftPlanMany(&plan, 1, &n, &in_len, 1, n_fft + 2, &out_len, 1, n_fft / 2 + 1,
                                                   HIPFFT_R2C, nb);
             if (r != HIPFFT_SUCCESS) return fail(c, LTGW_E_DEVICE, "FFT plan: %s", fft_error(r));
             c->sft_plans.push_back({n_fft, nb, (void *)plan});
         }
-        // out-of-place real-to-complex: the caller's strain is read, not written
+        // the chunk's segments are copied into the spectra buffer (rows padded
+        // to n_fft + 2 reals) and transformed there in place: the library's
+        // transform may use its input as scratch, and the caller's strain is
+        // only read
+        HIP_TRY(c, hipMemcpy2DAsync(c->sft_spec.p, (size_t)(n_fft + 2) * 4, strain + (int64_t)j0 * n_fft,
+                                    (size_t)n_fft * 4, (size_t)n_fft * 4, (size_t)nb, hipMemcpyDeviceToDevice,
+                                    c->stream),
+                "strain copy");
         hipfftResult r = hipfftSetStream(plan, c->stream);
         if (r == HIPFFT_SUCCESS)
-            r = hipfftExecR2C(plan, const_cast<hipfftReal *>(strain + (int64_t)j0 * n_fft),
-                              (hipfftComplex *)c->sft_spec.p);
+            r = hipfftExecR2C(plan, (hipfftReal *)c->sft_spec.p, (hipfftComplex *)c->sft_spec.p);
         if (r != HIPFFT_SUCCESS) return fail(c, LTGW_E_DEVICE, "FFT: %s", fft_error(r));
         hipLaunchKernelGGL(normalise_kernel, dim3((unsigned)((n_bins + kSftTile - 1) / kSftTile), (unsigned)nb),
                            dim3(256), 0, c->stream, (const float2 *)c->sft_spec.p, (int64_t)(n_fft / 2 + 1), k_lo,

@@ -72,6 +72,19 @@ __device__ inline double stack_ratio(double s, const StackMoments &m, int64_t tt
     return num / sqrt(var * m.w2[tt]);
 }
 
+// The ratio a stack kernel writes for a template with power sum s and count
+// c: power (above), or with m.count the count ratio in the operation order of
+// the single-search ratio (the same value bit for bit).
+__device__ inline double stack_stat(double s, int c, const StackMoments &m, int64_t tt, double mu, double var,
+                                    int nan_to_zero) {
+    if (!m.count) return stack_ratio(s, m, tt, mu, var, nan_to_zero);
+    const int nn = m.n[tt];
+    if (nn == 0) return nan_to_zero ? 0.0 : __builtin_nan("");
+    const double Nq = (double)nn * m.q;
+    const double num = (double)c - Nq;
+    return num / sqrt(Nq * (1.0 - m.q));
+}
+
 // Every template of a grid on every realisation: the power critical ratio.
 // One workgroup per (256 f0, group, output row) and pass.  The hardware deals
 // workgroups to the XCDs in turn; workgroup w goes to row x + 8 (k / per_row)
@@ -110,7 +123,7 @@ __global__ __launch_bounds__(256) void stack_eval_kernel(const EvalArgs a, int R
         accumulate_det<STORE, false, 1, 16, HTable, SHIFT>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc);
         if (i < a.n_f0)
             out_psi[(int64_t)rr * ((int64_t)a.n_groups * a.n_f0) + tt] =
-                stack_ratio(acc.s[0], m, tt, mu, var, nan_to_zero);
+                stack_stat(acc.s[0], acc.cnt[0], m, tt, mu, var, nan_to_zero);
     }
 }
 
@@ -131,13 +144,102 @@ hipError_t launch_stack_eval(int store, int shift, const EvalArgs &a, int R, int
         LTGW_STACK_EVAL(LTGW_STORE_F32, 0);
     else if (store == LTGW_STORE_BF16 && shift == 0)
         LTGW_STACK_EVAL(LTGW_STORE_BF16, 0);
-    else if (store == LTGW_STORE_BF16 && shift == 1)
-        LTGW_STACK_EVAL(LTGW_STORE_BF16, 1);
+    else if (store == kStoreCoarse && shift == 1)
+        LTGW_STACK_EVAL(kStoreCoarse, 1);
     else if (store == LTGW_STORE_FP8 && shift == 0)
         LTGW_STACK_EVAL(LTGW_STORE_FP8, 0);
     else
         return hipErrorInvalidValue;
 #undef LTGW_STACK_EVAL
+    return hipGetLastError();
+}
+
+// The network's input on the coarse store: for every template of the coarse
+// grid and every realisation, the power critical ratio (mean and variance
+// mu = 2 S per pixel) into channel g and, with counts, the number-count
+// critical ratio into channel G + g (G coarse groups): (c - N m q) /
+// sqrt(N m q (1 - q)) with m = 2 S pixels per coarse pixel, N the in-band
+// coarse segments, q = exp(-rho_th).  x[r][channel][f0] in FP32, 0 where N = 0.
+// psi (optional): the power ratio in FP64 as stack_eval_kernel writes it
+// (NaN -> 0), for the per-row coarse maximum.  One workgroup per (256 f0,
+// group, realisation), the XCD order of stack_eval_kernel.
+__global__ __launch_bounds__(256) void stack_features_kernel(const EvalArgs a, int R, int64_t stack_bytes,
+                                                             int64_t stack_rows, double mu, double q, int counts,
+                                                             const StackMoments m, float *__restrict__ x,
+                                                             double *__restrict__ psi) {
+    const int n_tiles = (a.n_f0 + 255) / 256;
+    const int per_row = n_tiles * a.n_groups;
+    const int P = (int)gridDim.x / per_row;
+    const int xc = (int)blockIdx.x % kXcds, k = (int)blockIdx.x / kXcds;
+    const int qq = k % per_row;
+    const int tile = qq / a.n_groups, grp = qq % a.n_groups;
+    if (tile * 256 + (int)(threadIdx.x & ~63u) >= a.n_f0) return;
+    const int i = tile * 256 + (int)threadIdx.x;
+    const double f0[1] = {a.f0_min + (double)i * a.f0_step};
+    const int64_t tt = (int64_t)grp * a.n_f0 + i;
+    const int64_t n_tpl = (int64_t)a.n_groups * a.n_f0;
+    const int channels = counts ? 2 * a.n_groups : a.n_groups;
+    for (int r = xc + kXcds * (k / per_row); r < R; r += P) {
+        DetView D = a.det[0];
+        D.store = (const char *)D.store + (int64_t)r * stack_bytes;
+        D.wq += (int64_t)r * stack_rows;
+        D.w += (int64_t)r * stack_rows;
+        Acc<1> acc;
+        acc.zero();
+        accumulate_det<kStoreCoarse, false, 1, 16, HTable, 1>(D, HTable{D.H + (int64_t)grp * D.n_seg}, f0, acc);
+        if (i >= a.n_f0) continue;
+        const double rp = stack_ratio(acc.s[0], m, tt, mu, mu, 1);
+        float *xr = x + (int64_t)r * channels * a.n_f0;
+        xr[tt] = (float)rp;
+        if (psi) psi[(int64_t)r * n_tpl + tt] = rp;
+        if (counts) {
+            const int nn = m.n[tt];
+            double rc = 0.0;
+            if (nn > 0) {
+                const double e = ((double)nn * mu) * q;  // N m q: the count's mean under noise
+                rc = ((double)acc.cnt[0] - e) / sqrt(e * (1.0 - q));
+            }
+            xr[n_tpl + tt] = (float)rc;
+        }
+    }
+}
+
+hipError_t launch_stack_features(const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows, double mu,
+                                 double q, int counts, StackMoments m, float *x, double *psi, hipStream_t st) {
+    const int P = (R + kXcds - 1) / kXcds * kXcds;
+    const int64_t blocks = (int64_t)((a.n_f0 + 255) / 256) * a.n_groups * P;
+    if (blocks > 0x7fffffff || R > 65535 || R < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stack_features_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a, R, stack_bytes,
+                       stack_rows, mu, q, counts, m, x, psi);
+    return hipGetLastError();
+}
+
+// The ranking without a network (the method alone): block b of fine group
+// G = b / nbg, fine f0 indices (b % nbg) W .. + W - 1 (below 2 L), scores the
+// largest coarse power ratio x[r][ch][i / 2] over its f0 and over the coarse
+// channels map[G][0], map[G][1] (-1: none) of the coarse groups nearest G.
+__global__ void coarse_block_scores_kernel(const float *__restrict__ x, int R, int nb, int c_in, int L, int W,
+                                           int nbg, const int32_t *__restrict__ map, float *__restrict__ score) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)R * nb) return;
+    const int r = (int)(e / nb), b = (int)(e % nb);
+    const int G = b / nbg, i0 = (b % nbg) * W, i1 = min(i0 + W, 2 * L);
+    const float *xr = x + (int64_t)r * c_in * L;
+    float best = -__builtin_inff();
+    for (int h = 0; h < 2; ++h) {
+        const int ch = map[2 * G + h];
+        if (ch < 0) continue;
+        for (int l = i0 / 2; l <= (i1 - 1) / 2; ++l) best = fmaxf(best, xr[(int64_t)ch * L + l]);
+    }
+    score[e] = best;
+}
+
+hipError_t launch_coarse_block_scores(const float *x, int R, int nb, int c_in, int L, int W, int nbg,
+                                      const int32_t *map, float *score, hipStream_t st) {
+    const int64_t total = (int64_t)R * nb;
+    if (total < 1 || (total + 255) / 256 > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(coarse_block_scores_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, x, R,
+                       nb, c_in, L, W, nbg, map, score);
     return hipGetLastError();
 }
 
@@ -198,7 +300,7 @@ __global__ __launch_bounds__(256) void list_eval_kernel(const EvalArgs a, int64_
         s += (double)sc;
     }
     if (q >= m) return;
-    out_psi[(int64_t)rr * m + q] = bad ? __builtin_nan("") : stack_ratio(s, mom, t, 1.0, 1.0, 0);
+    out_psi[(int64_t)rr * m + q] = bad ? __builtin_nan("") : stack_stat(s, cnt, mom, t, 1.0, 1.0, 0);
 }
 
 hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_bytes, int64_t stack_rows,

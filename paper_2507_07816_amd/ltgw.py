@@ -79,7 +79,7 @@ class ltgw_candidate(C.Structure):
 class ltgw_diag(C.Structure):
     _fields_ = [("pow_undecided", C.c_int64), ("templates", C.c_int64), ("evals", C.c_int64),
                 ("in_band", C.c_int64), ("eval_kernel_ms", C.c_double), ("tables_ms", C.c_double),
-                ("tile_shape", C.c_int32), ("eval_launches", C.c_int32)]
+                ("tile_shape", C.c_int32), ("eval_launches", C.c_int32), ("ingest_ms", C.c_double)]
 
 
 class ltgw_search(C.Structure):
@@ -98,7 +98,7 @@ class ltgw_proposer(C.Structure):
     _fields_ = [("params", C.c_void_p), ("c_in", C.c_int32), ("c_out", C.c_int32), ("L", C.c_int32),
                 ("n_select", C.c_int32), ("block", C.c_int32), ("n_select2", C.c_int32),
                 ("psi_threshold", C.c_double), ("coarse_threshold", C.c_double), ("tier2_threshold", C.c_double),
-                ("blocks", C.c_void_p)]
+                ("blocks", C.c_void_p), ("coarse_map", C.c_void_p)]
 
 
 class LtgwError(RuntimeError):
@@ -149,7 +149,7 @@ def library():
             "ltgw_inject_stack": (i32, [P, i32, P, i32, P, P, d]),
             "ltgw_load_stack": (i32, [P, i32, i32, P, i32, i32]),
             "ltgw_stack_psi": (i32, [P, C.POINTER(ltgw_grid), i32, i32, P]),
-            "ltgw_stack_psi_list": (i32, [P, C.POINTER(ltgw_grid), P, i32, P]),
+            "ltgw_stack_psi_list": (i32, [P, C.POINTER(ltgw_grid), u32, P, i32, P]),
             "ltgw_cnn_param_count": (C.c_int64, [i32, i32]),
             "ltgw_cnn_work_floats": (C.c_int64, [i32, i32, i32, i32]),
             "ltgw_cnn_forward": (i32, [P, P, P, i32, i32, i32, i32, P, P]),
@@ -157,8 +157,8 @@ def library():
             "ltgw_softmax_xent": (i32, [P, P, i32, i32, P, i32, P, P]),
             "ltgw_adam_step": (i32, [P, P, P, P, P, C.c_int64, f, f, f, f, i32]),
             "ltgw_select_top": (i32, [P, P, i32, i32, i32, P]),
-            "ltgw_stack_features": (i32, [P, C.POINTER(ltgw_grid), P]),
-            "ltgw_stack_best": (i32, [P, C.POINTER(ltgw_grid), P, P]),
+            "ltgw_stack_features": (i32, [P, C.POINTER(ltgw_grid), i32, P]),
+            "ltgw_stack_best": (i32, [P, C.POINTER(ltgw_grid), u32, P, P]),
             "ltgw_cells_from_templates": (i32, [P, P, i32, i32, P, P, d, P]),
             "ltgw_propose": (i32, [P, C.POINTER(ltgw_grid), C.POINTER(ltgw_grid), C.POINTER(ltgw_proposer),
                                    P, P, P]),
@@ -463,20 +463,20 @@ def ltgw_stack_psi(ctx, grid, level, out_psi, nan_to_zero=False):
                                          _dev(out_psi, torch.float64)))
 
 
-def ltgw_stack_psi_list(ctx, grid, idx, out_psi):
+def ltgw_stack_psi_list(ctx, grid, idx, out_psi, stat="power"):
     import torch
-    _check(ctx, library().ltgw_stack_psi_list(ctx, C.byref(grid), _dev(idx, torch.int32), int(idx.shape[1]),
-                                              _dev(out_psi, torch.float64)))
+    _check(ctx, library().ltgw_stack_psi_list(ctx, C.byref(grid), STATS.get(stat, stat), _dev(idx, torch.int32),
+                                              int(idx.shape[1]), _dev(out_psi, torch.float64)))
 
 
-def ltgw_stack_features(ctx, grid, x):
+def ltgw_stack_features(ctx, grid, x, counts=False):
     import torch
-    _check(ctx, library().ltgw_stack_features(ctx, C.byref(grid), _dev(x, torch.float32)))
+    _check(ctx, library().ltgw_stack_features(ctx, C.byref(grid), 1 if counts else 0, _dev(x, torch.float32)))
 
 
-def ltgw_stack_best(ctx, grid, best_index, best_psi):
+def ltgw_stack_best(ctx, grid, best_index, best_psi, stat="power"):
     import torch
-    _check(ctx, library().ltgw_stack_best(ctx, C.byref(grid), _dev(best_index, torch.int32),
+    _check(ctx, library().ltgw_stack_best(ctx, C.byref(grid), STATS.get(stat, stat), _dev(best_index, torch.int32),
                                           _dev(best_psi, torch.float64)))
 
 
@@ -542,15 +542,19 @@ def propose_block_counts(n_select, n_select2, block):
 
 
 def ltgw_propose(ctx, fine, coarse, params, c_in, c_out, L, n_select, psi_threshold, coarse_threshold, R,
-                 block=1, n_select2=0, return_blocks=False, tier2_threshold=-1e300):
+                 block=1, n_select2=0, return_blocks=False, tier2_threshold=-1e300, coarse_map=None):
     """(best_index[R], best_psi[R], fallback[R]) numpy arrays, and with
-    return_blocks the evaluated blocks [R][K1 + K2] (-1: tier not taken)."""
+    return_blocks the evaluated blocks [R][K1 + K2] (-1: tier not taken).
+    params None: rank by the coarse power ratios through coarse_map
+    ([fine groups][2] int32)."""
     import torch
     K1, K2 = propose_block_counts(n_select, n_select2, block)
     blocks = np.empty((R, K1 + K2), np.int32) if return_blocks else None
-    p = ltgw_proposer(_dev(params, torch.float32), int(c_in), int(c_out), int(L), int(n_select), int(block),
-                      int(n_select2), float(psi_threshold), float(coarse_threshold), float(tier2_threshold),
-                      blocks.ctypes.data if return_blocks else None)
+    cmap = None if coarse_map is None else np.ascontiguousarray(coarse_map, dtype=np.int32)
+    p = ltgw_proposer(None if params is None else _dev(params, torch.float32), int(c_in), int(c_out), int(L),
+                      int(n_select), int(block), int(n_select2), float(psi_threshold), float(coarse_threshold),
+                      float(tier2_threshold), blocks.ctypes.data if return_blocks else None,
+                      None if cmap is None else cmap.ctypes.data)
     bi = np.empty(R, np.int32)
     bp = np.empty(R, np.float64)
     fb = np.empty(R, np.int32)

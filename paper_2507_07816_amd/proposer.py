@@ -75,6 +75,26 @@ def close_region(fine, inj, df=2, dg=1):
     return np.where(ok, (k * len(tau) + j) * n_f0 + i, -1)
 
 
+def nearest_coarse_groups(fine, coarse):
+    """For each fine (sky, n, tau) group, the coarse groups nearest to it in
+    tau (by log) and in n, two at most ([n_fine][2] int32, -1 where there is
+    one): the cells the coarse map speaks for when no network ranks them."""
+    def nearest(v, grid):
+        d = np.abs(grid - v)
+        return [int(k) for k in np.nonzero(d <= d.min() * (1 + 1e-12) + 1e-300)[0]]
+    ft, fb = np.log(np.asarray(fine["tau"], np.float64)), np.asarray(fine["brake"], np.float64)
+    ct, cb = np.log(np.asarray(coarse["tau"], np.float64)), np.asarray(coarse["brake"], np.float64)
+    n_sky = len(np.asarray(fine["sky"]).reshape(-1, 3))
+    out = []
+    for s in range(n_sky):
+        for i_n in range(len(fb)):
+            for i_t in range(len(ft)):
+                cand = [(s * len(cb) + kn) * len(ct) + kt for kn in nearest(fb[i_n], cb) for kt in nearest(ft[i_t], ct)]
+                cand = sorted(cand)[:2]
+                out.append(cand + [-1] * (2 - len(cand)))
+    return np.asarray(out, np.int32)
+
+
 def evaluated(blocks, fallback, tpl, L, block):
     """Whether fine template tpl[r] (fine n_f0 = 2 L) was among the cells that
     realisation r evaluated exactly: its block (group, f0 index // block) in
@@ -90,7 +110,7 @@ class Proposer:
     `det` holds the geometry (segment times, weights, velocities)."""
 
     def __init__(self, ctx, det, shape, fine, coarse, seed=0, select_frac=0.05, store="f32", block=1,
-                 select2_frac=0.0, coarse_segments=2):
+                 select2_frac=0.0, coarse_segments=2, counts=True):
         import torch
 
         if fine["n_f0"] % 2:
@@ -101,7 +121,11 @@ class Proposer:
         self.n_seg, self.n_bins = shape
         self.fine, self.coarse = fine, coarse
         self.L = fine["n_f0"] // 2
-        self.c_in = _n_groups(coarse)
+        # input channels: the coarse power ratio of each coarse group, then
+        # (counts) its coarse number-count ratio
+        self.counts = bool(counts)
+        self.c_in = (2 if self.counts else 1) * _n_groups(coarse)
+        self.coarse_map = nearest_coarse_groups(fine, coarse)
         self.c_out = 2 * _n_groups(fine)
         self.n_cells = self.c_out * self.L
         self.n_select = max(1, int(round(select_frac * self.n_cells)))
@@ -168,7 +192,7 @@ class Proposer:
         ltgw.ltgw_inject_stack(h, self.det, b["stack"], inj, np.asarray(self.fine["sky"]).reshape(3),
                                self.fine.get("t0", 0.0))
         ltgw.ltgw_load_stack(h, self.det, b["stack"], self.store, coarse=self.coarse_segments)
-        ltgw.ltgw_stack_features(h, self._cg, b["x"])
+        ltgw.ltgw_stack_features(h, self._cg, b["x"], counts=self.counts)
         if with_labels:
             ltgw.ltgw_stack_best(h, self._fg, b["best"], b["best_psi"])
         return b
@@ -239,12 +263,15 @@ class Proposer:
                                               label_psi=label_psi, label=label))
         return losses
 
-    def propose(self, psi_threshold, coarse_threshold, R, return_blocks=False, tier2_threshold=-1e300):
-        """ltgw_propose on the loaded stack: (best_index, best_psi, fallback[, blocks])."""
-        return ltgw.ltgw_propose(self.ctx.h, self._fg, self._cg, self.params, self.c_in, self.c_out, self.L,
-                                 self.n_select, psi_threshold, coarse_threshold, R, block=self.block,
-                                 n_select2=self.n_select2, return_blocks=return_blocks,
-                                 tier2_threshold=tier2_threshold)
+    def propose(self, psi_threshold, coarse_threshold, R, return_blocks=False, tier2_threshold=-1e300,
+                network=True):
+        """ltgw_propose on the loaded stack: (best_index, best_psi, fallback[, blocks]).
+        network=False ranks the blocks by the coarse power ratios alone (the
+        nearest coarse groups of each fine group), the same budget otherwise."""
+        return ltgw.ltgw_propose(self.ctx.h, self._fg, self._cg, self.params if network else None, self.c_in,
+                                 self.c_out, self.L, self.n_select, psi_threshold, coarse_threshold, R,
+                                 block=self.block, n_select2=self.n_select2, return_blocks=return_blocks,
+                                 tier2_threshold=tier2_threshold, coarse_map=None if network else self.coarse_map)
 
     def save(self, path):
         """Write the network (ltgw_proposer_save)."""
@@ -271,48 +298,60 @@ class Proposer:
         ltgw.ltgw_stack_best(self.ctx.h, self._fg, b["best"], b["best_psi"])
         return b["best"].cpu().numpy().copy(), b["best_psi"].cpu().numpy().copy()
 
+    def _ingest_ms(self, stack, store, coarse, reps):
+        """Device time of the store kernels of ltgw_load_stack (best of reps)."""
+        t = []
+        for _ in range(reps):
+            ltgw.ltgw_load_stack(self.ctx.h, self.det, stack, store, coarse=coarse)
+            t.append(ltgw.ltgw_diagnostics(self.ctx.h)["ingest_ms"])
+        return min(t)
+
     def evaluate(self, R_noise=256, R_signal=256, amp_range=(1.0, 3.0), fine_store="bf16", reps=3,
-                 coarse_quantiles=(1.0,), target_recall=0.99, tier2_quantile=None):
-        """Recall and speed against the exhaustive search.
+                 coarse_quantiles=(1.0,), target_recall=0.99, tier2_quantile=None, baseline=True):
+        """Recall and speed against the exhaustive search, for the network and
+        (baseline) for the ranking by the coarse power ratios alone at the
+        same budget (blocks, tiers, thresholds, fallback rule).
 
         Thresholds: psi_threshold is the largest exhaustive fine ratio over
         R_noise noise-only realisations (the detection rule of Sec. 3); for
         each q in coarse_quantiles the fallback's coarse threshold is the q
-        quantile of the largest coarse ratio of each noise realisation (1.0:
-        their maximum); with tier2_quantile, the second tier is taken only
-        above that quantile of the same maxima.  On R_signal realisations with injections, an
-        injection is detectable when the exhaustive FP32 search passes
-        psi_threshold, and recalled when the proposer (coarse BF16 map,
-        network, n_select exact cells on the `fine_store` store, fallback)
-        passes it too; recall_no_fallback is the same with the fallback off.
-        Recall follows the detection rule with "close to the injection" read
-        as the neighbourhood of close_region: an injection is detectable when
-        the exhaustive FP32 search's best template of that neighbourhood
-        passes psi_threshold, and recalled when the proposer evaluated that
-        template exactly and its ratio there (on the `fine_store` store)
-        passes the threshold too.  recall_best is the looser figure over the
-        realisation's overall best (exhaustive best above the threshold;
-        proposer best above it).
-        Times: exhaustive FP32 search (ltgw_stack_best) and ltgw_propose on
-        the same realisations, HIP events on the context's stream, best of
-        `reps`.  The operating point reported at the top level is the fastest
-        quantile whose recall reaches target_recall, else the best recall;
-        every quantile's figures are under "points"."""
+        quantile of the largest coarse power ratio of each noise realisation
+        (1.0: their maximum); with tier2_quantile, the second tier is taken
+        only above that quantile of the same maxima.  Recall follows the
+        detection rule with "close to the injection" read as the
+        neighbourhood of close_region: an injection is detectable when the
+        exhaustive FP32 search's best template of that neighbourhood passes
+        psi_threshold, and recalled when the proposer evaluated that template
+        exactly and its ratio there (on the `fine_store` store) passes the
+        threshold too; recall_best is the looser figure over the
+        realisation's overall best; recall_no_fallback is recall with the
+        fallback off.
+        Times (HIP events on the context's stream, best of `reps`): the
+        exhaustive FP32 search (ltgw_stack_best) and ltgw_propose on the same
+        realisations.  The coarse store is written in the same pass as the
+        fine store; what it adds to that pass (ingest of the fine store with
+        the coarse one, less the ingest of the fine store alone) is charged
+        to the proposer: speedup = exhaustive / (propose + coarse_extra).
+        The FP32 store the exhaustive search reads costs more to ingest than
+        the BF16 one, which is not credited.  The operating point reported is
+        the fastest quantile whose recall reaches target_recall, else the
+        best recall; every quantile's figures are under "points"."""
         T = self.torch
         h = self.ctx.h
         zeros = np.zeros((R_noise, 4))
         b = self.make_batch(R_noise, 2, 0, zeros, with_labels=False)
         _, noise_best = self.exhaustive(R_noise)
         psi_thr = float(np.max(noise_best))
-        coarse_max = b["x"].cpu().numpy().reshape(R_noise, -1).max(axis=1)
+        G = _n_groups(self.coarse)
+        coarse_max = b["x"][:, :G].cpu().numpy().reshape(R_noise, -1).max(axis=1)
         # the held-out injections come from their own generator, so the
         # evaluation set does not depend on how long the network was trained
         inj, sig = self.draw_injections(R_signal, 1.0, amp_range,
                                         rng=np.random.Generator(np.random.PCG64(self.seed + 7919)))
         b = self.make_batch(R_signal, 3, 0, inj, with_labels=False)
         ev0, ev1 = T.cuda.Event(enable_timing=True), T.cuda.Event(enable_timing=True)
+        ingest = dict(f32=self._ingest_ms(b["stack"], "f32", 0, reps))
         t_ex = []
-        ltgw.ltgw_load_stack(h, self.det, b["stack"], "f32", coarse=False)
         for _ in range(reps):
             ev0.record()
             ltgw.ltgw_stack_best(h, self._fg, b["best"], b["best_psi"])
@@ -324,7 +363,9 @@ class Proposer:
         # the exhaustive search's best template close to each injection (the
         # listed evaluation gives the exhaustive kernel's sums, bit for bit)
         near_tpl, near_psi = self.near_best(inj)
-        ltgw.ltgw_load_stack(h, self.det, b["stack"], fine_store, coarse=self.coarse_segments)
+        ingest[fine_store] = self._ingest_ms(b["stack"], fine_store, 0, reps)
+        ingest[fine_store + "+coarse"] = self._ingest_ms(b["stack"], fine_store, self.coarse_segments, reps)
+        coarse_extra = max(0.0, ingest[fine_store + "+coarse"] - ingest[fine_store])
         near_prop = T.empty((R_signal, 1), dtype=T.float64, device=self.ctx.device)
         ltgw.ltgw_stack_psi_list(h, self._fg, T.from_numpy(np.maximum(near_tpl, 0).reshape(-1, 1)).to(self.ctx.device),
                                  near_prop)
@@ -340,35 +381,45 @@ class Proposer:
             return frac(hit, det_near, n_near), frac(pp > psi_thr, det_ex, n_det)
 
         t2 = -1e300 if tier2_quantile is None else float(np.quantile(coarse_max, tier2_quantile))
-        _, pp_nf, fb_nf, bl_nf = self.propose(psi_thr, 1e300, R_signal, return_blocks=True,
-                                              tier2_threshold=t2)          # fallback never taken
-        rec_nf, rec_best_nf = recalls(pp_nf, fb_nf, bl_nf)
-        points = []
-        for q in coarse_quantiles:
-            coarse_thr = float(np.quantile(coarse_max, q))
-            t_pr = []
-            for _ in range(reps):
-                ev0.record()
-                self.propose(psi_thr, coarse_thr, R_signal, tier2_threshold=t2)
-                ev1.record()
-                ev1.synchronize()
-                t_pr.append(ev0.elapsed_time(ev1))
-            pi, pp, fb, bl = self.propose(psi_thr, coarse_thr, R_signal, return_blocks=True, tier2_threshold=t2)
-            rec, rec_best = recalls(pp, fb, bl)
-            points.append(dict(coarse_quantile=q, coarse_threshold=coarse_thr, recall=rec, recall_best=rec_best,
-                               fallback_frac=float(fb.mean()), propose_ms=min(t_pr),
-                               speedup=min(t_ex) / min(t_pr),
-                               same_template=float((pi[det_ex] == ex_idx[det_ex]).mean()) if n_det else float("nan")))
-        ok = [p for p in points if p["recall"] >= target_recall]
-        best = max(ok, key=lambda p: p["speedup"]) if ok else max(points, key=lambda p: (p["recall"], p["speedup"]))
+
+        def operating_points(network):
+            _, pp_nf, fb_nf, bl_nf = self.propose(psi_thr, 1e300, R_signal, return_blocks=True,
+                                                  tier2_threshold=t2, network=network)  # fallback never taken
+            rec_nf, rec_best_nf = recalls(pp_nf, fb_nf, bl_nf)
+            points = []
+            for q in coarse_quantiles:
+                coarse_thr = float(np.quantile(coarse_max, q))
+                t_pr = []
+                for _ in range(reps):
+                    ev0.record()
+                    self.propose(psi_thr, coarse_thr, R_signal, tier2_threshold=t2, network=network)
+                    ev1.record()
+                    ev1.synchronize()
+                    t_pr.append(ev0.elapsed_time(ev1))
+                pi, pp, fb, bl = self.propose(psi_thr, coarse_thr, R_signal, return_blocks=True,
+                                              tier2_threshold=t2, network=network)
+                rec, rec_best = recalls(pp, fb, bl)
+                points.append(dict(coarse_quantile=q, coarse_threshold=coarse_thr, recall=rec, recall_best=rec_best,
+                                   fallback_frac=float(fb.mean()), propose_ms=min(t_pr),
+                                   speedup=min(t_ex) / (min(t_pr) + coarse_extra),
+                                   speedup_search_only=min(t_ex) / min(t_pr),
+                                   same_template=float((pi[det_ex] == ex_idx[det_ex]).mean()) if n_det
+                                   else float("nan")))
+            ok = [p for p in points if p["recall"] >= target_recall]
+            best = max(ok, key=lambda p: p["speedup"]) if ok else max(points, key=lambda p: (p["recall"], p["speedup"]))
+            out = dict(best)
+            out.update(recall_no_fallback=rec_nf, recall_best_no_fallback=rec_best_nf, points=points)
+            return out
+
         amp = inj[:, 3]
-        out = dict(best)
-        out.update(recall_no_fallback=rec_nf, recall_best_no_fallback=rec_best_nf, detectable=n_near,
-                   detectable_best=n_det, realisations=R_signal,
+        out = operating_points(True)
+        out.update(detectable=n_near, detectable_best=n_det, realisations=R_signal,
                    detectable_min_amp=float(amp[det_near].min()) if n_near else float("nan"),
                    psi_threshold=psi_thr, tier2_quantile=tier2_quantile, tier2_threshold=t2,
-                   exhaustive_ms=min(t_ex), n_select=self.n_select,
-                   n_select2=self.n_select2, block=self.block, coarse_segments=self.coarse_segments,
-                   n_cells=self.n_cells,
-                   fine_store=fine_store, target_recall=target_recall, points=points)
+                   exhaustive_ms=min(t_ex), ingest_ms=ingest, coarse_extra_ms=coarse_extra,
+                   n_select=self.n_select, n_select2=self.n_select2, block=self.block,
+                   coarse_segments=self.coarse_segments, input_channels=self.c_in, counts=self.counts,
+                   n_cells=self.n_cells, fine_store=fine_store, target_recall=target_recall)
+        if baseline:
+            out["coarse_only"] = operating_points(False)
         return out
