@@ -182,11 +182,14 @@ def precision_report(ref, runs):
 
 
 def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_signal=4096, eval_noise=1024, seed=7,
-                 coarse_segments=4, select2_frac=0.20, block=64, label="near", select_frac=0.10, tier2_quantile=None):
+                 coarse_segments=8, select2_frac=0.0, block=32, label="near", select_frac=0.05, tier2_quantile=None,
+                 counts=True):
     """The learned proposer on the small workload's shape (1024 segments x 800
     bins, 4800 fine templates): trained on `realisations` device-generated
     noise + injection realisations (amplitudes U[0.3, 3]), then recall and
-    speed against the plain FP32 exhaustive search.  Returns the JSON object."""
+    speed against the plain FP32 exhaustive search, beside the ranking by the
+    coarse power ratios alone at the same budget (the method without the
+    network).  Returns the JSON object."""
     import synth
     from paper_2507_07816_amd.proposer import Proposer, coarse_grid_for
 
@@ -204,7 +207,7 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
     cbrake = np.array([(brake[0] + brake[1]) / 2, (brake[-2] + brake[-1]) / 2])
     coarse = coarse_grid_for(fine, ctau, cbrake)
     pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=select_frac, store="f32", block=block,
-                  select2_frac=select2_frac, coarse_segments=coarse_segments)
+                  select2_frac=select2_frac, coarse_segments=coarse_segments, counts=counts)
     steps = max(1, realisations // batch)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -213,18 +216,19 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t
     ev = pr.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
-                     coarse_quantiles=(1.0, 0.9, 0.7, 0.5, 0.3), tier2_quantile=tier2_quantile)
-    untrained = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed + 1, select_frac=select_frac, store="f32",
-                         block=block, select2_frac=select2_frac, coarse_segments=coarse_segments)
-    ev0 = untrained.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
-                             reps=1)
+                     coarse_quantiles=(None, 1.0, 0.9, 0.7), tier2_quantile=tier2_quantile)
     ctx.close()
+    base = ev.pop("coarse_only")
     out = {"workload": "tiny-1024seg-800bin-4800tpl realisations", "train_realisations": steps * batch,
            "epochs": epochs, "label_psi": 4.5, "label": label,
            "train_s": train_s, "loss_first": float(np.mean(losses[:5])), "loss_last": float(np.mean(losses[-5:])),
-           "coarse_grid": f"{coarse['n_f0']} f0 x {len(ctau)} tau x {len(cbrake)} n", "network": "4-layer CNN, BF16 MFMA",
-           "untrained_recall_no_fallback": ev0["recall_no_fallback"], "untrained_fallback_frac": ev0["fallback_frac"]}
+           "coarse_grid": f"{coarse['n_f0']} f0 x {len(ctau)} tau x {len(cbrake)} n over {coarse_segments} segments",
+           "network": f"4-layer CNN, BF16 MFMA, {pr.c_in} input channels (coarse power{' and count' if counts else ''}"
+                      " ratios)",
+           "speedup_counts": "exhaustive FP32 search / (ltgw_propose + the coarse store's extra ingest time)"}
     out.update(ev)
+    out["coarse_only"] = {k: base[k] for k in ("recall", "recall_no_fallback", "recall_same_template", "recall_best",
+                                               "fallback_frac", "propose_ms", "speedup", "coarse_quantile")}
     return out
 
 
@@ -317,14 +321,16 @@ def antenna_leg(torch, ltgw, ctx, wl, power, t_seg, v, w, store, steps=5):
                             "unit": "one stored element per in-band template x segment evaluation"}}
 
 
-def campaign_leg(torch, ltgw, R_noise=128, amps=(1.0, 1.5, 2.0, 2.5, 3.0, 4.0), per_level=32, seed=2024):
+def campaign_leg(torch, ltgw, R_noise=256, amps=(0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0),
+                 per_level=100, seed=2024):
     """The synthetic sensitivity campaign (Sec. 3) on the small workload's
     geometry (1024 segments x 800 bins, U[0.5, 2] weights): thresholds from
     R_noise noise-only full searches, per_level injections (f0 uniform in the
     band, tau = 10000 s, n = 5) at each amplitude, detection near the
-    injection, logistic fit and A90, for the power and the count statistic,
-    over the cubic lattice (4800 templates) and a uniform random bank of as
-    many templates."""
+    injection, logistic fit and A90 (reported only inside the sampled
+    amplitudes), for the power and the count statistic, over the cubic
+    lattice (4800 templates; realisations in stacks) and a uniform random
+    bank of as many templates (one realisation at a time)."""
     import synth
     from paper_2507_07816_amd.campaign import Campaign
 
@@ -348,11 +354,15 @@ def campaign_leg(torch, ltgw, R_noise=128, amps=(1.0, 1.5, 2.0, 2.5, 3.0, 4.0), 
             wall = time.perf_counter() - t
             n_real = R_noise + len(amps) * per_level
             out[bank_name] = {"templates": int(wl.n_templates), "wall_s": wall, "realisations_per_s": n_real / wall,
-                              "bound": "host: one search per realisation through the C ABI, each a few ms of "
-                                       "calls around microseconds of kernels",
+                              "path": ("stacks of realisations: full searches and near-injection lists per stack"
+                                       if bank is None else
+                                       "one realisation per search through the C ABI (host-bound)"),
                               **{name: {"threshold": res["threshold"][name],
                                         "efficiency": [float(x) for x in res[name]["efficiency"]],
-                                        "a90": res[name]["fit"]["a90"]} for name in ("power", "count")}}
+                                        "a90": res[name]["a90"],
+                                        "a90_fitted": res[name]["fit"]["a90"],
+                                        "a90_in_sampled_range": res[name]["a90_in_sampled_range"]}
+                                 for name in ("power", "count")}}
     finally:
         ctx.close()
     return out

@@ -346,7 +346,7 @@ int32_t ltgw_load_stack(ltgw_ctx *c, int32_t det, int32_t R, const float *stack,
     int64_t pitch2 = 0;
     if (coarse) {
         const int64_t ns2 = ns / Sg, nb2 = nb / 2;
-        pitch2 = ((nb2 + 2 + 63) / 64) * 64;
+        pitch2 = ((nb2 + 2 + 31) / 32) * 32;  // rows of whole 128-byte lines
         if (ns2 * pitch2 * 4 >= ((int64_t)1 << 31))
             return fail(c, LTGW_E_UNSUPPORTED, "one realisation's coarse store exceeds 2^31 bytes");
         if ((rc = ensure(c, S.crs, (size_t)(R * ns2 * pitch2 * 4), "coarse store")) != LTGW_OK) return rc;

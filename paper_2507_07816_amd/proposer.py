@@ -98,11 +98,16 @@ def nearest_coarse_groups(fine, coarse):
 def evaluated(blocks, fallback, tpl, L, block):
     """Whether fine template tpl[r] (fine n_f0 = 2 L) was among the cells that
     realisation r evaluated exactly: its block (group, f0 index // block) in
-    the row's tier lists blocks[r] (-1: unused), or the row fell back."""
+    the row's tier lists blocks[r] (-1: unused), or the row fell back.
+    tpl may also be [R][m] (several templates per realisation)."""
     nbg = -(-2 * L // block)
     tpl = np.asarray(tpl, np.int64)
     blk = (tpl // (2 * L)) * nbg + (tpl % (2 * L)) // block
-    return (np.asarray(fallback) != 0) | (np.asarray(blocks) == blk[:, None]).any(axis=1)
+    fb = np.asarray(fallback) != 0
+    b = np.asarray(blocks)
+    if tpl.ndim == 1:
+        return fb | (b == blk[:, None]).any(axis=1)
+    return fb[:, None] | (b[:, None, :] == blk[:, :, None]).any(axis=2)
 
 
 class Proposer:
@@ -307,7 +312,8 @@ class Proposer:
         return min(t)
 
     def evaluate(self, R_noise=256, R_signal=256, amp_range=(1.0, 3.0), fine_store="bf16", reps=3,
-                 coarse_quantiles=(1.0,), target_recall=0.99, tier2_quantile=None, baseline=True):
+                 coarse_quantiles=(1.0,), target_recall=0.99, tier2_quantile=None, baseline=True,
+                 target_speedup=5.0):
         """Recall and speed against the exhaustive search, for the network and
         (baseline) for the ranking by the coarse power ratios alone at the
         same budget (blocks, tiers, thresholds, fallback rule).
@@ -316,16 +322,17 @@ class Proposer:
         R_noise noise-only realisations (the detection rule of Sec. 3); for
         each q in coarse_quantiles the fallback's coarse threshold is the q
         quantile of the largest coarse power ratio of each noise realisation
-        (1.0: their maximum); with tier2_quantile, the second tier is taken
+        (1.0: their maximum; None: no fallback); with tier2_quantile, the second tier is taken
         only above that quantile of the same maxima.  Recall follows the
-        detection rule with "close to the injection" read as the
+        detection rule of Sec. 3 with "close to the injection" read as the
         neighbourhood of close_region: an injection is detectable when the
-        exhaustive FP32 search's best template of that neighbourhood passes
-        psi_threshold, and recalled when the proposer evaluated that template
-        exactly and its ratio there (on the `fine_store` store) passes the
-        threshold too; recall_best is the looser figure over the
-        realisation's overall best; recall_no_fallback is recall with the
-        fallback off.
+        exhaustive FP32 search has a template of that neighbourhood above
+        psi_threshold, and recalled when the proposer evaluated a template of
+        that neighbourhood exactly whose ratio (on the `fine_store` store)
+        passes the threshold.  recall_same_template is the stricter figure
+        that asks for the exhaustive search's own best template of the
+        neighbourhood; recall_best the looser one over the realisation's
+        overall best; recall_no_fallback is recall with the fallback off.
         Times (HIP events on the context's stream, best of `reps`): the
         exhaustive FP32 search (ltgw_stack_best) and ltgw_propose on the same
         realisations.  The coarse store is written in the same pass as the
@@ -334,8 +341,10 @@ class Proposer:
         to the proposer: speedup = exhaustive / (propose + coarse_extra).
         The FP32 store the exhaustive search reads costs more to ingest than
         the BF16 one, which is not credited.  The operating point reported is
-        the fastest quantile whose recall reaches target_recall, else the
-        best recall; every quantile's figures are under "points"."""
+        the fastest quantile whose recall reaches target_recall; failing that,
+        the best recall among those at least target_speedup times faster;
+        failing that, the fastest.  Every quantile's figures are under
+        "points"."""
         T = self.torch
         h = self.ctx.h
         zeros = np.zeros((R_noise, 4))
@@ -370,6 +379,12 @@ class Proposer:
         ltgw.ltgw_stack_psi_list(h, self._fg, T.from_numpy(np.maximum(near_tpl, 0).reshape(-1, 1)).to(self.ctx.device),
                                  near_prop)
         near_prop = np.where(near_tpl >= 0, near_prop.cpu().numpy().ravel(), -np.inf)
+        # every template of each injection's neighbourhood on the proposer's store
+        region = self.close_region(inj)
+        reg_prop = T.empty(region.shape, dtype=T.float64, device=self.ctx.device)
+        ltgw.ltgw_stack_psi_list(h, self._fg, T.from_numpy(region.astype(np.int32)).to(self.ctx.device), reg_prop)
+        reg_prop = np.where(region >= 0, reg_prop.cpu().numpy(), -np.inf)
+        reg_prop = np.where(np.isnan(reg_prop), -np.inf, reg_prop)
         det_near = near_psi > psi_thr
         n_near = int(det_near.sum())
         det_ex = ex_psi > psi_thr
@@ -377,18 +392,21 @@ class Proposer:
         frac = lambda hit, of, n: float((of & hit).sum() / n) if n else float("nan")
 
         def recalls(pp, fb, blocks):
-            hit = self.evaluated(blocks, fb, near_tpl) & (near_prop > psi_thr)
-            return frac(hit, det_near, n_near), frac(pp > psi_thr, det_ex, n_det)
+            same = self.evaluated(blocks, fb, near_tpl) & (near_prop > psi_thr)
+            ev = self.evaluated(blocks, fb, np.maximum(region, 0)) & (region >= 0)
+            hit = (ev & (reg_prop > psi_thr)).any(axis=1)
+            return frac(hit, det_near, n_near), frac(pp > psi_thr, det_ex, n_det), frac(same, det_near, n_near)
 
         t2 = -1e300 if tier2_quantile is None else float(np.quantile(coarse_max, tier2_quantile))
 
         def operating_points(network):
             _, pp_nf, fb_nf, bl_nf = self.propose(psi_thr, 1e300, R_signal, return_blocks=True,
                                                   tier2_threshold=t2, network=network)  # fallback never taken
-            rec_nf, rec_best_nf = recalls(pp_nf, fb_nf, bl_nf)
+            rec_nf, rec_best_nf, rec_same_nf = recalls(pp_nf, fb_nf, bl_nf)
             points = []
             for q in coarse_quantiles:
-                coarse_thr = float(np.quantile(coarse_max, q))
+                # q None: no fallback
+                coarse_thr = 1e300 if q is None else float(np.quantile(coarse_max, q))
                 t_pr = []
                 for _ in range(reps):
                     ev0.record()
@@ -398,17 +416,25 @@ class Proposer:
                     t_pr.append(ev0.elapsed_time(ev1))
                 pi, pp, fb, bl = self.propose(psi_thr, coarse_thr, R_signal, return_blocks=True,
                                               tier2_threshold=t2, network=network)
-                rec, rec_best = recalls(pp, fb, bl)
+                rec, rec_best, rec_same = recalls(pp, fb, bl)
                 points.append(dict(coarse_quantile=q, coarse_threshold=coarse_thr, recall=rec, recall_best=rec_best,
+                                   recall_same_template=rec_same,
                                    fallback_frac=float(fb.mean()), propose_ms=min(t_pr),
                                    speedup=min(t_ex) / (min(t_pr) + coarse_extra),
                                    speedup_search_only=min(t_ex) / min(t_pr),
                                    same_template=float((pi[det_ex] == ex_idx[det_ex]).mean()) if n_det
                                    else float("nan")))
             ok = [p for p in points if p["recall"] >= target_recall]
-            best = max(ok, key=lambda p: p["speedup"]) if ok else max(points, key=lambda p: (p["recall"], p["speedup"]))
+            fast = [p for p in points if p["speedup"] >= target_speedup]
+            if ok:
+                best = max(ok, key=lambda p: p["speedup"])
+            elif fast:
+                best = max(fast, key=lambda p: (p["recall"], p["speedup"]))
+            else:
+                best = max(points, key=lambda p: p["speedup"])
             out = dict(best)
-            out.update(recall_no_fallback=rec_nf, recall_best_no_fallback=rec_best_nf, points=points)
+            out.update(recall_no_fallback=rec_nf, recall_best_no_fallback=rec_best_nf,
+                       recall_same_template_no_fallback=rec_same_nf, points=points)
             return out
 
         amp = inj[:, 3]

@@ -59,3 +59,9 @@ def test_evaluated_matches_expanded_blocks():
             cells |= {g * 2 * L + i for i in range(k * W, min(k * W + W, 2 * L))}
         assert got[q] == (bool(fb[q]) or int(tpl[q]) in cells)
     assert got[1]
+    # several templates per realisation: each column as the one-template call
+    tpl2 = np.stack([tpl, r.integers(0, 12 * 2 * L, R), tpl[::-1]], axis=1)
+    got2 = evaluated(blocks, fb, tpl2, L, W)
+    assert got2.shape == (R, 3)
+    for k in range(3):
+        assert np.array_equal(got2[:, k], evaluated(blocks, fb, tpl2[:, k], L, W))
