@@ -42,13 +42,14 @@ BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
 # the statistic kernel's code: a change to any of these voids the committed counters
 KERNEL_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_kernels.hip", "paper_2507_07816_amd/csrc/ltgw_gather.h",
                   "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_internal.h",
-                  "paper_2507_07816_amd/csrc/exp2_table.h")
+                  "paper_2507_07816_amd/csrc/exp2_table.h", "paper_2507_07816_amd/csrc/log_table.h")
 
 
 # the explicit-template kernel's code (its committed FP64 instruction count)
 LIST_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_list.hip", "paper_2507_07816_amd/csrc/ltgw_list.h",
                 "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_gather.h",
-                "paper_2507_07816_amd/csrc/ltgw_antenna.h", "paper_2507_07816_amd/csrc/exp2_table.h")
+                "paper_2507_07816_amd/csrc/ltgw_antenna.h", "paper_2507_07816_amd/csrc/exp2_table.h",
+                "paper_2507_07816_amd/csrc/log_table.h")
 
 
 def kernel_source_hash(sources=KERNEL_SOURCES):
@@ -266,7 +267,7 @@ def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, fp64_per_eval=Non
            "templates": n, "evals": evals, "in_band_fraction": dg["in_band"] / evals,
            "value": evals / wall, "unit": "template·segment evals/s", "wall_ms": wall * 1e3,
            "kernel_ms": kms, "kernel_evals_per_s": evals / (kms * 1e-3),
-           "pow_undecided": int(dg["pow_undecided"])}
+           "pow_undecided": int(dg["pow_undecided"]), "pow_slow": int(dg["pow_slow"])}
     if fp64_per_eval:
         rate = fp64_per_eval * evals / (kms * 1e-3)
         out["roofline"] = {"bound": "alu", "achieved": rate / 1e12, "peak": FP64_LANE_OPS / 1e12,
@@ -498,7 +499,7 @@ def timed_search(torch, ctx, wl, power, t_seg, v, w, store, steps, warmup, tile_
            "ms_per_step": elapsed * 1e3 / steps, "value": dg["evals"] * steps / elapsed,
            "eval_kernel_ms": kms, "eval_launches": launches, "eval_launch_ms": kms / launches,
            "tile_shape": int(dg["tile_shape"]), "pow_undecided": int(dg["pow_undecided"]),
-           "top_power": tp[0], "top_count": tc[0]}
+           "pow_slow": int(dg["pow_slow"]), "top_power": tp[0], "top_count": tc[0]}
     return fig, res
 
 

@@ -321,6 +321,9 @@ typedef struct {
                                ltgw_load_spectrogram or ltgw_load_stack (HIP
                                events on the context's stream; a stack's
                                coarse store is written in the same pass)     */
+    int64_t pow_slow;       /* powers of Eq. 1 (since the context was created)
+                               that the fast evaluation could not round with
+                               certainty and the double-double one took     */
 } ltgw_diag;
 
 /* ltgw_diagnostics: synchronous; reads the device counters of the last eval. */

@@ -919,7 +919,7 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
     a.out_c = out_c;
     a.out_n = out_n;
     a.in_band_total = (unsigned long long *)c->counters.p + kCntInBand;
-    a.undecided = (unsigned long long *)c->counters.p + kCntUndecided;
+    a.pow_counts = (unsigned long long *)c->counters.p + kCntUndecided;
     HIP_TRY(c, hipEventRecord(c->ev_h2d, c->stream), "event record");
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream), "event record");
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream), "event record");
@@ -1093,6 +1093,7 @@ int32_t ltgw_diagnostics(ltgw_ctx *c, ltgw_diag *out) {
     HIP_TRY(c, hipMemcpyAsync(v, c->counters.p, sizeof v, hipMemcpyDeviceToHost, c->stream), "diagnostics");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "diagnostics");
     out->pow_undecided = (int64_t)v[kCntUndecided];
+    out->pow_slow = (int64_t)v[kCntSlow];
     out->templates = c->have_eval ? c->n_templates : 0;
     out->evals = c->have_eval ? c->n_evals : 0;
     out->in_band = c->have_eval ? (int64_t)v[kCntInBand] : 0;

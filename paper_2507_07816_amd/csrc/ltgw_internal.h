@@ -9,6 +9,7 @@
 namespace ltgw {
 
 constexpr double kC = 299792458.0;  // m/s, exact by SI definition
+constexpr double kInvC = 1.0 / kC;  // RN(1/c), folded by the compiler
 
 // Internal store format (beside LTGW_STORE_F32/BF16/FP8): the proposer's
 // coarse store, 32-bit words holding a bfloat16 power sum in the upper half
@@ -74,7 +75,7 @@ hipError_t launch_check_velocity(const double *v, int32_t n_seg, unsigned long l
                                  hipStream_t st);
 hipError_t launch_spin_factor(const double *t_seg, int32_t n_seg, double t0, const double *tau,
                               int32_t n_tau, const double *brake, int32_t n_brake, double *g,
-                              unsigned long long *undecided, hipStream_t st);
+                              unsigned long long *pow_counts, hipStream_t st);  // [2]: undecided, slow phase
 hipError_t launch_track_factor(const double *g, int32_t n_tn, const double *v, int32_t n_seg,
                                const double *sky, int32_t n_sky, double t_sft, double *H,
                                hipStream_t st);

@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void spin_factor_kernel(const double *__restri
                                                           int n_tau,
                                                           const double *__restrict__ brake,
                                                           double *__restrict__ g,
-                                                          unsigned long long *undecided) {
+                                                          unsigned long long *pow_counts) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     const int grp = blockIdx.y;
     if (j >= n_seg) return;
@@ -251,18 +251,20 @@ __global__ __launch_bounds__(256) void spin_factor_kernel(const double *__restri
         const double u = 1.0 + q;
         const double e = 1.0 / (1.0 - n);
         int und = 0;
-        out = pow_cr(u, e, &und);
-        if (und) atomicAdd(undecided, 1ull);
+        int slow = 0;
+        out = pow_cr(u, e, &und, &slow);
+        if (und) atomicAdd(pow_counts, 1ull);
+        if (slow) atomicAdd(pow_counts + 1, 1ull);
     }
     g[(int64_t)grp * n_seg + j] = out;
 }
 
 hipError_t launch_spin_factor(const double *t_seg, int32_t n_seg, double t0, const double *tau,
                               int32_t n_tau, const double *brake, int32_t n_brake, double *g,
-                              unsigned long long *undecided, hipStream_t st) {
+                              unsigned long long *pow_counts, hipStream_t st) {
     dim3 grid((n_seg + 255) / 256, n_tau * n_brake), block(256);
     hipLaunchKernelGGL(spin_factor_kernel, grid, block, 0, st, t_seg, n_seg, t0, tau, n_tau, brake,
-                       g, undecided);
+                       g, pow_counts);
     return hipGetLastError();
 }
 

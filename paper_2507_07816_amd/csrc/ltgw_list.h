@@ -34,7 +34,8 @@ struct ListArgs {
     int32_t *c, *n_in;
     float *out_s;              // optional caller outputs
     int32_t *out_c, *out_n;
-    unsigned long long *in_band_total, *undecided;
+    unsigned long long *in_band_total;
+    unsigned long long *pow_counts;  // [0] undecided powers, [1] powers that took the double-double phase
 };
 
 hipError_t launch_template_list(int store, const ListArgs &a, hipStream_t st);

@@ -9,6 +9,14 @@
 
 namespace ltgw {
 
+// A per-segment value every lane of the wavefront reads at the same address,
+// through the constant address space: the segment arrays are not written
+// while the kernel runs, so this becomes a scalar load.
+template <typename T>
+__device__ inline T seg_load(const T *p, int i) {
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 // Lane q evaluates template perm[q] over every selected detector and segment
 // with the lattice's arithmetic, in its order:
 //   t < T0: masked (g = 0, so the column falls out of band)
@@ -16,18 +24,23 @@ namespace ltgw {
 //   D = 1 + ((vx nx + vy ny) + vz nz)/c, H = RN(RN(g D) T_sft)   (Eq. 2)
 //   x = f0 H, column = trunc(x + 1.5 - k_lo), gather, FP32 sums over chunks
 //   of 32 segments carried in FP64                               (Sec. 2)
-// so a template of a lattice gets that lattice's s, c and N bit for bit.
-// The power is correctly rounded per segment (double-double, the undecided
-// cases counted), which makes this mode bound by FP64 arithmetic: sorting
-// the list by f0 (the caller's perm) keeps neighbouring lanes on
-// neighbouring columns for the gathers.
-template <int STORE>
+// so a template of a lattice gets that lattice's s, c and N bit for bit (the
+// two quotients come from reciprocals by div_rn, which equals the division).
+// The power is correctly rounded per segment (the fast phase, and the
+// double-double phase where that cannot decide; both counted), which makes
+// this mode bound by FP64 arithmetic.  Sorting the list by f0 (the caller's
+// perm) keeps neighbouring lanes on neighbouring columns for the gathers.
+// ANT: some detector carries antenna-pattern weights.  Without, the kernel
+// holds none of their per-detector values, which leaves the scalar registers
+// to the power's constants (else they spill into vector-register lanes).
+template <int STORE, bool ANT>
 __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool live = q < a.n;
     const int32_t o = live ? a.perm[q] : a.perm[0];
     const ltgw_template T = a.tpl[o];
     const double e = 1.0 / (1.0 - T.brake);
+    const double rtau = 1.0 / T.tau;  // RN(1/tau): the per-segment quotients by div_rn
     double s = 0.0, w1 = 0.0, w2 = 0.0;
     int cnt = 0, nin = 0;
     for (int d = 0; d < a.n_det; ++d) {
@@ -39,21 +52,23 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
             const int je = min(j0 + kChunk, D.n_seg);
             float sc = 0.0f, w1c = 0.0f, w2c = 0.0f;
             for (int j = j0; j < je; ++j) {
-                const double t = D.t[j];
+                const double t = seg_load(D.t, j);
                 double g = 0.0;
                 if (!(t < a.t0)) {
                     const double dt = t - a.t0;
-                    const double qq = dt / T.tau;
+                    const double qq = div_rn(dt, T.tau, rtau);
                     const double u = 1.0 + qq;
                     int und = 0;
-                    g = pow_cr(u, e, &und);
-                    if (und) atomicAdd(a.undecided, 1ull);
+                    int slow = 0;
+                    g = pow_cr(u, e, &und, &slow);
+                    if (und) atomicAdd(a.pow_counts, 1ull);
+                    if (slow) atomicAdd(a.pow_counts + 1, 1ull);
                 }
-                const double va = D.v[3 * j + 0] * T.sky[0];
-                const double vb = D.v[3 * j + 1] * T.sky[1];
-                const double vz = D.v[3 * j + 2] * T.sky[2];
+                const double va = seg_load(D.v, 3 * j + 0) * T.sky[0];
+                const double vb = seg_load(D.v, 3 * j + 1) * T.sky[1];
+                const double vz = seg_load(D.v, 3 * j + 2) * T.sky[2];
                 const double vn = (va + vb) + vz;
-                const double r = vn / kC;
+                const double r = div_rn(vn, kC, kInvC);
                 const double Df = 1.0 + r;
                 const double h = g * Df;
                 const double H = h * D.t_sft;
@@ -61,9 +76,9 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
                 const double vv = x + D.cshift;
                 const unsigned idx = (unsigned)__double2int_rz(vv);
                 const float p = Store<STORE>::get(rs, (int)idx, j * D.pitch_bytes, cnt);
-                float wq = D.wq[j], wv = D.w[j];
-                if (D.era)  // antenna-pattern weights for this template's sky direction
-                    antenna_weights(D.arms, D.era[j], T.sky[0], T.sky[1], T.sky[2], wv, D.scale[j], wv, wq);
+                float wq = seg_load(D.wq, j), wv = seg_load(D.w, j);
+                if (ANT && D.era)  // antenna-pattern weights for this template's sky direction
+                    antenna_weights(D.arms, seg_load(D.era, j), T.sky[0], T.sky[1], T.sky[2], wv, seg_load(D.scale, j), wv, wq);
                 sc = __builtin_fmaf(wq, p, sc);
                 const bool inb = (idx - 1u) < nb;
                 nin += inb ? 1 : 0;
@@ -94,12 +109,18 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
 hipError_t launch_template_list(int store, const ListArgs &a, hipStream_t st) {
     if (a.n < 1 || a.n > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
-    if (store == LTGW_STORE_F32)
-        hipLaunchKernelGGL(template_list_kernel<LTGW_STORE_F32>, grid, block, 0, st, a);
-    else if (store == LTGW_STORE_BF16)
-        hipLaunchKernelGGL(template_list_kernel<LTGW_STORE_BF16>, grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL(template_list_kernel<LTGW_STORE_FP8>, grid, block, 0, st, a);
+    bool ant = false;
+    for (int d = 0; d < a.n_det; ++d) ant = ant || a.det[d].era != nullptr;
+    if (store == LTGW_STORE_F32) {
+        if (ant) hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_F32, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_F32, false>), grid, block, 0, st, a);
+    } else if (store == LTGW_STORE_BF16) {
+        if (ant) hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_BF16, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_BF16, false>), grid, block, 0, st, a);
+    } else {
+        if (ant) hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_FP8, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_FP8, false>), grid, block, 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -73,7 +73,7 @@ int main(void) {
   F(ltgw_batch_stats, templates); F(ltgw_batch_stats, kernel_ms); F(ltgw_batch_stats, total_ms);
   printf("ltgw_diag %zu\n", sizeof(ltgw_diag));
   F(ltgw_diag, in_band); F(ltgw_diag, eval_kernel_ms); F(ltgw_diag, tables_ms);
-  F(ltgw_diag, tile_shape); F(ltgw_diag, ingest_ms);
+  F(ltgw_diag, tile_shape); F(ltgw_diag, ingest_ms); F(ltgw_diag, pow_slow);
   printf("ltgw_proposer %zu\n", sizeof(ltgw_proposer));
   F(ltgw_proposer, c_in); F(ltgw_proposer, n_select); F(ltgw_proposer, psi_threshold);
   F(ltgw_proposer, coarse_threshold); F(ltgw_proposer, tier2_threshold); F(ltgw_proposer, blocks);
@@ -123,6 +123,36 @@ def test_exp2_table_and_ln2_split():
         hi, lo = float.fromhex(rows[j][0]), float.fromhex(rows[j][1])
         assert hi == float(x) and lo == float(x - Fraction(hi))
     assert all(float.fromhex(h) * 2 > 1.99 for h, _ in rows[128:])
+
+
+LOGT = os.path.join(ROOT, "paper_2507_07816_amd", "csrc", "log_table.h")
+
+
+def test_log_table():
+    """The fast log's table: r_i = K_i / 256 with K_i the integer nearest 256 / c_i,
+    c_i = 1 + (i + 1/2) / 128; -log(r_i) as hi, the nearest multiple of 2^-35,
+    and lo = RN(x - hi), together within 2^-89 of 60-digit decimals; ln 2's
+    head on the same grid, so that k times it plus hi is exact for |k| < 2^10;
+    and the reduction bound: for every m in [1, 2) whose top 7 fraction bits
+    are i, |m r_i - 1| < 0.0056 and m r_i - 1 is a multiple of 2^-60 below
+    2^53 of them (exact in FP64)."""
+    getcontext().prec = 60
+    head = float.fromhex(re.search(r"kLn2d256_1 = (0x[0-9a-fp.+-]+);", open(EXP2).read()).group(1))
+    assert (Fraction(head) * 256 * 2 ** 35).denominator == 1 and abs(head * 256) < 1
+    rows = re.findall(r"\{(-?0x[0-9a-fp.+-]+), (-?0x[0-9a-fp.+-]+), (-?0x[0-9a-fp.+-]+)\},", open(LOGT).read())
+    assert len(rows) == 128
+    for i, (r, hi, lo) in enumerate(rows):
+        r, hi, lo = float.fromhex(r), float.fromhex(hi), float.fromhex(lo)
+        c = Fraction(1) + Fraction(2 * i + 1, 256)
+        K = round(Fraction(256) / c)
+        assert Fraction(r) == Fraction(K, 256) and K <= 256
+        x = Fraction((Decimal(256) / Decimal(K)).ln())
+        assert (Fraction(hi) * 2 ** 35).denominator == 1 and abs(x - Fraction(hi)) <= Fraction(1, 2 ** 36)
+        assert lo == float(x - Fraction(hi)) and abs(x - Fraction(hi) - Fraction(lo)) < Fraction(1, 2 ** 89)
+        for m in (Fraction(1) + Fraction(i, 128), Fraction(1) + Fraction(i + 1, 128) - Fraction(1, 2 ** 52)):
+            z = m * Fraction(r) - 1
+            assert abs(z) < Fraction(56, 10000)
+            assert (z * 2 ** 60).denominator == 1 and abs(z * 2 ** 60) < 2 ** 53
 
 
 def test_reciprocal_constants():
