@@ -62,11 +62,11 @@ def kernel_source_hash(sources=KERNEL_SOURCES):
     return h.hexdigest()
 
 
-def measured_list_fp64():
-    """Executed FP64 VALU lane-instructions per evaluation of the
+def measured_list_counts():
+    """Executed VALU and FP64 lane-instructions per evaluation of the
     explicit-template kernel, from the committed rocprofv3 counter summary
-    (SQ_INSTS_VALU_*_F64 over the launch, times 64 lanes, over its
-    evaluations), or None when it is for another kernel source."""
+    (SQ_INSTS_VALU and SQ_INSTS_VALU_*_F64 over the launch, times 64 lanes,
+    over its evaluations), or None when it is for another kernel source."""
     path = os.path.join(ROOT, "profiles", "list_kernel_fp64.json")
     if not os.path.exists(path):
         return None
@@ -74,7 +74,7 @@ def measured_list_fp64():
         t = json.load(fh)
     if t.get("source_sha256") != kernel_source_hash(LIST_SOURCES):
         return None
-    return t["fp64_lane_instructions_per_eval"]
+    return {"valu": t["valu_lane_instructions_per_eval"], "fp64": t["fp64_lane_instructions_per_eval"]}
 
 
 def measured_valu(workload, store, variant):
@@ -238,13 +238,13 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
 FP64_LANE_OPS = 256 * 64 * 2.4e9
 
 
-def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, fp64_per_eval=None):
+def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, counts=None):
     """The uniform random bank over the loaded search: n templates drawn
     uniformly in f0 (the band), tau and n, at the search's sky point.  Every
     (template, segment) takes its own correctly rounded Eq. 1 power, so the
-    kernel is bound by FP64 issue; the rate is compared with the chip's FP64
-    lane-instruction rate given the instructions per evaluation of the
-    kernel's inner loop (counted in its gfx950 code)."""
+    kernel is bound by instruction issue; the rate is compared with the
+    chip's VALU lane-instruction rate given the instructions per evaluation
+    counted by rocprofv3 for this kernel source."""
     import synth
 
     d = wl.dets[0]
@@ -254,6 +254,7 @@ def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, fp64_per_eval=Non
                                (float(g["brake"][0]), float(g["brake"][-1])), g["sky"][0], seed)
     ctx.eval_list(params, g["t0"], outputs=False)            # warm-up
     torch.cuda.synchronize()
+    slow0 = ctx.diagnostics()["pow_slow"]
     runs = []
     for _ in range(reps):
         t = time.perf_counter()
@@ -267,12 +268,15 @@ def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, fp64_per_eval=Non
            "templates": n, "evals": evals, "in_band_fraction": dg["in_band"] / evals,
            "value": evals / wall, "unit": "template·segment evals/s", "wall_ms": wall * 1e3,
            "kernel_ms": kms, "kernel_evals_per_s": evals / (kms * 1e-3),
-           "pow_undecided": int(dg["pow_undecided"]), "pow_slow": int(dg["pow_slow"])}
-    if fp64_per_eval:
-        rate = fp64_per_eval * evals / (kms * 1e-3)
+           "pow_undecided": int(dg["pow_undecided"]),
+           "pow_slow_fraction": (dg["pow_slow"] - slow0) / (reps * evals)}
+    if counts:
+        rate = counts["valu"] * evals / (kms * 1e-3)
         out["roofline"] = {"bound": "alu", "achieved": rate / 1e12, "peak": FP64_LANE_OPS / 1e12,
-                           "unit": "T FP64 lane-instructions/s", "frac": rate / FP64_LANE_OPS,
-                           "fp64_instructions_per_eval": fp64_per_eval}
+                           "unit": "T VALU lane-instructions/s", "frac": rate / FP64_LANE_OPS,
+                           "valu_instructions_per_eval": counts["valu"],
+                           "fp64_instructions_per_eval": counts["fp64"],
+                           "fp64_frac": counts["fp64"] * evals / (kms * 1e-3) / FP64_LANE_OPS}
     return out
 
 
@@ -663,7 +667,7 @@ def main():
     if args.list_templates > 0:
         print("[bench] uniform random bank", file=sys.stderr, flush=True)
         out["random_bank"] = list_leg(torch, ltgw, ctx, wl, n=args.list_templates,
-                                      fp64_per_eval=measured_list_fp64())
+                                      counts=measured_list_counts())
         print(f"[bench] random bank: {json.dumps(out['random_bank'])}", file=sys.stderr, flush=True)
     ctx.close()
     if not args.no_sft:
