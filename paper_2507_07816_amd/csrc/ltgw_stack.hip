@@ -320,34 +320,44 @@ hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_b
 // Proposal blocks evaluated in place: workgroup (x, rr) takes NB = 256 / W
 // blocks blk[r][x NB .. x NB + NB) of realisation r = rmap[rr] (or rr), W
 // lanes per block, lane l on fine f0 index (b % nbg) W + l of group b / nbg.
-// The blocks' track factors are staged in LDS per chunk of 32 segments, so
-// the only vector-memory access per template and segment is the gather; the
-// sums are those of the listed evaluation, in the same order.  Writes the
-// expanded template (-1 past the grid) and its ratio (NaN there).
-template <int STORE, int W>
+// Each wavefront stages its own blocks' track factors in LDS per chunk of 32
+// segments (no workgroup barrier: a wavefront's LDS accesses complete in
+// order), so the only vector-memory access per template and segment is the
+// gather; the sums are those of the listed evaluation, in the same order.
+// Writes the expanded template (-1 past the grid) and its ratio (NaN there).
+template <typename T>
+__device__ inline T uniform_load(const T *p, int i) {
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
+// SB: segments per batch of gathers in flight.
+template <int STORE, int W, int SB>
 __global__ __launch_bounds__(256) void block_eval_kernel(const EvalArgs a, int R, int64_t stack_bytes,
                                                          int64_t stack_rows, const int32_t *__restrict__ blk, int K,
                                                          int nbg, const int32_t *__restrict__ rmap,
                                                          const int32_t *__restrict__ n_rows, const StackMoments mom,
                                                          int32_t *__restrict__ out_tpl,
                                                          double *__restrict__ out_psi) {
-    constexpr int NB = 256 / W;
+    constexpr int NB = 256 / W, SPW = 64 / W;  // blocks per workgroup, per wavefront
     __shared__ double sh[NB][kChunk];
-    __shared__ int sg[NB];
     // XCD order as in stack_eval_kernel: the workgroups of one row share an
     // XCD (and its L2), consecutive rows go to different XCDs
     const int per_row = (K + NB - 1) / NB;
     const int xcd = (int)blockIdx.x % kXcds, kk = (int)blockIdx.x / kXcds;
     const int rr = xcd + kXcds * (kk / per_row), part = kk % per_row;
-    if (rr >= R || (n_rows && rr >= *n_rows)) return;  // the whole workgroup, before any barrier
+    if (rr >= R || (n_rows && rr >= *n_rows)) return;  // the whole workgroup
     const int r = rmap ? rmap[rr] : rr;
     const int slot = (int)threadIdx.x / W, lf = (int)threadIdx.x % W;
+    const int lane = (int)threadIdx.x & 63, slot0 = ((int)threadIdx.x >> 6) * SPW;
     const int q = part * NB + slot;
     const int b = q < K ? blk[(int64_t)r * K + q] : -1;
     const int i = (b >= 0 ? (b % nbg) * W : 0) + lf;
     const bool valid = b >= 0 && i < a.n_f0;
     const int grp = b >= 0 ? b / nbg : 0;
-    if (lf == 0) sg[slot] = grp;
+    // the group of each of this wavefront's slots, for its staging lanes
+    int sgrp[SPW];
+#pragma unroll
+    for (int u = 0; u < SPW; ++u) sgrp[u] = __shfl(grp, u * W, 64);
     DetView D = a.det[0];
     D.store = (const char *)D.store + (int64_t)r * stack_bytes;
     D.wq += (int64_t)r * stack_rows;
@@ -359,40 +369,49 @@ __global__ __launch_bounds__(256) void block_eval_kernel(const EvalArgs a, int R
     int cnt = 0;
     for (int j0 = 0; j0 < D.n_seg; j0 += kChunk) {
         const int nj = min(kChunk, D.n_seg - j0);
-        __syncthreads();  // sg is written; the previous chunk's factors are read
-        for (int e = (int)threadIdx.x; e < NB * kChunk; e += 256) {
-            const int sl = e / kChunk, k = e % kChunk;
-            sh[sl][k] = k < nj ? D.H[(int64_t)sg[sl] * D.n_seg + j0 + k] : 0.0;
+        // the previous chunk's reads of this wavefront are ahead of these writes
+#pragma unroll
+        for (int u = 0; u < (SPW * kChunk + 63) / 64; ++u) {
+            const int e = u * 64 + lane;
+            if (e < SPW * kChunk) {
+                const int sl = e / kChunk, k = e % kChunk;
+                sh[slot0 + sl][k] = k < nj ? D.H[(int64_t)sgrp[sl] * D.n_seg + j0 + k] : 0.0;
+            }
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float sc = 0.0f;
         if (nj == kChunk) {
 #pragma unroll 1
-            for (int k0 = 0; k0 < kChunk; k0 += 8) {
-                unsigned ix[8];
+            for (int k0 = 0; k0 < kChunk; k0 += SB) {
+                unsigned ix[SB];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
+                for (int k = 0; k < SB; ++k) {
                     const double x = f0 * hrow[k0 + k];
                     const double vv = x + D.cshift;
                     ix[k] = (unsigned)__double2int_rz(vv);
                 }
-                float p[8];
+                float p[SB];
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
+                for (int k = 0; k < SB; ++k)
                     p[k] = Store<STORE>::get(rs, (int)ix[k], (j0 + k0 + k) * D.pitch_bytes, cnt);
 #pragma unroll
-                for (int k = 0; k < 8; ++k) sc = __builtin_fmaf(D.wq[j0 + k0 + k], p[k], sc);
+                for (int k = 0; k < SB; ++k) sc = __builtin_fmaf(uniform_load(D.wq, j0 + k0 + k), p[k], sc);
             }
         } else {
             for (int k = 0; k < nj; ++k) {
                 const double x = f0 * hrow[k];
                 const double vv = x + D.cshift;
                 const unsigned ix = (unsigned)__double2int_rz(vv);
-                sc = __builtin_fmaf(D.wq[j0 + k], Store<STORE>::get(rs, (int)ix, (j0 + k) * D.pitch_bytes, cnt),
-                                    sc);
+                sc = __builtin_fmaf(uniform_load(D.wq, j0 + k),
+                                    Store<STORE>::get(rs, (int)ix, (j0 + k) * D.pitch_bytes, cnt), sc);
             }
         }
         s += (double)sc;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (q >= K) return;
     const int64_t o = (int64_t)rr * K * W + (int64_t)q * W + lf;
@@ -413,7 +432,7 @@ hipError_t launch_block_eval(int store, int W, const EvalArgs &a, int R, int64_t
     if (wgs > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)wgs), block(256);
 #define LTGW_BLOCK_EVAL(S, WW)                                                                                      \
-    hipLaunchKernelGGL((block_eval_kernel<S, WW>), grid, block, 0, st, a, R, stack_bytes, stack_rows, blk, K, nbg, \
+    hipLaunchKernelGGL((block_eval_kernel<S, WW, 16>), grid, block, 0, st, a, R, stack_bytes, stack_rows, blk, K, nbg, \
                        rmap, n_rows, mom, out_tpl, out_psi)
 #define LTGW_BLOCK_EVAL_W(S)          \
     if (W == 16)                      \
