@@ -519,10 +519,16 @@ __global__ void cnn_pack_kernel(const float *__restrict__ params, CnnOffsets off
 // block k of fine group g covers positions [k pb, k pb + pb) of channels 2g
 // and 2g + 1 (fine f0 index 2 l + ch % 2, blocks of 2 pb f0), and scores the
 // largest of those logits (pb = 8, 16 or 32).
-template <int KT, int KW>
-__device__ void infer_layer(const short *__restrict__ wp, const float *__restrict__ bias, int O, int Cp,
-                            const short *in, int SXin, int L, bool relu, short *out, float *__restrict__ gout,
-                            float *__restrict__ score = nullptr, int pb = 0, int nbg = 0) {
+// Inlined with its shapes as constants: a call would pass them at run time
+// (integer divisions for every operand address) and its registers would
+// stay allocated across the whole kernel.
+template <int KT, int KW, int Cp, int SXin>
+__device__ __attribute__((always_inline)) inline void infer_layer(const short *__restrict__ wp,
+                                                                  const float *__restrict__ bias, int O,
+                                                                  const short *in, int L, bool relu, short *out,
+                                                                  float *__restrict__ gout,
+                                                                  float *__restrict__ score = nullptr, int pb = 0,
+                                                                  int nbg = 0) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r0 = (wv & 1) * 16, c0 = (wv >> 1) * 128;
     const int row = lane & 15, kq = (lane >> 4) * 4;
@@ -539,24 +545,39 @@ __device__ void infer_layer(const short *__restrict__ wp, const float *__restric
         const int t = k / Cp, c = k % Cp;
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
-            bf16x4 bv = {0, 0, 0, 0};
-            if (t < KT) bv = *(const bf16x4 *)&in[(c0 + h * 16 + row + t + 2 - KT / 2) * SXin + c];
+            // taps past KT are the zero padding of K: read a valid row, use zero
+            const bf16x4 raw = *(const bf16x4 *)&in[(c0 + h * 16 + row + (t < KT ? t : KT - 1) + 2 - KT / 2) * SXin + c];
+            const bf16x4 zero = {0, 0, 0, 0};
+            const bf16x4 bv = t < KT ? raw : zero;
             acc[h] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], bv, acc[h], 0, 0, 0);
         }
     }
+    if (out) {  // hidden layers (O = 32): the lane's four channels as one 8-byte write
+        float bo[4];
 #pragma unroll
-    for (int h = 0; h < 8; ++h) {
-        const int l = c0 + h * 16 + (lane & 15);
+        for (int i = 0; i < 4; ++i) bo[i] = bias[r0 + kq + i];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int o = r0 + kq + i;
-            if (o >= O) continue;
-            float y = acc[h][i] + bias[o];
-            if (relu) y = y > 0.f ? y : 0.f;
-            if (out)
-                out[(l + 2) * kInferSH + o] = l < L ? to_bf16(y) : (short)0;
-            else if (gout && l < L)
-                gout[(int64_t)o * L + l] = y;
+        for (int h = 0; h < 8; ++h) {
+            const int l = c0 + h * 16 + (lane & 15);
+            const bool in = l < L;
+            bf16x4 v;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float y = acc[h][i] + bo[i];
+                if (relu) y = y > 0.f ? y : 0.f;
+                v[i] = to_bf16(in ? y : 0.f);  // positions >= L hold zero (bf16 of 0)
+            }
+            *(bf16x4 *)&out[(l + 2) * kInferSH + r0 + kq] = v;
+        }
+    } else if (gout) {
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int l = c0 + h * 16 + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = r0 + kq + i;
+                if (o < O && l < L) gout[(int64_t)o * L + l] = acc[h][i] + bias[o];
+            }
         }
     }
     if (!score) return;
@@ -597,18 +618,18 @@ __device__ void infer_layer(const short *__restrict__ wp, const float *__restric
     }
 }
 
-template <int KW1>
+template <int CP1>
 __global__ __launch_bounds__(256) void cnn_infer_kernel(const float *__restrict__ params,
                                                         const short *__restrict__ packed,
                                                         const float *__restrict__ X, int c_in, int c_out, int L,
                                                         CnnOffsets off, CnnPacked P, float *__restrict__ logits,
                                                         float *__restrict__ score, int pb, int nbg) {
+    constexpr int KW1 = (kTaps * CP1 + 15) / 16 * 16, SX0 = CP1 + 4;
     __shared__ short hA[kInferRows * kInferSH], hB[kInferRows * kInferSH];
-    short *x0 = hB;  // the input window [260][Cp1 + 4] until layer 2 writes hB
-    const int SX0 = P.Cp1 + 4;
+    short *x0 = hB;  // the input window [260][CP1 + 4] until layer 2 writes hB
     const int b = blockIdx.x;
-    for (int e = threadIdx.x; e < kInferRows * P.Cp1; e += 256) {
-        const int rr = e / P.Cp1, c = e % P.Cp1, l = rr - 2;
+    for (int e = threadIdx.x; e < kInferRows * CP1; e += 256) {
+        const int rr = e / CP1, c = e % CP1, l = rr - 2;
         float v = 0.f;
         if (c < c_in && l >= 0 && l < L) v = X[((int64_t)b * c_in + c) * L + l];
         x0[rr * SX0 + c] = to_bf16(v);
@@ -618,19 +639,19 @@ __global__ __launch_bounds__(256) void cnn_infer_kernel(const float *__restrict_
         hA[(rr < 2 ? rr : kInferRows - 4 + rr) * kInferSH + c] = 0;
     }
     __syncthreads();
-    infer_layer<kTaps, KW1>(packed + P.o[0], params + off.o[1], kWidth, P.Cp1, x0, SX0, L, true, hA, nullptr);
+    infer_layer<kTaps, KW1, CP1, SX0>(packed + P.o[0], params + off.o[1], kWidth, x0, L, true, hA, nullptr);
     __syncthreads();
     for (int e = threadIdx.x; e < 4 * kWidth; e += 256) {  // halo rows of hB (the input window is spent)
         const int rr = e / kWidth, c = e % kWidth;
         hB[(rr < 2 ? rr : kInferRows - 4 + rr) * kInferSH + c] = 0;
     }
-    infer_layer<kTaps, kTaps * kWidth>(packed + P.o[1], params + off.o[3], kWidth, kWidth, hA, kInferSH, L, true,
-                                       hB, nullptr);
+    infer_layer<kTaps, kTaps * kWidth, kWidth, kInferSH>(packed + P.o[1], params + off.o[3], kWidth, hA, L, true,
+                                                         hB, nullptr);
     __syncthreads();
-    infer_layer<kTaps, kTaps * kWidth>(packed + P.o[2], params + off.o[5], kWidth, kWidth, hB, kInferSH, L, true,
-                                       hA, nullptr);
+    infer_layer<kTaps, kTaps * kWidth, kWidth, kInferSH>(packed + P.o[2], params + off.o[5], kWidth, hB, L, true,
+                                                         hA, nullptr);
     __syncthreads();
-    infer_layer<1, kWidth>(packed + P.o[3], params + off.o[7], c_out, kWidth, hA, kInferSH, L, false, nullptr,
+    infer_layer<1, kWidth, kWidth, kInferSH>(packed + P.o[3], params + off.o[7], c_out, hA, L, false, nullptr,
                            logits ? logits + (int64_t)b * c_out * L : nullptr,
                            score ? score + (int64_t)b * (c_out / 2) * nbg : nullptr, pb, nbg);
 }
@@ -705,18 +726,21 @@ hipError_t launch_cnn_infer(const float *params, const float *x, int B, int c_in
     hipLaunchKernelGGL(cnn_pack_kernel, dim3((unsigned)((P.total + 255) / 256)), dim3(256), 0, st, params, off, c_in,
                        c_out, P, scratch);
     const dim3 grid((unsigned)B), block(256);
-    // layer 1's K: 5 taps x channels rounded to 4, rounded to 16
-    switch (P.Kw1) {
-        case 32: hipLaunchKernelGGL(cnn_infer_kernel<32>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
-        case 48: hipLaunchKernelGGL(cnn_infer_kernel<48>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
-        case 64: hipLaunchKernelGGL(cnn_infer_kernel<64>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
-        case 80: hipLaunchKernelGGL(cnn_infer_kernel<80>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
-        case 96: hipLaunchKernelGGL(cnn_infer_kernel<96>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
-        case 112: hipLaunchKernelGGL(cnn_infer_kernel<112>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
-        case 128: hipLaunchKernelGGL(cnn_infer_kernel<128>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
-        case 144: hipLaunchKernelGGL(cnn_infer_kernel<144>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
-        default: hipLaunchKernelGGL(cnn_infer_kernel<160>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, score, pb, nbg); break;
+    // input channels rounded to 4 (layer 1's K: 5 taps x those, rounded to 16)
+#define LTGW_INFER(CP)                                                                                            \
+    hipLaunchKernelGGL(cnn_infer_kernel<CP>, grid, block, 0, st, params, scratch, x, c_in, c_out, L, off, P, logits, \
+                       score, pb, nbg)
+    switch (P.Cp1) {
+        case 4: LTGW_INFER(4); break;
+        case 8: LTGW_INFER(8); break;
+        case 12: LTGW_INFER(12); break;
+        case 16: LTGW_INFER(16); break;
+        case 20: LTGW_INFER(20); break;
+        case 24: LTGW_INFER(24); break;
+        case 28: LTGW_INFER(28); break;
+        default: LTGW_INFER(32); break;
     }
+#undef LTGW_INFER
     return hipGetLastError();
 }
 
