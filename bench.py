@@ -183,14 +183,18 @@ def precision_report(ref, runs):
 
 
 def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_signal=4096, eval_noise=1024, seed=7,
-                 coarse_segments=8, select2_frac=0.0, block=32, label="near", select_frac=0.05, tier2_quantile=None,
-                 counts=True):
+                 coarse_segments=8, select2_frac=0.0, block=32, label="near", select_blocks=(8, 9, 10),
+                 tier2_quantile=None, counts=True):
     """The learned proposer on the small workload's shape (1024 segments x 800
     bins, 4800 fine templates): trained on `realisations` device-generated
     noise + injection realisations (amplitudes U[0.3, 3]), then recall and
-    speed against the plain FP32 exhaustive search, beside the ranking by the
-    coarse power ratios alone at the same budget (the method without the
-    network).  Returns the JSON object."""
+    speed against the plain FP32 exhaustive search at each first-tier budget
+    (select_blocks blocks of `block` f0 per realisation: 256, 288 and 320 of
+    the 4800 cells) and fallback quantile; the point reported is the fastest
+    at recall 0.99, else the best recall at 5x or more, and best_at_5x is the
+    best recall at 5x or more.  Beside it, the ranking by the coarse power
+    ratios alone at the reported budget (the method without the network).
+    Returns the JSON object."""
     import synth
     from paper_2507_07816_amd.proposer import Proposer, coarse_grid_for
 
@@ -207,8 +211,8 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
     ctau = np.sqrt(tau[0::2] * tau[1::2])
     cbrake = np.array([(brake[0] + brake[1]) / 2, (brake[-2] + brake[-1]) / 2])
     coarse = coarse_grid_for(fine, ctau, cbrake)
-    pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=select_frac, store="f32", block=block,
-                  select2_frac=select2_frac, coarse_segments=coarse_segments, counts=counts)
+    pr = Proposer(ctx, 0, d["rho"].shape, fine, coarse, seed=seed, select_frac=0.05, store="f32",
+                  block=block, select2_frac=select2_frac, coarse_segments=coarse_segments, counts=counts)
     steps = max(1, realisations // batch)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -217,7 +221,8 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t
     ev = pr.evaluate(R_noise=eval_noise, R_signal=eval_signal, amp_range=(0.3, 3.0), fine_store="bf16",
-                     coarse_quantiles=(None, 1.0, 0.9, 0.7), tier2_quantile=tier2_quantile)
+                     coarse_quantiles=(None, 1.0, 0.9, 0.7), tier2_quantile=tier2_quantile,
+                     budgets=[k * block for k in select_blocks])
     ctx.close()
     base = ev.pop("coarse_only")
     out = {"workload": "tiny-1024seg-800bin-4800tpl realisations", "train_realisations": steps * batch,
@@ -228,8 +233,14 @@ def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_sig
                       " ratios)",
            "speedup_counts": "exhaustive FP32 search / (ltgw_propose + the coarse store's extra ingest time)"}
     out.update(ev)
-    out["coarse_only"] = {k: base[k] for k in ("recall", "recall_no_fallback", "recall_same_template", "recall_best",
-                                               "fallback_frac", "propose_ms", "speedup", "coarse_quantile")}
+    fast = [p for p in ev["points"] if p["speedup"] >= 5.0]
+    out["best_at_5x"] = None if not fast else {k: v for k, v in max(fast, key=lambda p: p["recall"]).items()
+                                               if k in ("n_select", "coarse_quantile", "recall",
+                                                        "recall_same_template", "recall_best", "fallback_frac",
+                                                        "propose_ms", "speedup")}
+    out["coarse_only"] = {k: base[k] for k in ("n_select", "recall", "recall_no_fallback", "recall_same_template",
+                                               "recall_best", "fallback_frac", "propose_ms", "speedup",
+                                               "coarse_quantile")}
     return out
 
 

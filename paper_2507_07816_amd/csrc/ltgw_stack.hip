@@ -317,9 +317,12 @@ hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_b
     return hipGetLastError();
 }
 
-// Proposal blocks evaluated in place: workgroup (x, rr) takes NB = 256 / W
-// blocks blk[r][x NB .. x NB + NB) of realisation r = rmap[rr] (or rr), W
-// lanes per block, lane l on fine f0 index (b % nbg) W + l of group b / nbg.
+// Proposal blocks evaluated in place: workgroup (x, rr) of TPB threads takes
+// NB = TPB / W blocks blk[r][x NB .. x NB + NB) of realisation r = rmap[rr]
+// (or rr), W lanes per block, lane l on fine f0 index (b % nbg) W + l of
+// group b / nbg.  Workgroups of one wavefront serve block counts that are not
+// a multiple of 256 / W (a realisation's last workgroup is then at most one
+// wavefront short of full).
 // Each wavefront stages its own blocks' track factors in LDS per chunk of 32
 // segments (no workgroup barrier: a wavefront's LDS accesses complete in
 // order), so the only vector-memory access per template and segment is the
@@ -331,14 +334,14 @@ __device__ inline T uniform_load(const T *p, int i) {
 }
 
 // SB: segments per batch of gathers in flight.
-template <int STORE, int W, int SB>
-__global__ __launch_bounds__(256) void block_eval_kernel(const EvalArgs a, int R, int64_t stack_bytes,
+template <int STORE, int W, int SB, int TPB>
+__global__ __launch_bounds__(TPB) void block_eval_kernel(const EvalArgs a, int R, int64_t stack_bytes,
                                                          int64_t stack_rows, const int32_t *__restrict__ blk, int K,
                                                          int nbg, const int32_t *__restrict__ rmap,
                                                          const int32_t *__restrict__ n_rows, const StackMoments mom,
                                                          int32_t *__restrict__ out_tpl,
                                                          double *__restrict__ out_psi) {
-    constexpr int NB = 256 / W, SPW = 64 / W;  // blocks per workgroup, per wavefront
+    constexpr int NB = TPB / W, SPW = 64 / W;  // blocks per workgroup, per wavefront
     __shared__ double sh[NB][kChunk];
     // XCD order as in stack_eval_kernel: the workgroups of one row share an
     // XCD (and its L2), consecutive rows go to different XCDs
@@ -426,14 +429,19 @@ hipError_t launch_block_eval(int store, int W, const EvalArgs &a, int R, int64_t
                              const int32_t *blk, int K, int nbg, const int32_t *rmap, const int32_t *n_rows,
                              StackMoments mom, int32_t *out_tpl, double *out_psi, hipStream_t st) {
     if (R > 65535 || R < 1 || K < 1 || !block_eval_supported(W)) return hipErrorInvalidValue;
-    const int NB = 256 / W;
+    const int tpb = K % (256 / W) == 0 ? 256 : 64;
+    const int NB = tpb / W;
     // rows rounded up to a multiple of the XCD count (the extra workgroups return)
     const int64_t wgs = (int64_t)((K + NB - 1) / NB) * ((R + kXcds - 1) / kXcds * kXcds);
     if (wgs > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)wgs), block(256);
-#define LTGW_BLOCK_EVAL(S, WW)                                                                                      \
-    hipLaunchKernelGGL((block_eval_kernel<S, WW, 16>), grid, block, 0, st, a, R, stack_bytes, stack_rows, blk, K, nbg, \
-                       rmap, n_rows, mom, out_tpl, out_psi)
+    const dim3 grid((unsigned)wgs), block(tpb);
+#define LTGW_BLOCK_EVAL(S, WW)                                                                                         \
+    if (tpb == 256)                                                                                                    \
+        hipLaunchKernelGGL((block_eval_kernel<S, WW, 16, 256>), grid, block, 0, st, a, R, stack_bytes, stack_rows, blk, \
+                           K, nbg, rmap, n_rows, mom, out_tpl, out_psi);                                               \
+    else                                                                                                               \
+        hipLaunchKernelGGL((block_eval_kernel<S, WW, 16, 64>), grid, block, 0, st, a, R, stack_bytes, stack_rows, blk,  \
+                           K, nbg, rmap, n_rows, mom, out_tpl, out_psi)
 #define LTGW_BLOCK_EVAL_W(S)          \
     if (W == 16)                      \
         LTGW_BLOCK_EVAL(S, 16);       \

@@ -313,7 +313,7 @@ class Proposer:
 
     def evaluate(self, R_noise=256, R_signal=256, amp_range=(1.0, 3.0), fine_store="bf16", reps=3,
                  coarse_quantiles=(1.0,), target_recall=0.99, tier2_quantile=None, baseline=True,
-                 target_speedup=5.0):
+                 target_speedup=5.0, budgets=None):
         """Recall and speed against the exhaustive search, for the network and
         (baseline) for the ranking by the coarse power ratios alone at the
         same budget (blocks, tiers, thresholds, fallback rule).
@@ -341,10 +341,12 @@ class Proposer:
         to the proposer: speedup = exhaustive / (propose + coarse_extra).
         The FP32 store the exhaustive search reads costs more to ingest than
         the BF16 one, which is not credited.  The operating point reported is
-        the fastest quantile whose recall reaches target_recall; failing that,
+        the fastest point whose recall reaches target_recall; failing that,
         the best recall among those at least target_speedup times faster;
-        failing that, the fastest.  Every quantile's figures are under
-        "points"."""
+        failing that, the fastest.  The points are every quantile at every
+        budget (first-tier cell counts; None: this proposer's n_select), and
+        their figures are under "points".  The coarse-only ranking is
+        measured at the chosen point's budget."""
         T = self.torch
         h = self.ctx.h
         zeros = np.zeros((R_noise, 4))
@@ -399,11 +401,7 @@ class Proposer:
 
         t2 = -1e300 if tier2_quantile is None else float(np.quantile(coarse_max, tier2_quantile))
 
-        def operating_points(network):
-            _, pp_nf, fb_nf, bl_nf = self.propose(psi_thr, 1e300, R_signal, return_blocks=True,
-                                                  tier2_threshold=t2, network=network)  # fallback never taken
-            rec_nf, rec_best_nf, rec_same_nf = recalls(pp_nf, fb_nf, bl_nf)
-            points = []
+        def budget_points(network, points):
             for q in coarse_quantiles:
                 # q None: no fallback
                 coarse_thr = 1e300 if q is None else float(np.quantile(coarse_max, q))
@@ -417,13 +415,23 @@ class Proposer:
                 pi, pp, fb, bl = self.propose(psi_thr, coarse_thr, R_signal, return_blocks=True,
                                               tier2_threshold=t2, network=network)
                 rec, rec_best, rec_same = recalls(pp, fb, bl)
-                points.append(dict(coarse_quantile=q, coarse_threshold=coarse_thr, recall=rec, recall_best=rec_best,
-                                   recall_same_template=rec_same,
+                points.append(dict(n_select=self.n_select, coarse_quantile=q, coarse_threshold=coarse_thr,
+                                   recall=rec, recall_best=rec_best, recall_same_template=rec_same,
                                    fallback_frac=float(fb.mean()), propose_ms=min(t_pr),
                                    speedup=min(t_ex) / (min(t_pr) + coarse_extra),
                                    speedup_search_only=min(t_ex) / min(t_pr),
                                    same_template=float((pi[det_ex] == ex_idx[det_ex]).mean()) if n_det
                                    else float("nan")))
+
+        def operating_points(network, budgets):
+            own = self.n_select
+            points = []
+            try:
+                for n_sel in budgets:
+                    self.n_select = own if n_sel is None else int(n_sel)
+                    budget_points(network, points)
+            finally:
+                self.n_select = own
             ok = [p for p in points if p["recall"] >= target_recall]
             fast = [p for p in points if p["speedup"] >= target_speedup]
             if ok:
@@ -432,20 +440,28 @@ class Proposer:
                 best = max(fast, key=lambda p: (p["recall"], p["speedup"]))
             else:
                 best = max(points, key=lambda p: p["speedup"])
+            # the chosen budget with the fallback never taken
+            self.n_select, keep = best["n_select"], self.n_select
+            try:
+                _, pp_nf, fb_nf, bl_nf = self.propose(psi_thr, 1e300, R_signal, return_blocks=True,
+                                                      tier2_threshold=t2, network=network)
+            finally:
+                self.n_select = keep
+            rec_nf, rec_best_nf, rec_same_nf = recalls(pp_nf, fb_nf, bl_nf)
             out = dict(best)
             out.update(recall_no_fallback=rec_nf, recall_best_no_fallback=rec_best_nf,
                        recall_same_template_no_fallback=rec_same_nf, points=points)
             return out
 
         amp = inj[:, 3]
-        out = operating_points(True)
+        out = operating_points(True, budgets if budgets else (None,))
         out.update(detectable=n_near, detectable_best=n_det, realisations=R_signal,
                    detectable_min_amp=float(amp[det_near].min()) if n_near else float("nan"),
                    psi_threshold=psi_thr, tier2_quantile=tier2_quantile, tier2_threshold=t2,
                    exhaustive_ms=min(t_ex), ingest_ms=ingest, coarse_extra_ms=coarse_extra,
-                   n_select=self.n_select, n_select2=self.n_select2, block=self.block,
+                   n_select2=self.n_select2, block=self.block,
                    coarse_segments=self.coarse_segments, input_channels=self.c_in, counts=self.counts,
                    n_cells=self.n_cells, fine_store=fine_store, target_recall=target_recall)
         if baseline:
-            out["coarse_only"] = operating_points(False)
+            out["coarse_only"] = operating_points(False, (out["n_select"],))
         return out
