@@ -313,7 +313,7 @@ class Proposer:
 
     def evaluate(self, R_noise=256, R_signal=256, amp_range=(1.0, 3.0), fine_store="bf16", reps=3,
                  coarse_quantiles=(1.0,), target_recall=0.99, tier2_quantile=None, baseline=True,
-                 target_speedup=5.0, budgets=None):
+                 target_speedup=5.0, budgets=None, ingest_reps=7):
         """Recall and speed against the exhaustive search, for the network and
         (baseline) for the ranking by the coarse power ratios alone at the
         same budget (blocks, tiers, thresholds, fallback rule).
@@ -335,7 +335,7 @@ class Proposer:
         overall best; recall_no_fallback is recall with the fallback off.
         Times (HIP events on the context's stream, best of `reps`): the
         exhaustive FP32 search (ltgw_stack_best) and ltgw_propose on the same
-        realisations.  The coarse store is written in the same pass as the
+        realisations; the two ingests below, best of `ingest_reps` each.  The coarse store is written in the same pass as the
         fine store; what it adds to that pass (ingest of the fine store with
         the coarse one, less the ingest of the fine store alone) is charged
         to the proposer: speedup = exhaustive / (propose + coarse_extra).
@@ -374,8 +374,15 @@ class Proposer:
         # the exhaustive search's best template close to each injection (the
         # listed evaluation gives the exhaustive kernel's sums, bit for bit)
         near_tpl, near_psi = self.near_best(inj)
-        ingest[fine_store] = self._ingest_ms(b["stack"], fine_store, 0, reps)
-        ingest[fine_store + "+coarse"] = self._ingest_ms(b["stack"], fine_store, self.coarse_segments, reps)
+        # the two ingests alternate (best of ingest_reps each), so that drift
+        # in the device's clock or load affects both alike; the coarse one
+        # runs last and leaves the stores loaded
+        t_f, t_c = [], []
+        for _ in range(max(1, ingest_reps)):
+            t_f.append(self._ingest_ms(b["stack"], fine_store, 0, 1))
+            t_c.append(self._ingest_ms(b["stack"], fine_store, self.coarse_segments, 1))
+        ingest[fine_store] = min(t_f)
+        ingest[fine_store + "+coarse"] = min(t_c)
         coarse_extra = max(0.0, ingest[fine_store + "+coarse"] - ingest[fine_store])
         near_prop = T.empty((R_signal, 1), dtype=T.float64, device=self.ctx.device)
         ltgw.ltgw_stack_psi_list(h, self._fg, T.from_numpy(np.maximum(near_tpl, 0).reshape(-1, 1)).to(self.ctx.device),
