@@ -249,7 +249,7 @@ void ltgw_destroy(ltgw_ctx *c) {
         release(d.scale); release(d.v); release(d.g); release(d.H); release(d.wfix); release(d.win);
         release(d.era); release(d.w_sky); release(d.wq_sky);
     }
-    DevBuf *all[] = {&c->staging, &c->counters, &c->cnn_packed, &c->list_d, &c->perm_d,
+    DevBuf *all[] = {&c->staging, &c->counters, &c->cnn_packed, &c->list_d, &c->perm_d, &c->list_dop, &c->list_sky,
                      &c->tau_d,   &c->brake_d,  &c->sky_d,      &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2, &c->diff,
                      &c->cand_pa, &c->cand_ia, &c->cand_pb, &c->cand_ib, &c->cand_out, &c->n_out};
     for (DevBuf *b : all) release(*b);
@@ -920,6 +920,29 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
     a.out_n = out_n;
     a.in_band_total = (unsigned long long *)c->counters.p + kCntInBand;
     a.pow_counts = (unsigned long long *)c->counters.p + kCntUndecided;
+    // one sky direction for the whole list (and no antenna weights): each
+    // detector's Doppler factors 1 + v.n/c as the lattice forms them (the
+    // same operations in the same order), read per segment by the kernel
+    bool one_sky = true, any_ant = false;
+    for (int64_t q = 1; q < n && one_sky; ++q) one_sky = std::memcmp(tpl[q].sky, tpl[0].sky, sizeof tpl[0].sky) == 0;
+    for (int q = 0; q < n_slots; ++q) any_ant = any_ant || a.det[q].era != nullptr;
+    if (one_sky && !any_ant) {
+        int64_t off = 0, tot = 0;
+        for (int q = 0; q < n_slots; ++q) tot += c->det[slots[q]].n_seg;
+        if ((rc = ensure(c, c->list_dop, (size_t)tot * 8, "list Doppler tables")) != LTGW_OK) return rc;
+        if ((rc = ensure(c, c->list_sky, 3 * sizeof(double), "list sky")) != LTGW_OK) return rc;
+        // from the context's host copy of the list (kept until the next upload has run)
+        if ((rc = h2d(c, c->list_sky.p, c->h_list[0].sky, 3 * sizeof(double), "list sky upload")) != LTGW_OK)
+            return rc;
+        for (int q = 0; q < n_slots; ++q) {
+            const Det &D = c->det[slots[q]];
+            double *dq = (double *)c->list_dop.p + off;
+            HIP_TRY(c, launch_doppler((const double *)D.v.p, D.n_seg, (const double *)c->list_sky.p, 1, dq, c->stream),
+                    "list Doppler launch");
+            a.det[q].dop = dq;
+            off += D.n_seg;
+        }
+    }
     HIP_TRY(c, hipEventRecord(c->ev_h2d, c->stream), "event record");
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream), "event record");
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream), "event record");

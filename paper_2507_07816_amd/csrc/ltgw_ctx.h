@@ -158,6 +158,7 @@ struct ltgw_ctx {
     std::vector<ltgw_template> h_list;  // host staging of its templates for the upload ...
     std::vector<int32_t> h_perm;        // ... and of their evaluation order
     ltgw::DevBuf list_d, perm_d;
+    ltgw::DevBuf list_dop, list_sky;    // Doppler tables of a one-sky list, and that sky
     // data preparation (ltgw_sft_normalise): spectra of a chunk, FFT plans
     struct SftPlan {
         int n_fft, batch;

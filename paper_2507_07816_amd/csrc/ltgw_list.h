@@ -21,6 +21,8 @@ struct ListDet {
     const double *era;     // [n_seg] Earth rotation angles, or NULL: no antenna factor
     const float *scale;    // [n_seg] store row scales (antenna weights are formed per template)
     Arms arms;
+    const double *dop;     // [n_seg] Doppler factor 1 + v.n/c when every template has the same sky
+                           // direction n (the lattice's table for it), or NULL: formed per template
 };
 
 struct ListArgs {

@@ -33,7 +33,9 @@ __device__ inline T seg_load(const T *p, int i) {
 // ANT: some detector carries antenna-pattern weights.  Without, the kernel
 // holds none of their per-detector values, which leaves the scalar registers
 // to the power's constants (else they spill into vector-register lanes).
-template <int STORE, bool ANT>
+// DOP: every detector has a Doppler table (one sky direction for the whole
+// list), read per segment instead of formed per template.
+template <int STORE, bool ANT, bool DOP>
 __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool live = q < a.n;
@@ -64,12 +66,17 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
                     if (und) atomicAdd(a.pow_counts, 1ull);
                     if (slow) atomicAdd(a.pow_counts + 1, 1ull);
                 }
-                const double va = seg_load(D.v, 3 * j + 0) * T.sky[0];
-                const double vb = seg_load(D.v, 3 * j + 1) * T.sky[1];
-                const double vz = seg_load(D.v, 3 * j + 2) * T.sky[2];
-                const double vn = (va + vb) + vz;
-                const double r = div_rn(vn, kC, kInvC);
-                const double Df = 1.0 + r;
+                double Df;
+                if (DOP) {
+                    Df = seg_load(D.dop, j);
+                } else {
+                    const double va = seg_load(D.v, 3 * j + 0) * T.sky[0];
+                    const double vb = seg_load(D.v, 3 * j + 1) * T.sky[1];
+                    const double vz = seg_load(D.v, 3 * j + 2) * T.sky[2];
+                    const double vn = (va + vb) + vz;
+                    const double r = div_rn(vn, kC, kInvC);
+                    Df = 1.0 + r;
+                }
                 const double h = g * Df;
                 const double H = h * D.t_sft;
                 const double x = T.f0 * H;
@@ -106,21 +113,30 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
     if (a.out_n) a.out_n[o] = nin;
 }
 
+template <int STORE>
+static void launch_list_store(bool ant, bool dop, const ListArgs &a, dim3 grid, hipStream_t st) {
+    if (ant)
+        hipLaunchKernelGGL((template_list_kernel<STORE, true, false>), grid, dim3(256), 0, st, a);
+    else if (dop)
+        hipLaunchKernelGGL((template_list_kernel<STORE, false, true>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((template_list_kernel<STORE, false, false>), grid, dim3(256), 0, st, a);
+}
+
 hipError_t launch_template_list(int store, const ListArgs &a, hipStream_t st) {
     if (a.n < 1 || a.n > 0x7fffffffLL) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
-    bool ant = false;
-    for (int d = 0; d < a.n_det; ++d) ant = ant || a.det[d].era != nullptr;
-    if (store == LTGW_STORE_F32) {
-        if (ant) hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_F32, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_F32, false>), grid, block, 0, st, a);
-    } else if (store == LTGW_STORE_BF16) {
-        if (ant) hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_BF16, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_BF16, false>), grid, block, 0, st, a);
-    } else {
-        if (ant) hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_FP8, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((template_list_kernel<LTGW_STORE_FP8, false>), grid, block, 0, st, a);
+    const dim3 grid((unsigned)((a.n + 255) / 256));
+    bool ant = false, dop = true;
+    for (int d = 0; d < a.n_det; ++d) {
+        ant = ant || a.det[d].era != nullptr;
+        dop = dop && a.det[d].dop != nullptr;
     }
+    if (store == LTGW_STORE_F32)
+        launch_list_store<LTGW_STORE_F32>(ant, dop, a, grid, st);
+    else if (store == LTGW_STORE_BF16)
+        launch_list_store<LTGW_STORE_BF16>(ant, dop, a, grid, st);
+    else
+        launch_list_store<LTGW_STORE_FP8>(ant, dop, a, grid, st);
     return hipGetLastError();
 }
 
