@@ -53,7 +53,7 @@ extern "C" {
                                    |v| >= c, shape mismatch, k out of range, NULL */
 #define LTGW_E_STATE (-2)       /* call order: eval before load/velocity, topk before eval,
                                    unknown detector */
-#define LTGW_E_NOMEM (-3)       /* device allocation failed */
+#define LTGW_E_NOMEM (-3)       /* device (or pinned host) allocation failed */
 #define LTGW_E_DEVICE (-4)      /* HIP runtime error; text in ltgw_last_error */
 #define LTGW_E_UNSUPPORTED (-5) /* valid request outside what the library supports */
 #define LTGW_E_IO (-6)          /* a file could not be opened, read or written, or is

@@ -98,6 +98,32 @@ void release(DevBuf &b) {
     b.cap = 0;
 }
 
+// Pinned host staging (hipHostMalloc), grown like ensure(); the caller has
+// waited for every copy that reads the old buffer.
+int ensure_pinned(ltgw_ctx *c, DevBuf &b, size_t bytes, const char *what) {
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return LTGW_OK;
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    void *p = nullptr;
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, LTGW_E_NOMEM, "pinned host allocation of %zu bytes for %s failed: %s", bytes, what,
+                    hipGetErrorString(e));
+    }
+    b.p = p;
+    b.cap = bytes;
+    return LTGW_OK;
+}
+
+void release_pinned(DevBuf &b) {
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
 bool is_device_ptr(const void *p) {
     hipPointerAttribute_t attr;
     hipError_t e = hipPointerGetAttributes(&attr, p);
@@ -253,6 +279,8 @@ void ltgw_destroy(ltgw_ctx *c) {
                      &c->tau_d,   &c->brake_d,  &c->sky_d,      &c->res_s, &c->res_c, &c->res_n, &c->res_w1, &c->res_w2, &c->diff,
                      &c->cand_pa, &c->cand_ia, &c->cand_pb, &c->cand_ib, &c->cand_out, &c->n_out};
     for (DevBuf *b : all) release(*b);
+    release_pinned(c->h_list);
+    release_pinned(c->h_perm);
     delete c;
 }
 
@@ -881,7 +909,7 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
     for (int64_t q = 1; q < n; ++q) f0_lo = tpl[q].f0 < f0_lo ? tpl[q].f0 : f0_lo;
     constexpr int kBuckets = 1 << 16;
     const double bscale = f0_max > f0_lo ? (kBuckets - 1) / (f0_max - f0_lo) : 0.0;
-    std::vector<int32_t> bucket_start(kBuckets + 1, 0), perm((size_t)n);
+    std::vector<int32_t> bucket_start(kBuckets + 1, 0);
     std::vector<uint16_t> key((size_t)n);
     for (int64_t q = 0; q < n; ++q) {
         const int b = (int)((tpl[q].f0 - f0_lo) * bscale);
@@ -889,16 +917,21 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
         ++bucket_start[key[(size_t)q] + 1];
     }
     for (int b = 0; b < kBuckets; ++b) bucket_start[b + 1] += bucket_start[b];
-    for (int64_t q = 0; q < n; ++q) perm[(size_t)bucket_start[key[(size_t)q]]++] = (int32_t)q;
+    // the staging is pinned (the uploads run at DMA rate) and reused: wait for
+    // the previous call's uploads from it first
     HIP_TRY(c, hipEventSynchronize(c->ev_h2d), "previous upload");
-    c->h_list.assign(tpl, tpl + n);
-    c->h_perm.swap(perm);
     int rc;
+    if ((rc = ensure_pinned(c, c->h_list, (size_t)n * sizeof(ltgw_template), "template staging")) != LTGW_OK)
+        return rc;
+    if ((rc = ensure_pinned(c, c->h_perm, (size_t)n * 4, "template order staging")) != LTGW_OK) return rc;
+    int32_t *perm = (int32_t *)c->h_perm.p;
+    for (int64_t q = 0; q < n; ++q) perm[(size_t)bucket_start[key[(size_t)q]]++] = (int32_t)q;
+    std::memcpy(c->h_list.p, tpl, (size_t)n * sizeof(ltgw_template));
     if ((rc = ensure(c, c->list_d, (size_t)n * sizeof(ltgw_template), "template list")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->perm_d, (size_t)n * 4, "template order")) != LTGW_OK) return rc;
-    if ((rc = h2d(c, c->list_d.p, c->h_list.data(), (size_t)n * sizeof(ltgw_template), "template upload")) != LTGW_OK)
+    if ((rc = h2d(c, c->list_d.p, c->h_list.p, (size_t)n * sizeof(ltgw_template), "template upload")) != LTGW_OK)
         return rc;
-    if ((rc = h2d(c, c->perm_d.p, c->h_perm.data(), (size_t)n * 4, "template order upload")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, c->perm_d.p, c->h_perm.p, (size_t)n * 4, "template order upload")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->res_s, n * 8, "results s")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->res_c, n * 4, "results c")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->res_n, n * 4, "results N")) != LTGW_OK) return rc;
@@ -932,7 +965,8 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
         if ((rc = ensure(c, c->list_dop, (size_t)tot * 8, "list Doppler tables")) != LTGW_OK) return rc;
         if ((rc = ensure(c, c->list_sky, 3 * sizeof(double), "list sky")) != LTGW_OK) return rc;
         // from the context's host copy of the list (kept until the next upload has run)
-        if ((rc = h2d(c, c->list_sky.p, c->h_list[0].sky, 3 * sizeof(double), "list sky upload")) != LTGW_OK)
+        if ((rc = h2d(c, c->list_sky.p, ((const ltgw_template *)c->h_list.p)[0].sky, 3 * sizeof(double),
+                      "list sky upload")) != LTGW_OK)
             return rc;
         for (int q = 0; q < n_slots; ++q) {
             const Det &D = c->det[slots[q]];

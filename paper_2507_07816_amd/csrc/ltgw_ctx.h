@@ -155,8 +155,7 @@ struct ltgw_ctx {
     int last_variant = 1;
     int last_launches = 0;  // statistic-kernel dispatches of the last eval
     bool list_mode = false;      // the last eval was an explicit template list
-    std::vector<ltgw_template> h_list;  // host staging of its templates for the upload ...
-    std::vector<int32_t> h_perm;        // ... and of their evaluation order
+    ltgw::DevBuf h_list, h_perm;  // pinned host staging of its templates and of their evaluation order
     ltgw::DevBuf list_d, perm_d;
     ltgw::DevBuf list_dop, list_sky;    // Doppler tables of a one-sky list, and that sky
     // data preparation (ltgw_sft_normalise): spectra of a chunk, FFT plans
@@ -180,6 +179,9 @@ int fail(ltgw_ctx *c, int code, const char *fmt, ...);
 int hip_fail(ltgw_ctx *c, hipError_t e, const char *what);
 int ensure(ltgw_ctx *c, DevBuf &b, size_t bytes, const char *what);
 void release(DevBuf &b);
+// pinned host staging, grown like ensure()
+int ensure_pinned(ltgw_ctx *c, DevBuf &b, size_t bytes, const char *what);
+void release_pinned(DevBuf &b);
 bool is_device_ptr(const void *p);
 void sft_release(ltgw_ctx *c);  // FFT plans and buffers of the data preparation
 int to_host(ltgw_ctx *c, void *dst, const void *src, size_t n, const char *what);
