@@ -148,6 +148,16 @@ const char *fft_error(hipfftResult r) {
 
 using namespace ltgw;
 
+// A chunk of strain rows (n_fft reals each) into the transform buffer's rows
+// of n_fft + 2 reals: 8-byte moves (n_fft is even, so every row of both is
+// 8-byte aligned), a grid-stride loop over each row.
+__global__ __launch_bounds__(256) void pad_rows_kernel(const float2 *__restrict__ src, int64_t src_pitch,
+                                                       float2 *__restrict__ dst, int64_t dst_pitch, int64_t pairs) {
+    const float2 *s = src + (int64_t)blockIdx.y * src_pitch;
+    float2 *d = dst + (int64_t)blockIdx.y * dst_pitch;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < pairs; i += (int64_t)gridDim.x * 256) d[i] = s[i];
+}
+
 extern "C" {
 
 int32_t ltgw_sft_normalise(ltgw_ctx *c, const float *strain, int32_t n_seg, int32_t n_fft, int64_t k_lo,
@@ -188,10 +198,14 @@ int32_t ltgw_sft_normalise(ltgw_ctx *c, const float *strain, int32_t n_seg, int3
         // to n_fft + 2 reals) and transformed there in place: the library's
         // transform may use its input as scratch, and the caller's strain is
         // only read
-        HIP_TRY(c, hipMemcpy2DAsync(c->sft_spec.p, (size_t)(n_fft + 2) * 4, strain + (int64_t)j0 * n_fft,
-                                    (size_t)n_fft * 4, (size_t)n_fft * 4, (size_t)nb, hipMemcpyDeviceToDevice,
-                                    c->stream),
-                "strain copy");
+        {
+            const int64_t pairs = n_fft / 2;
+            const unsigned gx = (unsigned)std::min<int64_t>((pairs + 255) / 256, 16);
+            hipLaunchKernelGGL(pad_rows_kernel, dim3(gx, (unsigned)nb), dim3(256), 0, c->stream,
+                               (const float2 *)(strain + (int64_t)j0 * n_fft), pairs, (float2 *)c->sft_spec.p,
+                               (int64_t)(n_fft / 2 + 1), pairs);
+            HIP_TRY(c, hipGetLastError(), "strain copy launch");
+        }
         hipfftResult r = hipfftSetStream(plan, c->stream);
         if (r == HIPFFT_SUCCESS)
             r = hipfftExecR2C(plan, (hipfftReal *)c->sft_spec.p, (hipfftComplex *)c->sft_spec.p);
