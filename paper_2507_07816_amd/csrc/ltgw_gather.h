@@ -268,6 +268,14 @@ __device__ inline void xcd_tile_group(int w, int n_blocks, int n_tiles, int &til
     grp = p % n_groups;
 }
 
+// An element every lane of the wavefront reads at the same address, through
+// the constant address space: for arrays no kernel writes while it runs,
+// this makes the read a scalar load.
+template <typename T>
+__device__ inline T uniform_load(const T *p, int64_t i) {
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 // A value that is the same in every lane, moved to scalar registers word by
 // word (lets the compiler treat descriptors read from memory as uniform).
 template <class T>

@@ -9,14 +9,6 @@
 
 namespace ltgw {
 
-// A per-segment value every lane of the wavefront reads at the same address,
-// through the constant address space: the segment arrays are not written
-// while the kernel runs, so this becomes a scalar load.
-template <typename T>
-__device__ inline T seg_load(const T *p, int i) {
-    return ((const __attribute__((address_space(4))) T *)p)[i];
-}
-
 // Lane q evaluates template perm[q] over every selected detector and segment
 // with the lattice's arithmetic, in its order:
 //   t < T0: masked (g = 0, so the column falls out of band)
@@ -54,7 +46,7 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
             const int je = min(j0 + kChunk, D.n_seg);
             float sc = 0.0f, w1c = 0.0f, w2c = 0.0f;
             for (int j = j0; j < je; ++j) {
-                const double t = seg_load(D.t, j);
+                const double t = uniform_load(D.t, j);
                 double g = 0.0;
                 if (!(t < a.t0)) {
                     const double dt = t - a.t0;
@@ -68,11 +60,11 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
                 }
                 double Df;
                 if (DOP) {
-                    Df = seg_load(D.dop, j);
+                    Df = uniform_load(D.dop, j);
                 } else {
-                    const double va = seg_load(D.v, 3 * j + 0) * T.sky[0];
-                    const double vb = seg_load(D.v, 3 * j + 1) * T.sky[1];
-                    const double vz = seg_load(D.v, 3 * j + 2) * T.sky[2];
+                    const double va = uniform_load(D.v, 3 * j + 0) * T.sky[0];
+                    const double vb = uniform_load(D.v, 3 * j + 1) * T.sky[1];
+                    const double vz = uniform_load(D.v, 3 * j + 2) * T.sky[2];
                     const double vn = (va + vb) + vz;
                     const double r = div_rn(vn, kC, kInvC);
                     Df = 1.0 + r;
@@ -83,9 +75,10 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
                 const double vv = x + D.cshift;
                 const unsigned idx = (unsigned)__double2int_rz(vv);
                 const float p = Store<STORE>::get(rs, (int)idx, j * D.pitch_bytes, cnt);
-                float wq = seg_load(D.wq, j), wv = seg_load(D.w, j);
+                float wq = uniform_load(D.wq, j), wv = uniform_load(D.w, j);
                 if (ANT && D.era)  // antenna-pattern weights for this template's sky direction
-                    antenna_weights(D.arms, seg_load(D.era, j), T.sky[0], T.sky[1], T.sky[2], wv, seg_load(D.scale, j), wv, wq);
+                    antenna_weights(D.arms, uniform_load(D.era, j), T.sky[0], T.sky[1], T.sky[2], wv,
+                                    uniform_load(D.scale, j), wv, wq);
                 sc = __builtin_fmaf(wq, p, sc);
                 const bool inb = (idx - 1u) < nb;
                 nin += inb ? 1 : 0;

@@ -328,11 +328,6 @@ hipError_t launch_list_eval(int store, const EvalArgs &a, int R, int64_t stack_b
 // order), so the only vector-memory access per template and segment is the
 // gather; the sums are those of the listed evaluation, in the same order.
 // Writes the expanded template (-1 past the grid) and its ratio (NaN there).
-template <typename T>
-__device__ inline T uniform_load(const T *p, int i) {
-    return ((const __attribute__((address_space(4))) T *)p)[i];
-}
-
 // SB: segments per batch of gathers in flight.
 template <int STORE, int W, int SB, int TPB>
 __global__ __launch_bounds__(TPB) void block_eval_kernel(const EvalArgs a, int R, int64_t stack_bytes,
