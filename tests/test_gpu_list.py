@@ -142,6 +142,34 @@ def test_list_ragged_shapes(n_seg, n_bins, n, t0, weights):
     _check(gpu, ref, params, min(7, n))
 
 
+def test_list_calls_of_changing_size_and_sky():
+    """Calls in a row on one context: small, larger (the pinned host staging and
+    the device lists grow), smaller again, then templates each with its own sky
+    direction, then one sky direction other than the earlier lists' (the
+    Doppler table is rebuilt per call).  Every call against the oracle."""
+    from paper_2507_07816_amd import ltgw
+
+    det = _small(6, 100, 300, k_lo=1900)
+    ctx = ltgw.Context(0)
+    try:
+        _load(ctx, [det])
+        for n, seed in ((50, 40), (3000, 41), (7, 42)):
+            print(f"case: list call of {n} templates", flush=True)
+            params = _bank(n, det, seed=seed, tau=(2000.0, 30000.0), brake=(2.0, 7.0))
+            _check(_run_list(ctx, params, k=min(7, n)), oracle.evaluate_params(det, params), params, min(7, n))
+        params = _bank(400, det, seed=43, tau=(2000.0, 30000.0), brake=(2.0, 7.0))
+        r = np.random.default_rng(44)
+        v = r.normal(size=(400, 3))
+        params[:, 3:6] = v / np.linalg.norm(v, axis=1, keepdims=True)
+        print("case: list call with a sky direction per template", flush=True)
+        _check(_run_list(ctx, params), oracle.evaluate_params(det, params), params, 10)
+        params = _bank(400, det, seed=45, tau=(2000.0, 30000.0), brake=(2.0, 7.0), sky=[0.0, -0.6, 0.8])
+        print("case: list call with one other sky direction", flush=True)
+        _check(_run_list(ctx, params), oracle.evaluate_params(det, params), params, 10)
+    finally:
+        ctx.close()
+
+
 def test_list_two_detectors_and_mask():
     d1 = _small(1, 60, 256, k_lo=1900)
     d2 = _small(2, 45, 200, k_lo=1930, t_sft=4.0)
