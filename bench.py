@@ -47,7 +47,8 @@ KERNEL_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_kernels.hip", "paper_2507_0781
 
 # the explicit-template kernel's code (its committed FP64 instruction count)
 LIST_SOURCES = ("paper_2507_07816_amd/csrc/ltgw_list.hip", "paper_2507_07816_amd/csrc/ltgw_list.h",
-                "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/ltgw_gather.h",
+                "paper_2507_07816_amd/csrc/ddpow.h", "paper_2507_07816_amd/csrc/pow_enclose.h",
+                "paper_2507_07816_amd/csrc/ltgw_gather.h",
                 "paper_2507_07816_amd/csrc/ltgw_antenna.h", "paper_2507_07816_amd/csrc/exp2_table.h",
                 "paper_2507_07816_amd/csrc/log_table.h")
 
@@ -252,8 +253,9 @@ FP64_LANE_OPS = 256 * 64 * 2.4e9
 def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, counts=None):
     """The uniform random bank over the loaded search: n templates drawn
     uniformly in f0 (the band), tau and n, at the search's sky point.  Every
-    (template, segment) takes its own correctly rounded Eq. 1 power, so the
-    kernel is bound by instruction issue; the rate is compared with the
+    (template, segment) takes its own Eq. 1 power: an FP64 enclosure of the
+    correctly rounded value, and that value itself where the enclosure leaves
+    the column open (pow_exact_fraction).  The rate is compared with the
     chip's VALU lane-instruction rate given the instructions per evaluation
     counted by rocprofv3 for this kernel source."""
     import synth
@@ -265,7 +267,7 @@ def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, counts=None):
                                (float(g["brake"][0]), float(g["brake"][-1])), g["sky"][0], seed)
     ctx.eval_list(params, g["t0"], outputs=False)            # warm-up
     torch.cuda.synchronize()
-    slow0 = ctx.diagnostics()["pow_slow"]
+    dg0 = ctx.diagnostics()
     runs = []
     for _ in range(reps):
         t = time.perf_counter()
@@ -280,7 +282,8 @@ def list_leg(torch, ltgw, ctx, wl, n=1000000, reps=3, seed=11, counts=None):
            "value": evals / wall, "unit": "template·segment evals/s", "wall_ms": wall * 1e3,
            "kernel_ms": kms, "kernel_evals_per_s": evals / (kms * 1e-3),
            "pow_undecided": int(dg["pow_undecided"]),
-           "pow_slow_fraction": (dg["pow_slow"] - slow0) / (reps * evals)}
+           "pow_exact_fraction": (dg["pow_exact"] - dg0["pow_exact"]) / (reps * evals),
+           "pow_slow_fraction": (dg["pow_slow"] - dg0["pow_slow"]) / (reps * evals)}
     if counts:
         rate = counts["valu"] * evals / (kms * 1e-3)
         out["roofline"] = {"bound": "alu", "achieved": rate / 1e12, "peak": FP64_LANE_OPS / 1e12,

@@ -232,8 +232,12 @@ typedef struct {
  * Eq. 2, the bin rule and FP32 sums over chunks of 32 segments carried in FP64,
  * so s, c and N of a lattice template are the lattice's bit for bit (W1, W2
  * are summed in that order too; the lattice forms them exactly, so they agree
- * to FP32 rounding of 32-term sums).  The evaluation runs in f0 order
- * (2^16 buckets over the list's range; results stay in list order) and is bound by FP64 arithmetic: no table is
+ * to FP32 rounding of 32-term sums).  Each segment's column is decided from
+ * an FP64 enclosure of the correctly rounded power (the column is monotone in
+ * it); the power itself is computed only where the enclosure straddles a
+ * column boundary (counted in ltgw_diag.pow_exact), so the results are those
+ * of the correctly rounded power.  The evaluation runs in f0 order (2^16
+ * buckets over the list's range; results stay in list order); no table is
  * shared between templates.  Outputs as ltgw_eval_templates, in list order;
  * the results are kept for ltgw_psi and ltgw_topk_candidates (whose records
  * then carry the listed parameters, index = list position and sky = -1).
@@ -324,6 +328,10 @@ typedef struct {
     int64_t pow_slow;       /* powers of Eq. 1 (since the context was created)
                                that the fast evaluation could not round with
                                certainty and the double-double one took     */
+    int64_t pow_exact;      /* evaluations of explicit template lists (since
+                               the context was created) whose column an
+                               enclosure of the Eq. 1 power could not decide,
+                               so the correctly rounded power was taken     */
 } ltgw_diag;
 
 /* ltgw_diagnostics: synchronous; reads the device counters of the last eval. */

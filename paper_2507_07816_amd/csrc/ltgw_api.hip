@@ -953,6 +953,7 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
     a.out_n = out_n;
     a.in_band_total = (unsigned long long *)c->counters.p + kCntInBand;
     a.pow_counts = (unsigned long long *)c->counters.p + kCntUndecided;
+    a.exact_count = (unsigned long long *)c->counters.p + kCntExact;
     // one sky direction for the whole list (and no antenna weights): each
     // detector's Doppler factors 1 + v.n/c as the lattice forms them (the
     // same operations in the same order), read per segment by the kernel
@@ -1151,6 +1152,7 @@ int32_t ltgw_diagnostics(ltgw_ctx *c, ltgw_diag *out) {
     HIP_TRY(c, hipStreamSynchronize(c->stream), "diagnostics");
     out->pow_undecided = (int64_t)v[kCntUndecided];
     out->pow_slow = (int64_t)v[kCntSlow];
+    out->pow_exact = (int64_t)v[kCntExact];
     out->templates = c->have_eval ? c->n_templates : 0;
     out->evals = c->have_eval ? c->n_evals : 0;
     out->in_band = c->have_eval ? (int64_t)v[kCntInBand] : 0;

@@ -191,7 +191,7 @@ bool fin(double x);
 // Context counters: [0] powers the double-double phase could not decide,
 // [1] powers that took the double-double phase (the kernels of Eq. 1 get
 // &counters[0] and count both), [2] bad power values, [3] in-band total.
-constexpr int kCntUndecided = 0, kCntSlow = 1, kCntBad = 2, kCntInBand = 3, kNumCnt = 4;
+constexpr int kCntUndecided = 0, kCntSlow = 1, kCntBad = 2, kCntInBand = 3, kCntExact = 4, kNumCnt = 5;
 int zero_counter(ltgw_ctx *c, int first, int n);
 int read_counter(ltgw_ctx *c, int i, unsigned long long *out);
 

@@ -38,6 +38,7 @@ struct ListArgs {
     int32_t *out_c, *out_n;
     unsigned long long *in_band_total;
     unsigned long long *pow_counts;  // [0] undecided powers, [1] powers that took the double-double phase
+    unsigned long long *exact_count;  // evaluations whose column the power's enclosure left open
 };
 
 hipError_t launch_template_list(int store, const ListArgs &a, hipStream_t st);

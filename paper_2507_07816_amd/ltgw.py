@@ -80,7 +80,7 @@ class ltgw_diag(C.Structure):
     _fields_ = [("pow_undecided", C.c_int64), ("templates", C.c_int64), ("evals", C.c_int64),
                 ("in_band", C.c_int64), ("eval_kernel_ms", C.c_double), ("tables_ms", C.c_double),
                 ("tile_shape", C.c_int32), ("eval_launches", C.c_int32), ("ingest_ms", C.c_double),
-                ("pow_slow", C.c_int64)]
+                ("pow_slow", C.c_int64), ("pow_exact", C.c_int64)]
 
 
 class ltgw_search(C.Structure):

@@ -73,7 +73,7 @@ int main(void) {
   F(ltgw_batch_stats, templates); F(ltgw_batch_stats, kernel_ms); F(ltgw_batch_stats, total_ms);
   printf("ltgw_diag %zu\n", sizeof(ltgw_diag));
   F(ltgw_diag, in_band); F(ltgw_diag, eval_kernel_ms); F(ltgw_diag, tables_ms);
-  F(ltgw_diag, tile_shape); F(ltgw_diag, ingest_ms); F(ltgw_diag, pow_slow);
+  F(ltgw_diag, tile_shape); F(ltgw_diag, ingest_ms); F(ltgw_diag, pow_slow); F(ltgw_diag, pow_exact);
   printf("ltgw_proposer %zu\n", sizeof(ltgw_proposer));
   F(ltgw_proposer, c_in); F(ltgw_proposer, n_select); F(ltgw_proposer, psi_threshold);
   F(ltgw_proposer, coarse_threshold); F(ltgw_proposer, tier2_threshold); F(ltgw_proposer, blocks);

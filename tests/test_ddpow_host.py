@@ -243,3 +243,171 @@ def test_div_rn_equals_division(tmp_path):
     bad = np.fromfile(fo, dtype=np.int32)
     assert bad.size == len(rows)
     assert not bad.any(), rows[np.nonzero(bad)[0][:5]]
+
+
+ENC_DRIVER = r'''
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+#include "pow_enclose.h"
+using namespace ltgw;
+// mode 0: rows of (u, e) -> ok, G, y, lo, hi, the double-double value
+//   (unrounded), RN(u^e) from the two-phase power and its undecided flag
+// mode 1: rows of (u, e, f0, D, t_sft, shift) -> the column by the
+//   explicit-template kernel's rule (enclosure, else the double-double power),
+//   whether the rule took the double-double power, and the column of the
+//   two-phase power's RN(u^e)
+static unsigned column(double g, double D, double tsft, double f0, double shift) {
+    const double h = g * D;
+    const double H = h * tsft;
+    const double x = f0 * H;
+    const double v = x + shift;
+    return (unsigned)(int)v;   // truncation toward zero; the rows keep v in int range
+}
+int main(int argc, char **argv) {
+    int mode = std::atoi(argv[4]);
+    if (mode == 2) { std::printf("%a\n", kLn2rn); return 0; }
+    FILE *fi = std::fopen(argv[1], "rb");
+    FILE *fo = std::fopen(argv[2], "wb");
+    long n = std::atol(argv[3]);
+    int w = mode == 0 ? 2 : 6;
+    std::vector<double> in(w * n);
+    if (std::fread(in.data(), 8, w * n, fi) != (size_t)(w * n)) return 1;
+    for (long i = 0; i < n; ++i) {
+        const double *r = &in[w * i];
+        const double u = r[0], e = r[1];
+        if (mode == 0) {
+            double o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            double G = 0, y = 0, lo = 0, hi = 0;
+            const bool ok = pow_enclose_value(u, e, &G, &y) && pow_enclose(u, e, &lo, &hi);
+            int und = 0;
+            o[0] = ok; o[1] = G; o[2] = y; o[3] = lo; o[4] = hi;
+            if (u > 0 && u < 0x1p1000) {
+                const dd Rd = dd_exp(dd_mul_d(dd_log(u), e));
+                o[5] = Rd.hi + Rd.lo;
+                o[6] = pow_cr(u, e, &und);
+            }
+            o[7] = und;
+            std::fwrite(o, 8, 8, fo);
+        } else {
+            const double f0 = r[2], D = r[3], tsft = r[4], shift = r[5];
+            double lo = 0, hi = 0;
+            const bool enc = pow_enclose(u, e, &lo, &hi);
+            unsigned idx = column(lo, D, tsft, f0, shift);
+            int took = 0;
+            if (!enc || column(hi, D, tsft, f0, shift) != idx) {
+                idx = column(pow_dd_call(u, e).g, D, tsft, f0, shift);
+                took = 1;
+            }
+            int und = 0;
+            const unsigned want = column(pow_cr(u, e, &und), D, tsft, f0, shift);
+            int o[4] = {(int)idx, took, (int)want, und};
+            std::fwrite(o, 4, 4, fo);
+        }
+    }
+    return 0;
+}
+'''
+
+
+def _enc_driver(tmp_path):
+    src = tmp_path / "enc_driver.cpp"
+    src.write_text(ENC_DRIVER)
+    exe = tmp_path / "enc_driver"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-I", CSRC, str(src), "-o",
+                    str(exe)], check=True)
+    return exe
+
+
+def _enc_run(exe, tmp_path, rows, mode):
+    rows = np.ascontiguousarray(rows, dtype=np.float64)
+    fi, fo = tmp_path / "in.bin", tmp_path / "out.bin"
+    rows.tofile(fi)
+    subprocess.run([str(exe), str(fi), str(fo), str(len(rows)), str(mode)], check=True)
+    return np.fromfile(fo, dtype=np.float64 if mode == 0 else np.int32).reshape(len(rows), -1)
+
+
+def test_power_enclosure_error_bound_and_containment(tmp_path):
+    """The enclosure the explicit-template kernel takes in place of RN(u^e)
+    (Eq. 1), over 1.2 million (u, e) pairs: u log-uniform in [1, 2^20], just
+    above 1 (down to 1 + 2^-52), at both ends of every log-table interval at
+    several binades, and the search's 1 + (t - T0)/tau; e the search's
+    1/(1 - n) and uniform in [-20, 20].  Its value G stays within the stated
+    2^-50 (1 + |y| + |e|) of u^e (the double-double value; the worst case
+    seen is printed); the interval holds the correctly rounded power every
+    time; it declines outside u >= 1 and -600 < e log u < 700.  ln 2's
+    constant is the nearest double (60-digit decimal arithmetic)."""
+    from decimal import Decimal, getcontext
+
+    exe = _enc_driver(tmp_path)
+    getcontext().prec = 60
+    got = subprocess.run([str(exe), "-", "-", "0", "2"], capture_output=True, text=True, check=True).stdout
+    assert float.fromhex(got.strip()) == float(Decimal(2).ln())
+
+    r = np.random.default_rng(53)
+    n = 200_000
+    parts = [np.exp(r.uniform(0.0, np.log(2.0 ** 20), n)),
+             1.0 + np.floor(r.uniform(0, 4096, n)) * 2.0 ** -52,
+             1.0 + r.uniform(0.0, 2.0 ** -20, n),
+             1.0 + np.floor(r.uniform(0, 10800, n)) * 8.0 / np.exp(r.uniform(np.log(300.0), np.log(40000.0), n))]
+    ends = []
+    for i in range(128):
+        for k in (0, 1, 5, 13):
+            lo = (1.0 + i / 128.0) * 2.0 ** k
+            hi = (1.0 + (i + 1) / 128.0) * 2.0 ** k
+            ends += [lo, np.nextafter(lo, np.inf), np.nextafter(hi, 0.0), (lo + hi) / 2]
+    ends = np.array(ends)
+    u = np.concatenate(parts + [np.tile(ends, 40)])
+    m = len(u)
+    e = np.where(r.uniform(size=m) < 0.5, 1.0 / (1.0 - r.uniform(1.5, 9.0, m)), r.uniform(-20.0, 20.0, m))
+    e[:50] = [-0.5, -0.25, -1.0, -2.0, 0.5] * 10
+    out = _enc_run(exe, tmp_path, np.column_stack([u, e]), 0)
+    ok, G, y, lo, hi, gd, gcr, und = out.T
+    ok = ok.astype(bool)
+    inside = (np.abs(e * np.log(u)) < 590.0)
+    assert np.all(ok[inside])
+    rel = np.abs(G[ok] - gd[ok]) / gd[ok] / (1.0 + np.abs(y[ok]) + np.abs(e[ok]))
+    print(f"worst enclosure error {np.log2(rel.max()):.2f} bits of (1 + |y| + |e|), over {ok.sum()} pairs")
+    assert rel.max() < 2.0 ** -50
+    dec = ok & (und == 0)
+    assert np.all(lo[dec] <= gcr[dec]) and np.all(gcr[dec] <= hi[dec])
+    # the domain
+    bad_u = np.array([0.5, 1.0 - 2.0 ** -53, 0.0, -1.0, np.inf, np.nan, 2.0 ** 1000, 1.0])
+    bad_e = np.array([-0.5, -0.5, -0.5, -0.5, -0.5, -0.5, -0.5, np.nan])
+    far = np.array([[2.0 ** 900, 2.0], [2.0 ** 900, -2.0], [30.0, 300.0], [30.0, -300.0]])
+    out = _enc_run(exe, tmp_path, np.concatenate([np.column_stack([bad_u, bad_e]), far]), 0)
+    assert not out[:, 0].any()
+
+
+def test_column_decision_by_enclosure_equals_correct_rounding(tmp_path):
+    """The explicit-template kernel's column rule (the column at both ends of
+    the enclosure, else the double-double power) against the column of the
+    correctly rounded power, over 2.2 million evaluations of the realistic
+    search's kind (f0 500-1500 Hz, T_sft = 4 s, Doppler factors 1 +- 1e-4,
+    tau 300-40000 s, n 1.5-9), a fifth of them placed within 1e-9 bins of a
+    column boundary so that the rule has to fall back: identical columns
+    everywhere, and the fallback taken only near boundaries."""
+    exe = _enc_driver(tmp_path)
+    r = np.random.default_rng(59)
+    n = 2_200_000
+    tau = np.exp(r.uniform(np.log(300.0), np.log(40000.0), n))
+    dt = np.floor(r.uniform(0, 10800, n)) * 8.0
+    u = 1.0 + dt / tau
+    e = 1.0 / (1.0 - r.uniform(1.5, 9.0, n))
+    f0 = r.uniform(500.0, 1500.0, n)
+    D = 1.0 + r.uniform(-1e-4, 1e-4, n)
+    tsft = np.full(n, 4.0)
+    shift = np.full(n, 1.5 - 1900.0)
+    near = r.uniform(size=n) < 0.2
+    # move f0 so that f0 g D T_sft + shift lies within 1e-9 of an integer
+    g = u ** e
+    x = f0 * g * D * tsft + shift
+    target = np.round(x) + r.uniform(-1e-9, 1e-9, n)
+    f0 = np.where(near, (target - shift) / (g * D * tsft), f0)
+    out = _enc_run(exe, tmp_path, np.column_stack([u, e, f0, D, tsft, shift]), 1)
+    idx, took, want, und = out.T
+    assert not und.any()
+    assert np.array_equal(idx, want)
+    print(f"fallback: {took[near].mean():.3f} of the near-boundary rows, {took[~near].sum()} of the others")
+    assert took[near].mean() > 0.5
+    assert took[~near].sum() <= 2
