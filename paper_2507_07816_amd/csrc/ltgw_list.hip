@@ -92,6 +92,8 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
     const LdsTables tab{s_log, s_exp};
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool live = q < a.n;
+    // lanes past the list evaluate its first template and discard it; they
+    // take no correctly rounded power and count nothing
     const int32_t o = live ? a.perm[q] : a.perm[0];
     const ltgw_template T = a.tpl[o];
     const double e = 1.0 / (1.0 - T.brake);
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(256) void template_list_kernel(const ListArgs a) {
                     enclose_ends(enclose_value(lg[b], x2[b]), lg[b].y, e, &glo, &ghi);
                     idx[b] = column(D, T, Df, before ? 0.0 : glo);
                     const bool decided = before || (lg[b].ok && column(D, T, Df, ghi) == idx[b]);
-                    if (!decided && jb + b < je) open |= 1u << b;
+                    if (!decided && jb + b < je && live) open |= 1u << b;
                 }
                 if (open) {
                     for (int b = 0; b < SB; ++b) {

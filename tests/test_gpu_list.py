@@ -170,6 +170,58 @@ def test_list_calls_of_changing_size_and_sky():
         ctx.close()
 
 
+def _at_boundaries(det, params, t0, seed, delta=1e-10):
+    """Move each template's f0 so that at one segment (drawn per template) its
+    track lands within delta bins of a column boundary: there the kernel's
+    enclosure of the Eq. 1 power straddles the boundary and the column has to
+    come from the correctly rounded power."""
+    r = np.random.default_rng(seed)
+    n = len(params)
+    j = r.integers(0, det.n_seg, n)
+    t = det.t_seg[j]
+    u = 1.0 + (t - t0) / params[:, 1]
+    g = u ** (1.0 / (1.0 - params[:, 2]))
+    v = det.v[j]
+    vn = (v[:, 0] * params[:, 3] + v[:, 1] * params[:, 4]) + v[:, 2] * params[:, 5]
+    D = 1.0 + vn / synth.C_LIGHT
+    H = (g * D) * det.t_sft
+    shift = 1.5 - det.k_lo
+    col = r.integers(20, det.n_bins - 20, n)
+    out = params.copy()
+    out[:, 0] = ((col + 1.0) + r.uniform(-delta, delta, n) - shift) / H
+    assert np.all(t >= t0)
+    return out
+
+
+def test_list_columns_at_boundaries_take_the_exact_power():
+    """Templates whose track sits within 1e-10 bins of a column boundary at one
+    segment each, at one sky direction (the Doppler table) and at a sky
+    direction per template: the columns there come from the correctly rounded
+    power (counted in pow_exact, about one per template) and s, c, N still
+    match the oracle's."""
+    from paper_2507_07816_amd import ltgw
+
+    det = _small(8, 120, 400, k_lo=1900)
+    ctx = ltgw.Context(0)
+    try:
+        _load(ctx, [det])
+        for per_sky in (False, True):
+            params = _bank(600, det, seed=61 + per_sky, pad=0.0, tau=(2000.0, 30000.0), brake=(2.0, 7.0))
+            if per_sky:
+                k = np.random.default_rng(63).normal(size=(len(params), 3))
+                params[:, 3:6] = k / np.linalg.norm(k, axis=1, keepdims=True)
+            params = _at_boundaries(det, params, 0.0, seed=64 + per_sky)
+            print(f"case: list at column boundaries, sky per template {per_sky}", flush=True)
+            before = ctx.diagnostics()["pow_exact"]
+            gpu = _run_list(ctx, params)
+            _check(gpu, oracle.evaluate_params(det, params), params, 10)
+            taken = gpu["diag"]["pow_exact"] - before
+            print(f"exact powers taken: {taken} for {len(params)} templates", flush=True)
+            assert 0.9 * len(params) <= taken <= 1.1 * len(params) + 5
+    finally:
+        ctx.close()
+
+
 def test_list_two_detectors_and_mask():
     d1 = _small(1, 60, 256, k_lo=1900)
     d2 = _small(2, 45, 200, k_lo=1930, t_sft=4.0)
