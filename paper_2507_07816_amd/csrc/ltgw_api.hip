@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ltgw_ctx.h"
@@ -179,6 +180,44 @@ int read_counter(ltgw_ctx *c, int i, unsigned long long *out) {
 
 }  // namespace ltgw
 
+
+// What is wrong with a listed template, or NULL.
+static const char *template_error(const ltgw_template &T) {
+    if (!fin(T.f0) || !(T.f0 > 0.0)) return "f0 must be > 0";
+    if (!fin(T.tau) || !(T.tau > 0.0)) return "tau must be > 0";
+    if (!fin(T.brake) || !(T.brake > 1.0)) return "the braking index must be > 1";
+    const double *k = T.sky;
+    if (!fin(k[0]) || !fin(k[1]) || !fin(k[2]) ||
+        std::fabs(std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]) - 1.0) > 1e-12)
+        return "sky is not a unit vector";
+    return nullptr;
+}
+
+// The host's work on a long list (checks, f0 range, ordering, the copy into
+// the staging) runs on several threads, each over one contiguous chunk.
+static int list_threads(int64_t n) {
+    if (n < ((int64_t)1 << 17)) return 1;
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::min<unsigned>(16u, hc ? hc : 1u);
+}
+static int64_t chunk_lo(int64_t n, int nt, int t) { return n * t / nt; }
+// f(t) for t in [0, nt): t = 0 on the calling thread; where a thread cannot be
+// started, its chunk runs on the calling thread instead
+template <class F>
+static void run_chunks(int nt, const F &f) {
+    std::vector<std::thread> th;
+    std::vector<int> inline_t;
+    for (int t = 1; t < nt; ++t) {
+        try {
+            th.emplace_back(f, t);
+        } catch (...) {
+            inline_t.push_back(t);
+        }
+    }
+    f(0);
+    for (int t : inline_t) f(t);
+    for (auto &x : th) x.join();
+}
 
 extern "C" {
 
@@ -851,19 +890,40 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
     if (n < 1 || n >= ((int64_t)1 << 31)) return fail(c, LTGW_E_INVALID_ARG, "n must be in 1 .. 2^31 - 1");
     if (is_device_ptr(tpl)) return fail(c, LTGW_E_INVALID_ARG, "the template list must be host memory");
     if (!fin(t0)) return fail(c, LTGW_E_INVALID_ARG, "t0 must be finite");
-    double f0_max = 0.0;
-    for (int64_t q = 0; q < n; ++q) {
-        const ltgw_template &T = tpl[q];
-        if (!fin(T.f0) || !(T.f0 > 0.0)) return fail(c, LTGW_E_INVALID_ARG, "template %lld: f0 must be > 0", (long long)q);
-        if (!fin(T.tau) || !(T.tau > 0.0))
-            return fail(c, LTGW_E_INVALID_ARG, "template %lld: tau must be > 0", (long long)q);
-        if (!fin(T.brake) || !(T.brake > 1.0))
-            return fail(c, LTGW_E_INVALID_ARG, "template %lld: the braking index must be > 1", (long long)q);
-        const double *k = T.sky;
-        if (!fin(k[0]) || !fin(k[1]) || !fin(k[2]) ||
-            std::fabs(std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]) - 1.0) > 1e-12)
-            return fail(c, LTGW_E_INVALID_ARG, "template %lld: sky is not a unit vector", (long long)q);
-        f0_max = T.f0 > f0_max ? T.f0 : f0_max;
+    // checks, f0 range and whether every template has the first one's sky
+    // direction, per chunk; the first invalid template is reported
+    const int nt = list_threads(n);
+    struct ChunkScan {
+        int64_t bad = -1;
+        double f0_lo = 0.0, f0_hi = 0.0;
+        bool one_sky = true;
+    };
+    std::vector<ChunkScan> scan(nt);
+    run_chunks(nt, [&](int t) {
+        ChunkScan &r = scan[t];
+        const int64_t lo = chunk_lo(n, nt, t), hi = chunk_lo(n, nt, t + 1);
+        r.f0_lo = tpl[lo].f0;
+        r.f0_hi = tpl[lo].f0;
+        for (int64_t q = lo; q < hi; ++q) {
+            const ltgw_template &T = tpl[q];
+            if (template_error(T)) {
+                r.bad = q;
+                return;
+            }
+            r.f0_lo = T.f0 < r.f0_lo ? T.f0 : r.f0_lo;
+            r.f0_hi = T.f0 > r.f0_hi ? T.f0 : r.f0_hi;
+            r.one_sky = r.one_sky && std::memcmp(T.sky, tpl[0].sky, sizeof T.sky) == 0;
+        }
+    });
+    double f0_max = 0.0, f0_lo = 0.0;
+    bool one_sky = true;
+    for (int t = 0; t < nt; ++t) {
+        if (scan[t].bad >= 0)
+            return fail(c, LTGW_E_INVALID_ARG, "template %lld: %s", (long long)scan[t].bad,
+                        template_error(tpl[scan[t].bad]));
+        f0_max = t == 0 || scan[t].f0_hi > f0_max ? scan[t].f0_hi : f0_max;
+        f0_lo = t == 0 || scan[t].f0_lo < f0_lo ? scan[t].f0_lo : f0_lo;
+        one_sky = one_sky && scan[t].one_sky;
     }
     int slots[LTGW_MAX_SEARCH_DET], n_slots = 0;
     for (int d = 0; d < 32; ++d) {
@@ -905,18 +965,6 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
     // evaluation order: f0 in 2^16 buckets over the list's range (a stable
     // counting sort), so that neighbouring lanes gather neighbouring columns;
     // every result goes to its list position, so the order changes none
-    double f0_lo = tpl[0].f0;
-    for (int64_t q = 1; q < n; ++q) f0_lo = tpl[q].f0 < f0_lo ? tpl[q].f0 : f0_lo;
-    constexpr int kBuckets = 1 << 16;
-    const double bscale = f0_max > f0_lo ? (kBuckets - 1) / (f0_max - f0_lo) : 0.0;
-    std::vector<int32_t> bucket_start(kBuckets + 1, 0);
-    std::vector<uint16_t> key((size_t)n);
-    for (int64_t q = 0; q < n; ++q) {
-        const int b = (int)((tpl[q].f0 - f0_lo) * bscale);
-        key[(size_t)q] = (uint16_t)(b < 0 ? 0 : b > kBuckets - 1 ? kBuckets - 1 : b);
-        ++bucket_start[key[(size_t)q] + 1];
-    }
-    for (int b = 0; b < kBuckets; ++b) bucket_start[b + 1] += bucket_start[b];
     // the staging is pinned (the uploads run at DMA rate) and reused: wait for
     // the previous call's uploads from it first
     HIP_TRY(c, hipEventSynchronize(c->ev_h2d), "previous upload");
@@ -924,9 +972,37 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
     if ((rc = ensure_pinned(c, c->h_list, (size_t)n * sizeof(ltgw_template), "template staging")) != LTGW_OK)
         return rc;
     if ((rc = ensure_pinned(c, c->h_perm, (size_t)n * 4, "template order staging")) != LTGW_OK) return rc;
+    // Each chunk counts its keys per bucket and copies itself into the
+    // staging; a bucket's positions then go to the chunks in list order, so
+    // the scatter below gives the serial stable order.
+    constexpr int kBuckets = 1 << 16;
+    const double bscale = f0_max > f0_lo ? (kBuckets - 1) / (f0_max - f0_lo) : 0.0;
+    std::vector<uint16_t> key((size_t)n);
+    std::vector<int32_t> pos((size_t)nt * kBuckets, 0);  // [chunk][bucket]
+    run_chunks(nt, [&](int t) {
+        const int64_t lo = chunk_lo(n, nt, t), hi = chunk_lo(n, nt, t + 1);
+        int32_t *cnt = pos.data() + (size_t)t * kBuckets;
+        for (int64_t q = lo; q < hi; ++q) {
+            const int b = (int)((tpl[q].f0 - f0_lo) * bscale);
+            key[(size_t)q] = (uint16_t)(b < 0 ? 0 : b > kBuckets - 1 ? kBuckets - 1 : b);
+            ++cnt[key[(size_t)q]];
+        }
+        std::memcpy((ltgw_template *)c->h_list.p + lo, tpl + lo, (size_t)(hi - lo) * sizeof(ltgw_template));
+    });
+    int32_t next = 0;
+    for (int b = 0; b < kBuckets; ++b)
+        for (int t = 0; t < nt; ++t) {
+            int32_t &p = pos[(size_t)t * kBuckets + b];
+            const int32_t m = p;
+            p = next;
+            next += m;
+        }
     int32_t *perm = (int32_t *)c->h_perm.p;
-    for (int64_t q = 0; q < n; ++q) perm[(size_t)bucket_start[key[(size_t)q]]++] = (int32_t)q;
-    std::memcpy(c->h_list.p, tpl, (size_t)n * sizeof(ltgw_template));
+    run_chunks(nt, [&](int t) {
+        int32_t *at = pos.data() + (size_t)t * kBuckets;
+        for (int64_t q = chunk_lo(n, nt, t), hi = chunk_lo(n, nt, t + 1); q < hi; ++q)
+            perm[at[key[(size_t)q]]++] = (int32_t)q;
+    });
     if ((rc = ensure(c, c->list_d, (size_t)n * sizeof(ltgw_template), "template list")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->perm_d, (size_t)n * 4, "template order")) != LTGW_OK) return rc;
     if ((rc = h2d(c, c->list_d.p, c->h_list.p, (size_t)n * sizeof(ltgw_template), "template upload")) != LTGW_OK)
@@ -957,8 +1033,7 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
     // one sky direction for the whole list (and no antenna weights): each
     // detector's Doppler factors 1 + v.n/c as the lattice forms them (the
     // same operations in the same order), read per segment by the kernel
-    bool one_sky = true, any_ant = false;
-    for (int64_t q = 1; q < n && one_sky; ++q) one_sky = std::memcmp(tpl[q].sky, tpl[0].sky, sizeof tpl[0].sky) == 0;
+    bool any_ant = false;
     for (int q = 0; q < n_slots; ++q) any_ant = any_ant || a.det[q].era != nullptr;
     if (one_sky && !any_ant) {
         int64_t off = 0, tot = 0;
