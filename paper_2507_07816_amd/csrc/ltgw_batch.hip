@@ -93,8 +93,13 @@ std::vector<unsigned char> signature(ltgw_ctx *c, const ltgw_search *S, int n, i
 
 int tpl_of(int variant) { return variant_templates_per_block(variant) / 256; }
 
-// Tile list for a tile shape: searches largest first (segments per template),
-// tiles of a search group-major; a tile is one wavefront's 64 x TPL f0.
+// Tile list for a tile shape: searches largest first (segments per template);
+// within a search, f0 tile by f0 tile, and for each the (tau, n) groups with
+// their sky points innermost; a tile is one wavefront's 64 x TPL f0 of one
+// (tau, n, sky) group.  The tracks of one f0 tile and (tau, n) differ across
+// the sky points only by their Doppler shifts (a bin or two), and start at
+// the same bins for every (tau, n): in this order the tiles in flight at any
+// time read nearly the same lines, which the caches then serve.
 int upload_tiles(ltgw_ctx *c, BatchState &B, int variant) {
     const int W = 64 * tpl_of(variant);
     std::vector<BatchTile> tiles;
@@ -107,8 +112,11 @@ int upload_tiles(ltgw_ctx *c, BatchState &B, int variant) {
         const SearchPlan &P = B.plans[i];
         const int nt = (P.n_f0 + W - 1) / W;
         B.hsearch[i].n_tiles = (int32_t)(nt * P.n_groups);
-        for (int64_t gr = 0; gr < P.n_groups; ++gr)
-            for (int t = 0; t < nt; ++t) tiles.push_back(BatchTile{i, (int32_t)gr, t, 0});
+        const int64_t n_sky = P.n_groups / P.n_tn;  // group = tn + n_tn * sky
+        for (int t = 0; t < nt; ++t)
+            for (int tn = 0; tn < P.n_tn; ++tn)
+                for (int64_t sky = 0; sky < n_sky; ++sky)
+                    tiles.push_back(BatchTile{i, (int32_t)(tn + P.n_tn * sky), t, 0});
     }
     B.n_tiles = (int)total;
     int rc;
