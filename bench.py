@@ -414,7 +414,7 @@ def sft_leg(torch, ltgw, n_seg=10800, n_fft=32768, k_lo=4000, n_bins=8000, windo
     return {"workload": f"{n_seg} segments x {n_fft} samples (8 s at 4096 Hz), band {k_lo}..{k_lo + n_bins - 1} "
                         f"(500-1500 Hz), running median of {window} bins, seed {seed}",
             "ms": wall * 1e3, "segments_per_s": n_seg / wall, "strain_gb_per_s": strain_bytes / wall / 1e9,
-            "bound": "lds (the running-median sort and scans take about two thirds of the call)",
+            "bound": "lds (the running-median sort and the median selection take about two thirds of the call)",
             "rho_mean": float(rho.mean()), "rho_tail_1.6": float((rho > 1.6).double().mean())}
 
 

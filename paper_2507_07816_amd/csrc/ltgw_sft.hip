@@ -8,9 +8,10 @@
 //   the windowed transform is X_k/2 - (X_{k-1} + X_{k+1})/4 (X_{-1} = conj X_1 and
 //   X_{N/2+1} = conj X_{N/2-1} for real input); P_k = |.|^2 for a 256-bin tile of the band
 //   and its median halo, a bitonic sort of (P, position) in LDS, then each bin's median is the
-//   (h + 1)-th smallest value whose position lies in its window, found by one
-//   scan of the sorted tile (every lane reads the same sorted entry at each
-//   step: an LDS broadcast).  Under Gaussian noise P_k is exponential with
+//   (h + 1)-th smallest value whose position lies in its window: position
+//   masks of the sorted tile's blocks of 64 entries, counted against the
+//   bin's window, give the block that holds it, and a scan of that block the
+//   entry.  Under Gaussian noise P_k is exponential with
 //   mean S_k and median S_k ln 2, hence rho_k = P_k ln 2 / median.
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
@@ -50,6 +51,9 @@ __global__ __launch_bounds__(256) void normalise_kernel(const float2 *__restrict
     __shared__ float val[kSftSort];
     __shared__ __attribute__((aligned(16))) short pos[kSftSort];
     __shared__ float pw[kSftSort];
+    // bit p of bmask[b][p / 64]: position p holds one of sorted entries 64 b .. 64 b + 63
+    constexpr int kBlk = kSftSort / 64;
+    __shared__ unsigned long long bmask[kBlk][kSftSort / 64];
     const int t = threadIdx.x;
     const int T = kSftTile;
     const int t0 = blockIdx.x * T;
@@ -75,8 +79,11 @@ __global__ __launch_bounds__(256) void normalise_kernel(const float2 *__restrict
         pw[p] = v;
         pos[p] = (short)p;
     }
+    if (t < kBlk * (kSftSort / 64)) (&bmask[0][0])[t] = 0ull;
     __syncthreads();
-    // bitonic sort of (val, pos) ascending in val
+    // bitonic sort of (val, pos) ascending in val (a workgroup barrier per
+    // stage: ordering the 39 stages that stay inside a wavefront by wavefront
+    // fences instead was measured slower)
     for (int size = 2; size <= kSftSort; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             const int a = 2 * t - (t & (stride - 1));
@@ -93,15 +100,34 @@ __global__ __launch_bounds__(256) void normalise_kernel(const float2 *__restrict
             __syncthreads();
         }
     }
+    for (int k = t; k < kSftSort; k += 256) {
+        const int p = pos[k];
+        atomicOr(&bmask[k >> 6][p >> 6], 1ull << (p & 63));
+    }
+    __syncthreads();
     // output o: window positions [o, o + 2h]; its median is the (h + 1)-th
-    // smallest value among them.  Four sorted positions per LDS read; the
-    // group that holds the (h + 1)-th in-window entry is resolved entry by entry.
+    // smallest value among them.  The in-window counts of the sorted blocks,
+    // in order, locate the block of that entry; within the block, four sorted
+    // positions per LDS read, and the group that holds it is resolved entry by
+    // entry.  The entry is the one a scan of the whole sorted tile finds.
     const short4 *pos4 = reinterpret_cast<const short4 *>(pos);
     for (int o = t; o < T && t0 + o < n_bins; o += 256) {
-        float med = 0.0f;
-        int cnt = 0;
         const int lo = o, hi = o + 2 * h;
-        for (int g = 0; g < kSftSort / 4 && cnt <= h; ++g) {
+        const int w0 = lo >> 6, w1 = hi >> 6;
+        int cnt = 0, blk = 0;
+        for (; blk < kBlk - 1; ++blk) {
+            int c = 0;
+            for (int w = w0; w <= w1; ++w) {
+                unsigned long long m = bmask[blk][w];
+                if (w == w0) m &= ~0ull << (lo & 63);
+                if (w == w1) m &= ~0ull >> (63 - (hi & 63));
+                c += __popcll(m);
+            }
+            if (cnt + c > h) break;
+            cnt += c;
+        }
+        float med = 0.0f;
+        for (int g = 16 * blk; g < 16 * blk + 16 && cnt <= h; ++g) {
             const short4 q = pos4[g];
             const int i0 = (q.x >= lo && q.x <= hi), i1 = (q.y >= lo && q.y <= hi);
             const int i2 = (q.z >= lo && q.z <= hi), i3 = (q.w >= lo && q.w <= hi);
