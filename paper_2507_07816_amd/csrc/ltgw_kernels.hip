@@ -546,21 +546,32 @@ __global__ __launch_bounds__(256) void doppler_kernel(const double *__restrict__
 // In-band segment windows.  For a segment, the column index trunc(f0 h +
 // 1.5 - k_lo) is non-decreasing in f0, so a run of consecutive f0 has a lane
 // in band exactly when its last f0 reaches column 1 and its first f0 is at
-// most column n_bins (the statistic kernel's arithmetic).  One wavefront per
-// (group, run): lanes stride over the segments, then min / max.
+// most column n_bins (the statistic kernel's arithmetic).
+// One wavefront per (group, kWinRuns consecutive runs of f0): each lane takes
+// segments lane, lane + 64, ... and tests every run of the wavefront against
+// its track factor, so the group's row of track factors is read once per
+// kWinRuns runs; each run's first and last in-band segment are then reduced
+// across the wavefront.
+constexpr int kWinRuns = 8;
 __global__ __launch_bounds__(256) void window_kernel(const DetView D, int n_groups, int n_tn, double f0_min,
                                                      double f0_step, int n_f0, int2 *__restrict__ win) {
     const int lane = threadIdx.x & 63;
-    const int per_group = (D.win_blocks + 3) / 4;
+    const int per_group = (D.win_blocks + 4 * kWinRuns - 1) / (4 * kWinRuns);
     const int grp = blockIdx.x / per_group;
-    const int blk = (blockIdx.x % per_group) * 4 + (threadIdx.x >> 6);
-    if (blk >= D.win_blocks) return;
-    const int ia = blk * D.win_run;
-    const int ib = min(ia + D.win_run - 1, n_f0 - 1);
-    const double fa = f0_min + (double)ia * f0_step;
-    const double fb = f0_min + (double)ib * f0_step;
+    const int blk0 = ((blockIdx.x % per_group) * 4 + (threadIdx.x >> 6)) * kWinRuns;
+    if (blk0 >= D.win_blocks) return;
+    double fa[kWinRuns], fb[kWinRuns];
+    int lo[kWinRuns], hi[kWinRuns];
+#pragma unroll
+    for (int r = 0; r < kWinRuns; ++r) {
+        const int ia = (blk0 + r) * D.win_run;
+        const int ib = min(ia + D.win_run - 1, n_f0 - 1);
+        fa[r] = f0_min + (double)ia * f0_step;
+        fb[r] = f0_min + (double)ib * f0_step;
+        lo[r] = D.n_seg;
+        hi[r] = -1;
+    }
     const int tn = grp % n_tn, sky = grp / n_tn;
-    int lo = D.n_seg, hi = -1;
     for (int j = lane; j < D.n_seg; j += 64) {
         double h;
         if (D.H) {
@@ -569,23 +580,30 @@ __global__ __launch_bounds__(256) void window_kernel(const DetView D, int n_grou
             const double hg = D.g[(int64_t)tn * D.n_seg + j] * D.D[(int64_t)sky * D.n_seg + j];
             h = hg * D.t_sft;
         }
-        const double xa = fa * h, xb = fb * h;
-        const int ca = __double2int_rz(xa + D.cshift), cb = __double2int_rz(xb + D.cshift);
-        if (cb >= 1 && ca <= D.n_bins) {
-            lo = min(lo, j);
-            hi = max(hi, j);
+#pragma unroll
+        for (int r = 0; r < kWinRuns; ++r) {
+            const double xa = fa[r] * h, xb = fb[r] * h;
+            const int ca = __double2int_rz(xa + D.cshift), cb = __double2int_rz(xb + D.cshift);
+            if (cb >= 1 && ca <= D.n_bins) {
+                lo[r] = min(lo[r], j);
+                hi[r] = max(hi[r], j);
+            }
         }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o, 64));
-        hi = max(hi, __shfl_xor(hi, o, 64));
+#pragma unroll
+    for (int r = 0; r < kWinRuns; ++r) {
+        int l = lo[r], u = hi[r];
+        for (int o = 32; o > 0; o >>= 1) {
+            l = min(l, __shfl_xor(l, o, 64));
+            u = max(u, __shfl_xor(u, o, 64));
+        }
+        if (lane == 0 && blk0 + r < D.win_blocks) win[(int64_t)grp * D.win_blocks + blk0 + r] = make_int2(l, u);
     }
-    if (lane == 0) win[(int64_t)grp * D.win_blocks + blk] = make_int2(lo, hi);
 }
 
 hipError_t launch_windows(const DetView &D, int n_groups, int n_tn, double f0_min, double f0_step, int n_f0,
                           int2 *win, hipStream_t st) {
-    const int64_t blocks = (int64_t)((D.win_blocks + 3) / 4) * n_groups;
+    const int64_t blocks = (int64_t)((D.win_blocks + 4 * kWinRuns - 1) / (4 * kWinRuns)) * n_groups;
     if (n_groups < 1 || D.win_blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(window_kernel, dim3((unsigned)blocks), dim3(256), 0, st, D, n_groups, n_tn, f0_min, f0_step,
                        n_f0, win);
