@@ -277,3 +277,41 @@ def test_slabs_and_generations_are_bit_identical_on_long_searches():
             for a, b in zip(got, ref):
                 assert np.array_equal(a, b, equal_nan=True), var
     ctx.close()
+
+
+def test_batch_long_ragged_searches_equal_single_and_oracle():
+    """Longer searches with segment counts that are not whole chunks: two
+    detectors of 1500 and 1333 segments, one detector of 1100, and a short
+    search beside them.  Every search equals its own single search bit for
+    bit, and the oracle."""
+    import torch
+    from paper_2507_07816_amd import ltgw
+
+    ctx = ltgw.Context(0)
+    dets = [_det(11, 1500, 200, 1900, "rand", spacing=20.0), _det(12, 1333, 200, 1905, None, spacing=22.0),
+            _det(13, 1100, 160, 1910, 0.75, spacing=25.0), _det(14, 90, 128, 1900, None)]
+    for d, det in enumerate(dets):
+        ctx.load_spectrogram(d, torch.from_numpy(det.rho).cuda(), det.k_lo, det.t_sft, det.t_seg,
+                             weights=det.w)
+        ctx.set_velocity_table(d, det.v)
+    searches = [
+        dict(f0_min=476.0, f0_step=0.25, n_f0=160, tau=[3500.0, 20000.0], brake=[3.0, 6.0], sky=SKY[:2],
+             t0=0.0, dets=[0, 1]),
+        dict(f0_min=478.0, f0_step=0.25, n_f0=130, tau=[9000.0], brake=[5.0], sky=SKY[2:], t0=300.0, dets=[2]),
+        dict(f0_min=476.0, f0_step=0.5, n_f0=70, tau=[12000.0], brake=[4.0], sky=SKY[:1], t0=0.0, dets=[3]),
+    ]
+    print("case: batch of long ragged searches", flush=True)
+    top_p, top_c, st = ctx.eval_batch(searches, k=8)
+    batch = [_batch(ctx, i, s) for i, s in enumerate(searches)]
+    for i, s in enumerate(searches):
+        single = _single(ctx, s)
+        _same(batch[i], single)
+        grid = oracle.Grid(s["f0_min"], s["f0_step"], s["n_f0"], s["tau"], s["brake"], s["sky"], s["t0"])
+        ref = oracle.evaluate([dets[d] for d in s["dets"]], grid)
+        assert np.array_equal(batch[i]["N"], ref["N"])
+        assert np.array_equal(batch[i]["c"], ref["c"])
+        assert_sums_close(batch[i]["s"].astype(np.float64), ref["s"])
+        assert_topk_count(top_c[i], ref, 8)
+    lat = ctx.batch_latency(len(searches))
+    assert np.all(lat > 0) and lat.max() <= st["kernel_ms"] + 1e-6
+    ctx.close()
