@@ -184,14 +184,14 @@ def precision_report(ref, runs):
 
 
 def proposer_leg(torch, ltgw, realisations=50000, batch=256, epochs=16, eval_signal=4096, eval_noise=1024, seed=7,
-                 coarse_segments=8, select2_frac=0.0, block=32, label="near", select_blocks=(8, 10, 12),
+                 coarse_segments=8, select2_frac=0.0, block=32, label="near", select_blocks=(8, 10, 11, 12),
                  tier2_quantile=None, counts=True):
     """The learned proposer on the small workload's shape (1024 segments x 800
     bins, 4800 fine templates): trained on `realisations` device-generated
     noise + injection realisations (amplitudes U[0.3, 3]), then recall and
     speed against the plain FP32 exhaustive search at each first-tier budget
-    (select_blocks blocks of `block` f0 per realisation: 256, 320 and 384 of
-    the 4800 cells) and fallback quantile; the point reported is the fastest
+    (select_blocks blocks of `block` f0 per realisation: 256, 320, 352 and 384
+    of the 4800 cells) and fallback quantile; the point reported is the fastest
     at recall 0.99, else the best recall at 5x or more, and best_at_5x is the
     best recall at 5x or more.  Beside it, the ranking by the coarse power
     ratios alone at the reported budget (the method without the network).
