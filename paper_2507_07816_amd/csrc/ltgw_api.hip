@@ -263,6 +263,8 @@ int32_t ltgw_create(int32_t device, void *hip_stream, ltgw_ctx **out) {
         if (ee == hipSuccess) ee = hipEventCreate(&c->ev_ing[0]);
         if (ee == hipSuccess) ee = hipEventCreate(&c->ev_ing[1]);
         if (ee == hipSuccess) ee = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        for (auto &e : c->ev_sft)
+            if (ee == hipSuccess) ee = hipEventCreateWithFlags(&e, hipEventDisableTiming);
         if (ee != hipSuccess) rc = hip_fail(c, ee, "event/stream create");
     }
     if (rc == LTGW_OK) {
@@ -304,6 +306,8 @@ void ltgw_destroy(ltgw_ctx *c) {
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (hipEvent_t e : c->ev_ing)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->ev_sft)
         if (e) (void)hipEventDestroy(e);
     if (c->side) (void)hipStreamDestroy(c->side);
     free_batch(c->batch);

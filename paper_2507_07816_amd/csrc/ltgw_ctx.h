@@ -163,7 +163,10 @@ struct ltgw_ctx {
         int n_fft, batch;
         void *plan;  // hipfftHandle
     };
-    ltgw::DevBuf sft_spec;
+    ltgw::DevBuf sft_spec, sft_spec2;  // spectra of alternate chunks
+    // data preparation across chunks: [0..1] transform of the chunk in buffer
+    // b done, [2..3] its normalisation done (the normalisation runs on `side`)
+    hipEvent_t ev_sft[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<SftPlan> sft_plans;
     int forced_variant = -1;      // ltgw_set_tile_shape; -1 = autotuner
     // device address of this device's static scratch array (the no-allocation

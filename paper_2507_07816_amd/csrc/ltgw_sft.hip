@@ -153,6 +153,7 @@ void sft_release(ltgw_ctx *c) {
     for (auto &pl : c->sft_plans) (void)hipfftDestroy((hipfftHandle)pl.plan);
     c->sft_plans.clear();
     release(c->sft_spec);
+    release(c->sft_spec2);
 }
 
 }  // namespace ltgw
@@ -206,8 +207,19 @@ int32_t ltgw_sft_normalise(ltgw_ctx *c, const float *strain, int32_t n_seg, int3
     const int64_t per_seg = (int64_t)(n_fft / 2 + 1) * 8;
     int batch = (int)std::max<int64_t>(1, std::min<int64_t>(n_seg, ((int64_t)512 << 20) / per_seg));
     if ((rc = ensure(c, c->sft_spec, (size_t)batch * (n_fft / 2 + 1) * 8, "spectra")) != LTGW_OK) return rc;
-    for (int j0 = 0; j0 < n_seg; j0 += batch) {
+    // More than one chunk: alternate two spectra buffers, and normalise on the
+    // side stream, so that a chunk's normalisation (LDS-bound) overlaps the
+    // next chunk's copy and transform (HBM-bound).  The copy into a buffer
+    // waits for the normalisation that last read it; the context's stream
+    // waits for the last normalisations before the call's work ends.
+    const bool two = n_seg > batch;
+    if (two && (rc = ensure(c, c->sft_spec2, (size_t)batch * (n_fft / 2 + 1) * 8, "spectra")) != LTGW_OK)
+        return rc;
+    int k = 0;
+    for (int j0 = 0; j0 < n_seg; j0 += batch, ++k) {
         const int nb = std::min(batch, n_seg - j0);
+        const int b = k & 1;
+        void *const spec = b ? c->sft_spec2.p : c->sft_spec.p;
         // a plan per (n_fft, batch size), kept for later calls
         hipfftHandle plan = nullptr;
         for (auto &pl : c->sft_plans)
@@ -224,23 +236,33 @@ int32_t ltgw_sft_normalise(ltgw_ctx *c, const float *strain, int32_t n_seg, int3
         // to n_fft + 2 reals) and transformed there in place: the library's
         // transform may use its input as scratch, and the caller's strain is
         // only read
+        if (two && k >= 2) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_sft[2 + b], 0), "spectra reuse");
         {
             const int64_t pairs = n_fft / 2;
             const unsigned gx = (unsigned)std::min<int64_t>((pairs + 255) / 256, 16);
             hipLaunchKernelGGL(pad_rows_kernel, dim3(gx, (unsigned)nb), dim3(256), 0, c->stream,
-                               (const float2 *)(strain + (int64_t)j0 * n_fft), pairs, (float2 *)c->sft_spec.p,
+                               (const float2 *)(strain + (int64_t)j0 * n_fft), pairs, (float2 *)spec,
                                (int64_t)(n_fft / 2 + 1), pairs);
             HIP_TRY(c, hipGetLastError(), "strain copy launch");
         }
         hipfftResult r = hipfftSetStream(plan, c->stream);
-        if (r == HIPFFT_SUCCESS)
-            r = hipfftExecR2C(plan, (hipfftReal *)c->sft_spec.p, (hipfftComplex *)c->sft_spec.p);
+        if (r == HIPFFT_SUCCESS) r = hipfftExecR2C(plan, (hipfftReal *)spec, (hipfftComplex *)spec);
         if (r != HIPFFT_SUCCESS) return fail(c, LTGW_E_DEVICE, "FFT: %s", fft_error(r));
+        hipStream_t ns = c->stream;
+        if (two) {
+            HIP_TRY(c, hipEventRecord(c->ev_sft[b], c->stream), "event record");
+            HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_sft[b], 0), "normalise order");
+            ns = c->side;
+        }
         hipLaunchKernelGGL(normalise_kernel, dim3((unsigned)((n_bins + kSftTile - 1) / kSftTile), (unsigned)nb),
-                           dim3(256), 0, c->stream, (const float2 *)c->sft_spec.p, (int64_t)(n_fft / 2 + 1), k_lo,
-                           n_bins, h, out + (int64_t)j0 * n_bins);
+                           dim3(256), 0, ns, (const float2 *)spec, (int64_t)(n_fft / 2 + 1), k_lo, n_bins, h,
+                           out + (int64_t)j0 * n_bins);
         HIP_TRY(c, hipGetLastError(), "normalise launch");
+        if (two) HIP_TRY(c, hipEventRecord(c->ev_sft[2 + b], c->side), "event record");
     }
+    if (two)
+        for (int b = 0; b < 2 && b < k; ++b)
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_sft[2 + b], 0), "normalise join");
     return LTGW_OK;
 }
 
