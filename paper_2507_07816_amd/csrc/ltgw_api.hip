@@ -993,6 +993,12 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
         }
         std::memcpy((ltgw_template *)c->h_list.p + lo, tpl + lo, (size_t)(hi - lo) * sizeof(ltgw_template));
     });
+    // the staging holds the whole list now: its upload runs while the host
+    // finishes the order
+    if ((rc = ensure(c, c->list_d, (size_t)n * sizeof(ltgw_template), "template list")) != LTGW_OK) return rc;
+    if ((rc = ensure(c, c->perm_d, (size_t)n * 4, "template order")) != LTGW_OK) return rc;
+    if ((rc = h2d(c, c->list_d.p, c->h_list.p, (size_t)n * sizeof(ltgw_template), "template upload")) != LTGW_OK)
+        return rc;
     int32_t next = 0;
     for (int b = 0; b < kBuckets; ++b)
         for (int t = 0; t < nt; ++t) {
@@ -1007,10 +1013,6 @@ int32_t ltgw_eval_list(ltgw_ctx *c, const ltgw_template *tpl, int64_t n, double 
         for (int64_t q = chunk_lo(n, nt, t), hi = chunk_lo(n, nt, t + 1); q < hi; ++q)
             perm[at[key[(size_t)q]]++] = (int32_t)q;
     });
-    if ((rc = ensure(c, c->list_d, (size_t)n * sizeof(ltgw_template), "template list")) != LTGW_OK) return rc;
-    if ((rc = ensure(c, c->perm_d, (size_t)n * 4, "template order")) != LTGW_OK) return rc;
-    if ((rc = h2d(c, c->list_d.p, c->h_list.p, (size_t)n * sizeof(ltgw_template), "template upload")) != LTGW_OK)
-        return rc;
     if ((rc = h2d(c, c->perm_d.p, c->h_perm.p, (size_t)n * 4, "template order upload")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->res_s, n * 8, "results s")) != LTGW_OK) return rc;
     if ((rc = ensure(c, c->res_c, n * 4, "results c")) != LTGW_OK) return rc;
